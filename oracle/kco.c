@@ -1,0 +1,459 @@
+/*
+ * kco.c -- CPU oracle for the snapshot / validation hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY (see kco.h).  Plain, slow, single-threaded C99,
+ * compiled without fast-math and with FP contraction off so that every fp64
+ * operation is one IEEE-754 round-to-nearest-even operation.
+ */
+#include "kco.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PAGE 4096u
+
+/* ------------------------------------------------------------------------ */
+/* XXH64, written from the public xxHash specification (Y. Collet): four     */
+/* accumulators over 32-byte stripes, merge, length, tail, avalanche.        */
+/* ------------------------------------------------------------------------ */
+
+static const uint64_t PRIME1 = 0x9E3779B185EBCA87ULL;
+static const uint64_t PRIME2 = 0xC2B2AE3D27D4EB4FULL;
+static const uint64_t PRIME3 = 0x165667B19E3779F9ULL;
+static const uint64_t PRIME4 = 0x85EBCA77C2B2AE63ULL;
+static const uint64_t PRIME5 = 0x27D4EB2F165667C5ULL;
+
+static uint64_t rotate_left(uint64_t x, unsigned r) {
+  return (x << r) | (x >> (64u - r));
+}
+
+static uint64_t read_u64_le(const uint8_t *p) {
+  uint64_t v = 0;
+  for (int i = 7; i >= 0; --i) v = (v << 8) | (uint64_t)p[i];
+  return v;
+}
+
+static uint32_t read_u32_le(const uint8_t *p) {
+  uint32_t v = 0;
+  for (int i = 3; i >= 0; --i) v = (v << 8) | (uint32_t)p[i];
+  return v;
+}
+
+static uint64_t xxh_round(uint64_t acc, uint64_t lane) {
+  acc = acc + lane * PRIME2;
+  acc = rotate_left(acc, 31);
+  return acc * PRIME1;
+}
+
+static uint64_t xxh_merge_accumulator(uint64_t acc, uint64_t v) {
+  acc = acc ^ xxh_round(0, v);
+  return acc * PRIME1 + PRIME4;
+}
+
+uint64_t kco_xxh64(const void *data, uint64_t len, uint64_t seed) {
+  const uint8_t *p = (const uint8_t *)data;
+  uint64_t remaining = len;
+  uint64_t acc;
+  if (len >= 32) {
+    uint64_t v1 = seed + PRIME1 + PRIME2;
+    uint64_t v2 = seed + PRIME2;
+    uint64_t v3 = seed;
+    uint64_t v4 = seed - PRIME1;
+    while (remaining >= 32) {
+      v1 = xxh_round(v1, read_u64_le(p + 0));
+      v2 = xxh_round(v2, read_u64_le(p + 8));
+      v3 = xxh_round(v3, read_u64_le(p + 16));
+      v4 = xxh_round(v4, read_u64_le(p + 24));
+      p += 32;
+      remaining -= 32;
+    }
+    acc = rotate_left(v1, 1) + rotate_left(v2, 7) + rotate_left(v3, 12) +
+          rotate_left(v4, 18);
+    acc = xxh_merge_accumulator(acc, v1);
+    acc = xxh_merge_accumulator(acc, v2);
+    acc = xxh_merge_accumulator(acc, v3);
+    acc = xxh_merge_accumulator(acc, v4);
+  } else {
+    acc = seed + PRIME5;
+  }
+  acc += len;
+  while (remaining >= 8) {
+    acc ^= xxh_round(0, read_u64_le(p));
+    acc = rotate_left(acc, 27) * PRIME1 + PRIME4;
+    p += 8;
+    remaining -= 8;
+  }
+  if (remaining >= 4) {
+    acc ^= (uint64_t)read_u32_le(p) * PRIME1;
+    acc = rotate_left(acc, 23) * PRIME2 + PRIME3;
+    p += 4;
+    remaining -= 4;
+  }
+  while (remaining > 0) {
+    acc ^= (uint64_t)(*p) * PRIME5;
+    acc = rotate_left(acc, 11) * PRIME1;
+    p += 1;
+    remaining -= 1;
+  }
+  acc ^= acc >> 33;
+  acc *= PRIME2;
+  acc ^= acc >> 29;
+  acc *= PRIME3;
+  acc ^= acc >> 32;
+  return acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Range table: the pointer-to-size map of tracked allocations               */
+/* (paper Sec. 4.1.1), as sorted, disjoint, page-aligned (base, size).       */
+/* ------------------------------------------------------------------------ */
+
+int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
+                    uint64_t *n_pages) {
+  uint64_t pages = 0;
+  if (n > 0 && ranges == NULL) return KCO_EINVAL;
+  if (first_page) first_page[0] = 0;
+  for (uint32_t a = 0; a < n; ++a) {
+    uint64_t base = ranges[a].base, size = ranges[a].size;
+    if (base == 0 || size == 0) return KCO_EINVAL;
+    if (base % PAGE != 0 || size % PAGE != 0) return KCO_EALIGN;
+    if (base + size < base) return KCO_EINVAL; /* wraps around 2^64 */
+    if (a > 0) {
+      uint64_t prev_end = ranges[a - 1].base + ranges[a - 1].size;
+      if (base < prev_end) return KCO_EORDER;
+    }
+    pages += size / PAGE;
+    if (first_page) first_page[a + 1] = pages;
+  }
+  if (n_pages) *n_pages = pages;
+  return KCO_OK;
+}
+
+int kco_default_window(const kco_range *ranges, uint32_t n, uint64_t *lo,
+                       uint64_t *hi) {
+  const uint64_t margin = 1ULL << 32; /* 4 GiB either side */
+  if (n == 0) {
+    *lo = 0;
+    *hi = 0;
+    return KCO_OK;
+  }
+  uint64_t min_base = ranges[0].base;
+  uint64_t max_end = ranges[n - 1].base + ranges[n - 1].size;
+  *lo = (min_base > margin + PAGE) ? min_base - margin : PAGE;
+  *hi = (max_end <= UINT64_MAX - margin) ? max_end + margin : UINT64_MAX;
+  return KCO_OK;
+}
+
+static int bit_get(const uint64_t *bm, uint64_t g) {
+  return (int)((bm[g / 64] >> (g % 64)) & 1u);
+}
+
+static void bit_set(uint64_t *bm, uint64_t g) {
+  bm[g / 64] |= 1ULL << (g % 64);
+}
+
+static int page_is_zero(const uint8_t *page) {
+  for (uint32_t i = 0; i < PAGE; ++i)
+    if (page[i] != 0) return 0;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Snapshot: page hash + zero + changed                                      */
+/* ------------------------------------------------------------------------ */
+
+int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
+                  uint32_t n, uint64_t seed, const uint64_t *prior,
+                  uint64_t *hash, uint64_t *zero_bm, uint64_t *changed_bm) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (n_pages > 0 && (hash == NULL || zero_bm == NULL)) return KCO_EINVAL;
+  if (prior != NULL && changed_bm == NULL) return KCO_EINVAL;
+  uint64_t n_words = (n_pages + 63) / 64;
+  for (uint64_t w = 0; w < n_words; ++w) {
+    zero_bm[w] = 0;
+    if (prior) changed_bm[w] = 0;
+  }
+  uint64_t g = 0;
+  for (uint32_t a = 0; a < n; ++a) {
+    uint64_t pages = ranges[a].size / PAGE;
+    for (uint64_t p = 0; p < pages; ++p, ++g) {
+      const uint8_t *page = host_ptr[a] + p * PAGE;
+      hash[g] = kco_xxh64(page, PAGE, seed);
+      if (page_is_zero(page)) bit_set(zero_bm, g);
+      if (prior && hash[g] != prior[g]) bit_set(changed_bm, g);
+    }
+  }
+  return KCO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Snapshot: compaction of the kept pages, ascending g                       */
+/* ------------------------------------------------------------------------ */
+
+int kco_compact(const kco_range *ranges, const uint8_t *const *host_ptr,
+                uint32_t n, const uint64_t *zero_bm, const uint64_t *changed_bm,
+                uint8_t *packed, uint64_t *page_va, uint64_t cap_pages,
+                uint64_t *n_kept) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (n_kept == NULL || (n_pages > 0 && zero_bm == NULL)) return KCO_EINVAL;
+  if (cap_pages > 0 && (packed == NULL || page_va == NULL)) return KCO_EINVAL;
+  uint64_t g = 0, slot = 0;
+  for (uint32_t a = 0; a < n; ++a) {
+    uint64_t pages = ranges[a].size / PAGE;
+    for (uint64_t p = 0; p < pages; ++p, ++g) {
+      int keep = !bit_get(zero_bm, g);
+      if (changed_bm != NULL) keep = keep && bit_get(changed_bm, g);
+      if (!keep) continue;
+      if (slot < cap_pages) {
+        memcpy(packed + slot * PAGE, host_ptr[a] + p * PAGE, PAGE);
+        page_va[slot] = ranges[a].base + p * PAGE;
+      }
+      ++slot;
+    }
+  }
+  *n_kept = slot;
+  return KCO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Restore at the original VAs                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Index of the range holding address va, or -1. */
+static int64_t find_range(const kco_range *ranges, uint32_t n, uint64_t va) {
+  uint32_t lo = 0, hi = n; /* search in [lo, hi) for last base <= va */
+  if (n == 0 || va < ranges[0].base) return -1;
+  while (hi - lo > 1) {
+    uint32_t mid = lo + (hi - lo) / 2;
+    if (ranges[mid].base <= va)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  if (va - ranges[lo].base < ranges[lo].size) return (int64_t)lo;
+  return -1;
+}
+
+int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
+                const uint64_t *zero_bm, const uint64_t *changed_bm,
+                const uint8_t *packed, const uint64_t *page_va,
+                uint64_t n_kept, uint64_t cap_pages, uint64_t *n_bad) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (n_pages > 0 && zero_bm == NULL) return KCO_EINVAL;
+  uint64_t n_copy = n_kept < cap_pages ? n_kept : cap_pages;
+  if (n_copy > 0 && (packed == NULL || page_va == NULL)) return KCO_EINVAL;
+  /* 1. zero-fill the selected zero pages */
+  uint64_t g = 0;
+  for (uint32_t a = 0; a < n; ++a) {
+    uint64_t pages = ranges[a].size / PAGE;
+    for (uint64_t p = 0; p < pages; ++p, ++g) {
+      int selected = changed_bm == NULL || bit_get(changed_bm, g);
+      if (selected && bit_get(zero_bm, g))
+        memset(host_ptr[a] + p * PAGE, 0, PAGE);
+    }
+  }
+  /* 2. scatter every packed page back to the VA the page table names */
+  uint64_t bad = 0;
+  for (uint64_t s = 0; s < n_copy; ++s) {
+    uint64_t va = page_va[s];
+    int64_t a = (va % PAGE == 0) ? find_range(ranges, n, va) : -1;
+    if (a < 0) {
+      ++bad;
+      continue;
+    }
+    memcpy(host_ptr[a] + (va - ranges[a].base), packed + s * PAGE, PAGE);
+  }
+  if (n_bad) *n_bad = bad;
+  return KCO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closure scan                                                              */
+/* ------------------------------------------------------------------------ */
+
+int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
+                     uint32_t n, uint64_t win_lo, uint64_t win_hi,
+                     kco_scan_result *res, kco_oob *oob, uint64_t oob_cap) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (res == NULL || (oob_cap > 0 && oob == NULL)) return KCO_EINVAL;
+  if (win_lo == 0 && win_hi == 0)
+    kco_default_window(ranges, n, &win_lo, &win_hi);
+  else if (win_lo == 0 || win_lo >= win_hi)
+    return KCO_EINVAL;
+  memset(res, 0, sizeof(*res));
+  for (uint32_t a = 0; a < n; ++a) {
+    for (uint64_t off = 0; off < ranges[a].size; off += 8) {
+      uint64_t w = read_u64_le(host_ptr[a] + off);
+      res->n_words += 1;
+      if (w < win_lo || w >= win_hi) continue;
+      res->n_ptr_like += 1;
+      if (find_range(ranges, n, w) >= 0) {
+        res->n_in_range += 1;
+      } else {
+        if (res->n_oob < oob_cap) {
+          oob[res->n_oob].word_va = ranges[a].base + off;
+          oob[res->n_oob].value = w;
+        }
+        res->n_oob += 1;
+      }
+    }
+  }
+  res->n_written = (uint32_t)(res->n_oob < oob_cap ? res->n_oob : oob_cap);
+  res->truncated = res->n_oob > oob_cap ? 1u : 0u;
+  return KCO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Typed compare                                                             */
+/* ------------------------------------------------------------------------ */
+
+static uint32_t elem_size(uint32_t dtype) {
+  switch (dtype) {
+    case KCO_F32: return 4;
+    case KCO_BF16: return 2;
+    case KCO_F16: return 2;
+    case KCO_FP8_E4M3FN: return 1;
+    case KCO_U8: return 1;
+    default: return 0;
+  }
+}
+
+static uint32_t read_elem_bits(const uint8_t *p, uint32_t size) {
+  uint32_t v = 0;
+  for (int i = (int)size - 1; i >= 0; --i) v = (v << 8) | (uint32_t)p[i];
+  return v;
+}
+
+/* magnitude mask, sign bit, NaN test, and exact value of an encoding */
+static uint32_t mag_mask(uint32_t dtype) {
+  switch (dtype) {
+    case KCO_F32: return 0x7FFFFFFFu;
+    case KCO_BF16: return 0x7FFFu;
+    case KCO_F16: return 0x7FFFu;
+    default: return 0x7Fu; /* fp8 e4m3fn */
+  }
+}
+
+static int is_nan_bits(uint32_t dtype, uint32_t bits) {
+  uint32_t mag = bits & mag_mask(dtype);
+  switch (dtype) {
+    case KCO_F32: return mag > 0x7F800000u;
+    case KCO_BF16: return mag > 0x7F80u;
+    case KCO_F16: return mag > 0x7C00u;
+    default: return mag == 0x7Fu;
+  }
+}
+
+static double decode_value(uint32_t dtype, uint32_t bits) {
+  uint32_t mag = bits & mag_mask(dtype);
+  int negative = (bits & (mag_mask(dtype) + 1u)) != 0;
+  double v;
+  if (dtype == KCO_F32 || dtype == KCO_BF16) {
+    /* bf16 is the upper half of an fp32 encoding */
+    uint32_t f32 = dtype == KCO_F32 ? mag : (mag << 16);
+    uint32_t e = f32 >> 23, m = f32 & 0x7FFFFFu;
+    if (e == 0)
+      v = ldexp((double)m, -149);
+    else if (e == 255)
+      v = INFINITY; /* NaN never reaches decode */
+    else
+      v = ldexp((double)(m | 0x800000u), (int)e - 150);
+  } else if (dtype == KCO_F16) {
+    uint32_t e = mag >> 10, m = mag & 0x3FFu;
+    if (e == 0)
+      v = ldexp((double)m, -24);
+    else if (e == 31)
+      v = INFINITY;
+    else
+      v = ldexp((double)(m | 0x400u), (int)e - 25);
+  } else { /* OCP fp8 e4m3fn: bias 7, no infinities */
+    uint32_t e = mag >> 3, m = mag & 0x7u;
+    if (e == 0)
+      v = ldexp((double)m, -9);
+    else
+      v = ldexp((double)(m | 0x8u), (int)e - 10);
+  }
+  return negative ? -v : v;
+}
+
+int kco_ulp(uint32_t dtype, uint32_t cand_bits, uint32_t gold_bits,
+            uint64_t *dist) {
+  if (dtype > KCO_FP8_E4M3FN) return KCO_EDTYPE;
+  uint32_t mm = mag_mask(dtype), sign = mm + 1u;
+  int64_t oc = (int64_t)(cand_bits & mm), og = (int64_t)(gold_bits & mm);
+  if (cand_bits & sign) oc = -oc;
+  if (gold_bits & sign) og = -og;
+  *dist = (uint64_t)(oc > og ? oc - og : og - oc);
+  return KCO_OK;
+}
+
+uint32_t kco_ulp_bin(uint64_t dist) {
+  if (dist <= 16) return (uint32_t)dist;
+  uint32_t k = 0; /* smallest k with 2^k >= dist */
+  while ((1ULL << k) < dist) ++k;
+  return 12u + k;
+}
+
+int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
+                uint32_t dtype, uint32_t ulp_tol, kco_cmp_result *res) {
+  if (res == NULL) return KCO_EINVAL;
+  uint32_t es = elem_size(dtype);
+  if (es == 0) return KCO_EDTYPE;
+  if (n_elems > 0 && (cand == NULL || gold == NULL)) return KCO_EINVAL;
+  memset(res, 0, sizeof(*res));
+  res->n_elems = n_elems;
+  res->first_mismatch = UINT64_MAX;
+  const uint8_t *cb = (const uint8_t *)cand, *gb = (const uint8_t *)gold;
+  for (uint64_t i = 0; i < n_elems; ++i) {
+    const uint8_t *pc = cb + i * es, *pg = gb + i * es;
+    uint32_t c = read_elem_bits(pc, es), g = read_elem_bits(pg, es);
+    if (c != g) {
+      res->n_mismatch_elems += 1;
+      if (res->first_mismatch == UINT64_MAX) res->first_mismatch = i;
+      for (uint32_t b = 0; b < es; ++b)
+        if (pc[b] != pg[b]) res->n_mismatch_bytes += 1;
+    }
+    if (dtype == KCO_U8) continue;
+    int nan_c = is_nan_bits(dtype, c), nan_g = is_nan_bits(dtype, g);
+    if (nan_c && nan_g) {
+      res->n_nan_both += 1;
+      continue;
+    }
+    if (nan_c) {
+      res->n_nan_cand_only += 1;
+      continue;
+    }
+    if (nan_g) {
+      res->n_nan_gold_only += 1;
+      continue;
+    }
+    uint64_t d = 0;
+    kco_ulp(dtype, c, g, &d);
+    res->ulp_hist[kco_ulp_bin(d)] += 1;
+    if (d > ulp_tol) res->n_over_tol += 1;
+    if (c == g) continue; /* identical encodings: abs 0, rel 0 */
+    double vc = decode_value(dtype, c), vg = decode_value(dtype, g);
+    double abs_err = fabs(vc - vg);
+    if (abs_err > res->max_abs) res->max_abs = abs_err;
+    if (vg != 0.0 && !isinf(vg)) {
+      double rel = abs_err / fabs(vg);
+      if (rel > res->max_rel) res->max_rel = rel;
+    }
+  }
+  if (dtype == KCO_U8)
+    res->pass = res->n_mismatch_elems == 0;
+  else
+    res->pass = res->n_over_tol == 0 && res->n_nan_cand_only == 0 &&
+                res->n_nan_gold_only == 0;
+  res->status = 0;
+  return KCO_OK;
+}

@@ -1,0 +1,131 @@
+/*
+ * kco.h -- the CPU oracle for the snapshot / validation hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; only the test suite, the smoke check and the CPU leg of
+ * the benchmark load the oracle.  It shares no code, header, table or
+ * constant generator with the HIP library.
+ *
+ * Plain single-threaded C99, host pointers only, no SIMD, no threads.  Each
+ * entry point computes the plain definition of one step of the method:
+ *
+ *   - the snapshot of every tracked allocation at its own virtual address,
+ *     driven by the pointer-to-size map (paper Sec. 4.1.1 "Memory tracking",
+ *     Sec. 4.2.1 snapshot of all tracked memory), here as a per-4-KiB-page
+ *     XXH64 hash table, a zero-page bitmap, a changed-page bitmap against a
+ *     prior hash table, and a packed snapshot of the kept pages with a
+ *     page-VA table;
+ *   - the restore of captured data into each region at the same virtual
+ *     address (paper Sec. 4.5.1, replay stage 5; Sec. 4.2.1 address-space
+ *     closure);
+ *   - the closure scan: every 8-byte-aligned word that looks like a device
+ *     pointer must land inside a captured range (paper Sec. 4.2.1,
+ *     "Bounds of the closure", cases 1 and 3);
+ *   - the output compare: differing bytes (paper Sec. 4.5.2, byte-exact
+ *     comparison), and for floating-point buffers a ULP-distance report with
+ *     explicit NaN accounting (paper Sec. 4.5.2, tolerance comparison).
+ *
+ * Conventions shared with the product ABI (same meaning, independent code):
+ * a range is (base VA, size in bytes), base and size multiples of 4096,
+ * base > 0, ranges sorted by base and disjoint.  Global page index g numbers
+ * the pages of range 0 first, then range 1, ...  Bitmaps are arrays of u64,
+ * bit (g % 64) of word (g / 64); bits past the last page are 0.
+ *
+ * The data of range a is read from / written to host_ptr[a] (a host copy of
+ * the bytes that live at VA base_a on the device); VAs are only used as
+ * values (page-VA table, pointer tests), never dereferenced.
+ */
+#ifndef KCO_H
+#define KCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KCO_OK = 0,
+  KCO_EINVAL = -1, /* null pointer, empty range, zero base, bad window      */
+  KCO_EALIGN = -2, /* base or size not a multiple of 4096                   */
+  KCO_EORDER = -3, /* ranges unsorted or overlapping                        */
+  KCO_ENOMEM = -4,
+  KCO_EDTYPE = -6
+};
+
+enum { KCO_F32 = 0, KCO_BF16 = 1, KCO_F16 = 2, KCO_FP8_E4M3FN = 3, KCO_U8 = 4 };
+
+typedef struct {
+  uint64_t base, size;
+} kco_range;
+
+typedef struct {
+  uint64_t n_words, n_ptr_like, n_in_range, n_oob;
+  uint32_t n_written, truncated;
+} kco_scan_result;
+
+typedef struct {
+  uint64_t word_va, value;
+} kco_oob;
+
+typedef struct {
+  uint64_t n_elems, n_mismatch_elems, n_mismatch_bytes, first_mismatch;
+  uint64_t n_nan_both, n_nan_cand_only, n_nan_gold_only, n_over_tol;
+  double max_abs, max_rel;
+  uint64_t ulp_hist[48];
+  uint32_t pass, status;
+} kco_cmp_result;
+
+/* XXH64 of len bytes at data with the given seed (public xxHash definition). */
+uint64_t kco_xxh64(const void *data, uint64_t len, uint64_t seed);
+
+/* Validate ranges; on success *n_pages = total pages and, if first_page is
+ * non-null, first_page[0..n] = page prefix (first_page[n] = *n_pages). */
+int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
+                    uint64_t *n_pages);
+
+/* Pointer window used by the closure scan when the caller passes (0, 0). */
+int kco_default_window(const kco_range *ranges, uint32_t n, uint64_t *lo,
+                       uint64_t *hi);
+
+/* hash[g], zero bitmap and (if prior != NULL) changed bitmap for every page. */
+int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
+                  uint32_t n, uint64_t seed, const uint64_t *prior,
+                  uint64_t *hash, uint64_t *zero_bm, uint64_t *changed_bm);
+
+/* Packed snapshot of kept pages (changed_bm == NULL: keep = not zero;
+ * otherwise keep = changed and not zero), ascending g.  Pages past cap_pages
+ * are not written; *n_kept is the true count. */
+int kco_compact(const kco_range *ranges, const uint8_t *const *host_ptr,
+                uint32_t n, const uint64_t *zero_bm, const uint64_t *changed_bm,
+                uint8_t *packed, uint64_t *page_va, uint64_t cap_pages,
+                uint64_t *n_kept);
+
+/* Restore: zero-fill every selected zero page (all pages when changed_bm is
+ * NULL, else the changed ones), then scatter packed[s] to page_va[s] for
+ * s < min(n_kept, cap_pages).  A page_va that is not a page of some range is
+ * skipped and counted in *n_bad. */
+int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
+                const uint64_t *zero_bm, const uint64_t *changed_bm,
+                const uint8_t *packed, const uint64_t *page_va,
+                uint64_t n_kept, uint64_t cap_pages, uint64_t *n_bad);
+
+/* Closure scan over every 8-byte-aligned word of every range. */
+int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
+                     uint32_t n, uint64_t win_lo, uint64_t win_hi,
+                     kco_scan_result *res, kco_oob *oob, uint64_t oob_cap);
+
+/* Typed compare of one candidate / golden pair of n_elems elements. */
+int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
+                uint32_t dtype, uint32_t ulp_tol, kco_cmp_result *res);
+
+/* ULP distance and histogram bin of one element pair (exposed for tests). */
+int kco_ulp(uint32_t dtype, uint32_t cand_bits, uint32_t gold_bits,
+            uint64_t *dist);
+uint32_t kco_ulp_bin(uint64_t dist);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
