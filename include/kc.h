@@ -1,0 +1,276 @@
+/*
+ * kc.h -- C ABI of libkc.so, the MI355X (gfx950) snapshot / validation hot
+ * path behind VA-faithful kernel capture and reproducer validation.
+ *
+ * The method (Kerncap, arXiv 2605.03208) snapshots every tracked device
+ * allocation at its original virtual address so that pointers embedded in
+ * device memory stay valid on replay (Sec. 4.2.1, "address-space closure"),
+ * restores that state before re-dispatch (Sec. 4.5.1, replay stage 5), and
+ * validates a variant's outputs against the captured ones (Sec. 4.5.2).  This
+ * library is the data-parallel core of those steps, done on the GPU:
+ *
+ *   kc_page_hash     XXH64 per 4 KiB page, zero-page and changed-page bitmaps
+ *   kc_compact       prefix-scan compaction of kept pages + page-VA table
+ *   kc_snapshot      the two above fused into one pass over the data
+ *   kc_restore       zero-fill + scatter of packed pages back to their VAs
+ *   kc_closure_scan  every aligned u64 that looks like a pointer must land
+ *                    inside a captured range
+ *   kc_compare       candidate vs golden: byte / element mismatches, first
+ *                    mismatch, fp64 max abs / rel error, ULP histogram, NaNs
+ *
+ * Conventions
+ *  - Pointers suffixed _d are device pointers owned by the caller; the
+ *    library never frees caller memory.  Host pointers are read during the
+ *    call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls enqueue work and return; outputs are valid once the stream has
+ *    reached that point.  Except for kc_compare, a call allocates nothing
+ *    and never synchronises, so the sequence can be recorded into a graph.
+ *  - The return value reports synchronous argument checks and launch
+ *    failures only.  Conditions found on the device (capacity overflow,
+ *    truncated lists, rejected page addresses) are reported through outputs.
+ *  - A kc_ctx, and any kc_rangeset made from it, is used by one host thread
+ *    and one stream at a time: rangesets own the scratch their calls use.
+ *  - Ranges: (base VA, size) with base > 0, base and size multiples of 4096,
+ *    sorted by base, disjoint.  They are the pointer-to-size map of tracked
+ *    allocations (Sec. 4.1.1, memory tracking).  Page g of the set numbers
+ *    the pages of range 0 first, then range 1, and so on.
+ *  - Bitmaps: u64 words, page g is bit (g % 64) of word (g / 64); a bitmap
+ *    over N pages has ceil(N / 64) words and its bits past N are 0.
+ *  - Limits: fewer than 2^32 pages per rangeset, fewer than 2^31 ranges.
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KC_PAGE_SIZE 4096u
+#define KC_ABI_VERSION 1
+
+/* Status codes. */
+enum {
+  KC_OK = 0,
+  KC_EINVAL = -1,  /* null where non-null is required, empty range, base 0,
+                      bad window, size overflow                            */
+  KC_EALIGN = -2,  /* range not 4096-aligned / buffer not 16-byte aligned  */
+  KC_EORDER = -3,  /* ranges unsorted or overlapping                       */
+  KC_ENOMEM = -4,  /* device or pinned host allocation failed             */
+  KC_EHIP = -5,    /* a HIP runtime call failed; see kc_last_error()       */
+  KC_EDTYPE = -6,  /* unknown element type                                 */
+  KC_ELIMIT = -7   /* a documented size limit is exceeded                  */
+};
+
+/* Element types understood by kc_compare. */
+enum {
+  KC_F32 = 0,         /* IEEE binary32                                       */
+  KC_BF16 = 1,        /* bfloat16 (upper half of binary32)                   */
+  KC_F16 = 2,         /* IEEE binary16                                       */
+  KC_FP8_E4M3FN = 3,  /* OCP fp8 E4M3 "fn": bias 7, no inf, NaN = S.1111.111 */
+  KC_U8 = 4           /* raw bytes                                           */
+};
+
+typedef struct kc_ctx kc_ctx;
+typedef struct kc_rangeset kc_rangeset;
+
+typedef struct {
+  uint64_t base; /* device VA of the allocation */
+  uint64_t size; /* bytes                       */
+} kc_range;
+
+/* Closure-scan totals. */
+typedef struct {
+  uint64_t n_words;    /* aligned u64 words scanned                           */
+  uint64_t n_ptr_like; /* words inside the pointer window                     */
+  uint64_t n_in_range; /* pointer-like words inside some range                */
+  uint64_t n_oob;      /* pointer-like words outside every range (exact)      */
+  uint32_t n_written;  /* min(n_oob, oob_cap) entries written to the list     */
+  uint32_t truncated;  /* 1 iff n_oob > oob_cap                               */
+} kc_scan_result;
+
+/* One out-of-range pointer-like word: where it sits and what it holds. */
+typedef struct {
+  uint64_t word_va;
+  uint64_t value;
+} kc_oob;
+
+/* Closure-scan arguments.  A word w is pointer-like iff win_lo <= w < win_hi;
+ * (0, 0) selects [min_base - 4 GiB, max_end + 4 GiB) clamped to [4096, 2^64-1].
+ * Otherwise 1 <= win_lo < win_hi is required (a null word is never a pointer).
+ * The list holds the first min(n_oob, oob_cap) words in ascending address. */
+typedef struct {
+  uint64_t win_lo, win_hi;
+  kc_scan_result *res_d; /* device, one struct                          */
+  kc_oob *oob_d;         /* device, oob_cap entries (may be NULL if 0)  */
+  uint64_t oob_cap;
+} kc_scan_args;
+
+/* One candidate / golden pair for kc_compare.  Both buffers 16-byte aligned
+ * device memory of n_elems elements of `dtype`. */
+typedef struct {
+  const void *cand_d;
+  const void *gold_d;
+  uint64_t n_elems;
+  uint32_t dtype;
+  uint32_t ulp_tol; /* an element fails if its ULP distance exceeds this */
+} kc_pair;
+
+/* Per-pair compare report (472 bytes). */
+typedef struct {
+  uint64_t n_elems;
+  uint64_t n_mismatch_elems; /* elements whose encodings differ            */
+  uint64_t n_mismatch_bytes; /* byte positions that differ                 */
+  uint64_t first_mismatch;   /* lowest differing element, UINT64_MAX if none */
+  uint64_t n_nan_both;       /* both NaN: passes, excluded from the rest   */
+  uint64_t n_nan_cand_only;  /* fails, excluded from the rest              */
+  uint64_t n_nan_gold_only;  /* fails, excluded from the rest              */
+  uint64_t n_over_tol;       /* non-NaN elements with ULP distance > tol   */
+  double max_abs;            /* max |c - g| in fp64 over non-NaN elements  */
+  double max_rel;            /* max |c - g| / |g| over finite non-zero g   */
+  uint64_t ulp_hist[48];     /* bin d for d <= 16, else 12 + ceil(log2 d)  */
+  uint32_t pass;             /* no over-tolerance element and no lone NaN;
+                                KC_U8: no differing byte                   */
+  uint32_t status;           /* 0                                          */
+} kc_cmp_result;
+
+/* Launch shape of one operation.  Zero fields keep the built-in choice. */
+typedef struct {
+  uint32_t grid_per_cu; /* persistent workgroups per compute unit          */
+  uint32_t tile_bytes;  /* compare: bytes of each side per work item        */
+  uint32_t per_item;    /* 1 = one launch per range / pair (no batching)    */
+  uint32_t reserved;
+} kc_tuning;
+
+enum {
+  KC_OP_PAGE_HASH = 0,
+  KC_OP_SNAPSHOT = 1,
+  KC_OP_COMPACT = 2,
+  KC_OP_RESTORE = 3,
+  KC_OP_CLOSURE = 4,
+  KC_OP_COMPARE = 5,
+  KC_OP_COUNT = 6
+};
+
+/* ---- host-only helpers (no device needed) ---------------------------- */
+
+/* Static text for a status code. */
+const char *kc_strerror(int code);
+
+/* Text of the last failure on this thread (HIP error name and call site). */
+const char *kc_last_error(void);
+
+/* KC_ABI_VERSION of the loaded library. */
+int kc_abi_version(void);
+
+/* Validate a range list as kc_rangeset_create does, without a device.
+ * On KC_OK *n_pages (if non-NULL) is the page count. */
+int kc_range_check(const kc_range *ranges, uint32_t n, uint64_t *n_pages);
+
+/* The pointer window kc_closure_scan uses for (0, 0). */
+int kc_default_window(const kc_range *ranges, uint32_t n, uint64_t *win_lo,
+                      uint64_t *win_hi);
+
+/* ---- context and range sets ------------------------------------------- */
+
+/* Create a context on HIP device `hip_device` (made current for the call).
+ * Owns launch tuning and the scratch of kc_compare. */
+int kc_ctx_create(kc_ctx **out, int hip_device);
+void kc_ctx_destroy(kc_ctx *ctx);
+
+/* Set / read the launch shape of an operation (KC_OP_*). */
+int kc_ctx_set_tuning(kc_ctx *ctx, uint32_t op, const kc_tuning *t);
+int kc_ctx_get_tuning(const kc_ctx *ctx, uint32_t op, kc_tuning *t);
+
+/* Kernel timing for measurement.  When on, each call records a pair of HIP
+ * events on its stream around the launches of its main kernel (the hashing
+ * pass of kc_page_hash / kc_snapshot, the gather of kc_compact, the scatter of
+ * kc_restore, the scanning pass of kc_closure_scan, the compare pass of
+ * kc_compare).  kc_ctx_kernel_ms waits for the last pair recorded for `op`
+ * and returns the elapsed milliseconds (KC_EINVAL if none was recorded).
+ * Off by default; leave it off while a stream is being captured. */
+int kc_ctx_enable_timing(kc_ctx *ctx, int on);
+int kc_ctx_kernel_ms(kc_ctx *ctx, uint32_t op, float *ms);
+
+/* Upload a validated range list (the tracked-allocation map) and allocate
+ * the scratch its calls need (about 40 bytes per page).  Synchronous.
+ * Errors: KC_EINVAL / KC_EALIGN / KC_EORDER as kc_range_check, KC_ELIMIT,
+ * KC_ENOMEM, KC_EHIP.  *n_pages (if non-NULL) receives the page count. */
+int kc_rangeset_create(kc_ctx *ctx, const kc_range *ranges, uint32_t n,
+                       kc_rangeset **out, uint64_t *n_pages);
+void kc_rangeset_destroy(kc_rangeset *rs);
+
+/* ---- snapshot (Sec. 4.2.1: snapshot of all tracked memory) ------------- */
+
+/* Hash every page: hash_d[g] = XXH64(page g, seed) (the public xxHash
+ * definition over the page's 4096 bytes).  zero_bm_d bit g = page g is all
+ * zero.  If prior_hash_d is non-NULL, changed_bm_d (then required) bit g =
+ * hash_d[g] != prior_hash_d[g].  If scan is non-NULL the closure scan runs in
+ * the same pass over the data (same results as kc_closure_scan).
+ * Sizes: hash_d / prior_hash_d N u64, bitmaps ceil(N/64) u64. */
+int kc_page_hash(kc_ctx *ctx, const kc_rangeset *rs, uint64_t seed,
+                 const uint64_t *prior_hash_d, uint64_t *hash_d,
+                 uint64_t *zero_bm_d, uint64_t *changed_bm_d,
+                 const kc_scan_args *scan, void *stream);
+
+/* Compact the kept pages in ascending g: keep = not zero (changed_bm_d NULL)
+ * or changed and not zero (delta).  packed_d[s*4096 ...] receives the page of
+ * slot s and page_va_d[s] its VA, for s < cap_pages; *n_kept_d (device u64)
+ * receives the exact kept count even when it exceeds cap_pages. */
+int kc_compact(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
+               const uint64_t *changed_bm_d, void *packed_d,
+               uint64_t *page_va_d, uint64_t cap_pages, uint64_t *n_kept_d,
+               void *stream);
+
+/* kc_page_hash followed by kc_compact with identical outputs.  Without a
+ * prior (full snapshot) the data is read once: a probe of each page's first
+ * 64 bytes (the whole page only when those are zero) fixes the zero bitmap
+ * and the slots, then one pass hashes, scans and writes the packed pages.
+ * With a prior (delta snapshot) the kept set depends on the hashes, so the
+ * changed pages are read a second time. */
+int kc_snapshot(kc_ctx *ctx, const kc_rangeset *rs, uint64_t seed,
+                const uint64_t *prior_hash_d, uint64_t *hash_d,
+                uint64_t *zero_bm_d, uint64_t *changed_bm_d, void *packed_d,
+                uint64_t *page_va_d, uint64_t cap_pages, uint64_t *n_kept_d,
+                const kc_scan_args *scan, void *stream);
+
+/* ---- restore (Sec. 4.5.1, replay stage 5: copy captured data into each
+ *      region at its original VA) ----------------------------------------- */
+
+/* 1) zero-fill every selected zero page (all pages for a full snapshot,
+ *    changed_bm_d NULL; the changed ones for a delta); then
+ * 2) copy packed_d page s to page_va_d[s] for s < min(*n_kept_d, cap_pages).
+ * A page_va that is not a 4096-aligned address inside some range is skipped
+ * and counted into *n_bad_d (device u64, set by the call; may be NULL). */
+int kc_restore(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
+               const uint64_t *changed_bm_d, const void *packed_d,
+               const uint64_t *page_va_d, const uint64_t *n_kept_d,
+               uint64_t cap_pages, uint64_t *n_bad_d, void *stream);
+
+/* ---- validation ----------------------------------------------------------- */
+
+/* Closure scan (Sec. 4.2.1, address-space closure and its bounds): every
+ * 8-byte-aligned word of every range is tested against the window; a
+ * pointer-like word is in range iff base_r <= w < base_r + size_r for some r
+ * (half-open: one past the end is out of range). */
+int kc_closure_scan(kc_ctx *ctx, const kc_rangeset *rs,
+                    const kc_scan_args *scan, void *stream);
+
+/* Compare each pair (Sec. 4.5.2: byte-exact comparison reports differing
+ * bytes; tolerance comparison reports NaNs explicitly).  Per element, bitwise
+ * equal -> distance 0; both NaN -> n_nan_both; one NaN -> n_nan_*_only;
+ * otherwise the ULP distance |ord(c) - ord(g)| with ord = +-magnitude bits
+ * goes to the histogram and the fp64 errors.  res_d: n_pairs device structs.
+ * All pairs run in one persistent launch unless the tuning sets per_item.
+ * Grows ctx scratch on demand and stages the pair list through pinned host
+ * memory: not for graph capture.  Errors: KC_EDTYPE, KC_EALIGN, KC_EINVAL. */
+int kc_compare(kc_ctx *ctx, const kc_pair *pairs, uint32_t n_pairs,
+               kc_cmp_result *res_d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

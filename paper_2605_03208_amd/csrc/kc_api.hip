@@ -1,0 +1,631 @@
+// kc_api.hip -- the extern "C" entry points of libkc.so: argument checks,
+// range-set upload, scratch ownership and the launch sequence of each op.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kc_internal.h"
+
+using namespace kc;
+
+struct kc_ctx {
+  int device = 0;
+  uint32_t n_cu = 256;
+  kc_tuning tune[KC_OP_COUNT];
+  uint8_t* cmp_dev = nullptr;  // pairs | tiles | accumulators
+  size_t cmp_dev_cap = 0;
+  uint8_t* cmp_host = nullptr;  // pinned staging of pairs | tiles
+  size_t cmp_host_cap = 0;
+  hipEvent_t staged = nullptr;  // completion of the last staging copy
+  bool staged_pending = false;
+  bool timing = false;  // record events around the main kernel of each op
+  hipEvent_t t_start[KC_OP_COUNT] = {};
+  hipEvent_t t_stop[KC_OP_COUNT] = {};
+  bool t_valid[KC_OP_COUNT] = {};
+};
+
+struct kc_rangeset {
+  kc_ctx* ctx = nullptr;
+  uint32_t n_ranges = 0, n_tiles = 0;
+  uint64_t n_pages = 0, n_words = 0;
+  std::vector<uint32_t> range_tile;  // first tile of each range (n + 1)
+  uint64_t win_lo = 0, win_hi = 0;   // default pointer window
+  void* dev = nullptr;
+  Tile* tiles = nullptr;
+  uint64_t* bases = nullptr;
+  uint64_t* ends = nullptr;
+  uint32_t* tile_oob = nullptr;
+  uint64_t* tile_prefix = nullptr;
+  uint64_t* word_prefix = nullptr;
+  uint64_t* block_sums = nullptr;
+  unsigned long long* counts = nullptr;  // [0] ptr-like, [1] in-range, [2] rejected page VAs
+  uint64_t* n_oob = nullptr;
+  RangeTable rt{};
+};
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+void set_error(const char* what, hipError_t e) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%s)", what, hipGetErrorName(e),
+                hipGetErrorString(e));
+}
+
+#define KC_HIP(call)                          \
+  do {                                        \
+    hipError_t kc_e_ = (call);                \
+    if (kc_e_ != hipSuccess) {                \
+      set_error(#call, kc_e_);                \
+      return KC_EHIP;                         \
+    }                                         \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+constexpr uint64_t kMaxPages = (1ull << 32) - 1;
+constexpr uint32_t kMaxRanges = 1u << 31;
+
+int range_check(const kc_range* r, uint32_t n, uint64_t* n_pages) {
+  if (n > 0 && r == nullptr) return KC_EINVAL;
+  if (n >= kMaxRanges) return KC_ELIMIT;
+  uint64_t pages = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint64_t base = r[i].base, size = r[i].size;
+    if (base == 0 || size == 0) return KC_EINVAL;
+    if ((base | size) & (KC_PAGE_SIZE - 1)) return KC_EALIGN;
+    if (base + size < base) return KC_EINVAL;
+    if (i > 0 && base < r[i - 1].base + r[i - 1].size) return KC_EORDER;
+    pages += size / KC_PAGE_SIZE;
+    if (pages > kMaxPages) return KC_ELIMIT;
+  }
+  if (n_pages) *n_pages = pages;
+  return KC_OK;
+}
+
+void default_window(const kc_range* r, uint32_t n, uint64_t* lo, uint64_t* hi) {
+  const uint64_t margin = 1ull << 32;
+  if (n == 0) {
+    *lo = *hi = 0;
+    return;
+  }
+  const uint64_t min_base = r[0].base, max_end = r[n - 1].base + r[n - 1].size;
+  *lo = min_base > margin + KC_PAGE_SIZE ? min_base - margin : KC_PAGE_SIZE;
+  *hi = max_end <= UINT64_MAX - margin ? max_end + margin : UINT64_MAX;
+}
+
+uint32_t grid_for(const kc_ctx* c, uint32_t op, uint32_t fallback_per_cu) {
+  const uint32_t per = c->tune[op].grid_per_cu ? c->tune[op].grid_per_cu : fallback_per_cu;
+  return std::max(1u, c->n_cu * per);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Brackets the main-kernel launches of one op with timing events when enabled.
+struct KernelTimer {
+  kc_ctx* c;
+  uint32_t op;
+  hipStream_t s;
+  KernelTimer(kc_ctx* c_, uint32_t op_, hipStream_t s_) : c(c_), op(op_), s(s_) {
+    if (c->timing) (void)hipEventRecord(c->t_start[op], s);
+  }
+  ~KernelTimer() {
+    if (c->timing && hipEventRecord(c->t_stop[op], s) == hipSuccess) c->t_valid[op] = true;
+  }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Resolve a closure-scan request into the device-side description.
+int make_scan(const kc_rangeset* rs, const kc_scan_args* sa, ScanDev* sd) {
+  if (sa->res_d == nullptr || (sa->oob_cap > 0 && sa->oob_d == nullptr)) return KC_EINVAL;
+  uint64_t lo = sa->win_lo, hi = sa->win_hi;
+  if (lo == 0 && hi == 0) {
+    lo = rs->win_lo;
+    hi = rs->win_hi;
+  } else if (lo == 0 || lo >= hi) {
+    return KC_EINVAL;
+  }
+  sd->lo = lo;
+  sd->span = hi - lo;
+  if (rs->n_ranges == 0) sd->span = 0;
+  sd->rt = rs->rt;
+  sd->tile_oob = rs->tile_oob;
+  sd->counts = rs->counts;
+  return KC_OK;
+}
+
+// Count-scan the per-tile out-of-range totals, emit the ordered list, write
+// the result struct.
+int finish_scan(kc_rangeset* rs, const kc_scan_args* sa, const ScanDev& sd, hipStream_t s) {
+  ScanSrc src{};
+  src.kind = kSrcCounts;
+  src.counts = rs->tile_oob;
+  src.n_items = rs->n_tiles;
+  KC_HIP(launch_scan(src, rs->tile_prefix, rs->block_sums, rs->n_oob, s));
+  KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, sa->oob_d, sa->oob_cap,
+                         grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
+  KC_HIP(launch_scan_finalize(sa->res_d, rs->counts, rs->n_oob, rs->n_pages * (KC_PAGE_SIZE / 8),
+                              sa->oob_cap, s));
+  return KC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kc_strerror(int code) {
+  switch (code) {
+    case KC_OK: return "ok";
+    case KC_EINVAL: return "invalid argument";
+    case KC_EALIGN: return "misaligned range or buffer";
+    case KC_EORDER: return "ranges unsorted or overlapping";
+    case KC_ENOMEM: return "out of memory";
+    case KC_EHIP: return "HIP runtime error";
+    case KC_EDTYPE: return "unknown element type";
+    case KC_ELIMIT: return "size limit exceeded";
+    default: return "unknown status";
+  }
+}
+
+const char* kc_last_error(void) { return g_last_error; }
+
+int kc_abi_version(void) { return KC_ABI_VERSION; }
+
+int kc_range_check(const kc_range* ranges, uint32_t n, uint64_t* n_pages) { return range_check(ranges, n, n_pages); }
+
+int kc_default_window(const kc_range* ranges, uint32_t n, uint64_t* win_lo, uint64_t* win_hi) {
+  if (win_lo == nullptr || win_hi == nullptr) return KC_EINVAL;
+  const int st = range_check(ranges, n, nullptr);
+  if (st != KC_OK) return st;
+  default_window(ranges, n, win_lo, win_hi);
+  return KC_OK;
+}
+
+int kc_ctx_create(kc_ctx** out, int hip_device) {
+  if (out == nullptr) return KC_EINVAL;
+  *out = nullptr;
+  DeviceGuard g(hip_device);
+  if (!g.ok) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "hipSetDevice(%d) failed", hip_device);
+    return KC_EHIP;
+  }
+  int cu = 0;
+  KC_HIP(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, hip_device));
+  kc_ctx* c = new (std::nothrow) kc_ctx();
+  if (c == nullptr) return KC_ENOMEM;
+  c->device = hip_device;
+  c->n_cu = cu > 0 ? (uint32_t)cu : 256u;
+  std::memset(c->tune, 0, sizeof(c->tune));
+  c->tune[KC_OP_COMPARE].tile_bytes = 64u << 10;
+  hipError_t e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    set_error("hipEventCreateWithFlags", e);
+    delete c;
+    return KC_EHIP;
+  }
+  *out = c;
+  return KC_OK;
+}
+
+void kc_ctx_destroy(kc_ctx* c) {
+  if (c == nullptr) return;
+  DeviceGuard g(c->device);
+  if (c->staged) {
+    (void)hipEventSynchronize(c->staged);
+    (void)hipEventDestroy(c->staged);
+  }
+  if (c->cmp_dev) (void)hipFree(c->cmp_dev);
+  if (c->cmp_host) (void)hipHostFree(c->cmp_host);
+  for (uint32_t op = 0; op < KC_OP_COUNT; ++op) {
+    if (c->t_start[op]) (void)hipEventDestroy(c->t_start[op]);
+    if (c->t_stop[op]) (void)hipEventDestroy(c->t_stop[op]);
+  }
+  delete c;
+}
+
+int kc_ctx_enable_timing(kc_ctx* c, int on) {
+  if (c == nullptr) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  if (on) {
+    for (uint32_t op = 0; op < KC_OP_COUNT; ++op) {
+      if (!c->t_start[op]) KC_HIP(hipEventCreate(&c->t_start[op]));
+      if (!c->t_stop[op]) KC_HIP(hipEventCreate(&c->t_stop[op]));
+    }
+  }
+  c->timing = on != 0;
+  return KC_OK;
+}
+
+int kc_ctx_kernel_ms(kc_ctx* c, uint32_t op, float* ms) {
+  if (c == nullptr || ms == nullptr || op >= KC_OP_COUNT || !c->t_valid[op]) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  KC_HIP(hipEventSynchronize(c->t_stop[op]));
+  KC_HIP(hipEventElapsedTime(ms, c->t_start[op], c->t_stop[op]));
+  return KC_OK;
+}
+
+int kc_ctx_set_tuning(kc_ctx* c, uint32_t op, const kc_tuning* t) {
+  if (c == nullptr || t == nullptr || op >= KC_OP_COUNT) return KC_EINVAL;
+  if (t->grid_per_cu > 1024u) return KC_EINVAL;
+  if (t->tile_bytes != 0 && (t->tile_bytes % 16u != 0 || t->tile_bytes < 4096u || t->tile_bytes > (64u << 20)))
+    return KC_EINVAL;
+  c->tune[op] = *t;
+  if (op == KC_OP_COMPARE && c->tune[op].tile_bytes == 0) c->tune[op].tile_bytes = 64u << 10;
+  return KC_OK;
+}
+
+int kc_ctx_get_tuning(const kc_ctx* c, uint32_t op, kc_tuning* t) {
+  if (c == nullptr || t == nullptr || op >= KC_OP_COUNT) return KC_EINVAL;
+  *t = c->tune[op];
+  return KC_OK;
+}
+
+int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangeset** out, uint64_t* n_pages_out) {
+  if (c == nullptr || out == nullptr) return KC_EINVAL;
+  *out = nullptr;
+  uint64_t n_pages = 0;
+  int st = range_check(ranges, n, &n_pages);
+  if (st != KC_OK) return st;
+  DeviceGuard g(c->device);
+  kc_rangeset* rs = new (std::nothrow) kc_rangeset();
+  if (rs == nullptr) return KC_ENOMEM;
+  rs->ctx = c;
+  rs->n_ranges = n;
+  rs->n_pages = n_pages;
+  rs->n_words = (n_pages + 63) / 64;
+  default_window(ranges, n, &rs->win_lo, &rs->win_hi);
+
+  std::vector<Tile> tiles;
+  std::vector<uint64_t> bases(n), ends(n);
+  rs->range_tile.assign(n + 1, 0);
+  uint64_t g0 = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    rs->range_tile[i] = (uint32_t)tiles.size();
+    const uint64_t pages = ranges[i].size / KC_PAGE_SIZE;
+    for (uint64_t p = 0; p < pages; p += kTilePages) {
+      Tile t;
+      t.va = ranges[i].base + p * KC_PAGE_SIZE;
+      t.g = (uint32_t)(g0 + p);
+      t.npages = (uint32_t)std::min<uint64_t>(kTilePages, pages - p);
+      tiles.push_back(t);
+    }
+    g0 += pages;
+    bases[i] = ranges[i].base;
+    ends[i] = ranges[i].base + ranges[i].size;
+  }
+  rs->range_tile[n] = (uint32_t)tiles.size();
+  rs->n_tiles = (uint32_t)tiles.size();
+
+  const uint64_t nb_words = (rs->n_words + 2047) / 2048, nb_tiles = ((uint64_t)rs->n_tiles + 2047) / 2048;
+  const size_t sz_tiles = align_up(sizeof(Tile) * std::max<size_t>(1, tiles.size()), 256);
+  const size_t sz_r = align_up(8 * std::max<size_t>(1, n), 256);
+  const size_t sz_oob = align_up(4 * std::max<size_t>(1, rs->n_tiles), 256);
+  const size_t sz_tp = align_up(8 * std::max<size_t>(1, rs->n_tiles), 256);
+  const size_t sz_wp = align_up(8 * std::max<uint64_t>(1, rs->n_words), 256);
+  const size_t sz_bs = align_up(8 * std::max<uint64_t>(1, std::max(nb_words, nb_tiles)), 256);
+  const size_t sz_misc = 256;
+  const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc;
+  hipError_t e = hipMalloc(&rs->dev, total);
+  if (e != hipSuccess) {
+    set_error("hipMalloc(rangeset)", e);
+    delete rs;
+    return e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
+  }
+  uint8_t* p = static_cast<uint8_t*>(rs->dev);
+  rs->tiles = reinterpret_cast<Tile*>(p); p += sz_tiles;
+  rs->bases = reinterpret_cast<uint64_t*>(p); p += sz_r;
+  rs->ends = reinterpret_cast<uint64_t*>(p); p += sz_r;
+  rs->tile_oob = reinterpret_cast<uint32_t*>(p); p += sz_oob;
+  rs->tile_prefix = reinterpret_cast<uint64_t*>(p); p += sz_tp;
+  rs->word_prefix = reinterpret_cast<uint64_t*>(p); p += sz_wp;
+  rs->block_sums = reinterpret_cast<uint64_t*>(p); p += sz_bs;
+  rs->counts = reinterpret_cast<unsigned long long*>(p);
+  rs->n_oob = reinterpret_cast<uint64_t*>(p + 64);
+
+  auto fail = [&](const char* what, hipError_t err) {
+    set_error(what, err);
+    (void)hipFree(rs->dev);
+    delete rs;
+    return KC_EHIP;
+  };
+  if (!tiles.empty() && (e = hipMemcpy(rs->tiles, tiles.data(), sizeof(Tile) * tiles.size(),
+                                       hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("hipMemcpy(tiles)", e);
+  if (n > 0) {
+    if ((e = hipMemcpy(rs->bases, bases.data(), 8 * n, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail("hipMemcpy(bases)", e);
+    if ((e = hipMemcpy(rs->ends, ends.data(), 8 * n, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail("hipMemcpy(ends)", e);
+  }
+  if ((e = hipMemset(rs->counts, 0, sz_misc)) != hipSuccess) return fail("hipMemset(counts)", e);
+  rs->rt.base = rs->bases;
+  rs->rt.end = rs->ends;
+  rs->rt.n = n;
+  rs->rt.stride = n <= kFences ? 1u : (n + kFences - 1) / kFences;
+  rs->rt.n_fence = n == 0 ? 0u : (n + rs->rt.stride - 1) / rs->rt.stride;
+  *out = rs;
+  if (n_pages_out) *n_pages_out = n_pages;
+  return KC_OK;
+}
+
+void kc_rangeset_destroy(kc_rangeset* rs) {
+  if (rs == nullptr) return;
+  DeviceGuard g(rs->ctx->device);
+  (void)hipFree(rs->dev);
+  delete rs;
+}
+
+// Launch the page-hash kernel over all tiles, or once per range.
+static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, bool scan, uint32_t op,
+                    hipStream_t s) {
+  kc_ctx* c = rs->ctx;
+  KernelTimer timer(c, op, s);
+  const uint32_t grid = grid_for(c, op, 8);
+  if (!c->tune[op].per_item) {
+    hp.tiles = rs->tiles;
+    hp.n_tiles = rs->n_tiles;
+    hp.tile0 = 0;
+    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, s));
+    return KC_OK;
+  }
+  for (uint32_t r = 0; r < rs->n_ranges; ++r) {
+    hp.tile0 = rs->range_tile[r];
+    hp.tiles = rs->tiles + hp.tile0;
+    hp.n_tiles = rs->range_tile[r + 1] - hp.tile0;
+    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, s));
+  }
+  return KC_OK;
+}
+
+int kc_page_hash(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t* prior_hash_d, uint64_t* hash_d,
+                 uint64_t* zero_bm_d, uint64_t* changed_bm_d, const kc_scan_args* scan, void* stream) {
+  kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
+  if (c == nullptr || rs == nullptr || rs->ctx != c) return KC_EINVAL;
+  if (rs->n_pages > 0 && (hash_d == nullptr || zero_bm_d == nullptr)) return KC_EINVAL;
+  if (prior_hash_d != nullptr && changed_bm_d == nullptr) return KC_EINVAL;
+  ScanDev sd{};
+  if (scan) {
+    const int st = make_scan(rs, scan, &sd);
+    if (st != KC_OK) return st;
+  }
+  DeviceGuard g(c->device);
+  const hipStream_t s = as_stream(stream);
+  KC_HIP(launch_fill_u64(zero_bm_d, rs->n_words, 0, s));
+  if (prior_hash_d) KC_HIP(launch_fill_u64(changed_bm_d, rs->n_words, 0, s));
+  if (scan) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
+  HashParams hp{};
+  hp.seed = seed;
+  hp.prior = prior_hash_d;
+  hp.hash = hash_d;
+  hp.zero_bm = zero_bm_d;
+  hp.changed_bm = changed_bm_d;
+  hp.scan = sd;
+  int st = run_hash(rs, hp, false, prior_hash_d != nullptr, scan != nullptr, KC_OP_PAGE_HASH, s);
+  if (st != KC_OK) return st;
+  if (scan) return finish_scan(rs, scan, sd, s);
+  return KC_OK;
+}
+
+int kc_compact(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, const uint64_t* changed_bm_d,
+               void* packed_d, uint64_t* page_va_d, uint64_t cap_pages, uint64_t* n_kept_d, void* stream) {
+  kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
+  if (c == nullptr || rs == nullptr || rs->ctx != c || n_kept_d == nullptr) return KC_EINVAL;
+  if (rs->n_pages > 0 && zero_bm_d == nullptr) return KC_EINVAL;
+  if (cap_pages > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  const hipStream_t s = as_stream(stream);
+  ScanSrc src{};
+  src.kind = kSrcKeepBits;
+  src.zero_bm = zero_bm_d;
+  src.changed_bm = changed_bm_d;
+  src.n_pages = rs->n_pages;
+  src.n_items = rs->n_words;
+  KC_HIP(launch_scan(src, rs->word_prefix, rs->block_sums, n_kept_d, s));
+  const uint32_t grid = grid_for(c, KC_OP_COMPACT, 8);
+  KernelTimer timer(c, KC_OP_COMPACT, s);
+  if (!c->tune[KC_OP_COMPACT].per_item) {
+    KC_HIP(launch_gather(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, rs->word_prefix,
+                         static_cast<uint8_t*>(packed_d), page_va_d, cap_pages, grid, s));
+  } else {
+    for (uint32_t r = 0; r < rs->n_ranges; ++r) {
+      const uint32_t t0 = rs->range_tile[r];
+      KC_HIP(launch_gather(rs->tiles + t0, rs->range_tile[r + 1] - t0, zero_bm_d, changed_bm_d,
+                           rs->word_prefix, static_cast<uint8_t*>(packed_d), page_va_d, cap_pages, grid, s));
+    }
+  }
+  return KC_OK;
+}
+
+int kc_snapshot(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t* prior_hash_d, uint64_t* hash_d,
+                uint64_t* zero_bm_d, uint64_t* changed_bm_d, void* packed_d, uint64_t* page_va_d,
+                uint64_t cap_pages, uint64_t* n_kept_d, const kc_scan_args* scan, void* stream) {
+  kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
+  if (c == nullptr || rs == nullptr || rs->ctx != c || n_kept_d == nullptr) return KC_EINVAL;
+  if (rs->n_pages > 0 && (hash_d == nullptr || zero_bm_d == nullptr)) return KC_EINVAL;
+  if (cap_pages > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
+  if (prior_hash_d != nullptr) {
+    const int st = kc_page_hash(c, rs, seed, prior_hash_d, hash_d, zero_bm_d, changed_bm_d, scan, stream);
+    if (st != KC_OK) return st;
+    return kc_compact(c, rs, zero_bm_d, changed_bm_d, packed_d, page_va_d, cap_pages, n_kept_d, stream);
+  }
+  ScanDev sd{};
+  if (scan) {
+    const int st = make_scan(rs, scan, &sd);
+    if (st != KC_OK) return st;
+  }
+  DeviceGuard g(c->device);
+  const hipStream_t s = as_stream(stream);
+  KC_HIP(launch_fill_u64(zero_bm_d, rs->n_words, 0, s));
+  if (scan) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
+  KC_HIP(launch_probe_zero(rs->tiles, rs->n_tiles, zero_bm_d, grid_for(c, KC_OP_SNAPSHOT, 8), s));
+  ScanSrc src{};
+  src.kind = kSrcKeepBits;
+  src.zero_bm = zero_bm_d;
+  src.n_pages = rs->n_pages;
+  src.n_items = rs->n_words;
+  KC_HIP(launch_scan(src, rs->word_prefix, rs->block_sums, n_kept_d, s));
+  HashParams hp{};
+  hp.seed = seed;
+  hp.hash = hash_d;
+  hp.zero_bm = zero_bm_d;
+  hp.word_prefix = rs->word_prefix;
+  hp.packed = static_cast<uint8_t*>(packed_d);
+  hp.page_va = page_va_d;
+  hp.cap_pages = cap_pages;
+  hp.scan = sd;
+  const int st = run_hash(rs, hp, true, false, scan != nullptr, KC_OP_SNAPSHOT, s);
+  if (st != KC_OK) return st;
+  if (scan) return finish_scan(rs, scan, sd, s);
+  return KC_OK;
+}
+
+int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, const uint64_t* changed_bm_d,
+               const void* packed_d, const uint64_t* page_va_d, const uint64_t* n_kept_d, uint64_t cap_pages,
+               uint64_t* n_bad_d, void* stream) {
+  kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
+  if (c == nullptr || rs == nullptr || rs->ctx != c || n_kept_d == nullptr) return KC_EINVAL;
+  if (rs->n_pages > 0 && zero_bm_d == nullptr) return KC_EINVAL;
+  if (cap_pages > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  const hipStream_t s = as_stream(stream);
+  unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->counts + 2;
+  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0, s));
+  const uint32_t grid = grid_for(c, KC_OP_RESTORE, 8);
+  KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, grid, s));
+  KernelTimer timer(c, KC_OP_RESTORE, s);
+  KC_HIP(launch_restore_scatter(rs->rt, static_cast<const uint8_t*>(packed_d), page_va_d, n_kept_d, cap_pages,
+                                bad, grid, s));
+  return KC_OK;
+}
+
+int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan, void* stream) {
+  kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
+  if (c == nullptr || rs == nullptr || rs->ctx != c || scan == nullptr) return KC_EINVAL;
+  ScanDev sd{};
+  const int st = make_scan(rs, scan, &sd);
+  if (st != KC_OK) return st;
+  DeviceGuard g(c->device);
+  const hipStream_t s = as_stream(stream);
+  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
+  const uint32_t grid = grid_for(c, KC_OP_CLOSURE, 8);
+  {
+    KernelTimer timer(c, KC_OP_CLOSURE, s);
+    if (!c->tune[KC_OP_CLOSURE].per_item) {
+      KC_HIP(launch_closure(rs->tiles, rs->n_tiles, 0, sd, grid, s));
+    } else {
+      for (uint32_t r = 0; r < rs->n_ranges; ++r) {
+        const uint32_t t0 = rs->range_tile[r];
+        KC_HIP(launch_closure(rs->tiles + t0, rs->range_tile[r + 1] - t0, t0, sd, grid, s));
+      }
+    }
+  }
+  return finish_scan(rs, scan, sd, s);
+}
+
+int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result* res_d, void* stream) {
+  if (c == nullptr || (n_pairs > 0 && (pairs == nullptr || res_d == nullptr))) return KC_EINVAL;
+  if (n_pairs == 0) return KC_OK;
+  const uint32_t tile_bytes = c->tune[KC_OP_COMPARE].tile_bytes ? c->tune[KC_OP_COMPARE].tile_bytes : (64u << 10);
+  std::vector<uint64_t> tile_off(n_pairs + 1, 0);
+  for (uint32_t i = 0; i < n_pairs; ++i) {
+    const kc_pair& pr = pairs[i];
+    if (pr.dtype > KC_U8) return KC_EDTYPE;
+    const uint64_t es = pr.dtype == KC_F32 ? 4 : (pr.dtype == KC_BF16 || pr.dtype == KC_F16 ? 2 : 1);
+    if (pr.n_elems > (1ull << 60)) return KC_ELIMIT;
+    if (pr.n_elems > 0) {
+      if (pr.cand_d == nullptr || pr.gold_d == nullptr) return KC_EINVAL;
+      if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & 15u) return KC_EALIGN;
+    }
+    const uint64_t nb = pr.n_elems * es;
+    const uint64_t nt = nb == 0 ? 1 : (nb + tile_bytes - 1) / tile_bytes;
+    tile_off[i + 1] = tile_off[i] + nt;
+  }
+  const uint64_t n_tiles = tile_off[n_pairs];
+  if (n_tiles > 0xFFFFFFFFull) return KC_ELIMIT;
+  const size_t sz_pairs = align_up(sizeof(CmpPairDev) * n_pairs, 256);
+  const size_t sz_tiles = align_up(sizeof(CmpTileDev) * n_tiles, 256);
+  const size_t sz_acc = (size_t)n_pairs * kAccWords * 8;
+  const size_t need_dev = sz_pairs + sz_tiles + sz_acc, need_host = sz_pairs + sz_tiles;
+  DeviceGuard g(c->device);
+  const hipStream_t s = as_stream(stream);
+  if (c->staged_pending) {
+    KC_HIP(hipEventSynchronize(c->staged));  // the staging buffer is free again
+    c->staged_pending = false;
+  }
+  if (need_dev > c->cmp_dev_cap) {
+    KC_HIP(hipStreamSynchronize(s));
+    const size_t cap = std::max(need_dev, c->cmp_dev_cap * 2);
+    if (c->cmp_dev) KC_HIP(hipFree(c->cmp_dev));
+    c->cmp_dev = nullptr;
+    c->cmp_dev_cap = 0;
+    hipError_t e = hipMalloc(&c->cmp_dev, cap);
+    if (e != hipSuccess) {
+      set_error("hipMalloc(compare scratch)", e);
+      return e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
+    }
+    c->cmp_dev_cap = cap;
+  }
+  if (need_host > c->cmp_host_cap) {
+    if (c->cmp_host) KC_HIP(hipHostFree(c->cmp_host));
+    c->cmp_host = nullptr;
+    c->cmp_host_cap = 0;
+    const size_t cap = std::max(need_host, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->cmp_host), cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      set_error("hipHostMalloc(compare staging)", e);
+      return KC_ENOMEM;
+    }
+    c->cmp_host_cap = cap;
+  }
+  CmpPairDev* hp = reinterpret_cast<CmpPairDev*>(c->cmp_host);
+  CmpTileDev* ht = reinterpret_cast<CmpTileDev*>(c->cmp_host + sz_pairs);
+  for (uint32_t i = 0; i < n_pairs; ++i) {
+    const kc_pair& pr = pairs[i];
+    CmpPairDev d;
+    d.cand = static_cast<const uint8_t*>(pr.cand_d);
+    d.gold = static_cast<const uint8_t*>(pr.gold_d);
+    d.n_elems = pr.n_elems;
+    d.dtype = pr.dtype;
+    d.tol = pr.ulp_tol;
+    d.n_tiles = (uint32_t)(tile_off[i + 1] - tile_off[i]);
+    d.esize = pr.dtype == KC_F32 ? 4 : (pr.dtype == KC_BF16 || pr.dtype == KC_F16 ? 2 : 1);
+    hp[i] = d;
+    for (uint64_t t = tile_off[i]; t < tile_off[i + 1]; ++t) {
+      ht[t].pair = i;
+      ht[t].idx = (uint32_t)(t - tile_off[i]);
+    }
+  }
+  CmpPairDev* dpairs = reinterpret_cast<CmpPairDev*>(c->cmp_dev);
+  CmpTileDev* dtiles = reinterpret_cast<CmpTileDev*>(c->cmp_dev + sz_pairs);
+  unsigned long long* dacc = reinterpret_cast<unsigned long long*>(c->cmp_dev + sz_pairs + sz_tiles);
+  KC_HIP(hipMemcpyAsync(c->cmp_dev, c->cmp_host, need_host, hipMemcpyHostToDevice, s));
+  KC_HIP(hipEventRecord(c->staged, s));
+  c->staged_pending = true;
+  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), (uint64_t)n_pairs * kAccWords, 0, s));
+  const uint32_t grid = grid_for(c, KC_OP_COMPARE, 4);
+  KernelTimer timer(c, KC_OP_COMPARE, s);
+  if (!c->tune[KC_OP_COMPARE].per_item) {
+    KC_HIP(launch_compare(dpairs, dtiles, (uint32_t)n_tiles, tile_bytes, dacc, res_d, grid, s));
+  } else {
+    for (uint32_t i = 0; i < n_pairs; ++i)
+      KC_HIP(launch_compare(dpairs, dtiles + tile_off[i], (uint32_t)(tile_off[i + 1] - tile_off[i]), tile_bytes,
+                            dacc, res_d, grid, s));
+  }
+  return KC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+// kc_compare.hip -- gfx950 typed compare of candidate / golden buffer pairs.
+//
+// One persistent launch walks a tile list that covers every pair (uneven
+// sizes, mixed element types).  A 256-thread workgroup takes a tile of up to
+// tile_bytes of each side, streams it with 16-byte loads, and keeps a fast
+// path for runs whose 16 bytes are bitwise equal and hold no NaN; anything
+// else goes element by element through the exact path (ULP distance, fp64
+// abs / rel error, NaN classes).  Tile partials go to per-pair accumulators
+// with integer atomics (max of non-negative doubles via their bit patterns,
+// first mismatch via max of its complement), and the last tile of a pair,
+// counted by a per-pair ticket, writes the pair's report.
+#include "kc_internal.h"
+
+namespace kc {
+namespace {
+
+constexpr uint32_t kThreads = 256;
+constexpr uint32_t kUnroll = 4;
+constexpr uint32_t kBins = 45;
+
+template <uint32_t DT> struct Fmt;
+template <> struct Fmt<KC_F32> {
+  static constexpr uint32_t size = 4, mag = 0x7FFFFFFFu, sign = 0x80000000u;
+  __device__ static bool nan(uint32_t b) { return (b & mag) > 0x7F800000u; }
+  __device__ static double value(uint32_t b) { return (double)__uint_as_float(b); }
+  __device__ static bool inf(uint32_t b) { return (b & mag) == 0x7F800000u; }
+};
+template <> struct Fmt<KC_BF16> {
+  static constexpr uint32_t size = 2, mag = 0x7FFFu, sign = 0x8000u;
+  __device__ static bool nan(uint32_t b) { return (b & mag) > 0x7F80u; }
+  __device__ static double value(uint32_t b) { return (double)__uint_as_float(b << 16); }
+  __device__ static bool inf(uint32_t b) { return (b & mag) == 0x7F80u; }
+};
+template <> struct Fmt<KC_F16> {
+  static constexpr uint32_t size = 2, mag = 0x7FFFu, sign = 0x8000u;
+  __device__ static bool nan(uint32_t b) { return (b & mag) > 0x7C00u; }
+  __device__ static bool inf(uint32_t b) { return (b & mag) == 0x7C00u; }
+  __device__ static double value(uint32_t b) {
+    const uint32_t e = (b >> 10) & 0x1Fu, m = b & 0x3FFu;
+    double v;
+    if (e == 0u) v = (double)m * 0x1p-24;                      // subnormal: m * 2^-24
+    else if (e == 31u) v = __builtin_inf();                       // NaN never decoded
+    else v = (double)(m | 0x400u) * __builtin_ldexp(1.0, (int)e - 25);
+    return (b & sign) ? -v : v;
+  }
+};
+template <> struct Fmt<KC_FP8_E4M3FN> {
+  static constexpr uint32_t size = 1, mag = 0x7Fu, sign = 0x80u;
+  __device__ static bool nan(uint32_t b) { return (b & mag) == 0x7Fu; }
+  __device__ static bool inf(uint32_t) { return false; }
+  __device__ static double value(uint32_t b) {
+    const uint32_t e = (b >> 3) & 0xFu, m = b & 0x7u;
+    const double v = e == 0u ? (double)m * 0x1p-9 : (double)(m | 0x8u) * __builtin_ldexp(1.0, (int)e - 10);
+    return (b & sign) ? -v : v;
+  }
+};
+template <> struct Fmt<KC_U8> {
+  static constexpr uint32_t size = 1, mag = 0xFFu, sign = 0u;
+  __device__ static bool nan(uint32_t) { return false; }
+  __device__ static bool inf(uint32_t) { return false; }
+  __device__ static double value(uint32_t) { return 0.0; }
+};
+
+// Any NaN encoding in a 32-bit word of packed elements.
+template <uint32_t DT> __device__ __forceinline__ bool word_has_nan(uint32_t w);
+template <> __device__ __forceinline__ bool word_has_nan<KC_F32>(uint32_t w) { return (w & 0x7FFFFFFFu) > 0x7F800000u; }
+template <> __device__ __forceinline__ bool word_has_nan<KC_BF16>(uint32_t w) {
+  return (w & 0x7FFFu) > 0x7F80u || ((w >> 16) & 0x7FFFu) > 0x7F80u;
+}
+template <> __device__ __forceinline__ bool word_has_nan<KC_F16>(uint32_t w) {
+  return (w & 0x7FFFu) > 0x7C00u || ((w >> 16) & 0x7FFFu) > 0x7C00u;
+}
+template <> __device__ __forceinline__ bool word_has_nan<KC_FP8_E4M3FN>(uint32_t w) {
+  const uint32_t y = (w & 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;  // zero byte where magnitude is 0x7F
+  return ((y - 0x01010101u) & ~y & 0x80808080u) != 0u;
+}
+template <> __device__ __forceinline__ bool word_has_nan<KC_U8>(uint32_t) { return false; }
+
+struct Partial {
+  uint32_t mis_elems, mis_bytes, nan_both, nan_c, nan_g, over;
+  double max_abs, max_rel;
+  uint64_t first;
+};
+
+__device__ __forceinline__ uint32_t ulp_bin(uint64_t d) {
+  if (d <= 16u) return (uint32_t)d;
+  return 12u + (64u - (uint32_t)__clzll(d - 1ull));  // 12 + ceil(log2 d)
+}
+
+__device__ __forceinline__ uint32_t diff_bytes(uint32_t a, uint32_t b) {
+  const uint32_t x = a ^ b;
+  return (uint32_t)((x & 0xFFu) != 0u) + (uint32_t)((x & 0xFF00u) != 0u) + (uint32_t)((x & 0xFF0000u) != 0u) +
+         (uint32_t)((x & 0xFF000000u) != 0u);
+}
+
+// Exact per-element path.
+template <uint32_t DT>
+__device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, uint32_t tol, Partial& p,
+                                        uint32_t* hist) {
+  using F = Fmt<DT>;
+  if (c != g) {
+    ++p.mis_elems;
+    p.mis_bytes += diff_bytes(c, g);
+    if (idx < p.first) p.first = idx;
+  }
+  if (DT == KC_U8) return;
+  const bool nc = F::nan(c), ng = F::nan(g);
+  if (nc || ng) {
+    if (nc && ng) ++p.nan_both;
+    else if (nc) ++p.nan_c;
+    else ++p.nan_g;
+    return;
+  }
+  const int64_t oc = (c & F::sign) ? -(int64_t)(c & F::mag) : (int64_t)(c & F::mag);
+  const int64_t og = (g & F::sign) ? -(int64_t)(g & F::mag) : (int64_t)(g & F::mag);
+  const uint64_t d = (uint64_t)(oc > og ? oc - og : og - oc);
+  if (d > tol) ++p.over;
+  if (d != 0u) atomicAdd(&hist[ulp_bin(d)], 1u);
+  if (c == g) return;
+  const double vc = F::value(c), vg = F::value(g);
+  const double a = __builtin_fabs(vc - vg);
+  if (a > p.max_abs) p.max_abs = a;
+  if (vg != 0.0 && !F::inf(g)) {
+    const double r = a / __builtin_fabs(vg);
+    if (r > p.max_rel) p.max_rel = r;
+  }
+}
+
+template <uint32_t DT>
+__device__ __forceinline__ uint32_t elem_of(const uint4& v, uint32_t e) {
+  const uint32_t w = e * Fmt<DT>::size / 4u;
+  const uint32_t word = w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+  if (Fmt<DT>::size == 4) return word;
+  if (Fmt<DT>::size == 2) return (e & 1u) ? (word >> 16) : (word & 0xFFFFu);
+  return (word >> (8u * (e & 3u))) & 0xFFu;
+}
+
+template <uint32_t DT>
+__device__ __forceinline__ void vec16(const uint4& c, const uint4& g, uint64_t e0, uint32_t tol, Partial& p,
+                                      uint32_t* hist) {
+  const bool eq = c.x == g.x && c.y == g.y && c.z == g.z && c.w == g.w;
+  if (eq && !(word_has_nan<DT>(g.x) || word_has_nan<DT>(g.y) || word_has_nan<DT>(g.z) || word_has_nan<DT>(g.w)))
+    return;
+  constexpr uint32_t epv = 16u / Fmt<DT>::size;
+#pragma unroll
+  for (uint32_t e = 0; e < epv; ++e) element<DT>(elem_of<DT>(c, e), elem_of<DT>(g, e), e0 + e, tol, p, hist);
+}
+
+template <uint32_t DT>
+__device__ void tile_body(const CmpPairDev& pr, uint64_t b0, uint64_t b1, Partial& p, uint32_t* hist) {
+  constexpr uint32_t es = Fmt<DT>::size;
+  const uint64_t nvec = (b1 - b0) / 16u;
+  const uint32_t tid = threadIdx.x;
+  for (uint64_t v0 = tid; v0 < nvec; v0 += (uint64_t)kThreads * kUnroll) {
+    uint4 c[kUnroll], g[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+      const uint64_t v = v0 + (uint64_t)u * kThreads;
+      if (v < nvec) {
+        c[u] = *reinterpret_cast<const uint4*>(pr.cand + b0 + v * 16u);
+        g[u] = *reinterpret_cast<const uint4*>(pr.gold + b0 + v * 16u);
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+      const uint64_t v = v0 + (uint64_t)u * kThreads;
+      if (v < nvec) vec16<DT>(c[u], g[u], (b0 + v * 16u) / es, pr.tol, p, hist);
+    }
+  }
+  // bytes past the last whole 16-byte run: element by element
+  if (tid == 0) {
+    for (uint64_t b = b0 + nvec * 16u; b < b1; b += es) {
+      uint32_t cv = 0, gv = 0;
+      for (uint32_t i = 0; i < es; ++i) {
+        cv |= (uint32_t)pr.cand[b + i] << (8u * i);
+        gv |= (uint32_t)pr.gold[b + i] << (8u * i);
+      }
+      element<DT>(cv, gv, b / es, pr.tol, p, hist);
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t dbl_bits(double x) { return (uint64_t)__double_as_longlong(x); }
+__device__ __forceinline__ double bits_dbl(uint64_t x) { return __longlong_as_double((long long)x); }
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_sum(T x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_reduce_max_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t y = __shfl_xor(x, d, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t load_acc(unsigned long long* p) {
+  return (uint64_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const CmpTileDev* tiles,
+                                                 uint32_t n_tiles, uint32_t tile_bytes,
+                                                 unsigned long long* acc_all, kc_cmp_result* res) {
+  __shared__ uint32_t hist[48];
+  __shared__ uint64_t red[4][9];
+  __shared__ uint32_t last;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const CmpTileDev tl = tiles[t];
+    const CmpPairDev pr = pairs[tl.pair];
+    if (tid < 48) hist[tid] = 0u;
+    __syncthreads();
+    Partial p{0, 0, 0, 0, 0, 0, 0.0, 0.0, ~0ull};
+    const uint64_t nbytes = pr.n_elems * pr.esize;
+    const uint64_t b0 = (uint64_t)tl.idx * tile_bytes;
+    const uint64_t b1 = b0 + tile_bytes < nbytes ? b0 + tile_bytes : nbytes;
+    if (b0 < b1) {
+      switch (pr.dtype) {
+        case KC_F32: tile_body<KC_F32>(pr, b0, b1, p, hist); break;
+        case KC_BF16: tile_body<KC_BF16>(pr, b0, b1, p, hist); break;
+        case KC_F16: tile_body<KC_F16>(pr, b0, b1, p, hist); break;
+        case KC_FP8_E4M3FN: tile_body<KC_FP8_E4M3FN>(pr, b0, b1, p, hist); break;
+        default: tile_body<KC_U8>(pr, b0, b1, p, hist); break;
+      }
+    }
+    // workgroup reduction of the partials
+    uint64_t v[9];
+    v[0] = wave_reduce_sum<uint32_t>(p.mis_elems);
+    v[1] = wave_reduce_sum<uint32_t>(p.mis_bytes);
+    v[2] = wave_reduce_sum<uint32_t>(p.nan_both);
+    v[3] = wave_reduce_sum<uint32_t>(p.nan_c);
+    v[4] = wave_reduce_sum<uint32_t>(p.nan_g);
+    v[5] = wave_reduce_sum<uint32_t>(p.over);
+    v[6] = wave_reduce_max_u64(dbl_bits(p.max_abs));
+    v[7] = wave_reduce_max_u64(dbl_bits(p.max_rel));
+    v[8] = wave_reduce_max_u64(~p.first);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) red[wave][i] = v[i];
+    }
+    __syncthreads();
+    unsigned long long* acc = acc_all + (uint64_t)tl.pair * kAccWords;
+    if (tid == 0) {
+      uint64_t s[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        s[i] = red[0][i];
+        for (int w = 1; w < 4; ++w) s[i] = i < 6 ? s[i] + red[w][i] : (red[w][i] > s[i] ? red[w][i] : s[i]);
+      }
+      for (int i = 0; i < 6; ++i)
+        if (s[i]) atomicAdd(&acc[kAccMisElems + i], (unsigned long long)s[i]);
+      if (s[6]) atomicMax(&acc[kAccMaxAbs], (unsigned long long)s[6]);
+      if (s[7]) atomicMax(&acc[kAccMaxRel], (unsigned long long)s[7]);
+      if (s[8]) atomicMax(&acc[kAccFirstInv], (unsigned long long)s[8]);
+    }
+    if (tid < kBins && hist[tid]) atomicAdd(&acc[kAccHist + tid], (unsigned long long)hist[tid]);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(&acc[kAccDone], 1ull) == (unsigned long long)(pr.n_tiles - 1u) ? 1u : 0u;
+    __syncthreads();
+    if (last && tid == 0) {
+      __threadfence();
+      kc_cmp_result* r = res + tl.pair;
+      const uint64_t nb = load_acc(&acc[kAccNanBoth]), ncand = load_acc(&acc[kAccNanCand]),
+                     ngold = load_acc(&acc[kAccNanGold]), over = load_acc(&acc[kAccOverTol]);
+      r->n_elems = pr.n_elems;
+      r->n_mismatch_elems = load_acc(&acc[kAccMisElems]);
+      r->n_mismatch_bytes = load_acc(&acc[kAccMisBytes]);
+      r->first_mismatch = ~load_acc(&acc[kAccFirstInv]);
+      r->n_nan_both = nb;
+      r->n_nan_cand_only = ncand;
+      r->n_nan_gold_only = ngold;
+      r->n_over_tol = over;
+      r->max_abs = bits_dbl(load_acc(&acc[kAccMaxAbs]));
+      r->max_rel = bits_dbl(load_acc(&acc[kAccMaxRel]));
+      uint64_t rest = 0;
+      for (uint32_t b = 1; b < 48; ++b) {
+        const uint64_t h = b < kBins ? load_acc(&acc[kAccHist + b]) : 0ull;
+        r->ulp_hist[b] = h;
+        rest += h;
+      }
+      if (pr.dtype == KC_U8) {
+        r->ulp_hist[0] = 0;
+        r->pass = r->n_mismatch_elems == 0 ? 1u : 0u;
+      } else {
+        r->ulp_hist[0] = pr.n_elems - nb - ncand - ngold - rest;
+        r->pass = (over == 0 && ncand == 0 && ngold == 0) ? 1u : 0u;
+      }
+      r->status = 0u;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
+                          uint32_t tile_bytes, unsigned long long* acc, kc_cmp_result* res, uint32_t grid,
+                          hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  grid = grid < 1u ? 1u : (grid > n_tiles ? n_tiles : grid);
+  hipLaunchKernelGGL(k_compare, dim3(grid), dim3(kThreads), 0, s, pairs, tiles, n_tiles, tile_bytes, acc, res);
+  return hipGetLastError();
+}
+
+}  // namespace kc

@@ -1,0 +1,119 @@
+// kc_internal.h -- shared definitions of the gfx950 kernels and the ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kc.h"
+
+namespace kc {
+
+constexpr uint32_t kPage = 4096;
+constexpr uint32_t kWave = 64;
+constexpr uint32_t kTilePages = 16;     // pages per wave tile (one lane quad per page)
+constexpr uint32_t kChunk = 512;        // bytes of each page staged per step
+constexpr uint32_t kStageStride = kChunk + 32;  // padded LDS row: quads land in distinct banks
+constexpr uint32_t kFences = 256;       // range-table entries held in LDS
+
+// A tile: up to 16 consecutive pages of one range.
+struct Tile {
+  uint64_t va;      // VA of the first page
+  uint32_t g;       // global index of the first page
+  uint32_t npages;  // 1..16
+};
+static_assert(sizeof(Tile) == 16, "tile layout");
+
+// Sorted range table on the device (bases and one-past-end addresses).
+struct RangeTable {
+  const uint64_t* base;
+  const uint64_t* end;
+  uint32_t n;
+  uint32_t stride;   // LDS fence stride: fence i = range i * stride
+  uint32_t n_fence;  // ceil(n / stride) <= kFences
+};
+
+struct ScanDev {
+  uint64_t lo, span;                 // pointer-like iff (w - lo) < span
+  RangeTable rt;
+  uint32_t* tile_oob;                // per-tile out-of-range count
+  unsigned long long* counts;        // [0] n_ptr_like, [1] n_in_range (accumulated)
+};
+
+struct HashParams {
+  const Tile* tiles;
+  uint32_t n_tiles;
+  uint32_t tile0;          // index of tiles[0] in the rangeset's tile list
+  uint64_t seed;
+  const uint64_t* prior;   // nullable
+  uint64_t* hash;
+  uint64_t* zero_bm;       // output, or input when gathering
+  uint64_t* changed_bm;
+  const uint64_t* word_prefix;  // keep prefix per bitmap word (gathering)
+  uint8_t* packed;
+  uint64_t* page_va;
+  uint64_t cap_pages;
+  ScanDev scan;
+};
+
+// Exclusive-scan sources.
+enum ScanSrcKind : uint32_t { kSrcKeepBits = 0, kSrcCounts = 1 };
+struct ScanSrc {
+  uint32_t kind;
+  const uint64_t* zero_bm;     // keep bits: ~zero (& changed)
+  const uint64_t* changed_bm;  // nullable
+  uint64_t n_pages;
+  const uint32_t* counts;      // per-item counts
+  uint64_t n_items;            // words or counts
+};
+
+struct CmpPairDev {
+  const uint8_t* cand;
+  const uint8_t* gold;
+  uint64_t n_elems;
+  uint32_t dtype, tol;
+  uint32_t n_tiles, esize;
+};
+static_assert(sizeof(CmpPairDev) == 40, "pair layout");
+
+struct CmpTileDev {
+  uint32_t pair, idx;
+};
+
+constexpr uint32_t kAccWords = 64;  // per-pair accumulator words
+// accumulator word map
+enum : uint32_t {
+  kAccMisElems = 0, kAccMisBytes, kAccNanBoth, kAccNanCand, kAccNanGold, kAccOverTol,
+  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccDone, kAccHist = 16  // 45 bins: 16..60
+};
+
+// ---- launchers (kc_kernels.hip) ------------------------------------------
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan,
+                            uint32_t grid, hipStream_t s);
+hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm,
+                             uint32_t grid, hipStream_t s);
+hipError_t launch_scan(const ScanSrc& src, uint64_t* out, uint64_t* block_sums,
+                       uint64_t* total_out, hipStream_t s);
+hipError_t launch_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
+                         const uint64_t* changed_bm, const uint64_t* word_prefix,
+                         uint8_t* packed, uint64_t* page_va, uint64_t cap_pages,
+                         uint32_t grid, hipStream_t s);
+hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
+                               const uint64_t* changed_bm, uint32_t grid, hipStream_t s);
+hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
+                                  const uint64_t* page_va, const uint64_t* n_kept,
+                                  uint64_t cap_pages, unsigned long long* n_bad,
+                                  uint32_t grid, hipStream_t s);
+hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
+                          const ScanDev& sd, uint32_t grid, hipStream_t s);
+hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
+                           const uint64_t* tile_prefix, kc_oob* oob, uint64_t cap,
+                           uint32_t grid, hipStream_t s);
+hipError_t launch_scan_finalize(kc_scan_result* res, const unsigned long long* counts,
+                                const uint64_t* n_oob, uint64_t n_words, uint64_t cap,
+                                hipStream_t s);
+hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
+                          uint32_t tile_bytes, unsigned long long* acc, kc_cmp_result* res,
+                          uint32_t grid, hipStream_t s);
+
+}  // namespace kc

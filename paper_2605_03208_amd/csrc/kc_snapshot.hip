@@ -1,0 +1,722 @@
+// kc_snapshot.hip -- gfx950 kernels of the snapshot, restore and closure scan.
+//
+// Memory-bound streaming kernels, one 64-lane wave per workgroup, persistent
+// grids striding over a tile list (16 pages of one range per tile).  Global
+// traffic is 16-byte loads / stores that cover whole 512-byte or 1-KiB runs;
+// the XXH64 lanes read their words from a padded LDS stage.
+#include <algorithm>
+
+#include "kc_internal.h"
+
+namespace kc {
+namespace {
+
+// ---------------------------------------------------------------- XXH64 ----
+// Public xxHash definition: four accumulators over 32-byte stripes.
+constexpr uint64_t kP1 = 0x9E3779B185EBCA87ull;
+constexpr uint64_t kP2 = 0xC2B2AE3D27D4EB4Full;
+constexpr uint64_t kP3 = 0x165667B19E3779F9ull;
+constexpr uint64_t kP4 = 0x85EBCA77C2B2AE63ull;
+
+__device__ __forceinline__ uint64_t rotl64(uint64_t x, uint32_t r) {
+  return (x << r) | (x >> (64u - r));
+}
+
+__device__ __forceinline__ uint64_t xround(uint64_t acc, uint64_t in) {
+  acc += in * kP2;
+  acc = rotl64(acc, 31);
+  return acc * kP1;
+}
+
+// 64-bit DPP move inside a lane quad (quad_perm control word).
+template <int CTRL>
+__device__ __forceinline__ uint64_t quad64(uint64_t x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, true);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Lane k of a quad holds accumulator k of one page after its 128 stripes.
+// Returns the page hash in every lane of the quad.
+__device__ __forceinline__ uint64_t xxh64_page_merge(uint64_t acc, uint32_t k) {
+  const uint32_t rot = k == 0 ? 1u : (k == 1 ? 7u : (k == 2 ? 12u : 18u));
+  uint64_t r = rotl64(acc, rot);
+  const uint64_t m = xround(0, acc);
+  r += quad64<0xB1>(r);  // quad_perm(1,0,3,2)
+  r += quad64<0x4E>(r);  // quad_perm(2,3,0,1)
+  uint64_t h = r;
+  h = (h ^ quad64<0x00>(m)) * kP1 + kP4;
+  h = (h ^ quad64<0x55>(m)) * kP1 + kP4;
+  h = (h ^ quad64<0xAA>(m)) * kP1 + kP4;
+  h = (h ^ quad64<0xFF>(m)) * kP1 + kP4;
+  h += kPage;
+  h ^= h >> 33;
+  h *= kP2;
+  h ^= h >> 29;
+  h *= kP3;
+  h ^= h >> 32;
+  return h;
+}
+
+__device__ __forceinline__ uint64_t acc_init(uint64_t seed, uint32_t k) {
+  return k == 0 ? seed + kP1 + kP2 : (k == 1 ? seed + kP2 : (k == 2 ? seed : seed - kP1));
+}
+
+// ------------------------------------------------------------- helpers ----
+__device__ __forceinline__ uint4 ld16(uint64_t addr) {
+  return *reinterpret_cast<const uint4*>(addr);
+}
+__device__ __forceinline__ void st16(uint64_t addr, uint4 v) {
+  *reinterpret_cast<uint4*>(addr) = v;
+}
+__device__ __forceinline__ bool nz16(uint4 v) { return (v.x | v.y | v.z | v.w) != 0u; }
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// OR page bits (bit i = page g0+i) into a bitmap; one lane calls this.
+__device__ __forceinline__ void or_page_bits(uint64_t* bm, uint32_t g0, uint32_t np, uint32_t bits) {
+  if (bits == 0u) return;
+  const uint32_t w = g0 >> 6, s = g0 & 63u;
+  const uint64_t b = (uint64_t)bits;
+  if ((b << s) != 0ull) atomicOr(reinterpret_cast<unsigned long long*>(bm + w), (unsigned long long)(b << s));
+  if (s + np > 64u && (b >> (64u - s)) != 0ull)
+    atomicOr(reinterpret_cast<unsigned long long*>(bm + w + 1), (unsigned long long)(b >> (64u - s)));
+}
+
+// Compress ballot bits at lanes 4q (q < 16) into bit q.
+__device__ __forceinline__ uint32_t quad_bits(uint64_t ballot) {
+  uint32_t out = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 16; ++q) out |= (uint32_t)((ballot >> (4u * q)) & 1ull) << q;
+  return out;
+}
+
+// ---------------------------------------------------------- range search --
+struct FenceLds {
+  uint64_t base[kFences];
+  uint64_t end[kFences];
+};
+
+__device__ __forceinline__ void load_fences(FenceLds& f, const RangeTable& rt, uint32_t tid,
+                                            uint32_t nthreads) {
+  for (uint32_t i = tid; i < rt.n_fence; i += nthreads) {
+    const uint32_t r = i * rt.stride;
+    f.base[i] = rt.base[r];
+    f.end[i] = rt.end[r];
+  }
+}
+
+// True iff w lies in [base_r, end_r) for some range r.
+__device__ __forceinline__ bool in_ranges(uint64_t w, const FenceLds& f, const RangeTable& rt) {
+  if (rt.n == 0u || w < f.base[0]) return false;
+  uint32_t i = 0;
+#pragma unroll
+  for (uint32_t step = kFences / 2; step > 0; step >>= 1)
+    if (i + step < rt.n_fence && f.base[i + step] <= w) i += step;
+  if (rt.stride == 1u) return w < f.end[i];
+  uint32_t a = i * rt.stride;
+  uint32_t b = min(a + rt.stride, rt.n);
+  while (b - a > 1u) {
+    const uint32_t m = (a + b) >> 1;
+    if (rt.base[m] <= w) a = m; else b = m;
+  }
+  return w < rt.end[a];
+}
+
+// --------------------------------------------------------------- fill -----
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------- page hash -----
+// One wave hashes a tile of up to 16 pages: lane quad q owns page q, lane k of
+// the quad runs XXH64 accumulator k over the words 8k + 32s of each stripe s.
+// The wave streams the tile in 8 chunks of 512 bytes per page: 8 loads of
+// 16 bytes per lane (instruction j covers pages 2j and 2j+1 with 32 lanes
+// each), the chunk goes to a padded LDS stage, and the quad lanes read their
+// 16 words of the chunk from there.  While chunk c is hashed, the loads of
+// chunk c+1 are in flight.
+//
+// GATHER: zero bits come from the probe, zero pages are not read (their hash
+// is computed from zeros), kept pages are also stored to their packed slot.
+template <bool GATHER, bool PRIOR, bool SCAN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_page_hash(HashParams p) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kTilePages * kStageStride];
+  __shared__ FenceLds fences;
+  const uint32_t lane = threadIdx.x;
+  const uint32_t q = lane >> 2, k = lane & 3u;
+  const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
+  const uint64_t scan_lo = p.scan.lo, scan_span = p.scan.span;
+  if (SCAN) {
+    load_fences(fences, p.scan.rt, lane, kWave);
+    __syncthreads();
+  }
+  uint32_t n_ptr = 0, n_in = 0;
+
+  for (uint32_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+    const Tile tile = p.tiles[t];
+    const uint32_t np = tile.npages;
+    const uint64_t va = tile.va;
+    uint32_t keep = (1u << np) - 1u;
+    uint64_t slot_j[8];
+    if (GATHER) {
+      uint64_t slot = 0;
+      bool kept = false;
+      if (lane < np) {
+        const uint64_t g = (uint64_t)tile.g + lane;
+        const uint64_t zw = p.zero_bm[g >> 6];
+        kept = ((zw >> (g & 63u)) & 1ull) == 0ull;
+        slot = p.word_prefix[g >> 6] + (uint64_t)__popcll(~zw & ((1ull << (g & 63u)) - 1ull));
+      }
+      keep = (uint32_t)__ballot(kept);
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) slot_j[j] = __shfl(slot, 2 * j + half, 64);
+      if (kept && slot < p.cap_pages) p.page_va[slot] = va + (uint64_t)lane * kPage;
+    }
+    uint32_t nonzero = 0, oob = 0;
+    uint64_t acc = acc_init(p.seed, k);
+
+    uint4 cur[8];
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+      const uint32_t pg = 2 * j + half;
+      cur[j] = ((keep >> pg) & 1u) ? ld16(va + (uint64_t)pg * kPage + off16) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll 1
+    for (uint32_t c = 0; c < kPage / kChunk; ++c) {
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t pg = 2 * j + half;
+        const uint4 v = cur[j];
+        if (!GATHER) {
+          const uint64_t b = __ballot(nz16(v));
+          nonzero |= ((uint32_t)((uint32_t)b != 0u) << (2 * j)) | ((uint32_t)((b >> 32) != 0ull) << (2 * j + 1));
+        }
+        if (SCAN) {
+          const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
+          const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
+          const bool p0 = (w0 - scan_lo) < scan_span;
+          const bool p1 = (w1 - scan_lo) < scan_span;
+          if (__ballot(p0 || p1)) {
+            if (p0) {
+              ++n_ptr;
+              if (in_ranges(w0, fences, p.scan.rt)) ++n_in; else ++oob;
+            }
+            if (p1) {
+              ++n_ptr;
+              if (in_ranges(w1, fences, p.scan.rt)) ++n_in; else ++oob;
+            }
+          }
+        }
+        if (GATHER) {
+          if (((keep >> pg) & 1u) && slot_j[j] < p.cap_pages)
+            st16((uint64_t)p.packed + slot_j[j] * kPage + c * kChunk + off16, v);
+        }
+        *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
+      }
+      __syncthreads();
+      // loads of the next chunk overlap the hashing of this one
+      const uint32_t cn = c + 1 < kPage / kChunk ? c + 1 : c;
+      const uint32_t more = c + 1 < kPage / kChunk ? keep : 0u;
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t pg = 2 * j + half;
+        cur[j] = ((more >> pg) & 1u) ? ld16(va + (uint64_t)pg * kPage + cn * kChunk + off16)
+                                     : make_uint4(0, 0, 0, 0);
+      }
+      const uint8_t* row = stage + q * kStageStride + k * 8u;
+#pragma unroll
+      for (uint32_t s = 0; s < kChunk / 32; ++s)
+        acc = xround(acc, *reinterpret_cast<const uint64_t*>(row + s * 32u));
+      __syncthreads();
+    }
+
+    const uint64_t h = xxh64_page_merge(acc, k);
+    const bool mine = (k == 0u) && (q < np);
+    if (mine) p.hash[tile.g + q] = h;
+    const uint32_t valid = (1u << np) - 1u;
+    if (!GATHER) {
+      const uint32_t zero = ~nonzero & valid;
+      if (lane == 0) or_page_bits(p.zero_bm, tile.g, np, zero);
+    }
+    if (PRIOR) {
+      const bool ch = mine && (h != p.prior[tile.g + q]);
+      const uint32_t cb = quad_bits(__ballot(ch));
+      if (lane == 0) or_page_bits(p.changed_bm, tile.g, np, cb);
+    }
+    if (SCAN) {
+      const uint32_t o = wave_sum_u32(oob);
+      if (lane == 0) p.scan.tile_oob[p.tile0 + t] = o;
+    }
+  }
+  if (SCAN) {
+    const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
+    if (lane == 0) {
+      if (a) atomicAdd(&p.scan.counts[0], (unsigned long long)a);
+      if (b) atomicAdd(&p.scan.counts[1], (unsigned long long)b);
+    }
+  }
+}
+
+// ------------------------------------------------------------ zero probe --
+// Exact zero bitmap for a tile: each quad reads the first 64 bytes of its
+// page; a page whose first 64 bytes are all zero is read in full.
+__global__ __launch_bounds__(64) void k_probe_zero(const Tile* tiles, uint32_t n_tiles,
+                                                   uint64_t* zero_bm) {
+  const uint32_t lane = threadIdx.x, q = lane >> 2, k = lane & 3u;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile tile = tiles[t];
+    const uint32_t np = tile.npages;
+    const uint4 v = (q < np) ? ld16(tile.va + (uint64_t)q * kPage + k * 16u) : make_uint4(0, 0, 0, 0);
+    const uint64_t b = __ballot(nz16(v));
+    uint32_t maybe = 0;
+    for (uint32_t i = 0; i < np; ++i)
+      if (((b >> (4u * i)) & 0xFull) == 0ull) maybe |= 1u << i;
+    uint32_t zero = 0;
+    while (maybe) {
+      uint32_t pg[4];
+      uint32_t cnt = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i) {
+        pg[i] = maybe ? (uint32_t)__builtin_ctz(maybe) : 0u;
+        if (maybe) {
+          maybe &= maybe - 1u;
+          ++cnt;
+        }
+      }
+      uint4 x[16];
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+          x[i * 4 + j] = (i < cnt) ? ld16(tile.va + (uint64_t)pg[i] * kPage + j * 1024u + lane * 16u)
+                                   : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i) {
+        const bool nzl = nz16(x[i * 4]) || nz16(x[i * 4 + 1]) || nz16(x[i * 4 + 2]) || nz16(x[i * 4 + 3]);
+        if (i < cnt && __ballot(nzl) == 0ull) zero |= 1u << pg[i];
+      }
+    }
+    if (lane == 0) or_page_bits(zero_bm, tile.g, np, zero);
+  }
+}
+
+// ------------------------------------------------ reduce-then-scan (u64) --
+constexpr uint32_t kScanThreads = 256, kScanPerThread = 8;
+constexpr uint32_t kScanBlock = kScanThreads * kScanPerThread;
+
+__device__ __forceinline__ uint32_t scan_item(const ScanSrc& s, uint64_t i) {
+  if (i >= s.n_items) return 0u;
+  if (s.kind == kSrcCounts) return s.counts[i];
+  uint64_t keep = ~s.zero_bm[i];
+  if (s.changed_bm) keep &= s.changed_bm[i];
+  if (i == s.n_items - 1 && (s.n_pages & 63u)) keep &= (1ull << (s.n_pages & 63u)) - 1ull;
+  return (uint32_t)__popcll(keep);
+}
+
+// Exclusive scan of one value per thread across a 256-thread block.
+__device__ __forceinline__ uint64_t block_exclusive(uint64_t x, uint64_t* lds4, uint64_t* total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(inc, d, 64);
+    if (lane >= (uint32_t)d) inc += y;
+  }
+  if (lane == 63) lds4[wave] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) pre += lds4[w];
+    tot += lds4[w];
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return pre + inc - x;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(ScanSrc src, uint64_t* block_sums) {
+  __shared__ uint64_t lds4[4];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPerThread;
+  uint64_t s = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPerThread; ++i) s += scan_item(src, i0 + i);
+  uint64_t tot = 0;
+  block_exclusive(s, lds4, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t* block_sums, uint32_t nb, uint64_t* total_out) {
+  __shared__ uint64_t lds[16];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    const uint32_t i = base + tid;
+    const uint64_t x = i < nb ? block_sums[i] : 0ull;
+    uint64_t inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(inc, d, 64);
+      if (lane >= (uint32_t)d) inc += y;
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      if (w < wave) pre += lds[w];
+      tot += lds[w];
+    }
+    if (i < nb) block_sums[i] = carry + pre + inc - x;
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(ScanSrc src, const uint64_t* block_sums, uint64_t* out) {
+  __shared__ uint64_t lds4[4];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPerThread;
+  uint32_t v[kScanPerThread];
+  uint64_t s = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPerThread; ++i) {
+    v[i] = scan_item(src, i0 + i);
+    s += v[i];
+  }
+  uint64_t run = block_exclusive(s, lds4, nullptr) + block_sums[blockIdx.x];
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPerThread; ++i) {
+    if (i0 + i < src.n_items) out[i0 + i] = run;
+    run += v[i];
+  }
+}
+
+// ------------------------------------------------------ slots of a tile ---
+// Lane i < np: keep bit and packed slot of page i of the tile.
+__device__ __forceinline__ void tile_slots(const Tile& tile, const uint64_t* zero_bm,
+                                           const uint64_t* changed_bm, const uint64_t* word_prefix,
+                                           uint32_t lane, bool& kept, uint64_t& slot) {
+  kept = false;
+  slot = 0;
+  if (lane < tile.npages) {
+    const uint64_t g = (uint64_t)tile.g + lane;
+    uint64_t kw = ~zero_bm[g >> 6];
+    if (changed_bm) kw &= changed_bm[g >> 6];
+    kept = ((kw >> (g & 63u)) & 1ull) != 0ull;
+    slot = word_prefix[g >> 6] + (uint64_t)__popcll(kw & ((1ull << (g & 63u)) - 1ull));
+  }
+}
+
+// --------------------------------------------------------------- gather ---
+__global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
+                                               const uint64_t* changed_bm, const uint64_t* word_prefix,
+                                               uint8_t* packed, uint64_t* page_va, uint64_t cap) {
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile tile = tiles[t];
+    bool kept;
+    uint64_t slot;
+    tile_slots(tile, zero_bm, changed_bm, word_prefix, lane, kept, slot);
+    const bool go = kept && slot < cap;
+    if (go) page_va[slot] = tile.va + (uint64_t)lane * kPage;
+    uint32_t mask = (uint32_t)__ballot(go);
+    while (mask) {
+      uint32_t pg[4];
+      uint64_t dst[4];
+      uint32_t cnt = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i) {
+        pg[i] = mask ? (uint32_t)__builtin_ctz(mask) : 0u;
+        dst[i] = __shfl(slot, pg[i], 64);
+        if (mask) {
+          mask &= mask - 1u;
+          ++cnt;
+        }
+      }
+      uint4 x[16];
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+          if (i < cnt) x[i * 4 + j] = ld16(tile.va + (uint64_t)pg[i] * kPage + j * 1024u + lane * 16u);
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+          if (i < cnt) st16((uint64_t)packed + dst[i] * kPage + j * 1024u + lane * 16u, x[i * 4 + j]);
+    }
+  }
+}
+
+// -------------------------------------------------------------- restore ---
+__global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t n_tiles,
+                                                     const uint64_t* zero_bm, const uint64_t* changed_bm) {
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile tile = tiles[t];
+    bool sel = false;
+    if (lane < tile.npages) {
+      const uint64_t g = (uint64_t)tile.g + lane;
+      uint64_t w = zero_bm[g >> 6];
+      if (changed_bm) w &= changed_bm[g >> 6];
+      sel = ((w >> (g & 63u)) & 1ull) != 0ull;
+    }
+    uint32_t mask = (uint32_t)__ballot(sel);
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    while (mask) {
+      const uint32_t pg = (uint32_t)__builtin_ctz(mask);
+      mask &= mask - 1u;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) st16(tile.va + (uint64_t)pg * kPage + j * 1024u + lane * 16u, z);
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uint8_t* packed,
+                                                        const uint64_t* page_va, const uint64_t* n_kept,
+                                                        uint64_t cap, unsigned long long* n_bad) {
+  __shared__ FenceLds fences;
+  const uint32_t lane = threadIdx.x;
+  load_fences(fences, rt, lane, kWave);
+  __syncthreads();
+  const uint64_t n = min(*n_kept, cap);
+  for (uint64_t s0 = (uint64_t)blockIdx.x * 4; s0 < n; s0 += (uint64_t)gridDim.x * 4) {
+    uint64_t va = 0;
+    bool ok = false;
+    if (lane < 4 && s0 + lane < n) {
+      va = page_va[s0 + lane];
+      ok = (va & (kPage - 1)) == 0 && in_ranges(va, fences, rt);
+      if (!ok) atomicAdd(n_bad, 1ull);
+    }
+    const uint32_t okm = (uint32_t)__ballot(ok);
+    uint64_t dst[4];
+    uint4 x[16];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+      dst[i] = __shfl(va, i, 64);
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if ((okm >> i) & 1u) x[i * 4 + j] = ld16((uint64_t)packed + (s0 + i) * kPage + j * 1024u + lane * 16u);
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if ((okm >> i) & 1u) st16(dst[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
+  }
+}
+
+// --------------------------------------------------------- closure scan ---
+__device__ __forceinline__ void closure_words(uint4 v, uint64_t lo, uint64_t span, const FenceLds& f,
+                                              const RangeTable& rt, uint32_t& n_ptr, uint32_t& n_in,
+                                              uint32_t& oob) {
+  const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
+  const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
+  const bool p0 = (w0 - lo) < span, p1 = (w1 - lo) < span;
+  if (__ballot(p0 || p1)) {
+    if (p0) {
+      ++n_ptr;
+      if (in_ranges(w0, f, rt)) ++n_in; else ++oob;
+    }
+    if (p1) {
+      ++n_ptr;
+      if (in_ranges(w1, f, rt)) ++n_in; else ++oob;
+    }
+  }
+}
+
+// Standalone scan: a tile's 16 pages are read as 64 contiguous 1-KiB runs.
+__global__ __launch_bounds__(64) void k_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, ScanDev sd) {
+  __shared__ FenceLds fences;
+  const uint32_t lane = threadIdx.x;
+  load_fences(fences, sd.rt, lane, kWave);
+  __syncthreads();
+  uint32_t n_ptr = 0, n_in = 0;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile tile = tiles[t];
+    const uint32_t nseg = tile.npages * 4u;
+    uint32_t oob = 0;
+    for (uint32_t s0 = 0; s0 < nseg; s0 += 16) {
+      uint4 x[16];
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i)
+        x[i] = (s0 + i < nseg) ? ld16(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i) closure_words(x[i], sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
+    }
+    const uint32_t o = wave_sum_u32(oob);
+    if (lane == 0) sd.tile_oob[tile0 + t] = o;
+  }
+  const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
+  if (lane == 0) {
+    if (a) atomicAdd(&sd.counts[0], (unsigned long long)a);
+    if (b) atomicAdd(&sd.counts[1], (unsigned long long)b);
+  }
+}
+
+// Writes the out-of-range words of each tile at its prefix position, in
+// ascending address order, up to the list capacity.
+__global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_tiles, ScanDev sd,
+                                                 const uint64_t* tile_prefix, kc_oob* oob, uint64_t cap) {
+  __shared__ FenceLds fences;
+  const uint32_t lane = threadIdx.x;
+  load_fences(fences, sd.rt, lane, kWave);
+  __syncthreads();
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint32_t cnt = sd.tile_oob[t];
+    const uint64_t pre = tile_prefix[t];
+    if (cnt == 0u || pre >= cap) continue;
+    const Tile tile = tiles[t];
+    const uint32_t nseg = tile.npages * 4u;
+    uint64_t done = 0;
+    for (uint32_t s = 0; s < nseg && done < cnt && pre + done < cap; ++s) {
+      const uint64_t a = tile.va + (uint64_t)s * 1024u + lane * 16u;
+      const uint4 v = ld16(a);
+      const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
+      const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
+      const bool o0 = (w0 - sd.lo) < sd.span && !in_ranges(w0, fences, sd.rt);
+      const bool o1 = (w1 - sd.lo) < sd.span && !in_ranges(w1, fences, sd.rt);
+      const uint64_t b0 = __ballot(o0), b1 = __ballot(o1);
+      const uint64_t r0 = pre + done + (uint64_t)__popcll(b0 & below) + (uint64_t)__popcll(b1 & below);
+      const uint64_t r1 = r0 + (o0 ? 1u : 0u);
+      if (o0 && r0 < cap) {
+        oob[r0].word_va = a;
+        oob[r0].value = w0;
+      }
+      if (o1 && r1 < cap) {
+        oob[r1].word_va = a + 8u;
+        oob[r1].value = w1;
+      }
+      done += (uint64_t)__popcll(b0) + (uint64_t)__popcll(b1);
+    }
+  }
+}
+
+__global__ void k_scan_finalize(kc_scan_result* res, const unsigned long long* counts, const uint64_t* n_oob,
+                                uint64_t n_words, uint64_t cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t no = *n_oob;
+  res->n_words = n_words;
+  res->n_ptr_like = counts[0];
+  res->n_in_range = counts[1];
+  res->n_oob = no;
+  res->n_written = (uint32_t)(no < cap ? no : cap);
+  res->truncated = no > cap ? 1u : 0u;
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers --
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t nb = blocks_for(n, 256);
+  const uint32_t grid = (uint32_t)(nb < 4096 ? nb : 4096);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t grid,
+                            hipStream_t s) {
+  if (p.n_tiles == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, p.n_tiles));
+#define KC_HASH_CASE(G, P, S)                                                     \
+  if (gather == G && prior == P && scan == S) {                                  \
+    hipLaunchKernelGGL((k_page_hash<G, P, S>), dim3(grid), dim3(64), 0, s, p);   \
+    return hipGetLastError();                                                    \
+  }
+  KC_HASH_CASE(false, false, false)
+  KC_HASH_CASE(false, false, true)
+  KC_HASH_CASE(false, true, false)
+  KC_HASH_CASE(false, true, true)
+  KC_HASH_CASE(true, false, false)
+  KC_HASH_CASE(true, false, true)
+#undef KC_HASH_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t grid,
+                             hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, n_tiles));
+  hipLaunchKernelGGL(k_probe_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const ScanSrc& src, uint64_t* out, uint64_t* block_sums, uint64_t* total_out,
+                       hipStream_t s) {
+  const uint32_t nb = blocks_for(src.n_items, kScanBlock);
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, src, block_sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, block_sums, nb, total_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nb == 0) return e;
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, src, (const uint64_t*)block_sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
+                         const uint64_t* changed_bm, const uint64_t* word_prefix, uint8_t* packed,
+                         uint64_t* page_va, uint64_t cap_pages, uint32_t grid, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, n_tiles));
+  hipLaunchKernelGGL(k_gather, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm, word_prefix,
+                     packed, page_va, cap_pages);
+  return hipGetLastError();
+}
+
+hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
+                               const uint64_t* changed_bm, uint32_t grid, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, n_tiles));
+  hipLaunchKernelGGL(k_restore_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, const uint64_t* page_va,
+                                  const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad,
+                                  uint32_t grid, hipStream_t s) {
+  if (cap_pages == 0) return hipSuccess;
+  const uint64_t groups = (cap_pages + 3) / 4;
+  grid = (uint32_t)(groups < grid ? groups : grid);
+  grid = grid < 1u ? 1u : grid;
+  hipLaunchKernelGGL(k_restore_scatter, dim3(grid), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
+                     n_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, const ScanDev& sd,
+                          uint32_t grid, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, n_tiles));
+  hipLaunchKernelGGL(k_closure, dim3(grid), dim3(64), 0, s, tiles, n_tiles, tile0, sd);
+  return hipGetLastError();
+}
+
+hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd, const uint64_t* tile_prefix,
+                           kc_oob* oob, uint64_t cap, uint32_t grid, hipStream_t s) {
+  if (n_tiles == 0 || cap == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, n_tiles));
+  hipLaunchKernelGGL(k_oob_emit, dim3(grid), dim3(64), 0, s, tiles, n_tiles, sd, tile_prefix, oob, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_finalize(kc_scan_result* res, const unsigned long long* counts, const uint64_t* n_oob,
+                                uint64_t n_words, uint64_t cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_finalize, dim3(1), dim3(64), 0, s, res, counts, n_oob, n_words, cap);
+  return hipGetLastError();
+}
+
+}  // namespace kc

@@ -1,0 +1,341 @@
+"""ctypes binding of ``libkc.so`` (the C ABI declared in ``include/kc.h``).
+
+Argument marshalling only: tensors become device pointers, the current torch
+stream becomes the HIP stream, result structs are decoded.  Every step of the
+path runs in the library's HIP kernels; if the library is missing this module
+raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkc.so")
+PAGE = 4096
+
+OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
+F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
+OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE = range(6)
+ELEM_SIZE = {F32: 4, BF16: 2, F16: 2, FP8_E4M3FN: 1, U8: 1}
+TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16,
+               torch.float8_e4m3fn: FP8_E4M3FN, torch.uint8: U8}
+
+SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "kc_default_window",
+           "kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_tuning", "kc_ctx_get_tuning",
+           "kc_ctx_enable_timing", "kc_ctx_kernel_ms",
+           "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
+           "kc_restore", "kc_closure_scan", "kc_compare"]
+
+
+class KCError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        msg = f"{what}: {code} ({strerror(code)})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+        self.code = code
+
+
+class Range(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_uint64), ("size", ctypes.c_uint64)]
+
+
+class ScanResult(ctypes.Structure):
+    _fields_ = [("n_words", ctypes.c_uint64), ("n_ptr_like", ctypes.c_uint64),
+                ("n_in_range", ctypes.c_uint64), ("n_oob", ctypes.c_uint64),
+                ("n_written", ctypes.c_uint32), ("truncated", ctypes.c_uint32)]
+
+
+class ScanArgs(ctypes.Structure):
+    _fields_ = [("win_lo", ctypes.c_uint64), ("win_hi", ctypes.c_uint64),
+                ("res_d", ctypes.c_void_p), ("oob_d", ctypes.c_void_p), ("oob_cap", ctypes.c_uint64)]
+
+
+class Pair(ctypes.Structure):
+    _fields_ = [("cand_d", ctypes.c_void_p), ("gold_d", ctypes.c_void_p), ("n_elems", ctypes.c_uint64),
+                ("dtype", ctypes.c_uint32), ("ulp_tol", ctypes.c_uint32)]
+
+
+class CmpResult(ctypes.Structure):
+    _fields_ = [("n_elems", ctypes.c_uint64), ("n_mismatch_elems", ctypes.c_uint64),
+                ("n_mismatch_bytes", ctypes.c_uint64), ("first_mismatch", ctypes.c_uint64),
+                ("n_nan_both", ctypes.c_uint64), ("n_nan_cand_only", ctypes.c_uint64),
+                ("n_nan_gold_only", ctypes.c_uint64), ("n_over_tol", ctypes.c_uint64),
+                ("max_abs", ctypes.c_double), ("max_rel", ctypes.c_double),
+                ("ulp_hist", ctypes.c_uint64 * 48), ("pass_", ctypes.c_uint32), ("status", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("grid_per_cu", ctypes.c_uint32), ("tile_bytes", ctypes.c_uint32),
+                ("per_item", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(CmpResult) == 472 and ctypes.sizeof(ScanResult) == 40
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libkc.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_03208_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        P = ctypes.POINTER
+        sig = {
+            "kc_strerror": ([i32], ctypes.c_char_p),
+            "kc_last_error": ([], ctypes.c_char_p),
+            "kc_abi_version": ([], i32),
+            "kc_range_check": ([P(Range), u32, P(u64)], i32),
+            "kc_default_window": ([P(Range), u32, P(u64), P(u64)], i32),
+            "kc_ctx_create": ([P(vp), i32], i32),
+            "kc_ctx_destroy": ([vp], None),
+            "kc_ctx_set_tuning": ([vp, u32, P(Tuning)], i32),
+            "kc_ctx_get_tuning": ([vp, u32, P(Tuning)], i32),
+            "kc_ctx_enable_timing": ([vp, i32], i32),
+            "kc_ctx_kernel_ms": ([vp, u32, P(ctypes.c_float)], i32),
+            "kc_rangeset_create": ([vp, P(Range), u32, P(vp), P(u64)], i32),
+            "kc_rangeset_destroy": ([vp], None),
+            "kc_page_hash": ([vp, vp, u64, vp, vp, vp, vp, P(ScanArgs), vp], i32),
+            "kc_compact": ([vp, vp, vp, vp, vp, vp, u64, vp, vp], i32),
+            "kc_snapshot": ([vp, vp, u64, vp, vp, vp, vp, vp, vp, u64, vp, P(ScanArgs), vp], i32),
+            "kc_restore": ([vp, vp, vp, vp, vp, vp, vp, u64, vp, vp], i32),
+            "kc_closure_scan": ([vp, vp, P(ScanArgs), vp], i32),
+            "kc_compare": ([vp, P(Pair), u32, vp, vp], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().kc_strerror(code).decode()
+    except Exception:  # library missing while formatting an error
+        return "?"
+
+
+def _check(code: int, what: str) -> None:
+    if code != OK:
+        detail = lib().kc_last_error().decode() if code == EHIP else ""
+        raise KCError(code, what, detail)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ranges(ranges):
+    arr = (Range * max(1, len(ranges)))()
+    for i, (b, s) in enumerate(ranges):
+        arr[i].base, arr[i].size = int(b), int(s)
+    return arr
+
+
+def range_check(ranges) -> tuple[int, int]:
+    n = ctypes.c_uint64(0)
+    st = lib().kc_range_check(_ranges(ranges), len(ranges), ctypes.byref(n))
+    return st, int(n.value)
+
+
+def default_window(ranges) -> tuple[int, int]:
+    lo, hi = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib().kc_default_window(_ranges(ranges), len(ranges), ctypes.byref(lo), ctypes.byref(hi)),
+           "kc_default_window")
+    return int(lo.value), int(hi.value)
+
+
+class Context:
+    """A kc_ctx on one HIP device (the current torch device by default)."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        self.handle = ctypes.c_void_p()
+        _check(lib().kc_ctx_create(ctypes.byref(self.handle), device), "kc_ctx_create")
+
+    def set_tuning(self, op: int, grid_per_cu: int = 0, tile_bytes: int = 0, per_item: int = 0) -> None:
+        t = Tuning(grid_per_cu, tile_bytes, per_item, 0)
+        _check(lib().kc_ctx_set_tuning(self.handle, op, ctypes.byref(t)), "kc_ctx_set_tuning")
+
+    def get_tuning(self, op: int) -> dict:
+        t = Tuning()
+        _check(lib().kc_ctx_get_tuning(self.handle, op, ctypes.byref(t)), "kc_ctx_get_tuning")
+        return dict(grid_per_cu=t.grid_per_cu, tile_bytes=t.tile_bytes, per_item=t.per_item)
+
+    def enable_timing(self, on: bool = True) -> None:
+        _check(lib().kc_ctx_enable_timing(self.handle, 1 if on else 0), "kc_ctx_enable_timing")
+
+    def kernel_ms(self, op: int) -> float:
+        """Duration of the main kernel(s) of the op's last call (waits for it)."""
+        ms = ctypes.c_float(0)
+        _check(lib().kc_ctx_kernel_ms(self.handle, op, ctypes.byref(ms)), "kc_ctx_kernel_ms")
+        return float(ms.value)
+
+    def close(self) -> None:
+        if self.handle:
+            lib().kc_ctx_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RangeSet:
+    """Uploaded range table (tracked allocations) plus the scratch its calls use."""
+
+    def __init__(self, ctx: Context, ranges):
+        self.ctx = ctx
+        self.ranges = [(int(b), int(s)) for b, s in ranges]
+        self.handle = ctypes.c_void_p()
+        n = ctypes.c_uint64(0)
+        _check(lib().kc_rangeset_create(ctx.handle, _ranges(self.ranges), len(self.ranges),
+                                        ctypes.byref(self.handle), ctypes.byref(n)), "kc_rangeset_create")
+        self.n_pages = int(n.value)
+        self.n_words = (self.n_pages + 63) // 64
+
+    def close(self) -> None:
+        if self.handle:
+            lib().kc_rangeset_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ScanOut:
+    """Device buffers receiving a closure-scan result and its out-of-range list."""
+
+    def __init__(self, device, oob_cap: int = 1024, win_lo: int = 0, win_hi: int = 0):
+        self.res = torch.zeros(40, dtype=torch.uint8, device=device)
+        self.oob = torch.zeros(max(1, oob_cap) * 16, dtype=torch.uint8, device=device)
+        self.cap = oob_cap
+        self.args = ScanArgs(win_lo, win_hi, self.res.data_ptr(), self.oob.data_ptr(), oob_cap)
+
+    def result(self) -> tuple[dict, list]:
+        r = ScanResult.from_buffer_copy(bytes(self.res.cpu().numpy()))
+        d = {k: int(getattr(r, k)) for k, _ in ScanResult._fields_}
+        raw = self.oob.cpu().numpy().view("<u8").reshape(-1, 2)
+        return d, [(int(a), int(v)) for a, v in raw[: d["n_written"]]]
+
+
+def _u64(n: int, device) -> torch.Tensor:
+    return torch.empty(max(1, n), dtype=torch.int64, device=device)
+
+
+def page_hash(ctx: Context, rs: RangeSet, seed: int = 0, prior: torch.Tensor | None = None,
+              scan: ScanOut | None = None, out=None, stream=None):
+    """Returns (hash[N], zero_bm[W], changed_bm[W] or None) as int64 device tensors."""
+    dev = torch.device("cuda", ctx.device)
+    h, z, c = out if out is not None else (_u64(rs.n_pages, dev), _u64(rs.n_words, dev),
+                                           _u64(rs.n_words, dev) if prior is not None else None)
+    _check(lib().kc_page_hash(ctx.handle, rs.handle, seed & (2**64 - 1), _ptr(prior), _ptr(h), _ptr(z),
+                              _ptr(c), ctypes.byref(scan.args) if scan else None, _stream(stream)),
+           "kc_page_hash")
+    return h, z, c
+
+
+def compact(ctx: Context, rs: RangeSet, zero_bm, changed_bm=None, cap_pages: int | None = None, out=None,
+            stream=None):
+    """Returns (packed u8[cap*4096], page_va int64[cap], n_kept int64[1]) device tensors."""
+    dev = torch.device("cuda", ctx.device)
+    cap = rs.n_pages if cap_pages is None else int(cap_pages)
+    packed, va, nk = out if out is not None else (
+        torch.empty(max(1, cap) * PAGE, dtype=torch.uint8, device=dev), _u64(cap, dev), _u64(1, dev))
+    _check(lib().kc_compact(ctx.handle, rs.handle, _ptr(zero_bm), _ptr(changed_bm), _ptr(packed), _ptr(va),
+                            cap, _ptr(nk), _stream(stream)), "kc_compact")
+    return packed, va, nk
+
+
+def snapshot(ctx: Context, rs: RangeSet, seed: int = 0, prior=None, cap_pages: int | None = None,
+             scan: ScanOut | None = None, out=None, stream=None):
+    """Returns dict(hash, zero_bm, changed_bm, packed, page_va, n_kept) device tensors."""
+    dev = torch.device("cuda", ctx.device)
+    cap = rs.n_pages if cap_pages is None else int(cap_pages)
+    if out is None:
+        out = dict(hash=_u64(rs.n_pages, dev), zero_bm=_u64(rs.n_words, dev),
+                   changed_bm=_u64(rs.n_words, dev) if prior is not None else None,
+                   packed=torch.empty(max(1, cap) * PAGE, dtype=torch.uint8, device=dev),
+                   page_va=_u64(cap, dev), n_kept=_u64(1, dev))
+    _check(lib().kc_snapshot(ctx.handle, rs.handle, seed & (2**64 - 1), _ptr(prior), _ptr(out["hash"]),
+                             _ptr(out["zero_bm"]), _ptr(out.get("changed_bm")), _ptr(out["packed"]),
+                             _ptr(out["page_va"]), cap, _ptr(out["n_kept"]),
+                             ctypes.byref(scan.args) if scan else None, _stream(stream)), "kc_snapshot")
+    return out
+
+
+def restore(ctx: Context, rs: RangeSet, zero_bm, changed_bm, packed, page_va, n_kept, cap_pages: int | None = None,
+            n_bad=None, stream=None):
+    cap = page_va.numel() if cap_pages is None else int(cap_pages)
+    _check(lib().kc_restore(ctx.handle, rs.handle, _ptr(zero_bm), _ptr(changed_bm), _ptr(packed), _ptr(page_va),
+                            _ptr(n_kept), cap, _ptr(n_bad), _stream(stream)), "kc_restore")
+
+
+def closure_scan(ctx: Context, rs: RangeSet, scan: ScanOut, stream=None) -> None:
+    _check(lib().kc_closure_scan(ctx.handle, rs.handle, ctypes.byref(scan.args), _stream(stream)),
+           "kc_closure_scan")
+
+
+def make_pairs(pairs) -> tuple[ctypes.Array, int]:
+    """pairs: iterable of (cand, gold, dtype, ulp_tol) with device tensors."""
+    pairs = list(pairs)
+    arr = (Pair * max(1, len(pairs)))()
+    for i, (c, g, dt, tol) in enumerate(pairs):
+        n = c.numel() * c.element_size() // ELEM_SIZE[dt]
+        assert g.numel() * g.element_size() == c.numel() * c.element_size()
+        arr[i] = Pair(_ptr(c), _ptr(g), n, dt, tol)
+    return arr, len(pairs)
+
+
+def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Returns the device buffer of kc_cmp_result structs (decode with ``decode_cmp``)."""
+    arr, n = pairs if isinstance(pairs, tuple) else make_pairs(pairs)
+    if res is None:
+        res = torch.empty(max(1, n) * 472, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
+    _check(lib().kc_compare(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare")
+    return res
+
+
+def decode_cmp(res: torch.Tensor, n: int) -> list[dict]:
+    raw = bytes(res.cpu().numpy()[: n * 472])
+    out = []
+    for i in range(n):
+        r = CmpResult.from_buffer_copy(raw[i * 472:(i + 1) * 472])
+        d = {}
+        for k, _ in CmpResult._fields_:
+            v = getattr(r, k)
+            if k == "ulp_hist":
+                d[k] = [int(x) for x in v]
+            elif k == "pass_":
+                d["pass"] = int(v)
+            else:
+                d[k] = float(v) if k.startswith("max_") else int(v)
+        out.append(d)
+    return out

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every function ``include/kc.h``
+declares; its host-only checks agree with the oracle (no device needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "kc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kc_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def kc():
+    from paper_2605_03208_amd import kc as K
+    if not os.path.exists(K.LIB_PATH):
+        from paper_2605_03208_amd import build
+        build.build()
+    K.lib()
+    return K
+
+
+def test_every_declared_symbol_is_exported(kc):
+    names = declared_functions()
+    assert len(names) >= 17
+    L = kc.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(kc.SYMBOLS)
+
+
+def test_abi_version_and_strerror(kc):
+    assert kc.lib().kc_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert kc.strerror(code) not in ("", "unknown status")
+
+
+def test_range_check_agrees_with_oracle(kc, oracle_lib):
+    rng = np.random.default_rng(7)
+    cases = [[], [(0x10000, 0x1000)], [(0x10001, 0x1000)], [(0x10000, 0x1001)], [(0, 0x1000)],
+             [(0x10000, 0)], [(2**64 - 0x1000, 0x2000)], [(0x20000, 0x1000), (0x10000, 0x1000)],
+             [(0x10000, 0x2000), (0x11000, 0x1000)], [(0x10000, 0x2000), (0x12000, 0x1000)]]
+    for _ in range(300):  # random mixes of good and bad ranges
+        n = int(rng.integers(1, 6))
+        base = 0x100000
+        rs = []
+        for _ in range(n):
+            base += int(rng.integers(-3, 8)) * 0x1000 + int(rng.integers(0, 2)) * int(rng.integers(0, 4096)) * (rng.random() < 0.1)
+            size = int(rng.integers(0, 5)) * 0x1000 + (1 if rng.random() < 0.05 else 0)
+            rs.append((max(0, base), size))
+            base += size
+        cases.append(rs)
+    for rs in cases:
+        st_o, n_o, _ = oracle_lib.range_check(rs)
+        st_k, n_k = kc.range_check(rs)
+        assert st_o == st_k, rs
+        if st_o == 0:
+            assert n_o == n_k
+
+
+def test_default_window_agrees_with_oracle(kc, oracle_lib):
+    for rs in ([(0x7F8A00000000, 0x4000), (0x7F8A00100000, 0x1000)], [(0x2000, 0x1000)],
+               [(2**64 - 2**33, 0x1000)]):
+        assert kc.default_window(rs) == oracle_lib.default_window(rs)
+
+
+def test_missing_library_fails_loudly(kc, monkeypatch, tmp_path):
+    import importlib
+    K = importlib.import_module("paper_2605_03208_amd.kc")
+    monkeypatch.setattr(K, "_lib", None)
+    monkeypatch.setattr(K, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        K.lib()
