@@ -617,14 +617,17 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
   c->staged_pending = true;
   KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), (uint64_t)n_pairs * kAccWords, 0, s));
   const uint32_t grid = grid_for(c, KC_OP_COMPARE, 4);
-  KernelTimer timer(c, KC_OP_COMPARE, s);
-  if (!c->tune[KC_OP_COMPARE].per_item) {
-    KC_HIP(launch_compare(dpairs, dtiles, (uint32_t)n_tiles, tile_bytes, dacc, res_d, grid, s));
-  } else {
-    for (uint32_t i = 0; i < n_pairs; ++i)
-      KC_HIP(launch_compare(dpairs, dtiles + tile_off[i], (uint32_t)(tile_off[i + 1] - tile_off[i]), tile_bytes,
-                            dacc, res_d, grid, s));
+  {
+    KernelTimer timer(c, KC_OP_COMPARE, s);
+    if (!c->tune[KC_OP_COMPARE].per_item) {
+      KC_HIP(launch_compare(dpairs, dtiles, (uint32_t)n_tiles, tile_bytes, dacc, grid, s));
+    } else {
+      for (uint32_t i = 0; i < n_pairs; ++i)
+        KC_HIP(launch_compare(dpairs, dtiles + tile_off[i], (uint32_t)(tile_off[i + 1] - tile_off[i]), tile_bytes,
+                              dacc, grid, s));
+    }
   }
+  KC_HIP(launch_compare_finalize(dpairs, n_pairs, dacc, res_d, s));
   return KC_OK;
 }
 

@@ -7,8 +7,9 @@
 // else goes element by element through the exact path (ULP distance, fp64
 // abs / rel error, NaN classes).  Tile partials go to per-pair accumulators
 // with integer atomics (max of non-negative doubles via their bit patterns,
-// first mismatch via max of its complement), and the last tile of a pair,
-// counted by a per-pair ticket, writes the pair's report.
+// first mismatch via max of its complement); tiles with nothing but equal
+// elements flush nothing.  A second small kernel writes each pair's report
+// once the pass has finished.
 #include "kc_internal.h"
 
 namespace kc {
@@ -147,7 +148,7 @@ __device__ __forceinline__ void vec16(const uint4& c, const uint4& g, uint64_t e
 }
 
 template <uint32_t DT>
-__device__ void tile_body(const CmpPairDev& pr, uint64_t b0, uint64_t b1, Partial& p, uint32_t* hist) {
+__device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uint64_t b1, Partial& p, uint32_t* hist) {
   constexpr uint32_t es = Fmt<DT>::size;
   const uint64_t nvec = (b1 - b0) / 16u;
   const uint32_t tid = threadIdx.x;
@@ -198,22 +199,17 @@ __device__ __forceinline__ uint64_t wave_reduce_max_u64(uint64_t x) {
   return x;
 }
 
-__device__ __forceinline__ uint64_t load_acc(unsigned long long* p) {
-  return (uint64_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const CmpTileDev* tiles,
                                                  uint32_t n_tiles, uint32_t tile_bytes,
-                                                 unsigned long long* acc_all, kc_cmp_result* res) {
+                                                 unsigned long long* acc_all) {
   __shared__ uint32_t hist[48];
   __shared__ uint64_t red[4][9];
-  __shared__ uint32_t last;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  if (tid < 48) hist[tid] = 0u;  // stays zero between tiles: flushed bins are reset
+  __syncthreads();
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const CmpTileDev tl = tiles[t];
     const CmpPairDev pr = pairs[tl.pair];
-    if (tid < 48) hist[tid] = 0u;
-    __syncthreads();
     Partial p{0, 0, 0, 0, 0, 0, 0.0, 0.0, ~0ull};
     const uint64_t nbytes = pr.n_elems * pr.esize;
     const uint64_t b0 = (uint64_t)tl.idx * tile_bytes;
@@ -227,82 +223,98 @@ __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const 
         default: tile_body<KC_U8>(pr, b0, b1, p, hist); break;
       }
     }
-    // workgroup reduction of the partials
-    uint64_t v[9];
-    v[0] = wave_reduce_sum<uint32_t>(p.mis_elems);
-    v[1] = wave_reduce_sum<uint32_t>(p.mis_bytes);
-    v[2] = wave_reduce_sum<uint32_t>(p.nan_both);
-    v[3] = wave_reduce_sum<uint32_t>(p.nan_c);
-    v[4] = wave_reduce_sum<uint32_t>(p.nan_g);
-    v[5] = wave_reduce_sum<uint32_t>(p.over);
-    v[6] = wave_reduce_max_u64(dbl_bits(p.max_abs));
-    v[7] = wave_reduce_max_u64(dbl_bits(p.max_rel));
-    v[8] = wave_reduce_max_u64(~p.first);
+    // Every non-equal element bumps mis_elems or a NaN class, so a tile with
+    // all of these zero contributed nothing but equal elements.
+    const bool any = (p.mis_elems | p.nan_both | p.nan_c | p.nan_g) != 0u;
+    if (!__syncthreads_or(any)) continue;
+    const uint64_t v0 = wave_reduce_sum<uint32_t>(p.mis_elems);
+    const uint64_t v1 = wave_reduce_sum<uint32_t>(p.mis_bytes);
+    const uint64_t v2 = wave_reduce_sum<uint32_t>(p.nan_both);
+    const uint64_t v3 = wave_reduce_sum<uint32_t>(p.nan_c);
+    const uint64_t v4 = wave_reduce_sum<uint32_t>(p.nan_g);
+    const uint64_t v5 = wave_reduce_sum<uint32_t>(p.over);
+    const uint64_t v6 = wave_reduce_max_u64(dbl_bits(p.max_abs));
+    const uint64_t v7 = wave_reduce_max_u64(dbl_bits(p.max_rel));
+    const uint64_t v8 = wave_reduce_max_u64(~p.first);
     if (lane == 0) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) red[wave][i] = v[i];
+      red[wave][0] = v0; red[wave][1] = v1; red[wave][2] = v2; red[wave][3] = v3; red[wave][4] = v4;
+      red[wave][5] = v5; red[wave][6] = v6; red[wave][7] = v7; red[wave][8] = v8;
     }
     __syncthreads();
     unsigned long long* acc = acc_all + (uint64_t)tl.pair * kAccWords;
-    if (tid == 0) {
-      uint64_t s[9];
+    if (tid < 9) {  // thread i folds slot i over the four waves and flushes it
+      const uint32_t i = tid;
+      uint64_t x = red[0][i];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        s[i] = red[0][i];
-        for (int w = 1; w < 4; ++w) s[i] = i < 6 ? s[i] + red[w][i] : (red[w][i] > s[i] ? red[w][i] : s[i]);
+      for (uint32_t w = 1; w < 4; ++w) {
+        const uint64_t y = red[w][i];
+        x = i < 6 ? x + y : (y > x ? y : x);
       }
-      for (int i = 0; i < 6; ++i)
-        if (s[i]) atomicAdd(&acc[kAccMisElems + i], (unsigned long long)s[i]);
-      if (s[6]) atomicMax(&acc[kAccMaxAbs], (unsigned long long)s[6]);
-      if (s[7]) atomicMax(&acc[kAccMaxRel], (unsigned long long)s[7]);
-      if (s[8]) atomicMax(&acc[kAccFirstInv], (unsigned long long)s[8]);
+      if (x) {
+        if (i < 6) atomicAdd(&acc[kAccMisElems + i], (unsigned long long)x);
+        else atomicMax(&acc[kAccMaxAbs + (i - 6)], (unsigned long long)x);
+      }
     }
-    if (tid < kBins && hist[tid]) atomicAdd(&acc[kAccHist + tid], (unsigned long long)hist[tid]);
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = atomicAdd(&acc[kAccDone], 1ull) == (unsigned long long)(pr.n_tiles - 1u) ? 1u : 0u;
-    __syncthreads();
-    if (last && tid == 0) {
-      __threadfence();
-      kc_cmp_result* r = res + tl.pair;
-      const uint64_t nb = load_acc(&acc[kAccNanBoth]), ncand = load_acc(&acc[kAccNanCand]),
-                     ngold = load_acc(&acc[kAccNanGold]), over = load_acc(&acc[kAccOverTol]);
-      r->n_elems = pr.n_elems;
-      r->n_mismatch_elems = load_acc(&acc[kAccMisElems]);
-      r->n_mismatch_bytes = load_acc(&acc[kAccMisBytes]);
-      r->first_mismatch = ~load_acc(&acc[kAccFirstInv]);
-      r->n_nan_both = nb;
-      r->n_nan_cand_only = ncand;
-      r->n_nan_gold_only = ngold;
-      r->n_over_tol = over;
-      r->max_abs = bits_dbl(load_acc(&acc[kAccMaxAbs]));
-      r->max_rel = bits_dbl(load_acc(&acc[kAccMaxRel]));
-      uint64_t rest = 0;
-      for (uint32_t b = 1; b < 48; ++b) {
-        const uint64_t h = b < kBins ? load_acc(&acc[kAccHist + b]) : 0ull;
-        r->ulp_hist[b] = h;
-        rest += h;
+    if (tid < kBins) {
+      const uint32_t h = hist[tid];
+      if (h) {
+        atomicAdd(&acc[kAccHist + tid], (unsigned long long)h);
+        hist[tid] = 0u;
       }
-      if (pr.dtype == KC_U8) {
-        r->ulp_hist[0] = 0;
-        r->pass = r->n_mismatch_elems == 0 ? 1u : 0u;
-      } else {
-        r->ulp_hist[0] = pr.n_elems - nb - ncand - ngold - rest;
-        r->pass = (over == 0 && ncand == 0 && ngold == 0) ? 1u : 0u;
-      }
-      r->status = 0u;
     }
+    __syncthreads();
   }
+}
+
+// One thread per pair turns the accumulators into the report.
+__global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs,
+                                                          const unsigned long long* acc_all, kc_cmp_result* res) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pairs) return;
+  const CmpPairDev pr = pairs[i];
+  const unsigned long long* acc = acc_all + (uint64_t)i * kAccWords;
+  kc_cmp_result* r = res + i;
+  const uint64_t nb = acc[kAccNanBoth], ncand = acc[kAccNanCand], ngold = acc[kAccNanGold], over = acc[kAccOverTol];
+  r->n_elems = pr.n_elems;
+  r->n_mismatch_elems = acc[kAccMisElems];
+  r->n_mismatch_bytes = acc[kAccMisBytes];
+  r->first_mismatch = ~(uint64_t)acc[kAccFirstInv];
+  r->n_nan_both = nb;
+  r->n_nan_cand_only = ncand;
+  r->n_nan_gold_only = ngold;
+  r->n_over_tol = over;
+  r->max_abs = bits_dbl(acc[kAccMaxAbs]);
+  r->max_rel = bits_dbl(acc[kAccMaxRel]);
+  uint64_t rest = 0;
+  for (uint32_t b = 1; b < 48; ++b) {
+    const uint64_t h = b < kBins ? (uint64_t)acc[kAccHist + b] : 0ull;
+    r->ulp_hist[b] = h;
+    rest += h;
+  }
+  if (pr.dtype == KC_U8) {
+    r->ulp_hist[0] = 0;
+    r->pass = r->n_mismatch_elems == 0 ? 1u : 0u;
+  } else {
+    r->ulp_hist[0] = pr.n_elems - nb - ncand - ngold - rest;
+    r->pass = (over == 0 && ncand == 0 && ngold == 0) ? 1u : 0u;
+  }
+  r->status = 0u;
 }
 
 }  // namespace
 
 hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
-                          uint32_t tile_bytes, unsigned long long* acc, kc_cmp_result* res, uint32_t grid,
-                          hipStream_t s) {
+                          uint32_t tile_bytes, unsigned long long* acc, uint32_t grid, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   grid = grid < 1u ? 1u : (grid > n_tiles ? n_tiles : grid);
-  hipLaunchKernelGGL(k_compare, dim3(grid), dim3(kThreads), 0, s, pairs, tiles, n_tiles, tile_bytes, acc, res);
+  hipLaunchKernelGGL(k_compare, dim3(grid), dim3(kThreads), 0, s, pairs, tiles, n_tiles, tile_bytes, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, const unsigned long long* acc,
+                                   kc_cmp_result* res, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compare_finalize, dim3((n_pairs + 255) / 256), dim3(256), 0, s, pairs, n_pairs, acc, res);
   return hipGetLastError();
 }
 

@@ -83,7 +83,7 @@ constexpr uint32_t kAccWords = 64;  // per-pair accumulator words
 // accumulator word map
 enum : uint32_t {
   kAccMisElems = 0, kAccMisBytes, kAccNanBoth, kAccNanCand, kAccNanGold, kAccOverTol,
-  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccDone, kAccHist = 16  // 45 bins: 16..60
+  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccHist = 16  // 45 bins: 16..60
 };
 
 // ---- launchers (kc_kernels.hip) ------------------------------------------
@@ -113,7 +113,8 @@ hipError_t launch_scan_finalize(kc_scan_result* res, const unsigned long long* c
                                 const uint64_t* n_oob, uint64_t n_words, uint64_t cap,
                                 hipStream_t s);
 hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
-                          uint32_t tile_bytes, unsigned long long* acc, kc_cmp_result* res,
-                          uint32_t grid, hipStream_t s);
+                          uint32_t tile_bytes, unsigned long long* acc, uint32_t grid, hipStream_t s);
+hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, const unsigned long long* acc,
+                                   kc_cmp_result* res, hipStream_t s);
 
 }  // namespace kc

@@ -533,7 +533,7 @@ __device__ __forceinline__ void closure_words(uint4 v, uint64_t lo, uint64_t spa
 }
 
 // Standalone scan: a tile's 16 pages are read as 64 contiguous 1-KiB runs.
-__global__ __launch_bounds__(64) void k_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, ScanDev sd) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, ScanDev sd) {
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
   load_fences(fences, sd.rt, lane, kWave);
@@ -543,13 +543,13 @@ __global__ __launch_bounds__(64) void k_closure(const Tile* tiles, uint32_t n_ti
     const Tile tile = tiles[t];
     const uint32_t nseg = tile.npages * 4u;
     uint32_t oob = 0;
-    for (uint32_t s0 = 0; s0 < nseg; s0 += 16) {
-      uint4 x[16];
+    for (uint32_t s0 = 0; s0 < nseg; s0 += 8) {
+      uint4 x[8];
 #pragma unroll
-      for (uint32_t i = 0; i < 16; ++i)
+      for (uint32_t i = 0; i < 8; ++i)
         x[i] = (s0 + i < nseg) ? ld16(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
 #pragma unroll
-      for (uint32_t i = 0; i < 16; ++i) closure_words(x[i], sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
+      for (uint32_t i = 0; i < 8; ++i) closure_words(x[i], sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
     }
     const uint32_t o = wave_sum_u32(oob);
     if (lane == 0) sd.tile_oob[tile0 + t] = o;

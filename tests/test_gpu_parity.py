@@ -246,9 +246,10 @@ def test_per_item_launches_equal_batched(kc, ctx):
         scan2 = kc.ScanOut("cuda", oob_cap=50)
         kc.closure_scan(c2, rs2, scan2)
         torch.cuda.synchronize()
-        outs.append((u64(o["hash"]).copy(), u64(o["zero_bm"]).copy(), o["packed"].cpu().numpy(),
-                     u64(o["page_va"]).copy(), int(u64(o["n_kept"])[0]), scan.result(), u64(h).copy(),
-                     p2.cpu().numpy(), scan2.result()))
+        nk = int(u64(o["n_kept"])[0])
+        outs.append((u64(o["hash"])[: rs2.n_pages].copy(), u64(o["zero_bm"])[: rs2.n_words].copy(),
+                     o["packed"][: nk * PAGE].cpu().numpy(), u64(o["page_va"])[:nk].copy(), nk, scan.result(),
+                     u64(h)[: rs2.n_pages].copy(), p2[: nk * PAGE].cpu().numpy(), scan2.result()))
         rs2.close()
         c2.close()
     for o in outs[1:]:
