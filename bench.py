@@ -96,6 +96,8 @@ def main() -> int:
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 30 GiB pool (1.0 = full)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--extras", action="store_true", help="also time batched vs per-buffer forms")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB three times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -104,6 +106,17 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 30
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(7)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "reps": 3}), flush=True)
+        return 0
 
     from paper_2605_03208_amd import kc
     from paper_2605_03208_amd import workloads as W

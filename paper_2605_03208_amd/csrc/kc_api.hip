@@ -374,7 +374,7 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
                     hipStream_t s) {
   kc_ctx* c = rs->ctx;
   KernelTimer timer(c, op, s);
-  const uint32_t grid = grid_for(c, op, 8);
+  const uint32_t grid = grid_for(c, op, 4);
   if (!c->tune[op].per_item) {
     hp.tiles = rs->tiles;
     hp.n_tiles = rs->n_tiles;
@@ -504,7 +504,7 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   const hipStream_t s = as_stream(stream);
   unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->counts + 2;
   KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0, s));
-  const uint32_t grid = grid_for(c, KC_OP_RESTORE, 8);
+  const uint32_t grid = grid_for(c, KC_OP_RESTORE, 16);
   KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, grid, s));
   KernelTimer timer(c, KC_OP_RESTORE, s);
   KC_HIP(launch_restore_scatter(rs->rt, static_cast<const uint8_t*>(packed_d), page_va_d, n_kept_d, cap_pages,
@@ -616,7 +616,7 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
   KC_HIP(hipEventRecord(c->staged, s));
   c->staged_pending = true;
   KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), (uint64_t)n_pairs * kAccWords, 0, s));
-  const uint32_t grid = grid_for(c, KC_OP_COMPARE, 4);
+  const uint32_t grid = grid_for(c, KC_OP_COMPARE, 2);
   {
     KernelTimer timer(c, KC_OP_COMPARE, s);
     if (!c->tune[KC_OP_COMPARE].per_item) {

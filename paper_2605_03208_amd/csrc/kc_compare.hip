@@ -158,8 +158,8 @@ __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uin
     for (uint32_t u = 0; u < kUnroll; ++u) {
       const uint64_t v = v0 + (uint64_t)u * kThreads;
       if (v < nvec) {
-        c[u] = *reinterpret_cast<const uint4*>(pr.cand + b0 + v * 16u);
-        g[u] = *reinterpret_cast<const uint4*>(pr.gold + b0 + v * 16u);
+        c[u] = ld16nt((uint64_t)(pr.cand + b0 + v * 16u));
+        g[u] = ld16nt((uint64_t)(pr.gold + b0 + v * 16u));
       }
     }
 #pragma unroll

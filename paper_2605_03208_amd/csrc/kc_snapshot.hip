@@ -63,12 +63,6 @@ __device__ __forceinline__ uint64_t acc_init(uint64_t seed, uint32_t k) {
 }
 
 // ------------------------------------------------------------- helpers ----
-__device__ __forceinline__ uint4 ld16(uint64_t addr) {
-  return *reinterpret_cast<const uint4*>(addr);
-}
-__device__ __forceinline__ void st16(uint64_t addr, uint4 v) {
-  *reinterpret_cast<uint4*>(addr) = v;
-}
 __device__ __forceinline__ bool nz16(uint4 v) { return (v.x | v.y | v.z | v.w) != 0u; }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
@@ -186,7 +180,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
     for (uint32_t j = 0; j < 8; ++j) {
       const uint32_t pg = 2 * j + half;
-      cur[j] = ((keep >> pg) & 1u) ? ld16(va + (uint64_t)pg * kPage + off16) : make_uint4(0, 0, 0, 0);
+      cur[j] = ((keep >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + off16) : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll 1
     for (uint32_t c = 0; c < kPage / kChunk; ++c) {
@@ -216,7 +210,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         if (GATHER) {
           if (((keep >> pg) & 1u) && slot_j[j] < p.cap_pages)
-            st16((uint64_t)p.packed + slot_j[j] * kPage + c * kChunk + off16, v);
+            st16nt((uint64_t)p.packed + slot_j[j] * kPage + c * kChunk + off16, v);
         }
         *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
       }
@@ -227,7 +221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
         const uint32_t pg = 2 * j + half;
-        cur[j] = ((more >> pg) & 1u) ? ld16(va + (uint64_t)pg * kPage + cn * kChunk + off16)
+        cur[j] = ((more >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + cn * kChunk + off16)
                                      : make_uint4(0, 0, 0, 0);
       }
       const uint8_t* row = stage + q * kStageStride + k * 8u;
@@ -445,12 +439,12 @@ __global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_til
       for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j)
-          if (i < cnt) x[i * 4 + j] = ld16(tile.va + (uint64_t)pg[i] * kPage + j * 1024u + lane * 16u);
+          if (i < cnt) x[i * 4 + j] = ld16nt(tile.va + (uint64_t)pg[i] * kPage + j * 1024u + lane * 16u);
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j)
-          if (i < cnt) st16((uint64_t)packed + dst[i] * kPage + j * 1024u + lane * 16u, x[i * 4 + j]);
+          if (i < cnt) st16nt((uint64_t)packed + dst[i] * kPage + j * 1024u + lane * 16u, x[i * 4 + j]);
     }
   }
 }
@@ -474,7 +468,7 @@ __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t
       const uint32_t pg = (uint32_t)__builtin_ctz(mask);
       mask &= mask - 1u;
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) st16(tile.va + (uint64_t)pg * kPage + j * 1024u + lane * 16u, z);
+      for (uint32_t j = 0; j < 4; ++j) st16nt(tile.va + (uint64_t)pg * kPage + j * 1024u + lane * 16u, z);
     }
   }
 }
@@ -503,13 +497,13 @@ __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uin
       dst[i] = __shfl(va, i, 64);
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
-        if ((okm >> i) & 1u) x[i * 4 + j] = ld16((uint64_t)packed + (s0 + i) * kPage + j * 1024u + lane * 16u);
+        if ((okm >> i) & 1u) x[i * 4 + j] = ld16nt((uint64_t)packed + (s0 + i) * kPage + j * 1024u + lane * 16u);
     }
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
-        if ((okm >> i) & 1u) st16(dst[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
+        if ((okm >> i) & 1u) st16nt(dst[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
   }
 }
 
@@ -547,7 +541,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       uint4 x[8];
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i)
-        x[i] = (s0 + i < nseg) ? ld16(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
+        x[i] = (s0 + i < nseg) ? ld16nt(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i) closure_words(x[i], sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
     }
