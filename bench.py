@@ -5,24 +5,31 @@ One step = one pass of the whole path over the 30 GiB MoE-shaped pool
 pointers, a 1 GiB fp32 workspace with 80 % zero pages, 6 fp16 activation
 buffers):
 
-  1. kc_snapshot  -- zero probe, keep scan, then one pass that hashes every
-                     page (XXH64), runs the closure scan over every aligned
-                     word and writes the packed snapshot + page-VA table;
-  2. kc_restore   -- zero-fill + scatter of the packed pages back to their
-                     original VAs;
-  3. kc_compare   -- the 200 restored buffers against a resident golden copy
-                     (typed: bf16 / u8 / fp32 / fp16), one persistent launch.
+  1. kc_snapshot        -- zero probe, keep scan, then one pass that hashes
+                           every page (XXH64), runs the closure scan over every
+                           aligned word and writes the packed snapshot and its
+                           page-VA table;
+  2. kc_restore         -- zero-fill + scatter of the packed pages back to their
+                           original VAs;
+  3. kc_compare_pairset -- the 200 restored buffers against a resident golden
+                           copy (typed: bf16 / u8 / fp32 / fp16), one launch.
 
 Inputs are resident in HBM before timing.  ``value`` is algorithmic bytes per
-step (see ``step_bytes``) over the timed wall time of K steps.  The roofline
-object reports the kernel with the largest time share, timed by HIP events
-the library records around it on the same stream.
+step (``step_bytes``) over the timed GPU time of K steps on the stream the
+library launches on.  Launch shapes come from the autotuner (every candidate
+must give bit-identical outputs).  The roofline object reports the kernel with
+the largest time share, timed by HIP events the library records around it.
+Also reported: the same step replayed from a HIP graph, the c1 latency case
+(stream vs graph), batched persistent launches vs one launch per buffer (c2
+delta snapshot over 4096 ranges, c3 compare over 10,000 pairs), and the
+validation serving loop (c5: p50 / p99 latency, aggregate GB/s).
 
-    python bench.py [--steps K] [--warmup W] [--scale S] [--no-cpu] [--extras]
+    python bench.py [--steps K] [--warmup W] [--scale S] [--no-cpu] [--no-extras]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,9 +42,29 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PAGE = 4096
 
+# HBM traffic of the main kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE) of `bench.py --steps 2 --warmup 1 --no-cpu --no-extras`,
+# per launch, scaled by the factors a plain 4 GiB device copy gives (fetch
+# x2.0, write x1.0).  Valid only for the kernel sources they were taken from.
+PMC_TRAFFIC = {
+    "source_sha256": None,
+    "snapshot": None,
+    "restore": None,
+    "compare": None,
+}
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_03208_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()
 
 
 def step_bytes(n_pages: int, n_kept: int, cmp_bytes: int) -> dict:
@@ -69,11 +96,10 @@ def cpu_baseline(case, ranges, sample_idx) -> dict:
     n_pages = nb // PAGE
     t0 = time.perf_counter()
     h, z, _ = oracle.page_hash(sub, views)
-    res, oob = oracle.closure_scan(sub, views, oob_cap=16)
+    oracle.closure_scan(sub, views, oob_cap=16)
     packed, va, n_kept = oracle.compact(sub, views, z)
     work = [np.empty_like(v) for v in views]
     oracle.restore(sub, work, z, None, packed, va, n_kept)
-    dt_map = {0: oracle.U8}
     for i, (w, g) in enumerate(zip(work, gold)):
         ri = sample_idx[i]
         dt = oracle.BF16 if ri < 192 else (oracle.U8 if ri == 192 else (oracle.F32 if ri == 193 else oracle.F16))
@@ -82,8 +108,8 @@ def cpu_baseline(case, ranges, sample_idx) -> dict:
     b = step_bytes(n_pages, n_kept, nb)
     total = sum(b.values())
     return {"value": round(total / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"ranges {sample_idx[0]}..{sample_idx[-1]} subset ({len(sample_idx)} ranges, "
-                      f"{nb / 2**30:.2f} GiB) of the 30 GiB pool: page hash + closure scan + compact + "
+            "sample": f"{len(sample_idx)} of the 200 ranges ({nb / 2**30:.2f} GiB: 8 experts, the pointer table, "
+                      f"the workspace, one activation buffer) through page hash + closure scan + compact + "
                       f"restore + compare, {t:.1f} s single-threaded",
             "seconds": round(t, 2)}
 
@@ -95,13 +121,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 30 GiB pool (1.0 = full)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--extras", action="store_true", help="also time batched vs per-buffer forms")
+    ap.add_argument("--no-extras", action="store_true", help="skip graph / batching / serving measurements")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB three times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
-              f"by allocation, see DESIGN.md).", file=sys.stderr)
+              f"by allocation: each GPU snapshots its own ranges).", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -118,7 +146,7 @@ def main() -> int:
         print(json.dumps({"copy_calibration_bytes": n, "reps": 3}), flush=True)
         return 0
 
-    from paper_2605_03208_amd import kc
+    from paper_2605_03208_amd import autotune, kc
     from paper_2605_03208_amd import workloads as W
 
     kc.lib()
@@ -143,17 +171,43 @@ def main() -> int:
     pair_list = []
     for i in range(len(ranges)):
         o, s = int(case.layout.offsets[i]), int(case.layout.sizes[i])
-        dt = kinds[i] if args.scale == 1.0 or i < len(kinds) else W.DT_U8
-        pair_list.append((case.arena.buf[o:o + s], golden[o:o + s], dt, 0))
-    pairs = kc.make_pairs(pair_list)
+        pair_list.append((case.arena.buf[o:o + s], golden[o:o + s], kinds[i] if i < len(kinds) else W.DT_U8, 0))
     cmp_bytes = sum(int(s) for _, s in ranges)
     res = torch.empty(len(pair_list) * 472, dtype=torch.uint8, device=dev)
+    state = {"ps": kc.PairSet(ctx, pair_list)}
 
-    def step():
+    def snap():
         kc.snapshot(ctx, rs, seed=0, scan=scan, out=out)
+
+    def restore():
         kc.restore(ctx, rs, out["zero_bm"], None, out["packed"], out["page_va"], out["n_kept"], cap_pages=cap,
                    n_bad=n_bad)
-        kc.compare(ctx, pairs, res=res)
+
+    def compare():
+        kc.compare_pairset(ctx, state["ps"], res=res)
+
+    def step():
+        snap()
+        restore()
+        compare()
+
+    tuned = {}
+    if not args.no_tune:
+        log("autotuning launch shapes on this workload")
+        sig = f"c4-moe-pool-scale{args.scale}"
+        snap_digest = lambda: autotune.digest_tensors(out["hash"], out["zero_bm"], out["n_kept"], scan.res)
+        tuned["snapshot"] = autotune.tune(ctx, kc.OP_SNAPSHOT, snap, snap_digest, sig, use_cache=False)["best"]
+        restore_digest = lambda: autotune.digest_tensors(n_bad)
+        tuned["restore"] = autotune.tune(ctx, kc.OP_RESTORE, restore, restore_digest, sig, use_cache=False)["best"]
+
+        def prep(cand):
+            state["ps"].close()
+            state["ps"] = kc.PairSet(ctx, pair_list)
+
+        cmp_digest = lambda: autotune.digest_tensors(res)
+        tuned["compare"] = autotune.tune(ctx, kc.OP_COMPARE, compare, cmp_digest, sig, use_cache=False,
+                                         prepare=prep)["best"]
+        log(f"tuned: {tuned}")
 
     log("warmup")
     for _ in range(args.warmup):
@@ -176,8 +230,7 @@ def main() -> int:
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
 
     log("per-kernel timing pass")
     ctx.enable_timing(True)
@@ -196,10 +249,12 @@ def main() -> int:
     dom = max(avg, key=avg.get)
     achieved = kb[dom] / (avg[dom] / 1e3) / 1e9
     kernel_names = {"snapshot": "k_page_hash<gather,scan>", "restore": "k_restore_scatter", "compare": "k_compare"}
+    traffic_ok = PMC_TRAFFIC["source_sha256"] == source_digest() and args.scale == 1.0
     ops = {k: {"kernel": kernel_names[k], "kernel_ms": round(avg[k], 4),
                "kernel_GBps": round(kb[k] / (avg[k] / 1e3) / 1e9, 1),
                "kernel_frac_of_peak": round(kb[k] / (avg[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-               "alg_bytes_per_step": sb[k]} for k in avg}
+               "kernel_alg_bytes": kb[k], "op_alg_bytes_per_step": sb[k],
+               "pmc_traffic_bytes": PMC_TRAFFIC[k] if traffic_ok else None} for k in avg}
 
     line = {
         "metric": "hash+compact/compare GB/s (% HBM peak), batched vs per-buffer; p99 latency",
@@ -212,76 +267,240 @@ def main() -> int:
                                "experts + 512 KiB pointer table + 1 GiB fp32 workspace (80% zero pages) + "
                                "6 fp16 activations; fused closure scan vs the 200 sorted ranges; "
                                "200-pair typed compare against a resident golden copy",
-                   "scale": args.scale, "pages": N, "kept_pages": n_kept, "alg_bytes_per_step": total_bytes},
+                   "scale": args.scale, "pages": N, "kept_pages": n_kept, "alg_bytes_per_step": total_bytes,
+                   "launch_shapes": tuned or "built-in"},
         "roofline": {"bound": "hbm", "kernel": kernel_names[dom], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": ops[dom]["pmc_traffic_bytes"]},
         "ops": ops,
         "wall_s_timed": round(wall, 3),
     }
-    if args.extras:
-        line["extras"] = extras(kc, W, ctx, dev, log)
+
+    # the snapshot op alone (probe + scans + fused pass + out-of-range emission)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        snap()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    snap_op_ms = e0.elapsed_time(e1) / args.steps
+    line["snapshot_op"] = {"ms": round(snap_op_ms, 4),
+                           "GBps": round(sb["snapshot"] / (snap_op_ms / 1e3) / 1e9, 1),
+                           "frac_of_peak": round(sb["snapshot"] / (snap_op_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    sample_idx = list(range(0, 8)) + [192, 193, 194] if args.scale == 1.0 else list(range(min(11, len(ranges))))
+    cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline on a bounded sample")
-        sample_idx = list(range(0, 8)) + [192, 193, 194] if args.scale == 1.0 else list(range(min(11, len(ranges))))
-        line["cpu_baseline"] = cpu_baseline(case, ranges, sample_idx)
+        cpu = cpu_baseline(case, ranges, sample_idx)
+    if not args.no_extras:
+        log("graph replay of the step")
+        line["graph"] = graph_step(torch, step, res, pair_list, kc, args.steps)
+        state["ps"].close()
+        rs.close()
+        del case, golden, out, state, pair_list, rs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        line["graph"]["c1_latency"] = c1_latency(torch, kc, W, dev)
+        line["batching"] = batching(torch, kc, W, dev)
+        line["serving"] = serving(torch, kc, W, dev, args.serve_seconds)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
 
 
-def extras(kc, W, ctx, dev, log) -> dict:
-    """Batched persistent launches vs one launch per buffer (c2 delta, c3 compare)."""
-    import torch
+def graph_step(torch, step, res, pair_list, kc, reps: int) -> dict:
+    """Record one step into a HIP graph, replay it, check the replays."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    got = kc.decode_cmp(res, len(pair_list))
+    ok = all(r["pass"] == 1 and r["n_mismatch_bytes"] == 0 for r in got)
+    return {"ms_per_step": round(e0.elapsed_time(e1) / reps, 4), "replays_checked": ok}
+
+
+def c1_latency(torch, kc, W, dev) -> dict:
+    """Latency-bound small case: 64 MiB snapshot + restore + 16-pair compare."""
+    log("c1 latency: stream vs graph")
+    case = W.c1_snapshot("cuda")
+    ctx = kc.Context(0)
+    rs = kc.RangeSet(ctx, case.ranges())
+    N = rs.n_pages
+    out = dict(hash=torch.empty(N, dtype=torch.int64, device=dev),
+               zero_bm=torch.empty(rs.n_words, dtype=torch.int64, device=dev), changed_bm=None,
+               packed=torch.empty(N * PAGE, dtype=torch.uint8, device=dev),
+               page_va=torch.empty(N, dtype=torch.int64, device=dev),
+               n_kept=torch.empty(1, dtype=torch.int64, device=dev))
+    scan = kc.ScanOut(dev, oob_cap=16)
+    pairs = W.c1_compare("cuda")
+    ps = kc.PairSet(ctx, [(p.cand, p.gold, W.DT_F32, 0) for p in pairs])
+    res = torch.empty(len(pairs) * 472, dtype=torch.uint8, device=dev)
+
+    def step():
+        kc.snapshot(ctx, rs, scan=scan, out=out)
+        kc.restore(ctx, rs, out["zero_bm"], None, out["packed"], out["page_va"], out["n_kept"])
+        kc.compare_pairset(ctx, ps, res=res)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    ref = res.clone()
+    reps = 50
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stream_us = e0.elapsed_time(e1) / reps * 1e3
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.stream(s):
+        step()
+    stream.wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    ok = True
+    for _ in range(3):  # replays with eager work in between, each checked
+        g.replay()
+        torch.cuda.synchronize()
+        ok = ok and torch.equal(res, ref)
+        res.zero_()
+        torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_us = e0.elapsed_time(e1) / reps * 1e3
+    ok = ok and torch.equal(res, ref)
+    ps.close()
+    rs.close()
+    ctx.close()
+    return {"workload": "c1: 64 MiB / 48 ranges snapshot + restore + 16 x 2^20 fp32 compare",
+            "stream_us": round(stream_us, 1), "graph_us": round(graph_us, 1),
+            "graph_speedup": round(stream_us / graph_us, 3), "replays_match_eager": ok}
+
+
+def batching(torch, kc, W, dev) -> dict:
+    """Batched persistent launches vs one launch per buffer on uneven sizes."""
     out = {}
-    log("extras: c3 compare, 10,000 pairs / 8 GiB per side")
+    log("batching: c3 compare, 10,000 pairs / 8 GiB per side")
     ps = W.c3_pairs("cuda", n_pairs=10000)
-    pairs = kc.make_pairs([(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))])
-    res = torch.empty(len(ps) * 472, dtype=torch.uint8, device=dev)
+    plist = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))]
+    arr = kc.make_pairs(plist)
     nbytes = 2 * int(ps.nbytes.sum())
+    res = torch.empty(len(ps) * 472, dtype=torch.uint8, device=dev)
+    results = {}
     for mode in ("batched", "per_buffer"):
         c2 = kc.Context(0)
         c2.set_tuning(kc.OP_COMPARE, per_item=1 if mode == "per_buffer" else 0)
-        kc.compare(c2, pairs, res=res)
+        kc.compare(c2, arr, res=res)
         torch.cuda.synchronize()
+        results[mode] = res.clone()
+        reps = 3
         t0 = time.perf_counter()
-        reps = 5
         for _ in range(reps):
-            kc.compare(c2, pairs, res=res)
+            kc.compare(c2, arr, res=res)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out[f"c3_compare_{mode}_GBps"] = round(nbytes / dt / 1e9, 1)
         out[f"c3_compare_{mode}_ms"] = round(dt * 1e3, 3)
+        out[f"c3_compare_{mode}_GBps"] = round(nbytes / dt / 1e9, 1)
         c2.close()
-    del ps, pairs
+    out["c3_results_identical"] = bool(torch.equal(results["batched"], results["per_buffer"]))
+    out["c3_batched_speedup"] = round(out["c3_compare_per_buffer_ms"] / out["c3_compare_batched_ms"], 2)
+    del ps, plist, arr, results
     torch.cuda.empty_cache()
-    log("extras: c2 delta snapshot, 4096 ranges / 2 GiB")
+    log("batching: c2 delta snapshot, 4096 ranges / 2 GiB")
     case = W.c2_snapshot("cuda")
-    rs_ranges = case.ranges()
+    rngs = case.ranges()
+    c0 = kc.Context(0)
+    rs0 = kc.RangeSet(c0, rngs)
+    prior = kc.snapshot(c0, rs0, seed=2)["hash"].clone()
+    W.c2_rewrite(case)
+    rs0.close()
+    c0.close()
+    digests = {}
     for mode in ("batched", "per_buffer"):
         c2 = kc.Context(0)
         for op in (kc.OP_PAGE_HASH, kc.OP_COMPACT):
             c2.set_tuning(op, per_item=1 if mode == "per_buffer" else 0)
-        rs = kc.RangeSet(c2, rs_ranges)
-        s1 = kc.snapshot(c2, rs, seed=2)
-        prior = s1["hash"].clone()
-        if mode == "batched":
-            W.c2_rewrite(case)
+        rs = kc.RangeSet(c2, rngs)
         s2 = kc.snapshot(c2, rs, seed=2, prior=prior)
         torch.cuda.synchronize()
+        nk = int(s2["n_kept"].item())
+        digests[mode] = (s2["hash"].cpu(), s2["changed_bm"].cpu(), s2["packed"][: nk * PAGE].cpu())
+        reps = 3
         t0 = time.perf_counter()
-        reps = 5
         for _ in range(reps):
             kc.snapshot(c2, rs, seed=2, prior=prior, out=s2)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         n = rs.n_pages
-        nk = int(s2["n_kept"].item())
         b = 4096 * n + 8 * n + 8 * n + n // 4 + nk * 4104
-        out[f"c2_delta_{mode}_GBps"] = round(b / dt / 1e9, 1)
         out[f"c2_delta_{mode}_ms"] = round(dt * 1e3, 3)
+        out[f"c2_delta_{mode}_GBps"] = round(b / dt / 1e9, 1)
+        out["c2_delta_kept_pages"] = nk
         rs.close()
         c2.close()
+    out["c2_results_identical"] = all(torch.equal(a, b) for a, b in zip(digests["batched"], digests["per_buffer"]))
+    out["c2_batched_speedup"] = round(out["c2_delta_per_buffer_ms"] / out["c2_delta_batched_ms"], 2)
+    del case
+    torch.cuda.empty_cache()
     return out
+
+
+def serving(torch, kc, W, dev, seconds: float) -> dict:
+    """c5: Poisson 200 req/s, 1-64 candidate buffers per request, 32 GiB budget."""
+    from paper_2605_03208_amd import serve
+    log(f"serving: c5 for {seconds:.1f} s at 200 req/s")
+    golds, dtypes = W.c5_pool("cuda")
+    reqs = W.c5_requests(rate_hz=200.0, duration_s=seconds)
+    reqs = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in reqs]
+    ex = serve.DeviceExecutor(golds, dtypes, n_streams=4)
+    warm = serve.Server(ex, 32 << 30)
+    warm.run(reqs[:8])
+    torch.cuda.synchronize()
+    srv = serve.Server(ex, 32 << 30)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    summ = serve.summarize(done, wall)
+    summ.update(offered_req_per_s=200.0, budget_GiB=32, budget_peak_GiB=round(srv.budget.peak / 2**30, 2),
+                streams=4, pool_buffers=len(golds),
+                pool_GiB=round(sum(g.numel() * g.element_size() for g in golds) / 2**30, 2))
+    log(f"serving: overload burst (2,000 req/s for {seconds / 3:.1f} s)")
+    burst = W.c5_requests(rate_hz=2000.0, duration_s=seconds / 3)
+    burst = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in burst]
+    srv2 = serve.Server(ex, 32 << 30)
+    t0 = time.perf_counter()
+    done2 = srv2.run(burst)
+    torch.cuda.synchronize()
+    wall2 = time.perf_counter() - t0
+    b = serve.summarize(done2, wall2)
+    b.update(offered_req_per_s=2000.0, budget_peak_GiB=round(srv2.budget.peak / 2**30, 2))
+    summ["overload"] = b
+    return summ
 
 
 if __name__ == "__main__":

@@ -24,8 +24,10 @@
  *    call only.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls enqueue work and return; outputs are valid once the stream has
- *    reached that point.  Except for kc_compare, a call allocates nothing
- *    and never synchronises, so the sequence can be recorded into a graph.
+ *    reached that point.  Apart from the *_create calls and kc_compare, a
+ *    call allocates nothing and never synchronises, so a sequence of
+ *    kc_snapshot / kc_restore / kc_closure_scan / kc_compare_pairset calls
+ *    can be recorded into a HIP graph and replayed.
  *  - The return value reports synchronous argument checks and launch
  *    failures only.  Conditions found on the device (capacity overflow,
  *    truncated lists, rejected page addresses) are reported through outputs.
@@ -76,6 +78,7 @@ enum {
 
 typedef struct kc_ctx kc_ctx;
 typedef struct kc_rangeset kc_rangeset;
+typedef struct kc_pairset kc_pairset;
 
 typedef struct {
   uint64_t base; /* device VA of the allocation */
@@ -269,6 +272,21 @@ int kc_closure_scan(kc_ctx *ctx, const kc_rangeset *rs,
  * memory: not for graph capture.  Errors: KC_EDTYPE, KC_EALIGN, KC_EINVAL. */
 int kc_compare(kc_ctx *ctx, const kc_pair *pairs, uint32_t n_pairs,
                kc_cmp_result *res_d, void *stream);
+
+/* A resident pair list for repeated or graph-recorded compares: the pair and
+ * tile tables (tile size taken from the context's compare tuning at creation)
+ * and the accumulators live on the device.  Creation validates like
+ * kc_compare, allocates and uploads synchronously; the buffers it names must
+ * stay alive and in place while the set is used. */
+int kc_pairset_create(kc_ctx *ctx, const kc_pair *pairs, uint32_t n_pairs,
+                      kc_pairset **out);
+void kc_pairset_destroy(kc_pairset *ps);
+
+/* kc_compare over a resident pair set: no allocation, no host
+ * synchronisation, so it can be recorded into a graph.  Results are identical
+ * to kc_compare on the same pairs.  One stream at a time per set. */
+int kc_compare_pairset(kc_ctx *ctx, const kc_pairset *ps, kc_cmp_result *res_d,
+                       void *stream);
 
 #ifdef __cplusplus
 }

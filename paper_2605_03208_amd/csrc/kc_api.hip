@@ -536,26 +536,100 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
   return finish_scan(rs, scan, sd, s);
 }
 
-int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result* res_d, void* stream) {
-  if (c == nullptr || (n_pairs > 0 && (pairs == nullptr || res_d == nullptr))) return KC_EINVAL;
-  if (n_pairs == 0) return KC_OK;
-  const uint32_t tile_bytes = c->tune[KC_OP_COMPARE].tile_bytes ? c->tune[KC_OP_COMPARE].tile_bytes : (64u << 10);
-  std::vector<uint64_t> tile_off(n_pairs + 1, 0);
+}  // extern "C"
+
+struct kc_pairset {
+  kc_ctx* ctx = nullptr;
+  uint32_t n_pairs = 0, tile_bytes = 0;
+  uint64_t n_tiles = 0;
+  std::vector<uint64_t> tile_off;
+  void* dev = nullptr;
+  CmpPairDev* pairs = nullptr;
+  CmpTileDev* tiles = nullptr;
+  unsigned long long* acc = nullptr;
+};
+
+namespace {
+
+uint32_t elem_size(uint32_t dtype) {
+  return dtype == KC_F32 ? 4u : (dtype == KC_BF16 || dtype == KC_F16 ? 2u : 1u);
+}
+
+// Validate a pair list and count its tiles.
+int plan_pairs(const kc_pair* pairs, uint32_t n_pairs, uint32_t tile_bytes, std::vector<uint64_t>& tile_off) {
+  tile_off.assign(n_pairs + 1, 0);
   for (uint32_t i = 0; i < n_pairs; ++i) {
     const kc_pair& pr = pairs[i];
     if (pr.dtype > KC_U8) return KC_EDTYPE;
-    const uint64_t es = pr.dtype == KC_F32 ? 4 : (pr.dtype == KC_BF16 || pr.dtype == KC_F16 ? 2 : 1);
     if (pr.n_elems > (1ull << 60)) return KC_ELIMIT;
     if (pr.n_elems > 0) {
       if (pr.cand_d == nullptr || pr.gold_d == nullptr) return KC_EINVAL;
       if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & 15u) return KC_EALIGN;
     }
-    const uint64_t nb = pr.n_elems * es;
+    const uint64_t nb = pr.n_elems * elem_size(pr.dtype);
     const uint64_t nt = nb == 0 ? 1 : (nb + tile_bytes - 1) / tile_bytes;
     tile_off[i + 1] = tile_off[i] + nt;
   }
+  if (tile_off[n_pairs] > 0xFFFFFFFFull) return KC_ELIMIT;
+  return KC_OK;
+}
+
+// Fill the device-layout pair and tile tables (host memory).
+void fill_pair_tables(const kc_pair* pairs, uint32_t n_pairs, const std::vector<uint64_t>& tile_off,
+                      CmpPairDev* hp, CmpTileDev* ht) {
+  for (uint32_t i = 0; i < n_pairs; ++i) {
+    const kc_pair& pr = pairs[i];
+    CmpPairDev d;
+    d.cand = static_cast<const uint8_t*>(pr.cand_d);
+    d.gold = static_cast<const uint8_t*>(pr.gold_d);
+    d.n_elems = pr.n_elems;
+    d.dtype = pr.dtype;
+    d.tol = pr.ulp_tol;
+    d.n_tiles = (uint32_t)(tile_off[i + 1] - tile_off[i]);
+    d.esize = elem_size(pr.dtype);
+    hp[i] = d;
+    for (uint64_t t = tile_off[i]; t < tile_off[i + 1]; ++t) {
+      ht[t].pair = i;
+      ht[t].idx = (uint32_t)(t - tile_off[i]);
+    }
+  }
+}
+
+// Clear the accumulators, run the pass (one launch, or one per pair), write the reports.
+int run_compare(kc_ctx* c, const CmpPairDev* dpairs, const CmpTileDev* dtiles, const std::vector<uint64_t>& tile_off,
+                uint32_t n_pairs, uint32_t tile_bytes, unsigned long long* dacc, kc_cmp_result* res_d, hipStream_t s) {
+  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), (uint64_t)n_pairs * kAccWords, 0, s));
+  const uint32_t grid = grid_for(c, KC_OP_COMPARE, 2);
+  {
+    KernelTimer timer(c, KC_OP_COMPARE, s);
+    if (!c->tune[KC_OP_COMPARE].per_item) {
+      KC_HIP(launch_compare(dpairs, dtiles, (uint32_t)tile_off[n_pairs], tile_bytes, dacc, grid, s));
+    } else {
+      for (uint32_t i = 0; i < n_pairs; ++i)
+        KC_HIP(launch_compare(dpairs, dtiles + tile_off[i], (uint32_t)(tile_off[i + 1] - tile_off[i]), tile_bytes,
+                              dacc, grid, s));
+    }
+  }
+  KC_HIP(launch_compare_finalize(dpairs, n_pairs, dacc, res_d, s));
+  return KC_OK;
+}
+
+uint32_t compare_tile_bytes(const kc_ctx* c) {
+  return c->tune[KC_OP_COMPARE].tile_bytes ? c->tune[KC_OP_COMPARE].tile_bytes : (64u << 10);
+}
+
+}  // namespace
+
+extern "C" {
+
+int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result* res_d, void* stream) {
+  if (c == nullptr || (n_pairs > 0 && (pairs == nullptr || res_d == nullptr))) return KC_EINVAL;
+  if (n_pairs == 0) return KC_OK;
+  const uint32_t tile_bytes = compare_tile_bytes(c);
+  std::vector<uint64_t> tile_off;
+  int st = plan_pairs(pairs, n_pairs, tile_bytes, tile_off);
+  if (st != KC_OK) return st;
   const uint64_t n_tiles = tile_off[n_pairs];
-  if (n_tiles > 0xFFFFFFFFull) return KC_ELIMIT;
   const size_t sz_pairs = align_up(sizeof(CmpPairDev) * n_pairs, 256);
   const size_t sz_tiles = align_up(sizeof(CmpTileDev) * n_tiles, 256);
   const size_t sz_acc = (size_t)n_pairs * kAccWords * 8;
@@ -591,44 +665,71 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
     }
     c->cmp_host_cap = cap;
   }
-  CmpPairDev* hp = reinterpret_cast<CmpPairDev*>(c->cmp_host);
-  CmpTileDev* ht = reinterpret_cast<CmpTileDev*>(c->cmp_host + sz_pairs);
-  for (uint32_t i = 0; i < n_pairs; ++i) {
-    const kc_pair& pr = pairs[i];
-    CmpPairDev d;
-    d.cand = static_cast<const uint8_t*>(pr.cand_d);
-    d.gold = static_cast<const uint8_t*>(pr.gold_d);
-    d.n_elems = pr.n_elems;
-    d.dtype = pr.dtype;
-    d.tol = pr.ulp_tol;
-    d.n_tiles = (uint32_t)(tile_off[i + 1] - tile_off[i]);
-    d.esize = pr.dtype == KC_F32 ? 4 : (pr.dtype == KC_BF16 || pr.dtype == KC_F16 ? 2 : 1);
-    hp[i] = d;
-    for (uint64_t t = tile_off[i]; t < tile_off[i + 1]; ++t) {
-      ht[t].pair = i;
-      ht[t].idx = (uint32_t)(t - tile_off[i]);
-    }
-  }
+  fill_pair_tables(pairs, n_pairs, tile_off, reinterpret_cast<CmpPairDev*>(c->cmp_host),
+                   reinterpret_cast<CmpTileDev*>(c->cmp_host + sz_pairs));
   CmpPairDev* dpairs = reinterpret_cast<CmpPairDev*>(c->cmp_dev);
   CmpTileDev* dtiles = reinterpret_cast<CmpTileDev*>(c->cmp_dev + sz_pairs);
   unsigned long long* dacc = reinterpret_cast<unsigned long long*>(c->cmp_dev + sz_pairs + sz_tiles);
   KC_HIP(hipMemcpyAsync(c->cmp_dev, c->cmp_host, need_host, hipMemcpyHostToDevice, s));
   KC_HIP(hipEventRecord(c->staged, s));
   c->staged_pending = true;
-  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), (uint64_t)n_pairs * kAccWords, 0, s));
-  const uint32_t grid = grid_for(c, KC_OP_COMPARE, 2);
-  {
-    KernelTimer timer(c, KC_OP_COMPARE, s);
-    if (!c->tune[KC_OP_COMPARE].per_item) {
-      KC_HIP(launch_compare(dpairs, dtiles, (uint32_t)n_tiles, tile_bytes, dacc, grid, s));
-    } else {
-      for (uint32_t i = 0; i < n_pairs; ++i)
-        KC_HIP(launch_compare(dpairs, dtiles + tile_off[i], (uint32_t)(tile_off[i + 1] - tile_off[i]), tile_bytes,
-                              dacc, grid, s));
-    }
+  return run_compare(c, dpairs, dtiles, tile_off, n_pairs, tile_bytes, dacc, res_d, s);
+}
+
+int kc_pairset_create(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_pairset** out) {
+  if (c == nullptr || out == nullptr || (n_pairs > 0 && pairs == nullptr)) return KC_EINVAL;
+  *out = nullptr;
+  const uint32_t tile_bytes = compare_tile_bytes(c);
+  std::vector<uint64_t> tile_off;
+  int st = plan_pairs(pairs, n_pairs, tile_bytes, tile_off);
+  if (st != KC_OK) return st;
+  DeviceGuard g(c->device);
+  kc_pairset* ps = new (std::nothrow) kc_pairset();
+  if (ps == nullptr) return KC_ENOMEM;
+  ps->ctx = c;
+  ps->n_pairs = n_pairs;
+  ps->tile_bytes = tile_bytes;
+  ps->n_tiles = tile_off[n_pairs];
+  ps->tile_off = std::move(tile_off);
+  const size_t sz_pairs = align_up(sizeof(CmpPairDev) * std::max<uint32_t>(1, n_pairs), 256);
+  const size_t sz_tiles = align_up(sizeof(CmpTileDev) * std::max<uint64_t>(1, ps->n_tiles), 256);
+  const size_t sz_acc = (size_t)std::max<uint32_t>(1, n_pairs) * kAccWords * 8;
+  hipError_t e = hipMalloc(&ps->dev, sz_pairs + sz_tiles + sz_acc);
+  if (e != hipSuccess) {
+    set_error("hipMalloc(pairset)", e);
+    delete ps;
+    return e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
   }
-  KC_HIP(launch_compare_finalize(dpairs, n_pairs, dacc, res_d, s));
+  uint8_t* base = static_cast<uint8_t*>(ps->dev);
+  ps->pairs = reinterpret_cast<CmpPairDev*>(base);
+  ps->tiles = reinterpret_cast<CmpTileDev*>(base + sz_pairs);
+  ps->acc = reinterpret_cast<unsigned long long*>(base + sz_pairs + sz_tiles);
+  std::vector<uint8_t> host(sz_pairs + sz_tiles);
+  fill_pair_tables(pairs, n_pairs, ps->tile_off, reinterpret_cast<CmpPairDev*>(host.data()),
+                   reinterpret_cast<CmpTileDev*>(host.data() + sz_pairs));
+  if ((e = hipMemcpy(ps->dev, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    set_error("hipMemcpy(pairset)", e);
+    (void)hipFree(ps->dev);
+    delete ps;
+    return KC_EHIP;
+  }
+  *out = ps;
   return KC_OK;
+}
+
+void kc_pairset_destroy(kc_pairset* ps) {
+  if (ps == nullptr) return;
+  DeviceGuard g(ps->ctx->device);
+  (void)hipFree(ps->dev);
+  delete ps;
+}
+
+int kc_compare_pairset(kc_ctx* c, const kc_pairset* ps, kc_cmp_result* res_d, void* stream) {
+  if (c == nullptr || ps == nullptr || ps->ctx != c || (ps->n_pairs > 0 && res_d == nullptr)) return KC_EINVAL;
+  if (ps->n_pairs == 0) return KC_OK;
+  DeviceGuard g(c->device);
+  return run_compare(c, ps->pairs, ps->tiles, ps->tile_off, ps->n_pairs, ps->tile_bytes, ps->acc, res_d,
+                     as_stream(stream));
 }
 
 }  // extern "C"

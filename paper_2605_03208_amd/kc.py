@@ -27,7 +27,8 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_tuning", "kc_ctx_get_tuning",
            "kc_ctx_enable_timing", "kc_ctx_kernel_ms",
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
-           "kc_restore", "kc_closure_scan", "kc_compare"]
+           "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
+           "kc_compare_pairset"]
 
 
 class KCError(RuntimeError):
@@ -108,6 +109,9 @@ def lib() -> ctypes.CDLL:
             "kc_restore": ([vp, vp, vp, vp, vp, vp, vp, u64, vp, vp], i32),
             "kc_closure_scan": ([vp, vp, P(ScanArgs), vp], i32),
             "kc_compare": ([vp, P(Pair), u32, vp, vp], i32),
+            "kc_pairset_create": ([vp, P(Pair), u32, P(vp)], i32),
+            "kc_pairset_destroy": ([vp], None),
+            "kc_compare_pairset": ([vp, vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -184,8 +188,11 @@ class Context:
         _check(lib().kc_ctx_get_tuning(self.handle, op, ctypes.byref(t)), "kc_ctx_get_tuning")
         return dict(grid_per_cu=t.grid_per_cu, tile_bytes=t.tile_bytes, per_item=t.per_item)
 
+    timing = False
+
     def enable_timing(self, on: bool = True) -> None:
         _check(lib().kc_ctx_enable_timing(self.handle, 1 if on else 0), "kc_ctx_enable_timing")
+        self.timing = bool(on)
 
     def kernel_ms(self, op: int) -> float:
         """Duration of the main kernel(s) of the op's last call (waits for it)."""
@@ -320,6 +327,36 @@ def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -
     if res is None:
         res = torch.empty(max(1, n) * 472, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
     _check(lib().kc_compare(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare")
+    return res
+
+
+class PairSet:
+    """A resident pair list (kc_pairset): compares through it allocate nothing
+    and never synchronise, so they can be recorded into a graph."""
+
+    def __init__(self, ctx: Context, pairs):
+        self.ctx = ctx
+        self.arr, self.n = pairs if isinstance(pairs, tuple) else make_pairs(pairs)
+        self.handle = ctypes.c_void_p()
+        _check(lib().kc_pairset_create(ctx.handle, self.arr, self.n, ctypes.byref(self.handle)),
+               "kc_pairset_create")
+
+    def close(self) -> None:
+        if self.handle:
+            lib().kc_pairset_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compare_pairset(ctx: Context, ps: PairSet, res: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if res is None:
+        res = torch.empty(max(1, ps.n) * 472, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
+    _check(lib().kc_compare_pairset(ctx.handle, ps.handle, _ptr(res), _stream(stream)), "kc_compare_pairset")
     return res
 
 

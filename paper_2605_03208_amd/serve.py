@@ -1,0 +1,246 @@
+"""Continuous-batching validation server.
+
+A tuning agent submits validation requests: "compare these candidate outputs
+of my reproducer against the captured goldens, with this ULP tolerance"
+(the validation step of Sec. 4.5.2, and reproducers as a substrate for
+tuning agents, Sec. 1 and Sec. 6).  Goldens stay resident on the device.
+
+The loop:
+  * requests arrive (Poisson schedule in the benchmark) into a FIFO queue;
+  * the head of the queue is admitted when its candidate buffers fit in the
+    HBM budget (head-of-line: a large request is never overtaken, so it
+    cannot starve);
+  * admitted requests are gathered into a batch as soon as a stream is free;
+    the batch's candidates are materialised on that stream and all its pairs
+    go to one persistent kc_compare launch, so requests that arrive while
+    other batches are on the GPU overlap with them on the device;
+  * completion is found by polling events; results are decoded, budget is
+    returned, latency = result on host - scheduled arrival.
+
+The executor is pluggable: ``DeviceExecutor`` runs on the GPU, ``MockExecutor``
+runs the same admission / batching logic on the CPU for tests.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    golden_ids: np.ndarray
+    ulp_tol: int
+    seed: int
+
+
+@dataclass
+class Completed:
+    rid: int
+    arrival_s: float
+    admit_s: float
+    launch_s: float
+    done_s: float
+    nbytes: int
+    results: list = field(default_factory=list)
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class Budget:
+    """Byte accounting of candidate buffers against the HBM budget."""
+
+    def __init__(self, limit: int):
+        self.limit = int(limit)
+        self.used = 0
+        self.peak = 0
+
+    def try_take(self, n: int) -> bool:
+        if self.used + n > self.limit:
+            return False
+        self.used += n
+        self.peak = max(self.peak, self.used)
+        return True
+
+    def give(self, n: int) -> None:
+        self.used -= n
+        assert self.used >= 0
+
+
+class MockExecutor:
+    """CPU stand-in: a batch takes ``bytes / rate`` seconds of simulated time
+    per stream; results are the request ids."""
+
+    def __init__(self, sizes, n_streams: int = 2, rate_Bps: float = 1e12):
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.n_streams = n_streams
+        self.rate = rate_Bps
+        self.busy_until = [0.0] * n_streams
+        self.batches = []
+
+    def request_bytes(self, req: Request) -> int:
+        return int(self.sizes[req.golden_ids].sum())
+
+    def free_stream(self, now: float):
+        for i, t in enumerate(self.busy_until):
+            if t <= now and not any(b[0] == i for b in self.batches):
+                return i
+        return None
+
+    def launch(self, stream: int, reqs, now: float):
+        nbytes = sum(self.request_bytes(r) for r in reqs)
+        self.busy_until[stream] = now + 2 * nbytes / self.rate
+        h = (stream, reqs, self.busy_until[stream])
+        self.batches.append(h)
+        return h
+
+    def done(self, h, now: float) -> bool:
+        return now >= h[2]
+
+    def finish(self, h):
+        self.batches.remove(h)
+        return [[dict(rid=r.rid)] for r in h[1]]
+
+
+class DeviceExecutor:
+    """Runs batches on ``n_streams`` HIP streams (one kc context each)."""
+
+    def __init__(self, goldens, dtypes, n_streams: int = 4, device=0, p_pert: float = 1e-4, kmax: int = 16):
+        import torch
+
+        from . import kc
+        from . import workloads as W
+        self.torch, self.kc, self.W = torch, kc, W
+        self.goldens = goldens
+        self.dtypes = [int(d) for d in dtypes]
+        self.sizes = np.array([g.numel() * g.element_size() for g in goldens], dtype=np.int64)
+        self.n_streams = n_streams
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.ctxs = [kc.Context(device) for _ in range(n_streams)]
+        self.busy = [None] * n_streams
+        self.p_pert, self.kmax = p_pert, kmax
+
+    def request_bytes(self, req: Request) -> int:
+        return int(self.sizes[req.golden_ids].sum())
+
+    def free_stream(self, now: float):
+        for i, b in enumerate(self.busy):
+            if b is None:
+                return i
+        return None
+
+    def launch(self, stream: int, reqs, now: float):
+        torch, kc, W = self.torch, self.kc, self.W
+        s = self.streams[stream]
+        with torch.cuda.stream(s):
+            cands, pairs, owners = [], [], []
+            for r in reqs:
+                for gid in r.golden_ids:
+                    gold = self.goldens[int(gid)]
+                    cand = torch.empty_like(gold)
+                    cand.copy_(gold)
+                    W.perturb_device(cand, self.dtypes[int(gid)], r.seed * 1000003 + int(gid), self.p_pert,
+                                     self.kmax)
+                    cands.append(cand)
+                    pairs.append((cand, gold, self.dtypes[int(gid)], r.ulp_tol))
+                    owners.append(r.rid)
+            res = kc.compare(self.ctxs[stream], pairs)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, cands=cands, n=len(pairs), owners=owners)
+        self.busy[stream] = h
+        return h
+
+    def done(self, h, now: float) -> bool:
+        return h["ev"].query()
+
+    def finish(self, h):
+        out = self.kc.decode_cmp(h["res"], h["n"])
+        self.busy[h["stream"]] = None
+        per = collections.defaultdict(list)
+        for rid, r in zip(h["owners"], out):
+            per[rid].append(r)
+        return [per[r.rid] for r in h["reqs"]]
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 64, clock=None, sleep=None):
+        self.ex = executor
+        self.budget = Budget(budget_bytes)
+        self.max_batch = max_batch
+        self.clock = clock or time.perf_counter
+        self.sleep = sleep or time.sleep
+        self.admit_order = []
+
+    def run(self, requests, real_time: bool = True, poll_s: float = 50e-6):
+        """Serve ``requests`` (sorted by arrival).  Returns Completed records
+        in completion order."""
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        for r in reqs:
+            if self.ex.request_bytes(r) > self.budget.limit:
+                raise ValueError(f"request {r.rid} needs more than the whole budget")
+        pending = collections.deque(reqs)
+        queue = collections.deque()
+        admitted = []          # (req, admit_s)
+        running = []           # (handle, [(req, admit_s)], launch_s)
+        done = []
+        t0 = self.clock()
+        now = 0.0
+        while pending or queue or admitted or running:
+            now = self.clock() - t0 if real_time else now
+            while pending and pending[0].arrival_s <= now:
+                queue.append(pending.popleft())
+            while queue and self.budget.try_take(self.ex.request_bytes(queue[0])):
+                r = queue.popleft()
+                admitted.append((r, now))
+                self.admit_order.append(r.rid)
+            progressed = False
+            while admitted:
+                st = self.ex.free_stream(now)
+                if st is None:
+                    break
+                batch, admitted = admitted[: self.max_batch], admitted[self.max_batch:]
+                h = self.ex.launch(st, [r for r, _ in batch], now)
+                running.append((h, batch, now))
+                progressed = True
+            still = []
+            for h, batch, t_launch in running:
+                if self.ex.done(h, now):
+                    results = self.ex.finish(h)
+                    t_done = self.clock() - t0 if real_time else now
+                    for (r, t_adm), res in zip(batch, results):
+                        self.budget.give(self.ex.request_bytes(r))
+                        done.append(Completed(r.rid, r.arrival_s, t_adm, t_launch, t_done,
+                                              self.ex.request_bytes(r), res))
+                    progressed = True
+                else:
+                    still.append((h, batch, t_launch))
+            running = still
+            if not progressed:
+                if real_time:
+                    nxt = pending[0].arrival_s - now if pending and not (queue or admitted or running) else poll_s
+                    self.sleep(max(0.0, min(nxt, 1e-3)))
+                else:
+                    # simulated time: jump to the next event
+                    cands = [pending[0].arrival_s] if pending else []
+                    cands += [h[2] for h, _, _ in running if isinstance(h, tuple)]
+                    nxt = min([c for c in cands if c > now], default=now + poll_s)
+                    now = nxt
+        return done
+
+
+def summarize(done, wall_s: float) -> dict:
+    lat = np.array([d.latency_s for d in done]) if done else np.zeros(1)
+    q = np.array([d.admit_s - d.arrival_s for d in done]) if done else np.zeros(1)
+    nbytes = sum(2 * d.nbytes for d in done)
+    return dict(requests=len(done), p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3),
+                queue_p99_ms=round(float(np.percentile(q, 99)) * 1e3, 3),
+                aggregate_GBps=round(nbytes / max(wall_s, 1e-9) / 1e9, 1), compared_bytes=nbytes,
+                wall_s=round(wall_s, 3))

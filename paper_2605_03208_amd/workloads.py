@@ -568,6 +568,46 @@ def c5_requests(rate_hz: float = 200.0, duration_s: float = 30.0, seed: int = 5,
     return out
 
 
+_FP8_DEV = {}
+
+
+def _fp8_tables_on(device):
+    key = str(device)
+    if key not in _FP8_DEV:
+        c, r = _fp8_tables()
+        _FP8_DEV[key] = (c.to(device), r.to(device))
+    return _FP8_DEV[key]
+
+
+def perturb_device(cand: torch.Tensor, dtype: int, seed: int, p_pert: float = 1e-4, kmax: int = 16) -> None:
+    """In place, on the tensor's device, without host synchronisation: one
+    element in each block of round(1/p_pert) elements (a seeded position) is
+    moved by a seeded 1..kmax ULP in a seeded direction."""
+    n = cand.numel()
+    if n == 0:
+        return
+    block = max(1, int(round(1.0 / p_pert)))
+    m = n // block
+    if m == 0:
+        return
+    dev = cand.device
+    gen = torch.Generator(device=dev).manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    pos = torch.arange(m, device=dev, dtype=torch.int64) * block + torch.randint(0, block, (m,), device=dev,
+                                                                                 generator=gen)
+    k = torch.randint(1, kmax + 1, (m,), device=dev, generator=gen)
+    k = torch.where(torch.randint(0, 2, (m,), device=dev, generator=gen) == 0, -k, k)
+    vals = cand[pos]
+    if dtype == DT_FP8:
+        code_of_rank, rank_of_code = _fp8_tables_on(dev)
+        r = (rank_of_code[vals.view(torch.uint8).to(torch.int64)] + k).clamp(0, len(code_of_rank) - 1)
+        cand[pos] = code_of_rank[r].view(torch.float8_e4m3fn)
+        return
+    target = torch.where(k > 0, torch.full_like(vals, float("inf")), torch.full_like(vals, float("-inf")))
+    for i in range(kmax):
+        vals = torch.where(k.abs() > i, torch.nextafter(vals, target), vals)
+    cand[pos] = vals
+
+
 def materialize_candidate(gold: torch.Tensor, dtype: int, seed: int, p_pert: float = 1e-4,
                           kmax: int = 16) -> torch.Tensor:
     """A candidate output: the golden buffer with a seeded sparse set of

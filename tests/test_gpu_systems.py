@@ -1,0 +1,145 @@
+"""Systems layers on the GPU: resident pair sets, graph replay, autotuner
+candidates, and the serving loop (alone vs in the mix, and vs the oracle)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_03208_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+PAGE = 4096
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kc():
+    from paper_2605_03208_amd import kc as K
+    K.lib()
+    assert torch.cuda.is_available()
+    return K
+
+
+def test_pairset_equals_compare(kc):
+    say("pair set vs one-shot compare, c3 scale 1/512")
+    ctx = kc.Context(0)
+    ps = W.c3_pairs("cuda", scale=1 / 512, n_pairs=300)
+    plist = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))]
+    a = kc.compare(ctx, plist)
+    pset = kc.PairSet(ctx, plist)
+    b = kc.compare_pairset(ctx, pset)
+    b2 = kc.compare_pairset(ctx, pset)
+    torch.cuda.synchronize()
+    assert torch.equal(a[: 300 * 472], b[: 300 * 472]) and torch.equal(b, b2)
+    pset.close()
+    ctx.close()
+
+
+def test_graph_replay_matches_eager(kc):
+    say("graph: snapshot + restore + compare recorded once, replayed with eager work between")
+    ctx = kc.Context(0)
+    case = W.c1_snapshot("cuda", scale=1 / 4)
+    rs = kc.RangeSet(ctx, case.ranges())
+    N = rs.n_pages
+    dev = torch.device("cuda", 0)
+    out = dict(hash=torch.empty(N, dtype=torch.int64, device=dev),
+               zero_bm=torch.empty(rs.n_words, dtype=torch.int64, device=dev), changed_bm=None,
+               packed=torch.empty(N * PAGE, dtype=torch.uint8, device=dev),
+               page_va=torch.empty(N, dtype=torch.int64, device=dev),
+               n_kept=torch.empty(1, dtype=torch.int64, device=dev))
+    scan = kc.ScanOut(dev, oob_cap=16)
+    pairs = W.c1_compare("cuda", scale=1 / 16, n_pairs=4)
+    pset = kc.PairSet(ctx, [(p.cand, p.gold, W.DT_F32, 0) for p in pairs])
+    res = torch.empty(4 * 472, dtype=torch.uint8, device=dev)
+
+    def step():
+        kc.snapshot(ctx, rs, scan=scan, out=out)
+        kc.restore(ctx, rs, out["zero_bm"], None, out["packed"], out["page_va"], out["n_kept"])
+        kc.compare_pairset(ctx, pset, res=res)
+
+    step()
+    torch.cuda.synchronize()
+    ref = (out["hash"].clone(), out["zero_bm"].clone(), out["packed"].clone(), out["page_va"].clone(),
+           out["n_kept"].clone(), scan.res.clone(), scan.oob.clone(), res.clone())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(4):
+        for t in (out["hash"], out["zero_bm"], out["page_va"], out["n_kept"], scan.res, res):
+            t.fill_(-1 if t.dtype == torch.int64 else 0xEE)   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (out["hash"], out["zero_bm"], out["packed"], out["page_va"], out["n_kept"], scan.res, scan.oob, res)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), rep
+    pset.close()
+    rs.close()
+    ctx.close()
+
+
+def test_autotuner_candidates_are_bit_identical(kc, tmp_path, monkeypatch):
+    say("autotuner: every candidate of snapshot / compare gives the same outputs")
+    from paper_2605_03208_amd import autotune
+    monkeypatch.setenv("KC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ctx = kc.Context(0)
+    case = W.c1_snapshot("cuda", scale=1 / 4)
+    rs = kc.RangeSet(ctx, case.ranges())
+    scan = kc.ScanOut("cuda", oob_cap=16)
+    out = kc.snapshot(ctx, rs, scan=scan)
+    run = lambda: kc.snapshot(ctx, rs, scan=scan, out=out)
+    dig = lambda: autotune.digest_tensors(out["hash"][: rs.n_pages], out["zero_bm"][: rs.n_words], out["n_kept"],
+                                          out["packed"][: int(out["n_kept"].item()) * PAGE], scan.res, scan.oob)
+    r = autotune.tune(ctx, kc.OP_SNAPSHOT, run, dig, signature="test-c1")
+    assert not r["cached"] and len(r["table"]) == len(autotune.CANDIDATES[kc.OP_SNAPSHOT])
+    r2 = autotune.tune(ctx, kc.OP_SNAPSHOT, run, dig, signature="test-c1")
+    assert r2["cached"] and r2["best"] == r["best"]
+    ps = W.c3_pairs("cuda", scale=1 / 1024, n_pairs=200)
+    plist = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))]
+    res = torch.empty(200 * 472, dtype=torch.uint8, device="cuda")
+    state = {}
+
+    def prep(c):
+        state["ps"] = kc.PairSet(ctx, plist)
+
+    r = autotune.tune(ctx, kc.OP_COMPARE, lambda: kc.compare_pairset(ctx, state["ps"], res=res),
+                      lambda: autotune.digest_tensors(res), signature="test-c3", prepare=prep)
+    assert len(r["table"]) == len(autotune.CANDIDATES[kc.OP_COMPARE])
+    rs.close()
+    ctx.close()
+
+
+def test_serving_alone_equals_mix_and_oracle(kc):
+    say("serving: 40 requests in the mix vs each alone, and vs the oracle")
+    from paper_2605_03208_amd import serve
+    golds, dtypes = W.c5_pool("cuda", scale=1 / 64, n_buffers=24)
+    raw = W.c5_requests(rate_hz=2000.0, duration_s=0.02, n_buffers=24, max_k=6)
+    reqs = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in raw][:40]
+    ex = serve.DeviceExecutor(golds, dtypes, n_streams=3)
+    budget = int(np.sort([ex.request_bytes(r) for r in reqs])[-1] * 3)
+    srv = serve.Server(ex, budget, max_batch=5)
+    mix = {d.rid: d for d in srv.run(reqs)}
+    assert len(mix) == len(reqs) and srv.budget.peak <= budget
+    for r in reqs:
+        alone = serve.Server(ex, budget).run([serve.Request(r.rid, 0.0, r.golden_ids, r.ulp_tol, r.seed)])
+        assert alone[0].results == mix[r.rid].results, r.rid
+    for r in reqs[:6]:
+        for gid, got in zip(r.golden_ids, mix[r.rid].results):
+            gold = golds[int(gid)]
+            cand = gold.clone()
+            W.perturb_device(cand, int(dtypes[int(gid)]), r.seed * 1000003 + int(gid))
+            want = oracle.compare(cand.cpu().view(torch.uint8).numpy(), gold.cpu().view(torch.uint8).numpy(),
+                                  int(dtypes[int(gid)]), r.ulp_tol)
+            assert got == want
