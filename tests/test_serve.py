@@ -19,7 +19,7 @@ def _reqs(n, rate, sizes_n, seed=0, max_k=8):
 
 def test_budget_never_exceeded_and_fifo():
     rng = np.random.default_rng(1)
-    sizes = rng.integers(1 << 20, 64 << 20, size=64)
+    sizes = rng.integers(1 << 20, 16 << 20, size=64)
     reqs = _reqs(300, 2000.0, len(sizes))
     ex = serve.MockExecutor(sizes, n_streams=3, rate_Bps=2e11)
     budget = 256 << 20
