@@ -135,25 +135,43 @@ class DeviceExecutor:
                 return i
         return None
 
+    def candidate_seed(self, req: Request, gid: int) -> int:
+        return (int(req.seed) * 1000003 + int(gid)) & 0x7FFFFFFF
+
     def launch(self, stream: int, reqs, now: float):
+        """Materialise the batch's candidates (per element type: one copy of
+        the goldens into a fresh arena, one vectorised perturbation) and run
+        all its pairs in one kc_compare launch."""
         torch, kc, W = self.torch, self.kc, self.W
         s = self.streams[stream]
+        entries = [(r, int(gid)) for r in reqs for gid in r.golden_ids]
         with torch.cuda.stream(s):
-            cands, pairs, owners = [], [], []
-            for r in reqs:
-                for gid in r.golden_ids:
-                    gold = self.goldens[int(gid)]
-                    cand = torch.empty_like(gold)
-                    cand.copy_(gold)
-                    W.perturb_device(cand, self.dtypes[int(gid)], r.seed * 1000003 + int(gid), self.p_pert,
-                                     self.kmax)
-                    cands.append(cand)
-                    pairs.append((cand, gold, self.dtypes[int(gid)], r.ulp_tol))
-                    owners.append(r.rid)
+            views = [None] * len(entries)
+            arenas = []
+            for dt in sorted({self.dtypes[g] for _, g in entries}):
+                idx = [i for i, (_, g) in enumerate(entries) if self.dtypes[g] == dt]
+                golds = [self.goldens[entries[i][1]] for i in idx]
+                lens = [g.numel() for g in golds]
+                align = max(1, 16 // golds[0].element_size())   # keep every candidate 16-byte aligned
+                padded = [-(-n // align) * align for n in lens]
+                offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
+                arena = torch.empty(int(sum(padded)), dtype=golds[0].dtype, device=s.device)
+                if padded == lens:
+                    torch.cat(golds, out=arena)
+                else:
+                    for g, o, n in zip(golds, offs, lens):
+                        arena[int(o): int(o) + n].copy_(g)
+                W.perturb_many(arena, dt, offs, lens, [self.candidate_seed(*entries[i]) for i in idx],
+                               self.p_pert, self.kmax)
+                arenas.append(arena)
+                for i, o, n in zip(idx, offs, lens):
+                    views[i] = arena[int(o): int(o) + n]
+            pairs = [(views[i], self.goldens[g], self.dtypes[g], r.ulp_tol) for i, (r, g) in enumerate(entries)]
             res = kc.compare(self.ctxs[stream], pairs)
             ev = torch.cuda.Event()
             ev.record(s)
-        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, cands=cands, n=len(pairs), owners=owners)
+        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, arenas=arenas, n=len(pairs),
+                 owners=[r.rid for r, _ in entries])
         self.busy[stream] = h
         return h
 

@@ -579,33 +579,62 @@ def _fp8_tables_on(device):
     return _FP8_DEV[key]
 
 
-def perturb_device(cand: torch.Tensor, dtype: int, seed: int, p_pert: float = 1e-4, kmax: int = 16) -> None:
-    """In place, on the tensor's device, without host synchronisation: one
-    element in each block of round(1/p_pert) elements (a seeded position) is
-    moved by a seeded 1..kmax ULP in a seeded direction."""
-    n = cand.numel()
-    if n == 0:
-        return
+def _hash32(x: torch.Tensor) -> torch.Tensor:
+    """A 32-bit integer mix on int64 tensors (values stay below 2^59, so no
+    overflow on any device)."""
+    m = 0xFFFFFFFF
+    x = x & m
+    for _ in range(2):
+        x = ((x >> 16) ^ x) * 0x45D9F3B & m
+    return ((x >> 16) ^ x) & m
+
+
+def perturb_many(arena: torch.Tensor, dtype: int, offsets, lengths, seeds, p_pert: float = 1e-4,
+                 kmax: int = 16) -> None:
+    """In place, on the arena's device, without host synchronisation.
+
+    ``arena`` is a 1-D typed tensor holding several candidate buffers at
+    element ``offsets`` with element ``lengths``.  In buffer b, element
+    j * B + (h mod B) of each block j of B = round(1/p_pert) elements moves by
+    1..kmax ULP in a direction, where h and the step come from a hash of
+    (seeds[b], j): a buffer's perturbation depends only on its own seed."""
     block = max(1, int(round(1.0 / p_pert)))
-    m = n // block
-    if m == 0:
+    offsets = np.asarray(offsets, dtype=np.int64)
+    lengths = np.asarray(lengths, dtype=np.int64)
+    seeds = np.asarray(seeds, dtype=np.int64) & 0x7FFFFFFF
+    m = lengths // block
+    total = int(m.sum())
+    if total == 0:
         return
-    dev = cand.device
-    gen = torch.Generator(device=dev).manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
-    pos = torch.arange(m, device=dev, dtype=torch.int64) * block + torch.randint(0, block, (m,), device=dev,
-                                                                                 generator=gen)
-    k = torch.randint(1, kmax + 1, (m,), device=dev, generator=gen)
-    k = torch.where(torch.randint(0, 2, (m,), device=dev, generator=gen) == 0, -k, k)
-    vals = cand[pos]
+    starts = np.concatenate([[0], np.cumsum(m)[:-1]])
+    j = np.arange(total, dtype=np.int64) - np.repeat(starts, m)
+    base = np.repeat(offsets, m)
+    sd = np.repeat(seeds, m)
+    dev = arena.device
+    host = torch.from_numpy(np.stack([j, sd, base]))
+    if dev.type == "cuda":
+        host = host.pin_memory()
+    j_t, sd_t, base_t = host.to(dev, non_blocking=True)
+    h1 = _hash32(sd_t * 0x9E37 + j_t * 0x85EB + 1)
+    h2 = _hash32(h1 + sd_t + 0x27D4EB2F)
+    pos = base_t + j_t * block + (h1 % block)
+    k = 1 + (h2 % kmax)
+    k = torch.where(((h2 >> 20) & 1) == 1, -k, k)
+    vals = arena[pos]
     if dtype == DT_FP8:
         code_of_rank, rank_of_code = _fp8_tables_on(dev)
         r = (rank_of_code[vals.view(torch.uint8).to(torch.int64)] + k).clamp(0, len(code_of_rank) - 1)
-        cand[pos] = code_of_rank[r].view(torch.float8_e4m3fn)
+        arena[pos] = code_of_rank[r].view(torch.float8_e4m3fn)
         return
     target = torch.where(k > 0, torch.full_like(vals, float("inf")), torch.full_like(vals, float("-inf")))
     for i in range(kmax):
         vals = torch.where(k.abs() > i, torch.nextafter(vals, target), vals)
-    cand[pos] = vals
+    arena[pos] = vals
+
+
+def perturb_device(cand: torch.Tensor, dtype: int, seed: int, p_pert: float = 1e-4, kmax: int = 16) -> None:
+    """``perturb_many`` on a single buffer."""
+    perturb_many(cand.view(-1), dtype, [0], [cand.numel()], [seed], p_pert, kmax)
 
 
 def materialize_candidate(gold: torch.Tensor, dtype: int, seed: int, p_pert: float = 1e-4,

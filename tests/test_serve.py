@@ -38,12 +38,12 @@ def test_overload_queues_but_completes():
     sizes = np.full(16, 32 << 20)
     reqs = _reqs(200, 1e6, len(sizes), seed=3)    # everything arrives at once
     ex = serve.MockExecutor(sizes, n_streams=2, rate_Bps=1e11)
-    srv = serve.Server(ex, 128 << 20)
+    srv = serve.Server(ex, 300 << 20)
     done = srv.run(reqs, real_time=False)
     assert len(done) == 200
     q = [d.admit_s - d.arrival_s for d in done]
     assert max(q) > 0                                  # the budget binds
-    assert srv.budget.peak <= 128 << 20
+    assert srv.budget.peak <= 300 << 20
 
 
 def test_batches_span_requests_admitted_together():
