@@ -1,0 +1,68 @@
+"""The pins have teeth: each plausible mistake planted in a copy of the
+oracle (a wrong constant, rotation or index, a dropped or flipped condition,
+an off-by-one) makes at least one oracle pin test fail.  Runs on the CPU only;
+the real oracle is untouched."""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PIN_TESTS = ["tests/test_oracle_xxh64.py", "tests/test_oracle_snapshot.py", "tests/test_oracle_compare.py",
+             "tests/test_golden.py"]
+
+MUTANTS = {
+    "round uses P1": ("acc = acc + lane * PRIME2;", "acc = acc + lane * PRIME1;"),
+    "round rotation 33": ("acc = rotate_left(acc, 31);", "acc = rotate_left(acc, 33);"),
+    "merge rotation": ("rotate_left(v2, 7)", "rotate_left(v2, 8)"),
+    "tail lane constant": ("acc = rotate_left(acc, 27) * PRIME1 + PRIME4;", "acc = rotate_left(acc, 27) * PRIME1 + PRIME3;"),
+    "avalanche shift": ("acc ^= acc >> 29;", "acc ^= acc >> 28;"),
+    "zero test skips last byte": ("for (uint32_t i = 0; i < PAGE; ++i)", "for (uint32_t i = 0; i + 1 < PAGE; ++i)"),
+    "changed inverted": ("if (prior && hash[g] != prior[g])", "if (prior && hash[g] == prior[g])"),
+    "page VA off by one page": ("page_va[slot] = ranges[a].base + p * PAGE;", "page_va[slot] = ranges[a].base + (p + 1) * PAGE;"),
+    "delta keep uses or": ("if (changed_bm != NULL) keep = keep && bit_get(changed_bm, g);",
+                           "if (changed_bm != NULL) keep = keep || bit_get(changed_bm, g);"),
+    "window upper edge inclusive": ("if (w < win_lo || w >= win_hi) continue;", "if (w < win_lo || w > win_hi) continue;"),
+    "range end inclusive": ("if (va - ranges[lo].base < ranges[lo].size) return (int64_t)lo;",
+                            "if (va - ranges[lo].base <= ranges[lo].size) return (int64_t)lo;"),
+    "adjacent ranges rejected": ("if (base < prev_end) return KCO_EORDER;", "if (base <= prev_end) return KCO_EORDER;"),
+    "window margin 2 GiB": ("const uint64_t margin = 1ULL << 32;", "const uint64_t margin = 1ULL << 31;"),
+    "ulp ignores cand sign": ("if (cand_bits & sign) oc = -oc;", ""),
+    "log bins shifted": ("return 12u + k;", "return 11u + k;"),
+    "rel includes zero golds": ("if (vg != 0.0 && !isinf(vg)) {", "if (!isinf(vg)) {"),
+    "last mismatch kept": ("if (res->first_mismatch == UINT64_MAX) res->first_mismatch = i;", "res->first_mismatch = i;"),
+    "byte count per element": ("if (pc[b] != pg[b]) res->n_mismatch_bytes += 1;", "res->n_mismatch_bytes += 1;"),
+    "NaN payloads split both-NaN": ("if (nan_c && nan_g) {", "if (nan_c && nan_g && c == g) {"),
+    "fp16 exponent bias": ("v = ldexp((double)(m | 0x400u), (int)e - 25);", "v = ldexp((double)(m | 0x400u), (int)e - 24);"),
+    "fp8 subnormal scale": ("v = ldexp((double)m, -9);", "v = ldexp((double)m, -10);"),
+    "tolerance inclusive": ("if (d > ulp_tol) res->n_over_tol += 1;", "if (d >= ulp_tol) res->n_over_tol += 1;"),
+}
+
+
+def _run_mutant(name, tmp):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "kco.c")).read()
+    assert src.count(old) == 1, f"mutant {name!r}: pattern not unique"
+    d = os.path.join(tmp, "m%d" % list(MUTANTS).index(name))
+    os.makedirs(d, exist_ok=True)
+    shutil.copy(os.path.join(ROOT, "oracle", "kco.h"), d)
+    with open(os.path.join(d, "kco.c"), "w") as f:
+        f.write(src.replace(old, new))
+    lib = os.path.join(d, "libkco.so")
+    subprocess.run(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", lib,
+                    os.path.join(d, "kco.c"), "-lm"], check=True, capture_output=True)
+    env = dict(os.environ, KCO_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        *PIN_TESTS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode
+
+
+def test_every_mutant_is_caught(tmp_path, oracle_lib):
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        codes = dict(zip(MUTANTS, ex.map(lambda n: _run_mutant(n, str(tmp_path)), MUTANTS)))
+    survived = [n for n, c in codes.items() if c == 0]
+    assert not survived, f"mutants not caught by any pin: {survived}"
+    assert all(c == 1 for c in codes.values()), codes   # failures, not crashes or collection errors

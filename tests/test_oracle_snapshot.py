@@ -195,7 +195,8 @@ def test_closure_scan_brute_force_tiny(oracle_lib):
     host = np.zeros(4 * PAGE, dtype=np.uint8)
     words = host.view("<u8")
     probes = [0x100000, 0x100FFF, 0x101000, 0x102FF8, 0x103000, 0x104FFF, 0x105000,
-              0x1FFFFF, 0x200000, 0x200FFF, 0x201000, 0x50, 0xFFFFFFFF00000000, 0x103001]
+              0x1FFFFF, 0x200000, 0x200FFF, 0x201000, 0x50, 0xFFFFFFFF00000000, 0x103001,
+              0x1000, 0xFFF, 0x300000, 0x2FFFFF]   # window edges: lo, lo - 1, hi, hi - 1
     for i, v in enumerate(probes):
         words[i * 37 % len(words)] = v
     views = [host[:PAGE], host[PAGE:3 * PAGE], host[3 * PAGE:]]
@@ -225,3 +226,17 @@ def test_empty_rangeset(oracle_lib):
     assert n == 0
     res, oob = oracle_lib.closure_scan([], [])
     assert res["n_words"] == 0 and oob == []
+
+
+def test_zero_flag_single_nonzero_byte_anywhere(oracle_lib):
+    """A page is zero only if every one of its 4096 bytes is zero: one set
+    byte at the first, last or any interior offset clears the flag."""
+    offsets = [0, 1, 7, 8, 63, 64, 2047, 2048, 4088, 4095]
+    host = np.zeros((len(offsets) + 2) * PAGE, dtype=np.uint8)
+    for i, off in enumerate(offsets):
+        host[(i + 1) * PAGE + off] = 0x80 if i % 2 else 1
+    rngs = [(0x200000, len(host))]
+    h, z, _ = oracle_lib.page_hash(rngs, [host])
+    pages = host.reshape(-1, PAGE)
+    assert np.array_equal(z, bits_to_words(~pages.any(axis=1)))
+    assert [int(x) for x in h] == [xxhash.xxh64_intdigest(p.tobytes(), 0) for p in pages]
