@@ -392,6 +392,28 @@ __global__ __launch_bounds__(256) void k_scan_down(ScanSrc src, const uint64_t* 
   }
 }
 
+// Whole scan in one block when the items fit in it (small inputs: one launch
+// instead of three).
+__global__ __launch_bounds__(256) void k_scan_small(ScanSrc src, uint64_t* out, uint64_t* total_out) {
+  __shared__ uint64_t lds4[4];
+  const uint64_t i0 = (uint64_t)threadIdx.x * kScanPerThread;
+  uint32_t v[kScanPerThread];
+  uint64_t s = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPerThread; ++i) {
+    v[i] = scan_item(src, i0 + i);
+    s += v[i];
+  }
+  uint64_t tot = 0;
+  uint64_t run = block_exclusive(s, lds4, &tot);
+#pragma unroll
+  for (uint32_t i = 0; i < kScanPerThread; ++i) {
+    if (i0 + i < src.n_items) out[i0 + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = tot;
+}
+
 // ------------------------------------------------------ slots of a tile ---
 // Lane i < np: keep bit and packed slot of page i of the tile.
 __device__ __forceinline__ void tile_slots(const Tile& tile, const uint64_t* zero_bm,
@@ -649,6 +671,10 @@ hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero
 hipError_t launch_scan(const ScanSrc& src, uint64_t* out, uint64_t* block_sums, uint64_t* total_out,
                        hipStream_t s) {
   const uint32_t nb = blocks_for(src.n_items, kScanBlock);
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanThreads), 0, s, src, out, total_out);
+    return hipGetLastError();
+  }
   if (nb > 0) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, src, block_sums);
     hipError_t e = hipGetLastError();
