@@ -156,7 +156,7 @@ int finish_scan(kc_rangeset* rs, const kc_scan_args* sa, const ScanDev& sd, hipS
   src.counts = rs->tile_oob;
   src.n_items = rs->n_tiles;
   KC_HIP(launch_scan(src, rs->tile_prefix, rs->block_sums, rs->n_oob, s));
-  KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, sa->oob_d, sa->oob_cap,
+  KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, rs->n_oob, sa->oob_d, sa->oob_cap,
                          grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
   KC_HIP(launch_scan_finalize(sa->res_d, rs->counts, rs->n_oob, rs->n_pages * (KC_PAGE_SIZE / 8),
                               sa->oob_cap, s));

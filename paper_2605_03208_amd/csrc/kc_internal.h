@@ -123,8 +123,8 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
                           const ScanDev& sd, uint32_t grid, hipStream_t s);
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
-                           const uint64_t* tile_prefix, kc_oob* oob, uint64_t cap,
-                           uint32_t grid, hipStream_t s);
+                           const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
+                           uint64_t cap, uint32_t grid, hipStream_t s);
 hipError_t launch_scan_finalize(kc_scan_result* res, const unsigned long long* counts,
                                 const uint64_t* n_oob, uint64_t n_words, uint64_t cap,
                                 hipStream_t s);

@@ -259,28 +259,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // ------------------------------------------------------------ zero probe --
-// Exact zero bitmap for a tile: each quad reads the first 64 bytes of its
-// page; a page whose first 64 bytes are all zero is read in full.
+// Exact zero bitmap.  A wave takes four tiles at a time, one lane per page:
+// each lane reads the first 16 bytes of its page; a page whose first 16 bytes
+// are zero is then read in full by the whole wave (four such pages at a time).
 __global__ __launch_bounds__(64) void k_probe_zero(const Tile* tiles, uint32_t n_tiles,
                                                    uint64_t* zero_bm) {
-  const uint32_t lane = threadIdx.x, q = lane >> 2, k = lane & 3u;
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const Tile tile = tiles[t];
-    const uint32_t np = tile.npages;
-    const uint4 v = (q < np) ? ld16(tile.va + (uint64_t)q * kPage + k * 16u) : make_uint4(0, 0, 0, 0);
-    const uint64_t b = __ballot(nz16(v));
-    uint32_t maybe = 0;
-    for (uint32_t i = 0; i < np; ++i)
-      if (((b >> (4u * i)) & 0xFull) == 0ull) maybe |= 1u << i;
-    uint32_t zero = 0;
+  const uint32_t lane = threadIdx.x, sub = lane >> 4, pl = lane & 15u;
+  for (uint32_t t0 = blockIdx.x * 4u; t0 < n_tiles; t0 += gridDim.x * 4u) {
+    const uint32_t t = t0 + sub;
+    Tile tile{0, 0, 0};
+    if (t < n_tiles) tile = tiles[t];
+    const bool valid = pl < tile.npages;
+    const uint64_t page_va = tile.va + (uint64_t)pl * kPage;
+    const uint4 v = valid ? ld16(page_va) : make_uint4(0, 0, 0, 0);
+    uint64_t maybe = __ballot(valid && !nz16(v));
+    uint64_t zero = 0;
     while (maybe) {
-      uint32_t pg[4];
+      uint32_t ln[4];
+      uint64_t pva[4];
       uint32_t cnt = 0;
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i) {
-        pg[i] = maybe ? (uint32_t)__builtin_ctz(maybe) : 0u;
+        ln[i] = maybe ? (uint32_t)__builtin_ctzll(maybe) : 0u;
+        pva[i] = __shfl(page_va, ln[i], 64);
         if (maybe) {
-          maybe &= maybe - 1u;
+          maybe &= maybe - 1ull;
           ++cnt;
         }
       }
@@ -289,15 +292,14 @@ __global__ __launch_bounds__(64) void k_probe_zero(const Tile* tiles, uint32_t n
       for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j)
-          x[i * 4 + j] = (i < cnt) ? ld16(tile.va + (uint64_t)pg[i] * kPage + j * 1024u + lane * 16u)
-                                   : make_uint4(0, 0, 0, 0);
+          x[i * 4 + j] = (i < cnt) ? ld16nt(pva[i] + j * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i) {
         const bool nzl = nz16(x[i * 4]) || nz16(x[i * 4 + 1]) || nz16(x[i * 4 + 2]) || nz16(x[i * 4 + 3]);
-        if (i < cnt && __ballot(nzl) == 0ull) zero |= 1u << pg[i];
+        if (i < cnt && __ballot(nzl) == 0ull) zero |= 1ull << ln[i];
       }
     }
-    if (lane == 0) or_page_bits(zero_bm, tile.g, np, zero);
+    if (pl == 0 && t < n_tiles) or_page_bits(zero_bm, tile.g, tile.npages, (uint32_t)((zero >> (16u * sub)) & 0xFFFFull));
   }
 }
 
@@ -580,9 +582,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // Writes the out-of-range words of each tile at its prefix position, in
 // ascending address order, up to the list capacity.
 __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_tiles, ScanDev sd,
-                                                 const uint64_t* tile_prefix, kc_oob* oob, uint64_t cap) {
+                                                 const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
+                                                 uint64_t cap) {
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
+  if (*n_oob == 0) return;  // nothing out of range: no tile to revisit
   load_fences(fences, sd.rt, lane, kWave);
   __syncthreads();
   const uint64_t below = (1ull << lane) - 1ull;
@@ -726,10 +730,10 @@ hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, c
 }
 
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd, const uint64_t* tile_prefix,
-                           kc_oob* oob, uint64_t cap, uint32_t grid, hipStream_t s) {
+                           const uint64_t* n_oob, kc_oob* oob, uint64_t cap, uint32_t grid, hipStream_t s) {
   if (n_tiles == 0 || cap == 0) return hipSuccess;
   grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_oob_emit, dim3(grid), dim3(64), 0, s, tiles, n_tiles, sd, tile_prefix, oob, cap);
+  hipLaunchKernelGGL(k_oob_emit, dim3(grid), dim3(64), 0, s, tiles, n_tiles, sd, tile_prefix, n_oob, oob, cap);
   return hipGetLastError();
 }
 
