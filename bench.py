@@ -173,7 +173,7 @@ def main() -> int:
         o, s = int(case.layout.offsets[i]), int(case.layout.sizes[i])
         pair_list.append((case.arena.buf[o:o + s], golden[o:o + s], kinds[i] if i < len(kinds) else W.DT_U8, 0))
     cmp_bytes = sum(int(s) for _, s in ranges)
-    res = torch.empty(len(pair_list) * 472, dtype=torch.uint8, device=dev)
+    res = torch.empty(len(pair_list) * kc.RESULT_BYTES, dtype=torch.uint8, device=dev)
     state = {"ps": kc.PairSet(ctx, pair_list)}
 
     def snap():
@@ -349,7 +349,7 @@ def c1_latency(torch, kc, W, dev) -> dict:
     scan = kc.ScanOut(dev, oob_cap=16)
     pairs = W.c1_compare("cuda")
     ps = kc.PairSet(ctx, [(p.cand, p.gold, W.DT_F32, 0) for p in pairs])
-    res = torch.empty(len(pairs) * 472, dtype=torch.uint8, device=dev)
+    res = torch.empty(len(pairs) * kc.RESULT_BYTES, dtype=torch.uint8, device=dev)
 
     def step():
         kc.snapshot(ctx, rs, scan=scan, out=out)
@@ -406,10 +406,10 @@ def batching(torch, kc, W, dev) -> dict:
     out = {}
     log("batching: c3 compare, 10,000 pairs / 8 GiB per side")
     ps = W.c3_pairs("cuda", n_pairs=10000)
-    plist = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))]
+    plist = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i]), 1e-8, 1e-5) for i in range(len(ps))]
     arr = kc.make_pairs(plist)
     nbytes = 2 * int(ps.nbytes.sum())
-    res = torch.empty(len(ps) * 472, dtype=torch.uint8, device=dev)
+    res = torch.empty(len(ps) * kc.RESULT_BYTES, dtype=torch.uint8, device=dev)
     results = {}
     for mode in ("batched", "per_buffer"):
         c2 = kc.Context(0)

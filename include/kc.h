@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define KC_PAGE_SIZE 4096u
-#define KC_ABI_VERSION 1
+#define KC_ABI_VERSION 2
 
 /* Status codes. */
 enum {
@@ -119,10 +119,12 @@ typedef struct {
   const void *gold_d;
   uint64_t n_elems;
   uint32_t dtype;
-  uint32_t ulp_tol; /* an element fails if its ULP distance exceeds this */
+  uint32_t ulp_tol; /* an element fails if its ULP distance exceeds this   */
+  double atol;      /* tolerance comparison (Sec. 4.5.2): an element is     */
+  double rtol;      /* close iff |c - g| <= atol + rtol * |g| in fp64       */
 } kc_pair;
 
-/* Per-pair compare report (472 bytes). */
+/* Per-pair compare report (488 bytes). */
 typedef struct {
   uint64_t n_elems;
   uint64_t n_mismatch_elems; /* elements whose encodings differ            */
@@ -138,6 +140,11 @@ typedef struct {
   uint32_t pass;             /* no over-tolerance element and no lone NaN;
                                 KC_U8: no differing byte                   */
   uint32_t status;           /* 0                                          */
+  uint64_t n_not_close;      /* non-NaN elements failing the atol / rtol test
+                                (an infinity is close only to itself)      */
+  uint32_t pass_close;       /* no element failing it and no lone NaN;
+                                KC_U8: no differing byte                   */
+  uint32_t reserved;
 } kc_cmp_result;
 
 /* Launch shape of one operation.  Zero fields keep the built-in choice. */

@@ -58,7 +58,8 @@ class CmpResult(ctypes.Structure):
                 ("n_nan_gold_only", ctypes.c_uint64), ("n_over_tol", ctypes.c_uint64),
                 ("max_abs", ctypes.c_double), ("max_rel", ctypes.c_double),
                 ("ulp_hist", ctypes.c_uint64 * 48),
-                ("pass_", ctypes.c_uint32), ("status", ctypes.c_uint32)]
+                ("pass_", ctypes.c_uint32), ("status", ctypes.c_uint32),
+                ("n_not_close", ctypes.c_uint64), ("pass_close", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -81,7 +82,7 @@ def lib() -> ctypes.CDLL:
         L.kco_compact.argtypes = [P(Range), P(vp), u32, vp, vp, vp, vp, u64, P(u64)]
         L.kco_restore.argtypes = [P(Range), P(vp), u32, vp, vp, vp, vp, u64, u64, P(u64)]
         L.kco_closure_scan.argtypes = [P(Range), P(vp), u32, u64, u64, P(ScanResult), P(Oob), u64]
-        L.kco_compare.argtypes = [vp, vp, u64, u32, u32, P(CmpResult)]
+        L.kco_compare.argtypes = [vp, vp, u64, u32, u32, ctypes.c_double, ctypes.c_double, P(CmpResult)]
         L.kco_ulp.argtypes = [u32, u32, u32, P(u64)]
         L.kco_ulp_bin.argtypes = [u64]
         L.kco_ulp_bin.restype = u32
@@ -212,18 +213,18 @@ def closure_scan(ranges, views, win_lo: int = 0, win_hi: int = 0, oob_cap: int =
     return d, [(int(oob[i].word_va), int(oob[i].value)) for i in range(d["n_written"])]
 
 
-def compare(cand, gold, dtype: int, ulp_tol: int = 0):
+def compare(cand, gold, dtype: int, ulp_tol: int = 0, atol: float = 0.0, rtol: float = 0.0):
     """cand / gold: numpy arrays (any dtype) holding n elements of ``dtype``."""
     es = {F32: 4, BF16: 2, F16: 2, FP8_E4M3FN: 1, U8: 1}.get(dtype)
     if es is None:
         res = CmpResult()
-        _check(lib().kco_compare(None, None, 0, dtype, ulp_tol, ctypes.byref(res)), "compare")
+        _check(lib().kco_compare(None, None, 0, dtype, ulp_tol, atol, rtol, ctypes.byref(res)), "compare")
     c = np.ascontiguousarray(cand).view(np.uint8)
     g = np.ascontiguousarray(gold).view(np.uint8)
     assert c.nbytes == g.nbytes and c.nbytes % es == 0
     res = CmpResult()
     _check(lib().kco_compare(_ptr(c) if c.size else None, _ptr(g) if g.size else None,
-                             c.nbytes // es, dtype, ulp_tol, ctypes.byref(res)), "compare")
+                             c.nbytes // es, dtype, ulp_tol, atol, rtol, ctypes.byref(res)), "compare")
     return cmp_to_dict(res)
 
 
@@ -235,6 +236,8 @@ def cmp_to_dict(res: CmpResult) -> dict:
             d[k] = [int(x) for x in v]
         elif k == "pass_":
             d["pass"] = int(v)
+        elif k == "reserved":
+            continue
         else:
             d[k] = float(v) if k.startswith("max_") else int(v)
     return d

@@ -404,10 +404,12 @@ uint32_t kco_ulp_bin(uint64_t dist) {
 }
 
 int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
-                uint32_t dtype, uint32_t ulp_tol, kco_cmp_result *res) {
+                uint32_t dtype, uint32_t ulp_tol, double atol, double rtol,
+                kco_cmp_result *res) {
   if (res == NULL) return KCO_EINVAL;
   uint32_t es = elem_size(dtype);
   if (es == 0) return KCO_EDTYPE;
+  if (!(atol >= 0.0) || !(rtol >= 0.0)) return KCO_EINVAL;
   if (n_elems > 0 && (cand == NULL || gold == NULL)) return KCO_EINVAL;
   memset(res, 0, sizeof(*res));
   res->n_elems = n_elems;
@@ -448,12 +450,22 @@ int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
       double rel = abs_err / fabs(vg);
       if (rel > res->max_rel) res->max_rel = rel;
     }
+    int close;
+    if (isinf(vc) || isinf(vg))
+      close = vc == vg;
+    else
+      close = abs_err <= atol + rtol * fabs(vg);
+    if (!close) res->n_not_close += 1;
   }
-  if (dtype == KCO_U8)
+  if (dtype == KCO_U8) {
     res->pass = res->n_mismatch_elems == 0;
-  else
+    res->pass_close = res->pass;
+  } else {
     res->pass = res->n_over_tol == 0 && res->n_nan_cand_only == 0 &&
                 res->n_nan_gold_only == 0;
+    res->pass_close = res->n_not_close == 0 && res->n_nan_cand_only == 0 &&
+                      res->n_nan_gold_only == 0;
+  }
   res->status = 0;
   return KCO_OK;
 }

@@ -75,6 +75,8 @@ typedef struct {
   double max_abs, max_rel;
   uint64_t ulp_hist[48];
   uint32_t pass, status;
+  uint64_t n_not_close;
+  uint32_t pass_close, reserved;
 } kco_cmp_result;
 
 /* XXH64 of len bytes at data with the given seed (public xxHash definition). */
@@ -116,9 +118,13 @@ int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
                      uint32_t n, uint64_t win_lo, uint64_t win_hi,
                      kco_scan_result *res, kco_oob *oob, uint64_t oob_cap);
 
-/* Typed compare of one candidate / golden pair of n_elems elements. */
+/* Typed compare of one candidate / golden pair of n_elems elements.  Besides
+ * the ULP report, an element pair (neither NaN) is close iff
+ * |c - g| <= atol + rtol * |g| in fp64, an infinity being close only to an
+ * equal value (tolerance comparison with atol / rtol, paper Sec. 4.5.2). */
 int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
-                uint32_t dtype, uint32_t ulp_tol, kco_cmp_result *res);
+                uint32_t dtype, uint32_t ulp_tol, double atol, double rtol,
+                kco_cmp_result *res);
 
 /* ULP distance and histogram bin of one element pair (exposed for tests). */
 int kco_ulp(uint32_t dtype, uint32_t cand_bits, uint32_t gold_bits,

@@ -562,6 +562,7 @@ int plan_pairs(const kc_pair* pairs, uint32_t n_pairs, uint32_t tile_bytes, std:
     const kc_pair& pr = pairs[i];
     if (pr.dtype > KC_U8) return KC_EDTYPE;
     if (pr.n_elems > (1ull << 60)) return KC_ELIMIT;
+    if (!(pr.atol >= 0.0) || !(pr.rtol >= 0.0)) return KC_EINVAL;  // negative or NaN tolerances
     if (pr.n_elems > 0) {
       if (pr.cand_d == nullptr || pr.gold_d == nullptr) return KC_EINVAL;
       if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & 15u) return KC_EALIGN;
@@ -587,6 +588,8 @@ void fill_pair_tables(const kc_pair* pairs, uint32_t n_pairs, const std::vector<
     d.tol = pr.ulp_tol;
     d.n_tiles = (uint32_t)(tile_off[i + 1] - tile_off[i]);
     d.esize = elem_size(pr.dtype);
+    d.atol = pr.atol;
+    d.rtol = pr.rtol;
     hp[i] = d;
     for (uint64_t t = tile_off[i]; t < tile_off[i + 1]; ++t) {
       ht[t].pair = i;

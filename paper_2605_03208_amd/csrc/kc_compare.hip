@@ -78,9 +78,14 @@ template <> __device__ __forceinline__ bool word_has_nan<KC_FP8_E4M3FN>(uint32_t
 template <> __device__ __forceinline__ bool word_has_nan<KC_U8>(uint32_t) { return false; }
 
 struct Partial {
-  uint32_t mis_elems, mis_bytes, nan_both, nan_c, nan_g, over;
+  uint32_t mis_elems, mis_bytes, nan_both, nan_c, nan_g, over, not_close;
   double max_abs, max_rel;
   uint64_t first;
+};
+
+struct Tol {
+  uint32_t ulp;
+  double atol, rtol;
 };
 
 __device__ __forceinline__ uint32_t ulp_bin(uint64_t d) {
@@ -96,7 +101,7 @@ __device__ __forceinline__ uint32_t diff_bytes(uint32_t a, uint32_t b) {
 
 // Exact per-element path.
 template <uint32_t DT>
-__device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, uint32_t tol, Partial& p,
+__device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, const Tol& tol, Partial& p,
                                         uint32_t* hist) {
   using F = Fmt<DT>;
   if (c != g) {
@@ -115,7 +120,7 @@ __device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, ui
   const int64_t oc = (c & F::sign) ? -(int64_t)(c & F::mag) : (int64_t)(c & F::mag);
   const int64_t og = (g & F::sign) ? -(int64_t)(g & F::mag) : (int64_t)(g & F::mag);
   const uint64_t d = (uint64_t)(oc > og ? oc - og : og - oc);
-  if (d > tol) ++p.over;
+  if (d > tol.ulp) ++p.over;
   if (d != 0u) atomicAdd(&hist[ulp_bin(d)], 1u);
   if (c == g) return;
   const double vc = F::value(c), vg = F::value(g);
@@ -124,6 +129,13 @@ __device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, ui
   if (vg != 0.0 && !F::inf(g)) {
     const double r = a / __builtin_fabs(vg);
     if (r > p.max_rel) p.max_rel = r;
+  }
+  // tolerance test: an infinity is close only to an equal value
+  if (F::inf(c) || F::inf(g)) {
+    if (vc != vg) ++p.not_close;
+  } else {
+    const double bound = tol.atol + tol.rtol * __builtin_fabs(vg);
+    if (a > bound) ++p.not_close;
   }
 }
 
@@ -137,7 +149,7 @@ __device__ __forceinline__ uint32_t elem_of(const uint4& v, uint32_t e) {
 }
 
 template <uint32_t DT>
-__device__ __forceinline__ void vec16(const uint4& c, const uint4& g, uint64_t e0, uint32_t tol, Partial& p,
+__device__ __forceinline__ void vec16(const uint4& c, const uint4& g, uint64_t e0, const Tol& tol, Partial& p,
                                       uint32_t* hist) {
   const bool eq = c.x == g.x && c.y == g.y && c.z == g.z && c.w == g.w;
   if (eq && !(word_has_nan<DT>(g.x) || word_has_nan<DT>(g.y) || word_has_nan<DT>(g.z) || word_has_nan<DT>(g.w)))
@@ -152,6 +164,7 @@ __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uin
   constexpr uint32_t es = Fmt<DT>::size;
   const uint64_t nvec = (b1 - b0) / 16u;
   const uint32_t tid = threadIdx.x;
+  const Tol tol{pr.tol, pr.atol, pr.rtol};
   for (uint64_t v0 = tid; v0 < nvec; v0 += (uint64_t)kThreads * kUnroll) {
     uint4 c[kUnroll], g[kUnroll];
 #pragma unroll
@@ -165,7 +178,7 @@ __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uin
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) {
       const uint64_t v = v0 + (uint64_t)u * kThreads;
-      if (v < nvec) vec16<DT>(c[u], g[u], (b0 + v * 16u) / es, pr.tol, p, hist);
+      if (v < nvec) vec16<DT>(c[u], g[u], (b0 + v * 16u) / es, tol, p, hist);
     }
   }
   // bytes past the last whole 16-byte run: element by element
@@ -176,7 +189,7 @@ __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uin
         cv |= (uint32_t)pr.cand[b + i] << (8u * i);
         gv |= (uint32_t)pr.gold[b + i] << (8u * i);
       }
-      element<DT>(cv, gv, b / es, pr.tol, p, hist);
+      element<DT>(cv, gv, b / es, tol, p, hist);
     }
   }
 }
@@ -203,14 +216,14 @@ __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const 
                                                  uint32_t n_tiles, uint32_t tile_bytes,
                                                  unsigned long long* acc_all) {
   __shared__ uint32_t hist[48];
-  __shared__ uint64_t red[4][9];
+  __shared__ uint64_t red[4][10];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   if (tid < 48) hist[tid] = 0u;  // stays zero between tiles: flushed bins are reset
   __syncthreads();
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const CmpTileDev tl = tiles[t];
     const CmpPairDev pr = pairs[tl.pair];
-    Partial p{0, 0, 0, 0, 0, 0, 0.0, 0.0, ~0ull};
+    Partial p{0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, ~0ull};
     const uint64_t nbytes = pr.n_elems * pr.esize;
     const uint64_t b0 = (uint64_t)tl.idx * tile_bytes;
     const uint64_t b1 = b0 + tile_bytes < nbytes ? b0 + tile_bytes : nbytes;
@@ -236,22 +249,25 @@ __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const 
     const uint64_t v6 = wave_reduce_max_u64(dbl_bits(p.max_abs));
     const uint64_t v7 = wave_reduce_max_u64(dbl_bits(p.max_rel));
     const uint64_t v8 = wave_reduce_max_u64(~p.first);
+    const uint64_t v9 = wave_reduce_sum<uint32_t>(p.not_close);
     if (lane == 0) {
       red[wave][0] = v0; red[wave][1] = v1; red[wave][2] = v2; red[wave][3] = v3; red[wave][4] = v4;
-      red[wave][5] = v5; red[wave][6] = v6; red[wave][7] = v7; red[wave][8] = v8;
+      red[wave][5] = v5; red[wave][6] = v6; red[wave][7] = v7; red[wave][8] = v8; red[wave][9] = v9;
     }
     __syncthreads();
     unsigned long long* acc = acc_all + (uint64_t)tl.pair * kAccWords;
-    if (tid < 9) {  // thread i folds slot i over the four waves and flushes it
+    if (tid < 10) {  // thread i folds slot i over the four waves and flushes it
       const uint32_t i = tid;
+      const bool is_sum = i < 6 || i == 9;
       uint64_t x = red[0][i];
 #pragma unroll
       for (uint32_t w = 1; w < 4; ++w) {
         const uint64_t y = red[w][i];
-        x = i < 6 ? x + y : (y > x ? y : x);
+        x = is_sum ? x + y : (y > x ? y : x);
       }
       if (x) {
         if (i < 6) atomicAdd(&acc[kAccMisElems + i], (unsigned long long)x);
+        else if (i == 9) atomicAdd(&acc[kAccNotClose], (unsigned long long)x);
         else atomicMax(&acc[kAccMaxAbs + (i - 6)], (unsigned long long)x);
       }
     }
@@ -291,14 +307,19 @@ __global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pair
     r->ulp_hist[b] = h;
     rest += h;
   }
+  const uint64_t not_close = acc[kAccNotClose];
+  r->n_not_close = not_close;
   if (pr.dtype == KC_U8) {
     r->ulp_hist[0] = 0;
     r->pass = r->n_mismatch_elems == 0 ? 1u : 0u;
+    r->pass_close = r->pass;
   } else {
     r->ulp_hist[0] = pr.n_elems - nb - ncand - ngold - rest;
     r->pass = (over == 0 && ncand == 0 && ngold == 0) ? 1u : 0u;
+    r->pass_close = (not_close == 0 && ncand == 0 && ngold == 0) ? 1u : 0u;
   }
   r->status = 0u;
+  r->reserved = 0u;
 }
 
 }  // namespace

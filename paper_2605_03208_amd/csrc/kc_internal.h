@@ -88,8 +88,9 @@ struct CmpPairDev {
   uint64_t n_elems;
   uint32_t dtype, tol;
   uint32_t n_tiles, esize;
+  double atol, rtol;
 };
-static_assert(sizeof(CmpPairDev) == 40, "pair layout");
+static_assert(sizeof(CmpPairDev) == 56, "pair layout");
 
 struct CmpTileDev {
   uint32_t pair, idx;
@@ -99,7 +100,7 @@ constexpr uint32_t kAccWords = 64;  // per-pair accumulator words
 // accumulator word map
 enum : uint32_t {
   kAccMisElems = 0, kAccMisBytes, kAccNanBoth, kAccNanCand, kAccNanGold, kAccOverTol,
-  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccHist = 16  // 45 bins: 16..60
+  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccNotClose, kAccHist = 16  // 45 bins: 16..60
 };
 
 // ---- launchers (kc_kernels.hip) ------------------------------------------

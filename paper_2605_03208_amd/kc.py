@@ -15,6 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
+ABI_VERSION = 2  # layout of the structs below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
@@ -57,7 +58,8 @@ class ScanArgs(ctypes.Structure):
 
 class Pair(ctypes.Structure):
     _fields_ = [("cand_d", ctypes.c_void_p), ("gold_d", ctypes.c_void_p), ("n_elems", ctypes.c_uint64),
-                ("dtype", ctypes.c_uint32), ("ulp_tol", ctypes.c_uint32)]
+                ("dtype", ctypes.c_uint32), ("ulp_tol", ctypes.c_uint32), ("atol", ctypes.c_double),
+                ("rtol", ctypes.c_double)]
 
 
 class CmpResult(ctypes.Structure):
@@ -66,7 +68,8 @@ class CmpResult(ctypes.Structure):
                 ("n_nan_both", ctypes.c_uint64), ("n_nan_cand_only", ctypes.c_uint64),
                 ("n_nan_gold_only", ctypes.c_uint64), ("n_over_tol", ctypes.c_uint64),
                 ("max_abs", ctypes.c_double), ("max_rel", ctypes.c_double),
-                ("ulp_hist", ctypes.c_uint64 * 48), ("pass_", ctypes.c_uint32), ("status", ctypes.c_uint32)]
+                ("ulp_hist", ctypes.c_uint64 * 48), ("pass_", ctypes.c_uint32), ("status", ctypes.c_uint32),
+                ("n_not_close", ctypes.c_uint64), ("pass_close", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Tuning(ctypes.Structure):
@@ -74,7 +77,8 @@ class Tuning(ctypes.Structure):
                 ("per_item", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
-assert ctypes.sizeof(CmpResult) == 472 and ctypes.sizeof(ScanResult) == 40
+RESULT_BYTES = 488
+assert ctypes.sizeof(CmpResult) == RESULT_BYTES and ctypes.sizeof(ScanResult) == 40 and ctypes.sizeof(Pair) == 48
 
 
 _lib = None
@@ -117,6 +121,8 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        if L.kc_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI {L.kc_abi_version()}, this binding expects {ABI_VERSION}: rebuild")
         _lib = L
     return _lib
 
@@ -311,13 +317,15 @@ def closure_scan(ctx: Context, rs: RangeSet, scan: ScanOut, stream=None) -> None
 
 
 def make_pairs(pairs) -> tuple[ctypes.Array, int]:
-    """pairs: iterable of (cand, gold, dtype, ulp_tol) with device tensors."""
+    """pairs: iterable of (cand, gold, dtype, ulp_tol[, atol, rtol]) with device tensors."""
     pairs = list(pairs)
     arr = (Pair * max(1, len(pairs)))()
-    for i, (c, g, dt, tol) in enumerate(pairs):
+    for i, p in enumerate(pairs):
+        c, g, dt, tol = p[:4]
+        atol, rtol = (p[4], p[5]) if len(p) > 4 else (0.0, 0.0)
         n = c.numel() * c.element_size() // ELEM_SIZE[dt]
         assert g.numel() * g.element_size() == c.numel() * c.element_size()
-        arr[i] = Pair(_ptr(c), _ptr(g), n, dt, tol)
+        arr[i] = Pair(_ptr(c), _ptr(g), n, dt, tol, float(atol), float(rtol))
     return arr, len(pairs)
 
 
@@ -325,7 +333,7 @@ def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -
     """Returns the device buffer of kc_cmp_result structs (decode with ``decode_cmp``)."""
     arr, n = pairs if isinstance(pairs, tuple) else make_pairs(pairs)
     if res is None:
-        res = torch.empty(max(1, n) * 472, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
+        res = torch.empty(max(1, n) * RESULT_BYTES, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
     _check(lib().kc_compare(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare")
     return res
 
@@ -355,16 +363,16 @@ class PairSet:
 
 def compare_pairset(ctx: Context, ps: PairSet, res: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     if res is None:
-        res = torch.empty(max(1, ps.n) * 472, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
+        res = torch.empty(max(1, ps.n) * RESULT_BYTES, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
     _check(lib().kc_compare_pairset(ctx.handle, ps.handle, _ptr(res), _stream(stream)), "kc_compare_pairset")
     return res
 
 
 def decode_cmp(res: torch.Tensor, n: int) -> list[dict]:
-    raw = bytes(res.cpu().numpy()[: n * 472])
+    raw = bytes(res.cpu().numpy()[: n * RESULT_BYTES])
     out = []
     for i in range(n):
-        r = CmpResult.from_buffer_copy(raw[i * 472:(i + 1) * 472])
+        r = CmpResult.from_buffer_copy(raw[i * RESULT_BYTES:(i + 1) * RESULT_BYTES])
         d = {}
         for k, _ in CmpResult._fields_:
             v = getattr(r, k)
@@ -372,6 +380,8 @@ def decode_cmp(res: torch.Tensor, n: int) -> list[dict]:
                 d[k] = [int(x) for x in v]
             elif k == "pass_":
                 d["pass"] = int(v)
+            elif k == "reserved":
+                continue
             else:
                 d[k] = float(v) if k.startswith("max_") else int(v)
         out.append(d)

@@ -291,8 +291,10 @@ def cmp_vs_oracle(kc, ctx, pairs, tile_bytes=None, per_item=0, grid=0):
     torch.cuda.synchronize()
     got = kc.decode_cmp(res, len(pairs))
     c2.close()
-    for (c, g, dt, tol), r in zip(pairs, got):
-        o = oracle.compare(c.cpu().view(torch.uint8).numpy(), g.cpu().view(torch.uint8).numpy(), dt, tol)
+    for p, r in zip(pairs, got):
+        c, g, dt, tol = p[:4]
+        atol, rtol = (p[4], p[5]) if len(p) > 4 else (0.0, 0.0)
+        o = oracle.compare(c.cpu().view(torch.uint8).numpy(), g.cpu().view(torch.uint8).numpy(), dt, tol, atol, rtol)
         assert r == o, (dt, tol, c.numel())
     return got
 
@@ -338,7 +340,7 @@ def test_compare_dtypes_specials_and_tails(kc, ctx, dt):
         n_al = n
         c, g = _special_pair(dt, max(n_al, 1), 100 * dt + i)
         c, g = c[:n_al], g[:n_al]
-        pairs.append((c, g, dt, int(i % 9)))
+        pairs.append((c, g, dt, int(i % 9), (0.0, 1e-8, 1e-3)[i % 3], (0.0, 1e-5, 0.0, 1e-2)[i % 4]))
     for tb, per_item in ((None, 0), (4096, 0), (4096, 1), (1 << 20, 0)):
         cmp_vs_oracle(kc, ctx, pairs, tile_bytes=tb, per_item=per_item)
 
@@ -346,7 +348,7 @@ def test_compare_dtypes_specials_and_tails(kc, ctx, dt):
 def test_compare_c3_scaled(kc, ctx):
     say("compare c3 scale 1/256: 1000 mixed pairs, batched vs per-buffer vs tile sizes")
     ps = W.c3_pairs("cuda", scale=1 / 256, n_pairs=1000)
-    pairs = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))]
+    pairs = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i]), 1e-8, 1e-5) for i in range(len(ps))]
     got = cmp_vs_oracle(kc, ctx, pairs)
     for i, r in enumerate(got):
         assert r["n_mismatch_elems"] == len(ps.pos[i])

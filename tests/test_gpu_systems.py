@@ -36,7 +36,7 @@ def test_pairset_equals_compare(kc):
     b = kc.compare_pairset(ctx, pset)
     b2 = kc.compare_pairset(ctx, pset)
     torch.cuda.synchronize()
-    assert torch.equal(a[: 300 * 472], b[: 300 * 472]) and torch.equal(b, b2)
+    assert torch.equal(a[: 300 * kc.RESULT_BYTES], b[: 300 * kc.RESULT_BYTES]) and torch.equal(b, b2)
     pset.close()
     ctx.close()
 
@@ -56,7 +56,7 @@ def test_graph_replay_matches_eager(kc):
     scan = kc.ScanOut(dev, oob_cap=16)
     pairs = W.c1_compare("cuda", scale=1 / 16, n_pairs=4)
     pset = kc.PairSet(ctx, [(p.cand, p.gold, W.DT_F32, 0) for p in pairs])
-    res = torch.empty(4 * 472, dtype=torch.uint8, device=dev)
+    res = torch.empty(4 * kc.RESULT_BYTES, dtype=torch.uint8, device=dev)
 
     def step():
         kc.snapshot(ctx, rs, scan=scan, out=out)
@@ -113,7 +113,7 @@ def test_autotuner_candidates_are_bit_identical(kc, tmp_path, monkeypatch):
     assert r2["cached"] and r2["best"] == r["best"]
     ps = W.c3_pairs("cuda", scale=1 / 1024, n_pairs=200)
     plist = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i])) for i in range(len(ps))]
-    res = torch.empty(200 * 472, dtype=torch.uint8, device="cuda")
+    res = torch.empty(200 * kc.RESULT_BYTES, dtype=torch.uint8, device="cuda")
     state = {}
 
     def prep(c):
@@ -146,5 +146,5 @@ def test_serving_alone_equals_mix_and_oracle(kc):
             cand = gold.clone()
             W.perturb_device(cand, int(dtypes[int(gid)]), ex.candidate_seed(r, int(gid)))
             want = oracle.compare(cand.cpu().view(torch.uint8).numpy(), gold.cpu().view(torch.uint8).numpy(),
-                                  int(dtypes[int(gid)]), r.ulp_tol)
+                                  int(dtypes[int(gid)]), r.ulp_tol, *serve.DEFAULT_CLOSE)
             assert got == want

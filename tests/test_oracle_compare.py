@@ -50,12 +50,12 @@ def test_ulp_bins(oracle_lib):
     assert o.ulp_bin((1 << 32) - 1) == 44
 
 
-def _check_pair(o, pair, dt):
+def _check_pair(o, pair, dt, atol=0.0, rtol=0.0):
     gold = pair.gold.cpu()
     cand = pair.cand.cpu()
     gv = gold.view(torch.uint8).numpy()
     cv = cand.view(torch.uint8).numpy()
-    r = o.compare(cv, gv, dt, pair.ulp_tol)
+    r = o.compare(cv, gv, dt, pair.ulp_tol, atol, rtol)
     n = gold.numel()
     assert r["n_elems"] == n
     mism = np.sort(np.concatenate([pair.pos, pair.nan_pos]))
@@ -77,6 +77,9 @@ def _check_pair(o, pair, dt):
     nz = ok & (g64 != 0)
     rel = np.abs(c64[nz] - g64[nz]) / np.abs(g64[nz])
     assert r["max_rel"] == (rel.max() if rel.size else 0.0)
+    close = np.isclose(c64[ok], g64[ok], rtol=rtol, atol=atol)    # library routine, float64
+    assert r["n_not_close"] == int((~close).sum())
+    assert r["pass_close"] == int(r["n_not_close"] == 0 and len(pair.nan_pos) == 0)
     return r
 
 
@@ -90,7 +93,8 @@ def test_known_perturbations(oracle_lib, dt):
             gold = (torch.randn(n, generator=gen) * 0.5).to(W.TORCH_DTYPE[dt])
         pair = W.perturb_pair(gold, dt, rng, max(1, n // 50), 16 if dt != W.DT_FP8 else 4,
                               n_nan=2 if n > 10 else 0, ulp_tol=tol)
-        _check_pair(oracle_lib, pair, dt)
+        for atol, rtol in ((0.0, 0.0), (1e-8, 1e-5), (1e-3, 0.0), (0.0, 1e-2)):
+            _check_pair(oracle_lib, pair, dt, atol, rtol)
 
 
 def test_c1_compare_pairs_scaled(oracle_lib):
@@ -149,6 +153,24 @@ def test_empty_and_bad_dtype(oracle_lib):
     assert r["n_elems"] == 0 and r["pass"] == 1 and r["first_mismatch"] == 2**64 - 1
     with pytest.raises(o.OracleError):
         o.compare(np.zeros(4, np.uint8), np.zeros(4, np.uint8), 9, 0)
+
+
+def test_tolerance_comparison_specials(oracle_lib):
+    """Infinities are close only to themselves; NaNs never enter the count;
+    the bound is atol + rtol * |golden| (checked against numpy.isclose)."""
+    o = oracle_lib
+    inf, ninf = float("inf"), float("-inf")
+    g = np.array([1.0, 1.0, 1.0, inf, inf, 0.0, -2.0, 1e-30, 3.0, np.nan], dtype=np.float32)
+    c = np.array([1.0, 1.00001, 1.1, inf, ninf, 1e-9, -2.00002, 0.0, np.float32(np.finfo(np.float32).max), 1.0],
+                 dtype=np.float32)
+    for atol, rtol in ((0.0, 0.0), (1e-8, 1e-5), (1e-6, 1e-4), (0.2, 0.0)):
+        r = o.compare(c, g, o.F32, 0, atol, rtol)
+        ok = ~np.isnan(c) & ~np.isnan(g)
+        want = int((~np.isclose(c[ok].astype(np.float64), g[ok].astype(np.float64), rtol=rtol, atol=atol)).sum())
+        assert r["n_not_close"] == want, (atol, rtol)
+        assert r["n_nan_gold_only"] == 1 and r["pass_close"] == 0
+    with pytest.raises(o.OracleError):
+        o.compare(c, g, o.F32, 0, -1.0, 0.0)
 
 
 def test_mismatch_bytes_count_per_byte(oracle_lib):

@@ -39,6 +39,8 @@ MUTANTS = {
     "fp16 exponent bias": ("v = ldexp((double)(m | 0x400u), (int)e - 25);", "v = ldexp((double)(m | 0x400u), (int)e - 24);"),
     "fp8 subnormal scale": ("v = ldexp((double)m, -9);", "v = ldexp((double)m, -10);"),
     "tolerance inclusive": ("if (d > ulp_tol) res->n_over_tol += 1;", "if (d >= ulp_tol) res->n_over_tol += 1;"),
+    "rtol scales the candidate": ("close = abs_err <= atol + rtol * fabs(vg);", "close = abs_err <= atol + rtol * fabs(vc);"),
+    "infinities always close": ("close = vc == vg;", "close = 1;"),
 }
 
 
