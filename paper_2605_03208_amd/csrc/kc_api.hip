@@ -28,6 +28,7 @@ struct kc_ctx {
 
 struct kc_rangeset {
   kc_ctx* ctx = nullptr;
+  int device = 0;  // recorded at creation: destroy never touches the context
   uint32_t n_ranges = 0, n_tiles = 0;
   uint64_t n_pages = 0, n_words = 0;
   std::vector<uint32_t> range_tile;  // first tile of each range (n + 1)
@@ -69,6 +70,10 @@ struct DeviceGuard {
   explicit DeviceGuard(int dev) {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();  // do not leave the failure for the caller's next HIP call
+      std::snprintf(g_last_error, sizeof(g_last_error), "hipSetDevice(%d) failed", dev);
+    }
   }
   ~DeviceGuard() {
     int cur = -1;
@@ -240,6 +245,7 @@ void kc_ctx_destroy(kc_ctx* c) {
 int kc_ctx_enable_timing(kc_ctx* c, int on) {
   if (c == nullptr) return KC_EINVAL;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   if (on) {
     for (uint32_t op = 0; op < KC_OP_COUNT; ++op) {
       if (!c->t_start[op]) KC_HIP(hipEventCreate(&c->t_start[op]));
@@ -253,6 +259,7 @@ int kc_ctx_enable_timing(kc_ctx* c, int on) {
 int kc_ctx_kernel_ms(kc_ctx* c, uint32_t op, float* ms) {
   if (c == nullptr || ms == nullptr || op >= KC_OP_COUNT || !c->t_valid[op]) return KC_EINVAL;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   KC_HIP(hipEventSynchronize(c->t_stop[op]));
   KC_HIP(hipEventElapsedTime(ms, c->t_start[op], c->t_stop[op]));
   return KC_OK;
@@ -281,9 +288,11 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   int st = range_check(ranges, n, &n_pages);
   if (st != KC_OK) return st;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   kc_rangeset* rs = new (std::nothrow) kc_rangeset();
   if (rs == nullptr) return KC_ENOMEM;
   rs->ctx = c;
+  rs->device = c->device;
   rs->n_ranges = n;
   rs->n_pages = n_pages;
   rs->n_words = (n_pages + 63) / 64;
@@ -364,7 +373,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
 
 void kc_rangeset_destroy(kc_rangeset* rs) {
   if (rs == nullptr) return;
-  DeviceGuard g(rs->ctx->device);
+  DeviceGuard g(rs->device);
   (void)hipFree(rs->dev);
   delete rs;
 }
@@ -403,6 +412,7 @@ int kc_page_hash(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_
     if (st != KC_OK) return st;
   }
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   KC_HIP(launch_fill_u64(zero_bm_d, rs->n_words, 0, s));
   if (prior_hash_d) KC_HIP(launch_fill_u64(changed_bm_d, rs->n_words, 0, s));
@@ -427,6 +437,7 @@ int kc_compact(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   if (rs->n_pages > 0 && zero_bm_d == nullptr) return KC_EINVAL;
   if (cap_pages > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   ScanSrc src{};
   src.kind = kSrcKeepBits;
@@ -468,6 +479,7 @@ int kc_snapshot(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t
     if (st != KC_OK) return st;
   }
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   KC_HIP(launch_fill_u64(zero_bm_d, rs->n_words, 0, s));
   if (scan) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
@@ -501,6 +513,7 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   if (rs->n_pages > 0 && zero_bm_d == nullptr) return KC_EINVAL;
   if (cap_pages > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->counts + 2;
   KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0, s));
@@ -519,6 +532,7 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
   const int st = make_scan(rs, scan, &sd);
   if (st != KC_OK) return st;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
   const uint32_t grid = grid_for(c, KC_OP_CLOSURE, 8);
@@ -540,6 +554,7 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
 
 struct kc_pairset {
   kc_ctx* ctx = nullptr;
+  int device = 0;  // recorded at creation: destroy never touches the context
   uint32_t n_pairs = 0, tile_bytes = 0;
   uint64_t n_tiles = 0;
   std::vector<uint64_t> tile_off;
@@ -638,6 +653,7 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
   const size_t sz_acc = (size_t)n_pairs * kAccWords * 8;
   const size_t need_dev = sz_pairs + sz_tiles + sz_acc, need_host = sz_pairs + sz_tiles;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   if (c->staged_pending) {
     KC_HIP(hipEventSynchronize(c->staged));  // the staging buffer is free again
@@ -687,9 +703,11 @@ int kc_pairset_create(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_pair
   int st = plan_pairs(pairs, n_pairs, tile_bytes, tile_off);
   if (st != KC_OK) return st;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   kc_pairset* ps = new (std::nothrow) kc_pairset();
   if (ps == nullptr) return KC_ENOMEM;
   ps->ctx = c;
+  ps->device = c->device;
   ps->n_pairs = n_pairs;
   ps->tile_bytes = tile_bytes;
   ps->n_tiles = tile_off[n_pairs];
@@ -722,7 +740,7 @@ int kc_pairset_create(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_pair
 
 void kc_pairset_destroy(kc_pairset* ps) {
   if (ps == nullptr) return;
-  DeviceGuard g(ps->ctx->device);
+  DeviceGuard g(ps->device);
   (void)hipFree(ps->dev);
   delete ps;
 }
@@ -731,6 +749,7 @@ int kc_compare_pairset(kc_ctx* c, const kc_pairset* ps, kc_cmp_result* res_d, vo
   if (c == nullptr || ps == nullptr || ps->ctx != c || (ps->n_pairs > 0 && res_d == nullptr)) return KC_EINVAL;
   if (ps->n_pairs == 0) return KC_OK;
   DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
   return run_compare(c, ps->pairs, ps->tiles, ps->tile_off, ps->n_pairs, ps->tile_bytes, ps->acc, res_d,
                      as_stream(stream));
 }

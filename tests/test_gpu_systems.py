@@ -148,3 +148,20 @@ def test_serving_alone_equals_mix_and_oracle(kc):
             want = oracle.compare(cand.cpu().view(torch.uint8).numpy(), gold.cpu().view(torch.uint8).numpy(),
                                   int(dtypes[int(gid)]), r.ulp_tol, *serve.DEFAULT_CLOSE)
             assert got == want
+
+
+def test_sets_may_outlive_their_context(kc):
+    say("context destroyed before its range set and pair set; caller's HIP state stays clean")
+    ctx = kc.Context(0)
+    case = W.c1_snapshot("cuda", scale=1 / 64)
+    rs = kc.RangeSet(ctx, case.ranges())
+    a = torch.ones(4096, dtype=torch.float32, device="cuda")
+    ps = kc.PairSet(ctx, [(a, a, W.DT_F32, 0)])
+    ctx.close()
+    with pytest.raises(kc.KCError):
+        kc.compare_pairset(ctx, ps)      # a closed context is rejected, not dereferenced
+    rs.close()
+    ps.close()
+    b = torch.zeros(1 << 20, device="cuda").add_(1.0)
+    torch.cuda.synchronize()
+    assert float(b.sum().item()) == float(1 << 20)
