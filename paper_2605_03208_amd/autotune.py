@@ -42,8 +42,21 @@ class TuningChangedResult(RuntimeError):
     """A candidate launch shape produced different outputs."""
 
 
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+
+
 def cache_path() -> str:
+    """The writable cache (tuning results of this machine)."""
     return os.environ.get("KC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "kc", "tune.json"))
+
+
+def lookup(key: str):
+    """A cached winner: this machine's cache first, then the table shipped
+    with the package (winners of this autotuner on an MI355X)."""
+    hit = _load_cache(cache_path()).get(key)
+    if hit is None and os.environ.get("KC_TUNE_SHIPPED", "1") != "0":
+        hit = _load_cache(SHIPPED).get(key)
+    return hit
 
 
 def size_class(nbytes: int) -> int:
@@ -94,7 +107,7 @@ def tune(ctx: kc.Context, op: int, run, digest=None, signature: str = "", candid
     key = cache_key(op, signature)
     path = cache_path()
     if use_cache and signature:
-        hit = _load_cache(path).get(key)
+        hit = lookup(key)
         if hit:
             best = hit["best"]
             ctx.set_tuning(op, **best)
