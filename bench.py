@@ -307,6 +307,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         line["graph"]["c1_latency"] = c1_latency(torch, kc, W, dev)
         line["batching"] = batching(torch, kc, W, dev)
+        line["snapshot_files"] = snapshot_files(torch, kc, W, dev)
         line["serving"] = serving(torch, kc, W, dev, args.serve_seconds)
     if cpu is not None:
         line["cpu_baseline"] = cpu
@@ -471,6 +472,37 @@ def batching(torch, kc, W, dev) -> dict:
     del case
     torch.cuda.empty_cache()
     return out
+
+
+def snapshot_files(torch, kc, W, dev) -> dict:
+    """The packed snapshot of the 2 GiB / 4096-range pool streamed to host
+    files and loaded back (the paper's capture writes regions to files at
+    ~1.7 GB/s, Sec. 5.3), through 64 MiB pinned double buffers."""
+    import shutil
+    import tempfile
+    log("snapshot files: c2 full snapshot saved and loaded back")
+    case = W.c2_snapshot("cuda")
+    ctx = kc.Context(0)
+    rs = kc.RangeSet(ctx, case.ranges())
+    out = kc.snapshot(ctx, rs, seed=2)
+    torch.cuda.synchronize()
+    base = "/dev/shm" if os.path.isdir("/dev/shm") and shutil.disk_usage("/dev/shm").free > (8 << 30) else None
+    d = tempfile.mkdtemp(prefix="kc_snap_", dir=base)
+    try:
+        save = kc.snapshot_save(ctx, rs, os.path.join(d, "s"), out, seed=2)
+        back, load = kc.snapshot_load(ctx, rs, os.path.join(d, "s"))
+        ok = bool(torch.equal(back["packed"][: int(out["n_kept"].item()) * PAGE],
+                              out["packed"][: int(out["n_kept"].item()) * PAGE]))
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    res = {"workload": "c2 full snapshot (4096 ranges, 2 GiB)", "target": base or tempfile.gettempdir(),
+           "bytes": save["bytes"], "save_GBps": round(save["bytes"] / save["seconds"] / 1e9, 2),
+           "load_GBps": round(load["bytes"] / load["seconds"] / 1e9, 2), "reload_identical": ok}
+    rs.close()
+    ctx.close()
+    del case, out, back
+    torch.cuda.empty_cache()
+    return res
 
 
 def serving(torch, kc, W, dev, seconds: float) -> dict:

@@ -295,6 +295,43 @@ void kc_pairset_destroy(kc_pairset *ps);
 int kc_compare_pairset(kc_ctx *ctx, const kc_pairset *ps, kc_cmp_result *res_d,
                        void *stream);
 
+/* ---- snapshot files (Sec. 4.2.1: every region streamed to files in
+ *      fixed-size chunks, metadata written before the data) ------------------ */
+
+typedef struct {
+  uint64_t bytes;  /* data bytes moved (metadata files not counted) */
+  double seconds;  /* wall time of the call                          */
+} kc_io_stats;
+
+/* Write a snapshot to directory `dir` (created if missing): manifest.json
+ * (human-readable: seed, counts, every region's base and size, file list) and
+ * header.bin + ranges.bin (the same metadata, binary) first, then hash.bin
+ * (N u64), zero_bm.bin, changed_bm.bin (delta snapshots: changed_bm_d non-NULL),
+ * page_va.bin (min(n_kept, cap_pages) u64) and packed.bin (that many pages).
+ * Device-to-host copies go through two pinned buffers of chunk_bytes (0 = 64
+ * MiB) on `stream`, overlapping the file writes.  Synchronous: returns when the
+ * files are complete.  Allocates pinned memory for the call.  Errors:
+ * KC_EINVAL (bad arguments, file system errors; see kc_last_error), KC_EHIP. */
+int kc_snapshot_save(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
+                     uint64_t seed, const uint64_t *hash_d,
+                     const uint64_t *zero_bm_d, const uint64_t *changed_bm_d,
+                     const void *packed_d, const uint64_t *page_va_d,
+                     const uint64_t *n_kept_d, uint64_t cap_pages,
+                     uint64_t chunk_bytes, void *stream, kc_io_stats *stats);
+
+/* Load a saved snapshot into device buffers for kc_restore.  The snapshot's
+ * ranges must equal the range set's (same VAs and sizes: the restore is
+ * VA-faithful), else KC_EINVAL.  hash_d may be NULL (not loaded); a delta
+ * snapshot needs changed_bm_d; more packed pages than cap_pages is
+ * KC_ELIMIT.  Host-to-device copies are chunked and double-buffered like the
+ * save.  Synchronous. */
+int kc_snapshot_load(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
+                     uint64_t *hash_d, uint64_t *zero_bm_d,
+                     uint64_t *changed_bm_d, void *packed_d,
+                     uint64_t *page_va_d, uint64_t *n_kept_d,
+                     uint64_t cap_pages, uint64_t chunk_bytes, void *stream,
+                     kc_io_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

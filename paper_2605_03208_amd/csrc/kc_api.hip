@@ -10,76 +10,21 @@
 
 using namespace kc;
 
-struct kc_ctx {
-  int device = 0;
-  uint32_t n_cu = 256;
-  kc_tuning tune[KC_OP_COUNT];
-  uint8_t* cmp_dev = nullptr;  // pairs | tiles | accumulators
-  size_t cmp_dev_cap = 0;
-  uint8_t* cmp_host = nullptr;  // pinned staging of pairs | tiles
-  size_t cmp_host_cap = 0;
-  hipEvent_t staged = nullptr;  // completion of the last staging copy
-  bool staged_pending = false;
-  bool timing = false;  // record events around the main kernel of each op
-  hipEvent_t t_start[KC_OP_COUNT] = {};
-  hipEvent_t t_stop[KC_OP_COUNT] = {};
-  bool t_valid[KC_OP_COUNT] = {};
-};
-
-struct kc_rangeset {
-  kc_ctx* ctx = nullptr;
-  int device = 0;  // recorded at creation: destroy never touches the context
-  uint32_t n_ranges = 0, n_tiles = 0;
-  uint64_t n_pages = 0, n_words = 0;
-  std::vector<uint32_t> range_tile;  // first tile of each range (n + 1)
-  uint64_t win_lo = 0, win_hi = 0;   // default pointer window
-  void* dev = nullptr;
-  Tile* tiles = nullptr;
-  uint64_t* bases = nullptr;
-  uint64_t* ends = nullptr;
-  uint32_t* tile_oob = nullptr;
-  uint64_t* tile_prefix = nullptr;
-  uint64_t* word_prefix = nullptr;
-  uint64_t* block_sums = nullptr;
-  unsigned long long* counts = nullptr;  // [0] ptr-like, [1] in-range, [2] rejected page VAs
-  uint64_t* n_oob = nullptr;
-  RangeTable rt{};
-};
-
 namespace {
-
 thread_local char g_last_error[256] = "";
+}  // namespace
 
+namespace kc {
+void set_error_text(const char* text) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", text); }
 void set_error(const char* what, hipError_t e) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%s)", what, hipGetErrorName(e),
                 hipGetErrorString(e));
 }
+}  // namespace kc
 
-#define KC_HIP(call)                          \
-  do {                                        \
-    hipError_t kc_e_ = (call);                \
-    if (kc_e_ != hipSuccess) {                \
-      set_error(#call, kc_e_);                \
-      return KC_EHIP;                         \
-    }                                         \
-  } while (0)
+namespace {
 
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    if (!ok) {
-      (void)hipGetLastError();  // do not leave the failure for the caller's next HIP call
-      std::snprintf(g_last_error, sizeof(g_last_error), "hipSetDevice(%d) failed", dev);
-    }
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+
 
 constexpr uint64_t kMaxPages = (1ull << 32) - 1;
 constexpr uint32_t kMaxRanges = 1u << 31;
@@ -296,6 +241,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->n_ranges = n;
   rs->n_pages = n_pages;
   rs->n_words = (n_pages + 63) / 64;
+  rs->host_ranges.assign(ranges, ranges + n);
   default_window(ranges, n, &rs->win_lo, &rs->win_hi);
 
   std::vector<Tile> tiles;
@@ -552,17 +498,6 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
 
 }  // extern "C"
 
-struct kc_pairset {
-  kc_ctx* ctx = nullptr;
-  int device = 0;  // recorded at creation: destroy never touches the context
-  uint32_t n_pairs = 0, tile_bytes = 0;
-  uint64_t n_tiles = 0;
-  std::vector<uint64_t> tile_off;
-  void* dev = nullptr;
-  CmpPairDev* pairs = nullptr;
-  CmpTileDev* tiles = nullptr;
-  unsigned long long* acc = nullptr;
-};
 
 namespace {
 

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdio>
+#include <vector>
+
 #include "kc.h"
 
 namespace kc {
@@ -134,4 +137,88 @@ hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint
 hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, const unsigned long long* acc,
                                    kc_cmp_result* res, hipStream_t s);
 
+// ---- errors and device selection (kc_api.hip) ------------------------------
+void set_error_text(const char* text);
+void set_error(const char* what, hipError_t e);
+
+#define KC_HIP(call)                          \
+  do {                                        \
+    hipError_t kc_e_ = (call);                \
+    if (kc_e_ != hipSuccess) {                \
+      ::kc::set_error(#call, kc_e_);          \
+      return KC_EHIP;                         \
+    }                                         \
+  } while (0)
+
+// Makes `dev` current for the scope of a call and restores the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();  // do not leave the failure for the caller's next HIP call
+      char msg[64];
+      std::snprintf(msg, sizeof(msg), "hipSetDevice(%d) failed", dev);
+      set_error_text(msg);
+    }
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 }  // namespace kc
+
+// ---- library objects --------------------------------------------------------
+struct kc_ctx {
+  int device = 0;
+  uint32_t n_cu = 256;
+  kc_tuning tune[KC_OP_COUNT];
+  uint8_t* cmp_dev = nullptr;  // pairs | tiles | accumulators
+  size_t cmp_dev_cap = 0;
+  uint8_t* cmp_host = nullptr;  // pinned staging of pairs | tiles
+  size_t cmp_host_cap = 0;
+  hipEvent_t staged = nullptr;  // completion of the last staging copy
+  bool staged_pending = false;
+  bool timing = false;  // record events around the main kernel of each op
+  hipEvent_t t_start[KC_OP_COUNT] = {};
+  hipEvent_t t_stop[KC_OP_COUNT] = {};
+  bool t_valid[KC_OP_COUNT] = {};
+};
+
+struct kc_rangeset {
+  kc_ctx* ctx = nullptr;
+  int device = 0;  // recorded at creation: destroy never touches the context
+  uint32_t n_ranges = 0, n_tiles = 0;
+  uint64_t n_pages = 0, n_words = 0;
+  std::vector<uint32_t> range_tile;  // first tile of each range (n + 1)
+  uint64_t win_lo = 0, win_hi = 0;   // default pointer window
+  std::vector<kc_range> host_ranges;
+  void* dev = nullptr;
+  kc::Tile* tiles = nullptr;
+  uint64_t* bases = nullptr;
+  uint64_t* ends = nullptr;
+  uint32_t* tile_oob = nullptr;
+  uint64_t* tile_prefix = nullptr;
+  uint64_t* word_prefix = nullptr;
+  uint64_t* block_sums = nullptr;
+  unsigned long long* counts = nullptr;  // [0] ptr-like, [1] in-range, [2] rejected page VAs
+  uint64_t* n_oob = nullptr;
+  kc::RangeTable rt{};
+};
+
+struct kc_pairset {
+  kc_ctx* ctx = nullptr;
+  int device = 0;  // recorded at creation: destroy never touches the context
+  uint32_t n_pairs = 0, tile_bytes = 0;
+  uint64_t n_tiles = 0;
+  std::vector<uint64_t> tile_off;
+  void* dev = nullptr;
+  kc::CmpPairDev* pairs = nullptr;
+  kc::CmpTileDev* tiles = nullptr;
+  unsigned long long* acc = nullptr;
+};
+

@@ -1,0 +1,361 @@
+// kc_io.hip -- snapshot files: the packed snapshot streamed to host files
+// through pinned, double-buffered chunks, and loaded back for a restore.
+#include <errno.h>
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kc_internal.h"
+
+namespace kc {
+
+struct Pinned {
+  uint8_t* p[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~Pinned() {
+    for (int i = 0; i < 2; ++i) {
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      if (p[i]) (void)hipHostFree(p[i]);
+    }
+  }
+  hipError_t init(size_t bytes) {
+    for (int i = 0; i < 2; ++i) {
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p[i]), bytes, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
+namespace {
+
+bool write_all(int fd, const uint8_t* p, size_t n) {
+  while (n > 0) {
+    const ssize_t w = ::write(fd, p, n);
+    if (w <= 0) return false;
+    p += w;
+    n -= (size_t)w;
+  }
+  return true;
+}
+
+bool read_all(int fd, uint8_t* p, size_t n) {
+  while (n > 0) {
+    const ssize_t r = ::read(fd, p, n);
+    if (r <= 0) return false;
+    p += r;
+    n -= (size_t)r;
+  }
+  return true;
+}
+
+}  // namespace
+
+// Device -> file in chunks: chunk i+1 is copied while chunk i is written.
+int stream_to_file(const std::string& path, const void* src_d, uint64_t bytes, Pinned& pin, size_t chunk,
+                   hipStream_t s, std::string& err) {
+  const int fd = ::open(path.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+  if (fd < 0) {
+    err = "cannot create " + path;
+    return KC_EINVAL;
+  }
+  const uint8_t* src = static_cast<const uint8_t*>(src_d);
+  const uint64_t n_chunks = (bytes + chunk - 1) / chunk;
+  int st = KC_OK;
+  for (uint64_t i = 0; i <= n_chunks && st == KC_OK; ++i) {
+    if (i < n_chunks) {
+      const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+      hipError_t e = hipMemcpyAsync(pin.p[i & 1], src + off, len, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(pin.ev[i & 1], s);
+      if (e != hipSuccess) {
+        err = std::string("D2H copy: ") + hipGetErrorName(e);
+        st = KC_EHIP;
+        break;
+      }
+    }
+    if (i > 0) {
+      const uint64_t j = i - 1, off = j * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+      hipError_t e = hipEventSynchronize(pin.ev[j & 1]);
+      if (e != hipSuccess) {
+        err = std::string("D2H wait: ") + hipGetErrorName(e);
+        st = KC_EHIP;
+      } else if (!write_all(fd, pin.p[j & 1], len)) {
+        err = "short write to " + path;
+        st = KC_EINVAL;
+      }
+    }
+  }
+  if (::close(fd) != 0 && st == KC_OK) {
+    err = "close " + path;
+    st = KC_EINVAL;
+  }
+  return st;
+}
+
+// File -> device in chunks: chunk i+1 is read while chunk i is copied.
+int stream_from_file(const std::string& path, void* dst_d, uint64_t bytes, Pinned& pin, size_t chunk,
+                     hipStream_t s, std::string& err) {
+  const int fd = ::open(path.c_str(), O_RDONLY);
+  if (fd < 0) {
+    err = "cannot open " + path;
+    return KC_EINVAL;
+  }
+  struct stat stt;
+  if (::fstat(fd, &stt) != 0 || (uint64_t)stt.st_size != bytes) {
+    ::close(fd);
+    err = path + ": size does not match the manifest";
+    return KC_EINVAL;
+  }
+  uint8_t* dst = static_cast<uint8_t*>(dst_d);
+  const uint64_t n_chunks = (bytes + chunk - 1) / chunk;
+  int st = KC_OK;
+  for (uint64_t i = 0; i < n_chunks && st == KC_OK; ++i) {
+    const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+    if (i >= 2) {  // the buffer's previous copy must have left it
+      hipError_t e = hipEventSynchronize(pin.ev[i & 1]);
+      if (e != hipSuccess) {
+        err = std::string("H2D wait: ") + hipGetErrorName(e);
+        st = KC_EHIP;
+        break;
+      }
+    }
+    if (!read_all(fd, pin.p[i & 1], len)) {
+      err = "short read from " + path;
+      st = KC_EINVAL;
+      break;
+    }
+    hipError_t e = hipMemcpyAsync(dst + off, pin.p[i & 1], len, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(pin.ev[i & 1], s);
+    if (e != hipSuccess) {
+      err = std::string("H2D copy: ") + hipGetErrorName(e);
+      st = KC_EHIP;
+    }
+  }
+  ::close(fd);
+  if (st == KC_OK) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      err = std::string("H2D drain: ") + hipGetErrorName(e);
+      st = KC_EHIP;
+    }
+  }
+  return st;
+}
+
+int write_text(const std::string& path, const std::string& text) {
+  const int fd = ::open(path.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+  if (fd < 0) return KC_EINVAL;
+  const bool ok = write_all(fd, reinterpret_cast<const uint8_t*>(text.data()), text.size());
+  return (::close(fd) == 0 && ok) ? KC_OK : KC_EINVAL;
+}
+
+int write_bytes(const std::string& path, const void* p, size_t n) {
+  const int fd = ::open(path.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+  if (fd < 0) return KC_EINVAL;
+  const bool ok = write_all(fd, static_cast<const uint8_t*>(p), n);
+  return (::close(fd) == 0 && ok) ? KC_OK : KC_EINVAL;
+}
+
+int read_bytes(const std::string& path, std::vector<uint8_t>& out) {
+  const int fd = ::open(path.c_str(), O_RDONLY);
+  if (fd < 0) return KC_EINVAL;
+  struct stat stt;
+  if (::fstat(fd, &stt) != 0) {
+    ::close(fd);
+    return KC_EINVAL;
+  }
+  out.resize((size_t)stt.st_size);
+  const bool ok = read_all(fd, out.data(), out.size());
+  ::close(fd);
+  return ok ? KC_OK : KC_EINVAL;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace kc
+
+// ---------------------------------------------------------------------------
+// extern "C" entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FileHeader {  // header.bin: 64 bytes, little-endian
+  char magic[8];     // "KCSNAP01"
+  uint32_t version;
+  uint32_t page_size;
+  uint64_t seed;
+  uint64_t n_ranges, n_pages, n_kept, n_packed;
+  uint32_t delta, reserved;
+};
+static_assert(sizeof(FileHeader) == 64, "header layout");
+
+constexpr uint64_t kDefaultChunk = 64ull << 20;  // the paper's default chunk size
+
+std::string join(const char* dir, const char* name) { return std::string(dir) + "/" + name; }
+
+}  // namespace
+
+using namespace kc;
+
+extern "C" {
+
+int kc_snapshot_save(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t seed, const uint64_t* hash_d,
+                     const uint64_t* zero_bm_d, const uint64_t* changed_bm_d, const void* packed_d,
+                     const uint64_t* page_va_d, const uint64_t* n_kept_d, uint64_t cap_pages, uint64_t chunk_bytes,
+                     void* stream, kc_io_stats* stats) {
+  if (c == nullptr || rs == nullptr || rs->ctx != c || dir == nullptr || n_kept_d == nullptr) return KC_EINVAL;
+  if (rs->n_pages > 0 && (hash_d == nullptr || zero_bm_d == nullptr)) return KC_EINVAL;
+  if (cap_pages > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
+  const uint64_t chunk = chunk_bytes ? chunk_bytes : kDefaultChunk;
+  if (chunk < 4096 || chunk > (1ull << 32)) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const double t0 = now_s();
+  if (::mkdir(dir, 0755) != 0 && errno != EEXIST) {
+    set_error_text("cannot create the snapshot directory");
+    return KC_EINVAL;
+  }
+  uint64_t n_kept = 0;
+  KC_HIP(hipMemcpyAsync(&n_kept, n_kept_d, 8, hipMemcpyDeviceToHost, s));
+  KC_HIP(hipStreamSynchronize(s));
+  const uint64_t n_packed = std::min(n_kept, cap_pages);
+  // metadata first, so a failure while streaming data leaves a readable manifest
+  FileHeader h{};
+  std::memcpy(h.magic, "KCSNAP01", 8);
+  h.version = 1;
+  h.page_size = KC_PAGE_SIZE;
+  h.seed = seed;
+  h.n_ranges = rs->n_ranges;
+  h.n_pages = rs->n_pages;
+  h.n_kept = n_kept;
+  h.n_packed = n_packed;
+  h.delta = changed_bm_d != nullptr ? 1u : 0u;
+  std::string js = "{\n  \"format\": \"kc-snapshot\",\n  \"version\": 1,\n  \"page_size\": 4096,\n";
+  char buf[256];
+  std::snprintf(buf, sizeof(buf),
+                "  \"seed\": %llu,\n  \"n_ranges\": %llu,\n  \"n_pages\": %llu,\n  \"n_kept\": %llu,\n"
+                "  \"n_packed\": %llu,\n  \"delta\": %s,\n  \"chunk_bytes\": %llu,\n  \"regions\": [\n",
+                (unsigned long long)seed, (unsigned long long)rs->n_ranges, (unsigned long long)rs->n_pages,
+                (unsigned long long)n_kept, (unsigned long long)n_packed, h.delta ? "true" : "false",
+                (unsigned long long)chunk);
+  js += buf;
+  for (uint32_t i = 0; i < rs->n_ranges; ++i) {
+    std::snprintf(buf, sizeof(buf), "    {\"base\": \"0x%llx\", \"size\": %llu}%s\n",
+                  (unsigned long long)rs->host_ranges[i].base, (unsigned long long)rs->host_ranges[i].size,
+                  i + 1 < rs->n_ranges ? "," : "");
+    js += buf;
+  }
+  js += "  ],\n  \"files\": [\"header.bin\", \"ranges.bin\", \"hash.bin\", \"zero_bm.bin\"";
+  js += h.delta ? ", \"changed_bm.bin\"" : "";
+  js += ", \"page_va.bin\", \"packed.bin\"]\n}\n";
+  if (write_text(join(dir, "manifest.json"), js) != KC_OK ||
+      write_bytes(join(dir, "header.bin"), &h, sizeof(h)) != KC_OK ||
+      write_bytes(join(dir, "ranges.bin"), rs->host_ranges.data(), sizeof(kc_range) * rs->n_ranges) != KC_OK) {
+    set_error_text("cannot write the snapshot metadata");
+    return KC_EINVAL;
+  }
+  Pinned pin;
+  KC_HIP(pin.init(chunk));
+  std::string err;
+  struct Part {
+    const char* name;
+    const void* src;
+    uint64_t bytes;
+  } parts[] = {{"hash.bin", hash_d, 8 * rs->n_pages},
+               {"zero_bm.bin", zero_bm_d, 8 * rs->n_words},
+               {"changed_bm.bin", changed_bm_d, changed_bm_d ? 8 * rs->n_words : 0},
+               {"page_va.bin", page_va_d, 8 * n_packed},
+               {"packed.bin", packed_d, KC_PAGE_SIZE * n_packed}};
+  uint64_t total = 0;
+  for (const Part& p : parts) {
+    if (p.src == nullptr && std::strcmp(p.name, "changed_bm.bin") == 0) continue;
+    const int st = stream_to_file(join(dir, p.name), p.src, p.bytes, pin, chunk, s, err);
+    if (st != KC_OK) {
+      set_error_text(err.c_str());
+      return st;
+    }
+    total += p.bytes;
+  }
+  if (stats) {
+    stats->bytes = total;
+    stats->seconds = now_s() - t0;
+  }
+  return KC_OK;
+}
+
+int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t* hash_d, uint64_t* zero_bm_d,
+                     uint64_t* changed_bm_d, void* packed_d, uint64_t* page_va_d, uint64_t* n_kept_d,
+                     uint64_t cap_pages, uint64_t chunk_bytes, void* stream, kc_io_stats* stats) {
+  if (c == nullptr || rs == nullptr || rs->ctx != c || dir == nullptr || n_kept_d == nullptr) return KC_EINVAL;
+  if (rs->n_pages > 0 && zero_bm_d == nullptr) return KC_EINVAL;
+  const uint64_t chunk = chunk_bytes ? chunk_bytes : kDefaultChunk;
+  if (chunk < 4096 || chunk > (1ull << 32)) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const double t0 = now_s();
+  std::vector<uint8_t> hb, rb;
+  if (read_bytes(join(dir, "header.bin"), hb) != KC_OK || hb.size() != sizeof(FileHeader)) {
+    set_error_text("missing or short header.bin");
+    return KC_EINVAL;
+  }
+  FileHeader h;
+  std::memcpy(&h, hb.data(), sizeof(h));
+  if (std::memcmp(h.magic, "KCSNAP01", 8) != 0 || h.version != 1 || h.page_size != KC_PAGE_SIZE) {
+    set_error_text("not a snapshot directory of this format");
+    return KC_EINVAL;
+  }
+  // the snapshot must describe exactly this range set (same VAs, same sizes)
+  if (read_bytes(join(dir, "ranges.bin"), rb) != KC_OK || h.n_ranges != rs->n_ranges || h.n_pages != rs->n_pages ||
+      rb.size() != sizeof(kc_range) * rs->n_ranges ||
+      (rs->n_ranges && std::memcmp(rb.data(), rs->host_ranges.data(), rb.size()) != 0)) {
+    set_error_text("snapshot ranges differ from the range set");
+    return KC_EINVAL;
+  }
+  if (h.n_packed > cap_pages) return KC_ELIMIT;
+  if (h.n_packed > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
+  if (h.delta && changed_bm_d == nullptr) return KC_EINVAL;
+  Pinned pin;
+  KC_HIP(pin.init(chunk));
+  std::string err;
+  struct Part {
+    const char* name;
+    void* dst;
+    uint64_t bytes;
+  } parts[] = {{"hash.bin", hash_d, 8 * rs->n_pages},
+               {"zero_bm.bin", zero_bm_d, 8 * rs->n_words},
+               {"changed_bm.bin", h.delta ? changed_bm_d : nullptr, 8 * rs->n_words},
+               {"page_va.bin", page_va_d, 8 * h.n_packed},
+               {"packed.bin", packed_d, KC_PAGE_SIZE * h.n_packed}};
+  uint64_t total = 0;
+  for (const Part& p : parts) {
+    if (p.dst == nullptr || p.bytes == 0) continue;
+    const int st = stream_from_file(join(dir, p.name), p.dst, p.bytes, pin, chunk, s, err);
+    if (st != KC_OK) {
+      set_error_text(err.c_str());
+      return st;
+    }
+    total += p.bytes;
+  }
+  KC_HIP(hipMemcpyAsync(n_kept_d, &h.n_kept, 8, hipMemcpyHostToDevice, s));
+  KC_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->bytes = total;
+    stats->seconds = now_s() - t0;
+  }
+  return KC_OK;
+}
+
+}  // extern "C"

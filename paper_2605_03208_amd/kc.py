@@ -29,7 +29,7 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_ctx_enable_timing", "kc_ctx_kernel_ms",
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
-           "kc_compare_pairset"]
+           "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load"]
 
 
 class KCError(RuntimeError):
@@ -70,6 +70,10 @@ class CmpResult(ctypes.Structure):
                 ("max_abs", ctypes.c_double), ("max_rel", ctypes.c_double),
                 ("ulp_hist", ctypes.c_uint64 * 48), ("pass_", ctypes.c_uint32), ("status", ctypes.c_uint32),
                 ("n_not_close", ctypes.c_uint64), ("pass_close", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class IoStats(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -116,6 +120,9 @@ def lib() -> ctypes.CDLL:
             "kc_pairset_create": ([vp, P(Pair), u32, P(vp)], i32),
             "kc_pairset_destroy": ([vp], None),
             "kc_compare_pairset": ([vp, vp, vp, vp], i32),
+            "kc_snapshot_save": ([vp, vp, ctypes.c_char_p, u64, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)],
+                                 i32),
+            "kc_snapshot_load": ([vp, vp, ctypes.c_char_p, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -336,6 +343,35 @@ def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -
         res = torch.empty(max(1, n) * RESULT_BYTES, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
     _check(lib().kc_compare(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare")
     return res
+
+
+def snapshot_save(ctx: Context, rs: RangeSet, directory: str, out: dict, seed: int = 0, cap_pages=None,
+                  chunk_bytes: int = 0, stream=None) -> dict:
+    """Write the snapshot in ``out`` (as returned by ``snapshot``) to files."""
+    cap = out["page_va"].numel() if cap_pages is None else int(cap_pages)
+    st = IoStats()
+    _check(lib().kc_snapshot_save(ctx.handle, rs.handle, directory.encode(), seed & (2**64 - 1), _ptr(out["hash"]),
+                                  _ptr(out["zero_bm"]), _ptr(out.get("changed_bm")), _ptr(out["packed"]),
+                                  _ptr(out["page_va"]), _ptr(out["n_kept"]), cap, chunk_bytes, _stream(stream),
+                                  ctypes.byref(st)), "kc_snapshot_save")
+    return dict(bytes=int(st.bytes), seconds=float(st.seconds))
+
+
+def snapshot_load(ctx: Context, rs: RangeSet, directory: str, cap_pages: int | None = None, delta: bool = False,
+                  chunk_bytes: int = 0, stream=None):
+    """Load a saved snapshot into fresh device buffers; returns (out dict, stats)."""
+    dev = torch.device("cuda", ctx.device)
+    cap = rs.n_pages if cap_pages is None else int(cap_pages)
+    out = dict(hash=_u64(rs.n_pages, dev), zero_bm=_u64(rs.n_words, dev),
+               changed_bm=_u64(rs.n_words, dev) if delta else None,
+               packed=torch.empty(max(1, cap) * PAGE, dtype=torch.uint8, device=dev),
+               page_va=_u64(cap, dev), n_kept=_u64(1, dev))
+    st = IoStats()
+    _check(lib().kc_snapshot_load(ctx.handle, rs.handle, directory.encode(), _ptr(out["hash"]), _ptr(out["zero_bm"]),
+                                  _ptr(out["changed_bm"]), _ptr(out["packed"]), _ptr(out["page_va"]),
+                                  _ptr(out["n_kept"]), cap, chunk_bytes, _stream(stream), ctypes.byref(st)),
+           "kc_snapshot_load")
+    return out, dict(bytes=int(st.bytes), seconds=float(st.seconds))
 
 
 class PairSet:
