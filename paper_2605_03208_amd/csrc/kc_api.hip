@@ -107,9 +107,7 @@ int finish_scan(kc_rangeset* rs, const kc_scan_args* sa, const ScanDev& sd, hipS
   src.n_items = rs->n_tiles;
   KC_HIP(launch_scan(src, rs->tile_prefix, rs->block_sums, rs->n_oob, s));
   KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, rs->n_oob, sa->oob_d, sa->oob_cap,
-                         grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
-  KC_HIP(launch_scan_finalize(sa->res_d, rs->counts, rs->n_oob, rs->n_pages * (KC_PAGE_SIZE / 8),
-                              sa->oob_cap, s));
+                         sa->res_d, rs->n_pages * (KC_PAGE_SIZE / 8), grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
   return KC_OK;
 }
 
@@ -179,6 +177,7 @@ void kc_ctx_destroy(kc_ctx* c) {
     (void)hipEventDestroy(c->staged);
   }
   if (c->cmp_dev) (void)hipFree(c->cmp_dev);
+  if (c->cmp_acc) (void)hipFree(c->cmp_acc);
   if (c->cmp_host) (void)hipHostFree(c->cmp_host);
   for (uint32_t op = 0; op < KC_OP_COUNT; ++op) {
     if (c->t_start[op]) (void)hipEventDestroy(c->t_start[op]);
@@ -360,9 +359,8 @@ int kc_page_hash(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
-  KC_HIP(launch_fill_u64(zero_bm_d, rs->n_words, 0, s));
-  if (prior_hash_d) KC_HIP(launch_fill_u64(changed_bm_d, rs->n_words, 0, s));
-  if (scan) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
+  KC_HIP(launch_zero3(zero_bm_d, rs->n_words, changed_bm_d, prior_hash_d ? rs->n_words : 0,
+                      reinterpret_cast<uint64_t*>(rs->counts), scan ? 2 : 0, s));
   HashParams hp{};
   hp.seed = seed;
   hp.prior = prior_hash_d;
@@ -427,8 +425,8 @@ int kc_snapshot(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
-  KC_HIP(launch_fill_u64(zero_bm_d, rs->n_words, 0, s));
-  if (scan) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
+  KC_HIP(launch_zero3(zero_bm_d, rs->n_words, nullptr, 0, reinterpret_cast<uint64_t*>(rs->counts), scan ? 2 : 0,
+                      s));
   KC_HIP(launch_probe_zero(rs->tiles, rs->n_tiles, zero_bm_d, grid_for(c, KC_OP_SNAPSHOT, 8), s));
   ScanSrc src{};
   src.kind = kSrcKeepBits;
@@ -462,9 +460,8 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->counts + 2;
-  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0, s));
   const uint32_t grid = grid_for(c, KC_OP_RESTORE, 16);
-  KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, grid, s));
+  KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, bad, grid, s));
   KernelTimer timer(c, KC_OP_RESTORE, s);
   KC_HIP(launch_restore_scatter(rs->rt, static_cast<const uint8_t*>(packed_d), page_va_d, n_kept_d, cap_pages,
                                 bad, grid, s));
@@ -548,11 +545,17 @@ void fill_pair_tables(const kc_pair* pairs, uint32_t n_pairs, const std::vector<
   }
 }
 
-// Clear the accumulators, run the pass (one launch, or one per pair), write the reports.
+// Run the pass (one launch, or one per pair), write the reports.  The
+// accumulators are zero on entry and the finalize kernel zeroes them again.
+// A call that failed between the pass and the finalize leaves *acc_dirty set;
+// the next call clears the whole accumulator area first (fill kernel, so the
+// call stays capturable).
 int run_compare(kc_ctx* c, const CmpPairDev* dpairs, const CmpTileDev* dtiles, const std::vector<uint64_t>& tile_off,
-                uint32_t n_pairs, uint32_t tile_bytes, unsigned long long* dacc, kc_cmp_result* res_d, hipStream_t s) {
-  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), (uint64_t)n_pairs * kAccWords, 0, s));
+                uint32_t n_pairs, uint32_t tile_bytes, unsigned long long* dacc, uint64_t acc_words, bool* acc_dirty,
+                kc_cmp_result* res_d, hipStream_t s) {
   const uint32_t grid = grid_for(c, KC_OP_COMPARE, 2);
+  if (*acc_dirty) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), acc_words, 0, s));
+  *acc_dirty = true;
   {
     KernelTimer timer(c, KC_OP_COMPARE, s);
     if (!c->tune[KC_OP_COMPARE].per_item) {
@@ -564,6 +567,7 @@ int run_compare(kc_ctx* c, const CmpPairDev* dpairs, const CmpTileDev* dtiles, c
     }
   }
   KC_HIP(launch_compare_finalize(dpairs, n_pairs, dacc, res_d, s));
+  *acc_dirty = false;
   return KC_OK;
 }
 
@@ -586,7 +590,7 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
   const size_t sz_pairs = align_up(sizeof(CmpPairDev) * n_pairs, 256);
   const size_t sz_tiles = align_up(sizeof(CmpTileDev) * n_tiles, 256);
   const size_t sz_acc = (size_t)n_pairs * kAccWords * 8;
-  const size_t need_dev = sz_pairs + sz_tiles + sz_acc, need_host = sz_pairs + sz_tiles;
+  const size_t need_dev = sz_pairs + sz_tiles, need_host = sz_pairs + sz_tiles;
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
@@ -607,6 +611,21 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
     }
     c->cmp_dev_cap = cap;
   }
+  if (sz_acc > c->cmp_acc_cap) {
+    KC_HIP(hipStreamSynchronize(s));
+    const size_t cap = std::max(sz_acc, c->cmp_acc_cap * 2);
+    if (c->cmp_acc) KC_HIP(hipFree(c->cmp_acc));
+    c->cmp_acc = nullptr;
+    c->cmp_acc_cap = 0;
+    hipError_t e = hipMalloc(&c->cmp_acc, cap);
+    if (e != hipSuccess) {
+      set_error("hipMalloc(compare accumulators)", e);
+      return e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
+    }
+    KC_HIP(hipMemset(c->cmp_acc, 0, cap));
+    c->cmp_acc_cap = cap;
+    c->cmp_acc_dirty = false;
+  }
   if (need_host > c->cmp_host_cap) {
     if (c->cmp_host) KC_HIP(hipHostFree(c->cmp_host));
     c->cmp_host = nullptr;
@@ -623,11 +642,12 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
                    reinterpret_cast<CmpTileDev*>(c->cmp_host + sz_pairs));
   CmpPairDev* dpairs = reinterpret_cast<CmpPairDev*>(c->cmp_dev);
   CmpTileDev* dtiles = reinterpret_cast<CmpTileDev*>(c->cmp_dev + sz_pairs);
-  unsigned long long* dacc = reinterpret_cast<unsigned long long*>(c->cmp_dev + sz_pairs + sz_tiles);
+  unsigned long long* dacc = c->cmp_acc;
   KC_HIP(hipMemcpyAsync(c->cmp_dev, c->cmp_host, need_host, hipMemcpyHostToDevice, s));
   KC_HIP(hipEventRecord(c->staged, s));
   c->staged_pending = true;
-  return run_compare(c, dpairs, dtiles, tile_off, n_pairs, tile_bytes, dacc, res_d, s);
+  return run_compare(c, dpairs, dtiles, tile_off, n_pairs, tile_bytes, dacc, c->cmp_acc_cap / 8, &c->cmp_acc_dirty,
+                     res_d, s);
 }
 
 int kc_pairset_create(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_pairset** out) {
@@ -663,7 +683,8 @@ int kc_pairset_create(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_pair
   std::vector<uint8_t> host(sz_pairs + sz_tiles);
   fill_pair_tables(pairs, n_pairs, ps->tile_off, reinterpret_cast<CmpPairDev*>(host.data()),
                    reinterpret_cast<CmpTileDev*>(host.data() + sz_pairs));
-  if ((e = hipMemcpy(ps->dev, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((e = hipMemcpy(ps->dev, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(ps->acc, 0, sz_acc)) != hipSuccess) {
     set_error("hipMemcpy(pairset)", e);
     (void)hipFree(ps->dev);
     delete ps;
@@ -685,8 +706,8 @@ int kc_compare_pairset(kc_ctx* c, const kc_pairset* ps, kc_cmp_result* res_d, vo
   if (ps->n_pairs == 0) return KC_OK;
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
-  return run_compare(c, ps->pairs, ps->tiles, ps->tile_off, ps->n_pairs, ps->tile_bytes, ps->acc, res_d,
-                     as_stream(stream));
+  return run_compare(c, ps->pairs, ps->tiles, ps->tile_off, ps->n_pairs, ps->tile_bytes, ps->acc,
+                     (uint64_t)ps->n_pairs * kAccWords, &ps->acc_dirty, res_d, as_stream(stream));
 }
 
 }  // extern "C"

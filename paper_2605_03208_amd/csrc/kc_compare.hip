@@ -282,13 +282,13 @@ __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const 
   }
 }
 
-// One thread per pair turns the accumulators into the report.
+// One thread per pair turns the accumulators into the report and zeroes them.
 __global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs,
-                                                          const unsigned long long* acc_all, kc_cmp_result* res) {
+                                                          unsigned long long* acc_all, kc_cmp_result* res) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pairs) return;
   const CmpPairDev pr = pairs[i];
-  const unsigned long long* acc = acc_all + (uint64_t)i * kAccWords;
+  unsigned long long* acc = acc_all + (uint64_t)i * kAccWords;
   kc_cmp_result* r = res + i;
   const uint64_t nb = acc[kAccNanBoth], ncand = acc[kAccNanCand], ngold = acc[kAccNanGold], over = acc[kAccOverTol];
   r->n_elems = pr.n_elems;
@@ -320,6 +320,7 @@ __global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pair
   }
   r->status = 0u;
   r->reserved = 0u;
+  for (uint32_t w = 0; w < kAccWords; ++w) acc[w] = 0ull;  // ready for the next call
 }
 
 }  // namespace
@@ -332,7 +333,7 @@ hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint
   return hipGetLastError();
 }
 
-hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, const unsigned long long* acc,
+hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, unsigned long long* acc,
                                    kc_cmp_result* res, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_compare_finalize, dim3((n_pairs + 255) / 256), dim3(256), 0, s, pairs, n_pairs, acc, res);

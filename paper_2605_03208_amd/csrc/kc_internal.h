@@ -108,6 +108,8 @@ enum : uint32_t {
 
 // ---- launchers (kc_kernels.hip) ------------------------------------------
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint64_t* c, uint64_t nc,
+                        hipStream_t s);
 hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan,
                             uint32_t grid, hipStream_t s);
 hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm,
@@ -119,7 +121,8 @@ hipError_t launch_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* ze
                          uint8_t* packed, uint64_t* page_va, uint64_t cap_pages,
                          uint32_t grid, hipStream_t s);
 hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
-                               const uint64_t* changed_bm, uint32_t grid, hipStream_t s);
+                               const uint64_t* changed_bm, unsigned long long* n_bad, uint32_t grid,
+                               hipStream_t s);
 hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
                                   const uint64_t* page_va, const uint64_t* n_kept,
                                   uint64_t cap_pages, unsigned long long* n_bad,
@@ -128,13 +131,11 @@ hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
                           const ScanDev& sd, uint32_t grid, hipStream_t s);
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
                            const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
-                           uint64_t cap, uint32_t grid, hipStream_t s);
-hipError_t launch_scan_finalize(kc_scan_result* res, const unsigned long long* counts,
-                                const uint64_t* n_oob, uint64_t n_words, uint64_t cap,
-                                hipStream_t s);
+                           uint64_t cap, kc_scan_result* res, uint64_t n_words, uint32_t grid,
+                           hipStream_t s);
 hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
                           uint32_t tile_bytes, unsigned long long* acc, uint32_t grid, hipStream_t s);
-hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, const unsigned long long* acc,
+hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, unsigned long long* acc,
                                    kc_cmp_result* res, hipStream_t s);
 
 // ---- errors and device selection (kc_api.hip) ------------------------------
@@ -177,8 +178,11 @@ struct kc_ctx {
   int device = 0;
   uint32_t n_cu = 256;
   kc_tuning tune[KC_OP_COUNT];
-  uint8_t* cmp_dev = nullptr;  // pairs | tiles | accumulators
+  uint8_t* cmp_dev = nullptr;  // pairs | tiles
   size_t cmp_dev_cap = 0;
+  unsigned long long* cmp_acc = nullptr;  // accumulators: zero between calls (finalize resets them)
+  size_t cmp_acc_cap = 0;
+  bool cmp_acc_dirty = false;
   uint8_t* cmp_host = nullptr;  // pinned staging of pairs | tiles
   size_t cmp_host_cap = 0;
   hipEvent_t staged = nullptr;  // completion of the last staging copy
@@ -220,5 +224,6 @@ struct kc_pairset {
   kc::CmpPairDev* pairs = nullptr;
   kc::CmpTileDev* tiles = nullptr;
   unsigned long long* acc = nullptr;
+  mutable bool acc_dirty = false;  // a failed compare left accumulators set
 };
 

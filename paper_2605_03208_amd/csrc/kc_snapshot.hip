@@ -128,6 +128,17 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
     p[i] = v;
 }
 
+// Zero up to three arrays in one launch (index space = their concatenation).
+__global__ void k_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint64_t* c, uint64_t nc) {
+  const uint64_t n = na + nb + nc;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (i < na) a[i] = 0;
+    else if (i < na + nb) b[i - na] = 0;
+    else c[i - na - nb] = 0;
+  }
+}
+
 // ---------------------------------------------------------- page hash -----
 // One wave hashes a tile of up to 16 pages: lane quad q owns page q, lane k of
 // the quad runs XXH64 accumulator k over the words 8k + 32s of each stripe s.
@@ -475,8 +486,10 @@ __global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_til
 
 // -------------------------------------------------------------- restore ---
 __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t n_tiles,
-                                                     const uint64_t* zero_bm, const uint64_t* changed_bm) {
+                                                     const uint64_t* zero_bm, const uint64_t* changed_bm,
+                                                     unsigned long long* n_bad) {
   const uint32_t lane = threadIdx.x;
+  if (blockIdx.x == 0 && lane == 0) *n_bad = 0ull;  // the scatter that follows counts into it
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const Tile tile = tiles[t];
     bool sel = false;
@@ -583,10 +596,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // ascending address order, up to the list capacity.
 __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_tiles, ScanDev sd,
                                                  const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
-                                                 uint64_t cap) {
+                                                 uint64_t cap, kc_scan_result* res, uint64_t n_words) {
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
-  if (*n_oob == 0) return;  // nothing out of range: no tile to revisit
+  const uint64_t total = *n_oob;
+  if (blockIdx.x == 0 && lane == 0) {  // the result struct
+    res->n_words = n_words;
+    res->n_ptr_like = sd.counts[0];
+    res->n_in_range = sd.counts[1];
+    res->n_oob = total;
+    res->n_written = (uint32_t)(total < cap ? total : cap);
+    res->truncated = total > cap ? 1u : 0u;
+  }
+  if (total == 0 || cap == 0) return;  // nothing to list: no tile to revisit
   load_fences(fences, sd.rt, lane, kWave);
   __syncthreads();
   const uint64_t below = (1ull << lane) - 1ull;
@@ -620,23 +642,21 @@ __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_t
   }
 }
 
-__global__ void k_scan_finalize(kc_scan_result* res, const unsigned long long* counts, const uint64_t* n_oob,
-                                uint64_t n_words, uint64_t cap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const uint64_t no = *n_oob;
-  res->n_words = n_words;
-  res->n_ptr_like = counts[0];
-  res->n_in_range = counts[1];
-  res->n_oob = no;
-  res->n_written = (uint32_t)(no < cap ? no : cap);
-  res->truncated = no > cap ? 1u : 0u;
-}
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 }  // namespace
 
 // ------------------------------------------------------------- launchers --
+hipError_t launch_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint64_t* c, uint64_t nc,
+                        hipStream_t s) {
+  const uint64_t n = na + nb + nc;
+  if (n == 0) return hipSuccess;
+  const uint64_t nbk = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_zero3, dim3((uint32_t)(nbk < 4096 ? nbk : 4096)), dim3(256), 0, s, a, na, b, nb, c, nc);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint64_t nb = blocks_for(n, 256);
@@ -702,10 +722,10 @@ hipError_t launch_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* ze
 }
 
 hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
-                               const uint64_t* changed_bm, uint32_t grid, hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_restore_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm);
+                               const uint64_t* changed_bm, unsigned long long* n_bad, uint32_t grid,
+                               hipStream_t s) {
+  grid = std::max(1u, std::min(grid, std::max(1u, n_tiles)));
+  hipLaunchKernelGGL(k_restore_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm, n_bad);
   return hipGetLastError();
 }
 
@@ -730,17 +750,13 @@ hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, c
 }
 
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd, const uint64_t* tile_prefix,
-                           const uint64_t* n_oob, kc_oob* oob, uint64_t cap, uint32_t grid, hipStream_t s) {
-  if (n_tiles == 0 || cap == 0) return hipSuccess;
-  grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_oob_emit, dim3(grid), dim3(64), 0, s, tiles, n_tiles, sd, tile_prefix, n_oob, oob, cap);
+                           const uint64_t* n_oob, kc_oob* oob, uint64_t cap, kc_scan_result* res, uint64_t n_words,
+                           uint32_t grid, hipStream_t s) {
+  grid = std::max(1u, std::min(grid, std::max(1u, n_tiles)));
+  hipLaunchKernelGGL(k_oob_emit, dim3(grid), dim3(64), 0, s, tiles, n_tiles, sd, tile_prefix, n_oob, oob, cap, res,
+                     n_words);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_finalize(kc_scan_result* res, const unsigned long long* counts, const uint64_t* n_oob,
-                                uint64_t n_words, uint64_t cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_finalize, dim3(1), dim3(64), 0, s, res, counts, n_oob, n_words, cap);
-  return hipGetLastError();
-}
 
 }  // namespace kc
