@@ -22,6 +22,9 @@ SOURCES = [os.path.join(HERE, "kco.c")]
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EDTYPE = 0, -1, -2, -3, -4, -6
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
+F64, FP8_E4M3FNUZ, FP8_E5M2, FP8_E5M2FNUZ, I8, I16, I32, I64 = 5, 6, 7, 8, 9, 10, 11, 12
+ELEM_SIZE = {F32: 4, BF16: 2, F16: 2, FP8_E4M3FN: 1, U8: 1, F64: 8, FP8_E4M3FNUZ: 1, FP8_E5M2: 1,
+             FP8_E5M2FNUZ: 1, I8: 1, I16: 2, I32: 4, I64: 8}
 PAGE = 4096
 
 
@@ -83,7 +86,7 @@ def lib() -> ctypes.CDLL:
         L.kco_restore.argtypes = [P(Range), P(vp), u32, vp, vp, vp, vp, u64, u64, P(u64)]
         L.kco_closure_scan.argtypes = [P(Range), P(vp), u32, u64, u64, P(ScanResult), P(Oob), u64]
         L.kco_compare.argtypes = [vp, vp, u64, u32, u32, ctypes.c_double, ctypes.c_double, P(CmpResult)]
-        L.kco_ulp.argtypes = [u32, u32, u32, P(u64)]
+        L.kco_ulp.argtypes = [u32, u64, u64, P(u64)]
         L.kco_ulp_bin.argtypes = [u64]
         L.kco_ulp_bin.restype = u32
         for name in ("kco_range_check", "kco_default_window", "kco_page_hash", "kco_compact",
@@ -215,7 +218,7 @@ def closure_scan(ranges, views, win_lo: int = 0, win_hi: int = 0, oob_cap: int =
 
 def compare(cand, gold, dtype: int, ulp_tol: int = 0, atol: float = 0.0, rtol: float = 0.0):
     """cand / gold: numpy arrays (any dtype) holding n elements of ``dtype``."""
-    es = {F32: 4, BF16: 2, F16: 2, FP8_E4M3FN: 1, U8: 1}.get(dtype)
+    es = ELEM_SIZE.get(dtype)
     if es is None:
         res = CmpResult()
         _check(lib().kco_compare(None, None, 0, dtype, ulp_tol, atol, rtol, ctypes.byref(res)), "compare")

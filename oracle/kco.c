@@ -318,89 +318,123 @@ int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
 
 static uint32_t elem_size(uint32_t dtype) {
   switch (dtype) {
-    case KCO_F32: return 4;
-    case KCO_BF16: return 2;
-    case KCO_F16: return 2;
-    case KCO_FP8_E4M3FN: return 1;
-    case KCO_U8: return 1;
+    case KCO_F64: case KCO_I64: return 8;
+    case KCO_F32: case KCO_I32: return 4;
+    case KCO_BF16: case KCO_F16: case KCO_I16: return 2;
+    case KCO_FP8_E4M3FN: case KCO_FP8_E4M3FNUZ: case KCO_FP8_E5M2:
+    case KCO_FP8_E5M2FNUZ: case KCO_I8: case KCO_U8: return 1;
     default: return 0;
   }
 }
 
-static uint32_t read_elem_bits(const uint8_t *p, uint32_t size) {
-  uint32_t v = 0;
-  for (int i = (int)size - 1; i >= 0; --i) v = (v << 8) | (uint32_t)p[i];
+static int is_int_type(uint32_t dtype) {
+  return dtype == KCO_I8 || dtype == KCO_I16 || dtype == KCO_I32 || dtype == KCO_I64;
+}
+
+static uint64_t read_elem_bits(const uint8_t *p, uint32_t size) {
+  uint64_t v = 0;
+  for (int i = (int)size - 1; i >= 0; --i) v = (v << 8) | (uint64_t)p[i];
   return v;
 }
 
-/* magnitude mask, sign bit, NaN test, and exact value of an encoding */
-static uint32_t mag_mask(uint32_t dtype) {
-  switch (dtype) {
-    case KCO_F32: return 0x7FFFFFFFu;
-    case KCO_BF16: return 0x7FFFu;
-    case KCO_F16: return 0x7FFFu;
-    default: return 0x7Fu; /* fp8 e4m3fn */
-  }
+/* Floating formats: the sign bit is the top bit of the element, the
+ * magnitude is the rest. */
+static uint64_t sign_bit(uint32_t dtype) {
+  return 1ULL << (8u * elem_size(dtype) - 1u);
 }
 
-static int is_nan_bits(uint32_t dtype, uint32_t bits) {
-  uint32_t mag = bits & mag_mask(dtype);
+static int is_nan_bits(uint32_t dtype, uint64_t bits) {
+  uint64_t mag = bits & (sign_bit(dtype) - 1u);
   switch (dtype) {
+    case KCO_F64: return mag > 0x7FF0000000000000ULL;
     case KCO_F32: return mag > 0x7F800000u;
     case KCO_BF16: return mag > 0x7F80u;
     case KCO_F16: return mag > 0x7C00u;
-    default: return mag == 0x7Fu;
+    case KCO_FP8_E4M3FN: return mag == 0x7Fu;
+    case KCO_FP8_E5M2: return mag > 0x7Cu;
+    case KCO_FP8_E4M3FNUZ: case KCO_FP8_E5M2FNUZ: return bits == 0x80u;
+    default: return 0; /* integers */
   }
 }
 
-static double decode_value(uint32_t dtype, uint32_t bits) {
-  uint32_t mag = bits & mag_mask(dtype);
-  int negative = (bits & (mag_mask(dtype) + 1u)) != 0;
+/* Value of a small binary format with exponent field e (ebits wide),
+ * mantissa field m (mbits wide) and the given bias: subnormal when e == 0. */
+static double small_float(uint32_t e, uint32_t m, int mbits, int bias) {
+  if (e == 0) return ldexp((double)m, 1 - bias - mbits);
+  return ldexp((double)(m | (1u << mbits)), (int)e - bias - mbits);
+}
+
+static double decode_value(uint32_t dtype, uint64_t bits) {
+  if (is_int_type(dtype)) {
+    uint32_t nb = 8u * elem_size(dtype);
+    int64_t v = (nb < 64 && (bits >> (nb - 1)) & 1u) ? (int64_t)(bits | (~0ULL << nb)) : (int64_t)bits;
+    return (double)v;
+  }
+  if (dtype == KCO_F64) {
+    double d;
+    memcpy(&d, &bits, sizeof d); /* the host's own binary64 */
+    return d;
+  }
+  uint64_t mag = bits & (sign_bit(dtype) - 1u);
+  int negative = (bits & sign_bit(dtype)) != 0;
   double v;
   if (dtype == KCO_F32 || dtype == KCO_BF16) {
     /* bf16 is the upper half of an fp32 encoding */
-    uint32_t f32 = dtype == KCO_F32 ? mag : (mag << 16);
+    uint32_t f32 = dtype == KCO_F32 ? (uint32_t)mag : (uint32_t)(mag << 16);
     uint32_t e = f32 >> 23, m = f32 & 0x7FFFFFu;
-    if (e == 0)
-      v = ldexp((double)m, -149);
-    else if (e == 255)
-      v = INFINITY; /* NaN never reaches decode */
-    else
-      v = ldexp((double)(m | 0x800000u), (int)e - 150);
+    v = e == 255 ? INFINITY /* NaN never reaches decode */ : small_float(e, m, 23, 127);
   } else if (dtype == KCO_F16) {
-    uint32_t e = mag >> 10, m = mag & 0x3FFu;
-    if (e == 0)
-      v = ldexp((double)m, -24);
-    else if (e == 31)
-      v = INFINITY;
-    else
-      v = ldexp((double)(m | 0x400u), (int)e - 25);
+    uint32_t e = (uint32_t)mag >> 10, m = (uint32_t)mag & 0x3FFu;
+    v = e == 31 ? INFINITY : small_float(e, m, 10, 15);
+  } else if (dtype == KCO_FP8_E5M2) {
+    uint32_t e = (uint32_t)mag >> 2, m = (uint32_t)mag & 0x3u;
+    v = e == 31 ? INFINITY : small_float(e, m, 2, 15);
+  } else if (dtype == KCO_FP8_E5M2FNUZ) { /* every exponent is finite */
+    v = small_float((uint32_t)mag >> 2, (uint32_t)mag & 0x3u, 2, 16);
+  } else if (dtype == KCO_FP8_E4M3FNUZ) {
+    v = small_float((uint32_t)mag >> 3, (uint32_t)mag & 0x7u, 3, 8);
   } else { /* OCP fp8 e4m3fn: bias 7, no infinities */
-    uint32_t e = mag >> 3, m = mag & 0x7u;
-    if (e == 0)
-      v = ldexp((double)m, -9);
-    else
-      v = ldexp((double)(m | 0x8u), (int)e - 10);
+    v = small_float((uint32_t)mag >> 3, (uint32_t)mag & 0x7u, 3, 7);
   }
   return negative ? -v : v;
 }
 
-int kco_ulp(uint32_t dtype, uint32_t cand_bits, uint32_t gold_bits,
+static int is_inf_value(uint32_t dtype, double v) {
+  return !is_int_type(dtype) && isinf(v);
+}
+
+int kco_ulp(uint32_t dtype, uint64_t cand_bits, uint64_t gold_bits,
             uint64_t *dist) {
-  if (dtype > KCO_FP8_E4M3FN) return KCO_EDTYPE;
-  uint32_t mm = mag_mask(dtype), sign = mm + 1u;
-  int64_t oc = (int64_t)(cand_bits & mm), og = (int64_t)(gold_bits & mm);
-  if (cand_bits & sign) oc = -oc;
-  if (gold_bits & sign) og = -og;
-  *dist = (uint64_t)(oc > og ? oc - og : og - oc);
+  uint32_t es = elem_size(dtype);
+  if (es == 0 || dtype == KCO_U8) return KCO_EDTYPE;
+  if (is_int_type(dtype)) {
+    /* sign-extend, then the exact difference (it fits in 64 unsigned bits) */
+    uint32_t nb = 8u * es;
+    uint64_t c = cand_bits, g = gold_bits;
+    if (nb < 64) {
+      if ((c >> (nb - 1)) & 1u) c |= ~0ULL << nb;
+      if ((g >> (nb - 1)) & 1u) g |= ~0ULL << nb;
+    }
+    int64_t ci = (int64_t)c, gi = (int64_t)g;
+    *dist = ci >= gi ? c - g : g - c; /* modulo 2^64, exact since < 2^64 */
+    return KCO_OK;
+  }
+  /* floats: position in sign-magnitude order; +0 and -0 coincide */
+  uint64_t sb = sign_bit(dtype), mm = sb - 1u;
+  uint64_t mc = cand_bits & mm, mg = gold_bits & mm;
+  int sc = (cand_bits & sb) != 0, sg = (gold_bits & sb) != 0;
+  if (sc == sg)
+    *dist = mc > mg ? mc - mg : mg - mc;
+  else
+    *dist = mc + mg; /* through zero: each magnitude is below 2^63 */
   return KCO_OK;
 }
 
 uint32_t kco_ulp_bin(uint64_t dist) {
   if (dist <= 16) return (uint32_t)dist;
   uint32_t k = 0; /* smallest k with 2^k >= dist */
-  while ((1ULL << k) < dist) ++k;
-  return 12u + k;
+  while (k < 64 && (1ULL << k) < dist) ++k;
+  return 12u + k < 47u ? 12u + k : 47u;
 }
 
 int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
@@ -417,7 +451,7 @@ int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
   const uint8_t *cb = (const uint8_t *)cand, *gb = (const uint8_t *)gold;
   for (uint64_t i = 0; i < n_elems; ++i) {
     const uint8_t *pc = cb + i * es, *pg = gb + i * es;
-    uint32_t c = read_elem_bits(pc, es), g = read_elem_bits(pg, es);
+    uint64_t c = read_elem_bits(pc, es), g = read_elem_bits(pg, es);
     if (c != g) {
       res->n_mismatch_elems += 1;
       if (res->first_mismatch == UINT64_MAX) res->first_mismatch = i;
@@ -444,14 +478,18 @@ int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
     if (d > ulp_tol) res->n_over_tol += 1;
     if (c == g) continue; /* identical encodings: abs 0, rel 0 */
     double vc = decode_value(dtype, c), vg = decode_value(dtype, g);
-    double abs_err = fabs(vc - vg);
+    double abs_err;
+    if (is_int_type(dtype))
+      abs_err = (double)d; /* exact difference, one rounding */
+    else
+      abs_err = fabs(vc - vg);
     if (abs_err > res->max_abs) res->max_abs = abs_err;
-    if (vg != 0.0 && !isinf(vg)) {
+    if (vg != 0.0 && !is_inf_value(dtype, vg)) {
       double rel = abs_err / fabs(vg);
       if (rel > res->max_rel) res->max_rel = rel;
     }
     int close;
-    if (isinf(vc) || isinf(vg))
+    if (is_inf_value(dtype, vc) || is_inf_value(dtype, vg))
       close = vc == vg;
     else
       close = abs_err <= atol + rtol * fabs(vg);

@@ -54,7 +54,17 @@ enum {
   KCO_EDTYPE = -6
 };
 
-enum { KCO_F32 = 0, KCO_BF16 = 1, KCO_F16 = 2, KCO_FP8_E4M3FN = 3, KCO_U8 = 4 };
+/* Element types.  Floating formats: IEEE binary32 / binary16 / binary64,
+ * bfloat16, OCP fp8 E4M3FN (bias 7, NaN = S.1111.111, no inf) and E5M2
+ * (bias 15, IEEE-like inf / NaN), and the FNUZ fp8 variants E4M3FNUZ (bias 8)
+ * and E5M2FNUZ (bias 16), whose only NaN is 0x80 and which have no -0 and no
+ * inf.  Integers are two's complement, compared by their exact difference.
+ * KCO_U8 is raw bytes (bitwise report only). */
+enum {
+  KCO_F32 = 0, KCO_BF16 = 1, KCO_F16 = 2, KCO_FP8_E4M3FN = 3, KCO_U8 = 4,
+  KCO_F64 = 5, KCO_FP8_E4M3FNUZ = 6, KCO_FP8_E5M2 = 7, KCO_FP8_E5M2FNUZ = 8,
+  KCO_I8 = 9, KCO_I16 = 10, KCO_I32 = 11, KCO_I64 = 12
+};
 
 typedef struct {
   uint64_t base, size;
@@ -121,13 +131,17 @@ int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
 /* Typed compare of one candidate / golden pair of n_elems elements.  Besides
  * the ULP report, an element pair (neither NaN) is close iff
  * |c - g| <= atol + rtol * |g| in fp64, an infinity being close only to an
- * equal value (tolerance comparison with atol / rtol, paper Sec. 4.5.2). */
+ * equal value (tolerance comparison with atol / rtol, paper Sec. 4.5.2).
+ * For integers |c - g| is the exact difference rounded once to fp64.
+ * Histogram bins: d for d <= 16, else min(12 + ceil(log2 d), 47). */
 int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
                 uint32_t dtype, uint32_t ulp_tol, double atol, double rtol,
                 kco_cmp_result *res);
 
-/* ULP distance and histogram bin of one element pair (exposed for tests). */
-int kco_ulp(uint32_t dtype, uint32_t cand_bits, uint32_t gold_bits,
+/* ULP distance (floats: steps between the encodings in sign-magnitude order;
+ * integers: |c - g| exactly) and histogram bin of one element pair (exposed
+ * for tests).  Bits are the element's little-endian encoding, zero-extended. */
+int kco_ulp(uint32_t dtype, uint64_t cand_bits, uint64_t gold_bits,
             uint64_t *dist);
 uint32_t kco_ulp_bin(uint64_t dist);
 

@@ -32,9 +32,20 @@ KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
 SYNTH_BASE = 0x7F8A00000000  # synthetic arena VA for CPU-only runs
 
 DT_F32, DT_BF16, DT_F16, DT_FP8, DT_U8 = 0, 1, 2, 3, 4
+DT_F64, DT_FP8_E4M3FNUZ, DT_FP8_E5M2, DT_FP8_E5M2FNUZ = 5, 6, 7, 8
+DT_I8, DT_I16, DT_I32, DT_I64 = 9, 10, 11, 12
 TORCH_DTYPE = {DT_F32: torch.float32, DT_BF16: torch.bfloat16, DT_F16: torch.float16,
-               DT_FP8: torch.float8_e4m3fn, DT_U8: torch.uint8}
-ELEM_SIZE = {DT_F32: 4, DT_BF16: 2, DT_F16: 2, DT_FP8: 1, DT_U8: 1}
+               DT_FP8: torch.float8_e4m3fn, DT_U8: torch.uint8, DT_F64: torch.float64,
+               DT_FP8_E4M3FNUZ: torch.float8_e4m3fnuz, DT_FP8_E5M2: torch.float8_e5m2,
+               DT_FP8_E5M2FNUZ: torch.float8_e5m2fnuz, DT_I8: torch.int8, DT_I16: torch.int16,
+               DT_I32: torch.int32, DT_I64: torch.int64}
+ELEM_SIZE = {dt: torch.empty(0, dtype=t).element_size() for dt, t in TORCH_DTYPE.items()}
+FP8_TYPES = (torch.float8_e4m3fn, torch.float8_e4m3fnuz, torch.float8_e5m2, torch.float8_e5m2fnuz)
+INT_TYPES = (torch.int8, torch.int16, torch.int32, torch.int64)
+# one NaN encoding per fp8 format (E4M3FN: S.1111.111; E5M2: exponent 31 with a
+# non-zero mantissa; the FNUZ formats: 0x80, their only NaN)
+FP8_NAN = {torch.float8_e4m3fn: 0x7F, torch.float8_e4m3fnuz: 0x80, torch.float8_e5m2: 0x7E,
+           torch.float8_e5m2fnuz: 0x80}
 
 
 # --------------------------------------------------------------------------
@@ -242,28 +253,41 @@ def c1_snapshot(device="cpu", scale: float = 1.0, seed: int = 1) -> SnapshotCase
 # perturbation by k ULP (library nextafter / sorted fp8 code table)
 # --------------------------------------------------------------------------
 
-def _fp8_tables():
-    codes = torch.arange(256, dtype=torch.uint8)
-    vals = codes.view(torch.float8_e4m3fn).to(torch.float32)
-    keep = [c for c in range(256) if not math.isnan(vals[c].item()) and c != 0x80]
-    order = sorted(keep, key=lambda c: vals[c].item())
-    code_of_rank = torch.tensor(order, dtype=torch.uint8)
-    rank_of_code = torch.full((256,), -1, dtype=torch.int64)
-    for r, c in enumerate(order):
-        rank_of_code[c] = r
-    rank_of_code[0x80] = rank_of_code[0x00]  # -0 sits where +0 does
-    return code_of_rank, rank_of_code
+_FP8_TABLES = {}
+
+
+def _fp8_tables(tdtype=torch.float8_e4m3fn):
+    """Codes of an fp8 format sorted by their torch-decoded value (NaNs left
+    out, -0 sharing the rank of +0), and the rank of every code (-1: NaN)."""
+    if tdtype not in _FP8_TABLES:
+        codes = torch.arange(256, dtype=torch.uint8)
+        vals = codes.view(tdtype).to(torch.float32)
+        keep = [c for c in range(256) if not math.isnan(vals[c].item())
+                and not (vals[c].item() == 0.0 and c != 0)]
+        order = sorted(keep, key=lambda c: vals[c].item())
+        code_of_rank = torch.tensor(order, dtype=torch.uint8)
+        rank_of_code = torch.full((256,), -1, dtype=torch.int64)
+        for r, c in enumerate(order):
+            rank_of_code[c] = r
+        for c in range(256):  # -0 sits where +0 does
+            if vals[c].item() == 0.0:
+                rank_of_code[c] = rank_of_code[0]
+        _FP8_TABLES[tdtype] = (code_of_rank, rank_of_code)
+    return _FP8_TABLES[tdtype]
 
 
 def step_ulps(vals: torch.Tensor, k: torch.Tensor) -> torch.Tensor:
     """Move each element |k| representable values toward sign(k) * inf
     (CPU tensors).  fp32/bf16/fp16 use ``torch.nextafter``."""
     k = k.to(torch.int64)
-    if vals.dtype == torch.float8_e4m3fn:
-        code_of_rank, rank_of_code = _fp8_tables()
+    if vals.dtype in FP8_TYPES:
+        code_of_rank, rank_of_code = _fp8_tables(vals.dtype)
         r = rank_of_code[vals.view(torch.uint8).to(torch.int64)] + k
         r = r.clamp(0, len(code_of_rank) - 1)
-        return code_of_rank[r].view(torch.float8_e4m3fn)
+        return code_of_rank[r].view(vals.dtype)
+    if vals.dtype in INT_TYPES:  # integers: one step is one unit
+        info = torch.iinfo(vals.dtype)
+        return (vals.to(torch.int64) + k).clamp(info.min, info.max).to(vals.dtype)
     out = vals.clone()
     up = torch.full_like(out, float("inf"))
     down = torch.full_like(out, float("-inf"))
@@ -301,8 +325,10 @@ def perturb_pair(gold: torch.Tensor, dtype: int, rng: np.random.Generator, n_per
         cand[idx] = moved
     if n_nan:
         idx = torch.from_numpy(nan_pos).to(gold.device)
-        if dtype == DT_FP8:
-            cand.view(torch.uint8)[idx] = 0x7F
+        if gold.dtype in FP8_TYPES:
+            cand.view(torch.uint8)[idx] = FP8_NAN[gold.dtype]
+        elif gold.dtype in INT_TYPES:
+            raise ValueError("integers have no NaN")
         else:
             cand[idx] = float("nan")
     return ComparePair(gold, cand, dtype, ulp_tol, pos, k, nan_pos)
@@ -571,10 +597,10 @@ def c5_requests(rate_hz: float = 200.0, duration_s: float = 30.0, seed: int = 5,
 _FP8_DEV = {}
 
 
-def _fp8_tables_on(device):
-    key = str(device)
+def _fp8_tables_on(device, tdtype=torch.float8_e4m3fn):
+    key = (str(device), tdtype)
     if key not in _FP8_DEV:
-        c, r = _fp8_tables()
+        c, r = _fp8_tables(tdtype)
         _FP8_DEV[key] = (c.to(device), r.to(device))
     return _FP8_DEV[key]
 
@@ -621,10 +647,14 @@ def perturb_many(arena: torch.Tensor, dtype: int, offsets, lengths, seeds, p_per
     k = 1 + (h2 % kmax)
     k = torch.where(((h2 >> 20) & 1) == 1, -k, k)
     vals = arena[pos]
-    if dtype == DT_FP8:
-        code_of_rank, rank_of_code = _fp8_tables_on(dev)
+    if arena.dtype in FP8_TYPES:
+        code_of_rank, rank_of_code = _fp8_tables_on(dev, arena.dtype)
         r = (rank_of_code[vals.view(torch.uint8).to(torch.int64)] + k).clamp(0, len(code_of_rank) - 1)
-        arena[pos] = code_of_rank[r].view(torch.float8_e4m3fn)
+        arena[pos] = code_of_rank[r].view(arena.dtype)
+        return
+    if arena.dtype in INT_TYPES:
+        info = torch.iinfo(arena.dtype)
+        arena[pos] = (vals.to(torch.int64) + k).clamp(info.min, info.max).to(arena.dtype)
         return
     target = torch.where(k > 0, torch.full_like(vals, float("inf")), torch.full_like(vals, float("-inf")))
     for i in range(kmax):

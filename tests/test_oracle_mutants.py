@@ -30,14 +30,28 @@ MUTANTS = {
                             "if (va - ranges[lo].base <= ranges[lo].size) return (int64_t)lo;"),
     "adjacent ranges rejected": ("if (base < prev_end) return KCO_EORDER;", "if (base <= prev_end) return KCO_EORDER;"),
     "window margin 2 GiB": ("const uint64_t margin = 1ULL << 32;", "const uint64_t margin = 1ULL << 31;"),
-    "ulp ignores cand sign": ("if (cand_bits & sign) oc = -oc;", ""),
-    "log bins shifted": ("return 12u + k;", "return 11u + k;"),
-    "rel includes zero golds": ("if (vg != 0.0 && !isinf(vg)) {", "if (!isinf(vg)) {"),
+    "ulp ignores cand sign": ("int sc = (cand_bits & sb) != 0,", "int sc = 0,"),
+    "log bins shifted": ("return 12u + k < 47u ? 12u + k : 47u;", "return 11u + k < 47u ? 11u + k : 47u;"),
+    "rel includes zero golds": ("if (vg != 0.0 && !is_inf_value(dtype, vg)) {", "if (!is_inf_value(dtype, vg)) {"),
     "last mismatch kept": ("if (res->first_mismatch == UINT64_MAX) res->first_mismatch = i;", "res->first_mismatch = i;"),
     "byte count per element": ("if (pc[b] != pg[b]) res->n_mismatch_bytes += 1;", "res->n_mismatch_bytes += 1;"),
     "NaN payloads split both-NaN": ("if (nan_c && nan_g) {", "if (nan_c && nan_g && c == g) {"),
-    "fp16 exponent bias": ("v = ldexp((double)(m | 0x400u), (int)e - 25);", "v = ldexp((double)(m | 0x400u), (int)e - 24);"),
-    "fp8 subnormal scale": ("v = ldexp((double)m, -9);", "v = ldexp((double)m, -10);"),
+    "fp16 exponent bias": ("small_float(e, m, 10, 15)", "small_float(e, m, 10, 14)"),
+    "subnormal scale": ("if (e == 0) return ldexp((double)m, 1 - bias - mbits);",
+                        "if (e == 0) return ldexp((double)m, -bias - mbits);"),
+    "e4m3fnuz bias 7": ("small_float((uint32_t)mag >> 3, (uint32_t)mag & 0x7u, 3, 8)",
+                        "small_float((uint32_t)mag >> 3, (uint32_t)mag & 0x7u, 3, 7)"),
+    "e5m2fnuz bias 15": ("small_float((uint32_t)mag >> 2, (uint32_t)mag & 0x3u, 2, 16)",
+                         "small_float((uint32_t)mag >> 2, (uint32_t)mag & 0x3u, 2, 15)"),
+    "e5m2 without infinities": ("v = e == 31 ? INFINITY : small_float(e, m, 2, 15);", "v = small_float(e, m, 2, 15);"),
+    "fnuz NaN by magnitude": ("case KCO_FP8_E4M3FNUZ: case KCO_FP8_E5M2FNUZ: return bits == 0x80u;",
+                              "case KCO_FP8_E4M3FNUZ: case KCO_FP8_E5M2FNUZ: return mag == 0x7Fu;"),
+    "f64 inf taken for NaN": ("case KCO_F64: return mag > 0x7FF0000000000000ULL;",
+                              "case KCO_F64: return mag >= 0x7FF0000000000000ULL;"),
+    "integers not sign-extended": ("if ((c >> (nb - 1)) & 1u) c |= ~0ULL << nb;", ""),
+    "integer order unsigned": ("*dist = ci >= gi ? c - g : g - c;", "*dist = c >= g ? c - g : g - c;"),
+    "integer error by fp64 subtraction": ("abs_err = (double)d; /* exact difference, one rounding */",
+                                          "abs_err = fabs(vc - vg);"),
     "tolerance inclusive": ("if (d > ulp_tol) res->n_over_tol += 1;", "if (d >= ulp_tol) res->n_over_tol += 1;"),
     "rtol scales the candidate": ("close = abs_err <= atol + rtol * fabs(vg);", "close = abs_err <= atol + rtol * fabs(vc);"),
     "infinities always close": ("close = vc == vg;", "close = 1;"),
