@@ -67,13 +67,24 @@ enum {
   KC_ELIMIT = -7   /* a documented size limit is exceeded                  */
 };
 
-/* Element types understood by kc_compare. */
+/* Element types understood by kc_compare.  Floating types get the ULP
+ * distance (steps between the two encodings in sign-magnitude order, +0 and
+ * -0 coinciding) and NaN classes; integer types get the exact difference
+ * |c - g| as their distance and have no NaN; KC_U8 is compared bytewise only. */
 enum {
-  KC_F32 = 0,         /* IEEE binary32                                       */
-  KC_BF16 = 1,        /* bfloat16 (upper half of binary32)                   */
-  KC_F16 = 2,         /* IEEE binary16                                       */
-  KC_FP8_E4M3FN = 3,  /* OCP fp8 E4M3 "fn": bias 7, no inf, NaN = S.1111.111 */
-  KC_U8 = 4           /* raw bytes                                           */
+  KC_F32 = 0,            /* IEEE binary32                                     */
+  KC_BF16 = 1,           /* bfloat16 (upper half of binary32)                 */
+  KC_F16 = 2,            /* IEEE binary16                                     */
+  KC_FP8_E4M3FN = 3,     /* OCP fp8 E4M3: bias 7, no inf, NaN = S.1111.111    */
+  KC_U8 = 4,             /* raw bytes                                         */
+  KC_F64 = 5,            /* IEEE binary64                                     */
+  KC_FP8_E4M3FNUZ = 6,   /* fp8 E4M3 FNUZ: bias 8, no inf, no -0, NaN = 0x80  */
+  KC_FP8_E5M2 = 7,       /* OCP fp8 E5M2: bias 15, IEEE-style inf and NaN     */
+  KC_FP8_E5M2FNUZ = 8,   /* fp8 E5M2 FNUZ: bias 16, no inf, no -0, NaN = 0x80 */
+  KC_I8 = 9,             /* two's complement integers                         */
+  KC_I16 = 10,
+  KC_I32 = 11,
+  KC_I64 = 12
 };
 
 typedef struct kc_ctx kc_ctx;
@@ -134,9 +145,11 @@ typedef struct {
   uint64_t n_nan_cand_only;  /* fails, excluded from the rest              */
   uint64_t n_nan_gold_only;  /* fails, excluded from the rest              */
   uint64_t n_over_tol;       /* non-NaN elements with ULP distance > tol   */
-  double max_abs;            /* max |c - g| in fp64 over non-NaN elements  */
+  double max_abs;            /* max |c - g| in fp64 over non-NaN elements
+                                (integers: exact difference, rounded once) */
   double max_rel;            /* max |c - g| / |g| over finite non-zero g   */
-  uint64_t ulp_hist[48];     /* bin d for d <= 16, else 12 + ceil(log2 d)  */
+  uint64_t ulp_hist[48];     /* bin d for d <= 16, else
+                                min(12 + ceil(log2 d), 47)                 */
   uint32_t pass;             /* no over-tolerance element and no lone NaN;
                                 KC_U8: no differing byte                   */
   uint32_t status;           /* 0                                          */

@@ -499,7 +499,12 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
 namespace {
 
 uint32_t elem_size(uint32_t dtype) {
-  return dtype == KC_F32 ? 4u : (dtype == KC_BF16 || dtype == KC_F16 ? 2u : 1u);
+  switch (dtype) {
+    case KC_F64: case KC_I64: return 8u;
+    case KC_F32: case KC_I32: return 4u;
+    case KC_BF16: case KC_F16: case KC_I16: return 2u;
+    default: return 1u;
+  }
 }
 
 // Validate a pair list and count its tiles.
@@ -507,7 +512,7 @@ int plan_pairs(const kc_pair* pairs, uint32_t n_pairs, uint32_t tile_bytes, std:
   tile_off.assign(n_pairs + 1, 0);
   for (uint32_t i = 0; i < n_pairs; ++i) {
     const kc_pair& pr = pairs[i];
-    if (pr.dtype > KC_U8) return KC_EDTYPE;
+    if (pr.dtype > KC_I64) return KC_EDTYPE;
     if (pr.n_elems > (1ull << 60)) return KC_ELIMIT;
     if (!(pr.atol >= 0.0) || !(pr.rtol >= 0.0)) return KC_EINVAL;  // negative or NaN tolerances
     if (pr.n_elems > 0) {

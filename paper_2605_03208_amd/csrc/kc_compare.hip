@@ -17,65 +17,148 @@ namespace {
 
 constexpr uint32_t kThreads = 256;
 constexpr uint32_t kUnroll = 4;
-constexpr uint32_t kBins = 45;
+constexpr uint32_t kBins = 48;
 
+// Element formats.  B holds one element's encoding; kind 0 = floating point
+// in sign-magnitude order, 1 = two's complement integer, 2 = raw bytes.
 template <uint32_t DT> struct Fmt;
 template <> struct Fmt<KC_F32> {
-  static constexpr uint32_t size = 4, mag = 0x7FFFFFFFu, sign = 0x80000000u;
-  __device__ static bool nan(uint32_t b) { return (b & mag) > 0x7F800000u; }
-  __device__ static double value(uint32_t b) { return (double)__uint_as_float(b); }
-  __device__ static bool inf(uint32_t b) { return (b & mag) == 0x7F800000u; }
+  using B = uint32_t;
+  static constexpr uint32_t size = 4, kind = 0;
+  static constexpr B mag = 0x7FFFFFFFu;
+  __device__ static bool nan(B b) { return (b & mag) > 0x7F800000u; }
+  __device__ static bool inf(B b) { return (b & mag) == 0x7F800000u; }
+  __device__ static double value(B b) { return (double)__uint_as_float(b); }
+};
+template <> struct Fmt<KC_F64> {
+  using B = uint64_t;
+  static constexpr uint32_t size = 8, kind = 0;
+  static constexpr B mag = 0x7FFFFFFFFFFFFFFFull;
+  __device__ static bool nan(B b) { return (b & mag) > 0x7FF0000000000000ull; }
+  __device__ static bool inf(B b) { return (b & mag) == 0x7FF0000000000000ull; }
+  __device__ static double value(B b) { return __longlong_as_double((long long)b); }
 };
 template <> struct Fmt<KC_BF16> {
-  static constexpr uint32_t size = 2, mag = 0x7FFFu, sign = 0x8000u;
-  __device__ static bool nan(uint32_t b) { return (b & mag) > 0x7F80u; }
-  __device__ static double value(uint32_t b) { return (double)__uint_as_float(b << 16); }
-  __device__ static bool inf(uint32_t b) { return (b & mag) == 0x7F80u; }
+  using B = uint32_t;
+  static constexpr uint32_t size = 2, kind = 0;
+  static constexpr B mag = 0x7FFFu;
+  __device__ static bool nan(B b) { return (b & mag) > 0x7F80u; }
+  __device__ static bool inf(B b) { return (b & mag) == 0x7F80u; }
+  __device__ static double value(B b) { return (double)__uint_as_float(b << 16); }
 };
+// value of a finite small-float encoding: subnormal when the exponent is 0
+__device__ __forceinline__ double small_value(uint32_t e, uint32_t m, uint32_t mbits, int bias) {
+  return e == 0u ? (double)m * __builtin_ldexp(1.0, 1 - bias - (int)mbits)
+                 : (double)(m | (1u << mbits)) * __builtin_ldexp(1.0, (int)e - bias - (int)mbits);
+}
 template <> struct Fmt<KC_F16> {
-  static constexpr uint32_t size = 2, mag = 0x7FFFu, sign = 0x8000u;
-  __device__ static bool nan(uint32_t b) { return (b & mag) > 0x7C00u; }
-  __device__ static bool inf(uint32_t b) { return (b & mag) == 0x7C00u; }
-  __device__ static double value(uint32_t b) {
-    const uint32_t e = (b >> 10) & 0x1Fu, m = b & 0x3FFu;
-    double v;
-    if (e == 0u) v = (double)m * 0x1p-24;                      // subnormal: m * 2^-24
-    else if (e == 31u) v = __builtin_inf();                       // NaN never decoded
-    else v = (double)(m | 0x400u) * __builtin_ldexp(1.0, (int)e - 25);
-    return (b & sign) ? -v : v;
+  using B = uint32_t;
+  static constexpr uint32_t size = 2, kind = 0;
+  static constexpr B mag = 0x7FFFu;
+  __device__ static bool nan(B b) { return (b & mag) > 0x7C00u; }
+  __device__ static bool inf(B b) { return (b & mag) == 0x7C00u; }
+  __device__ static double value(B b) {
+    const uint32_t e = (b >> 10) & 0x1Fu;
+    const double v = e == 31u ? __builtin_inf() : small_value(e, b & 0x3FFu, 10, 15);  // NaN never decoded
+    return (b & 0x8000u) ? -v : v;
   }
 };
 template <> struct Fmt<KC_FP8_E4M3FN> {
-  static constexpr uint32_t size = 1, mag = 0x7Fu, sign = 0x80u;
-  __device__ static bool nan(uint32_t b) { return (b & mag) == 0x7Fu; }
-  __device__ static bool inf(uint32_t) { return false; }
-  __device__ static double value(uint32_t b) {
-    const uint32_t e = (b >> 3) & 0xFu, m = b & 0x7u;
-    const double v = e == 0u ? (double)m * 0x1p-9 : (double)(m | 0x8u) * __builtin_ldexp(1.0, (int)e - 10);
-    return (b & sign) ? -v : v;
+  using B = uint32_t;
+  static constexpr uint32_t size = 1, kind = 0;
+  static constexpr B mag = 0x7Fu;
+  __device__ static bool nan(B b) { return (b & mag) == 0x7Fu; }
+  __device__ static bool inf(B) { return false; }
+  __device__ static double value(B b) {
+    const double v = small_value((b >> 3) & 0xFu, b & 0x7u, 3, 7);
+    return (b & 0x80u) ? -v : v;
   }
 };
+template <> struct Fmt<KC_FP8_E4M3FNUZ> {
+  using B = uint32_t;
+  static constexpr uint32_t size = 1, kind = 0;
+  static constexpr B mag = 0x7Fu;
+  __device__ static bool nan(B b) { return b == 0x80u; }
+  __device__ static bool inf(B) { return false; }
+  __device__ static double value(B b) {
+    const double v = small_value((b >> 3) & 0xFu, b & 0x7u, 3, 8);
+    return (b & 0x80u) ? -v : v;
+  }
+};
+template <> struct Fmt<KC_FP8_E5M2> {
+  using B = uint32_t;
+  static constexpr uint32_t size = 1, kind = 0;
+  static constexpr B mag = 0x7Fu;
+  __device__ static bool nan(B b) { return (b & mag) > 0x7Cu; }
+  __device__ static bool inf(B b) { return (b & mag) == 0x7Cu; }
+  __device__ static double value(B b) {
+    const uint32_t e = (b >> 2) & 0x1Fu;
+    const double v = e == 31u ? __builtin_inf() : small_value(e, b & 0x3u, 2, 15);
+    return (b & 0x80u) ? -v : v;
+  }
+};
+template <> struct Fmt<KC_FP8_E5M2FNUZ> {
+  using B = uint32_t;
+  static constexpr uint32_t size = 1, kind = 0;
+  static constexpr B mag = 0x7Fu;
+  __device__ static bool nan(B b) { return b == 0x80u; }
+  __device__ static bool inf(B) { return false; }
+  __device__ static double value(B b) {
+    const double v = small_value((b >> 2) & 0x1Fu, b & 0x3u, 2, 16);
+    return (b & 0x80u) ? -v : v;
+  }
+};
+template <uint32_t SIZE, typename BT> struct IntFmt {
+  using B = BT;
+  static constexpr uint32_t size = SIZE, kind = 1;
+  static constexpr B mag = 0;
+  __device__ static bool nan(B) { return false; }
+  __device__ static bool inf(B) { return false; }
+  __device__ static int64_t sext(B b) {
+    if (SIZE == 1) return (int64_t)(int8_t)(uint8_t)b;
+    if (SIZE == 2) return (int64_t)(int16_t)(uint16_t)b;
+    if (SIZE == 4) return (int64_t)(int32_t)(uint32_t)b;
+    return (int64_t)b;
+  }
+  __device__ static double value(B b) { return (double)sext(b); }
+};
+template <> struct Fmt<KC_I8> : IntFmt<1, uint32_t> {};
+template <> struct Fmt<KC_I16> : IntFmt<2, uint32_t> {};
+template <> struct Fmt<KC_I32> : IntFmt<4, uint32_t> {};
+template <> struct Fmt<KC_I64> : IntFmt<8, uint64_t> {};
 template <> struct Fmt<KC_U8> {
-  static constexpr uint32_t size = 1, mag = 0xFFu, sign = 0u;
-  __device__ static bool nan(uint32_t) { return false; }
-  __device__ static bool inf(uint32_t) { return false; }
-  __device__ static double value(uint32_t) { return 0.0; }
+  using B = uint32_t;
+  static constexpr uint32_t size = 1, kind = 2;
+  static constexpr B mag = 0xFFu;
+  __device__ static bool nan(B) { return false; }
+  __device__ static bool inf(B) { return false; }
+  __device__ static double value(B) { return 0.0; }
 };
 
-// Any NaN encoding in a 32-bit word of packed elements.
-template <uint32_t DT> __device__ __forceinline__ bool word_has_nan(uint32_t w);
-template <> __device__ __forceinline__ bool word_has_nan<KC_F32>(uint32_t w) { return (w & 0x7FFFFFFFu) > 0x7F800000u; }
-template <> __device__ __forceinline__ bool word_has_nan<KC_BF16>(uint32_t w) {
-  return (w & 0x7FFFu) > 0x7F80u || ((w >> 16) & 0x7FFFu) > 0x7F80u;
+// Zero byte anywhere in a 32-bit word.
+__device__ __forceinline__ bool has_zero_byte(uint32_t y) { return ((y - 0x01010101u) & ~y & 0x80808080u) != 0u; }
+
+// Any NaN encoding among the elements packed in 16 bytes.
+template <uint32_t DT> __device__ __forceinline__ bool vec_has_nan(const uint4& v) {
+  if (Fmt<DT>::kind != 0) return false;
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t x = w[i];
+    if (DT == KC_F32) any |= (x & 0x7FFFFFFFu) > 0x7F800000u;
+    if (DT == KC_BF16) any |= (x & 0x7FFFu) > 0x7F80u || ((x >> 16) & 0x7FFFu) > 0x7F80u;
+    if (DT == KC_F16) any |= (x & 0x7FFFu) > 0x7C00u || ((x >> 16) & 0x7FFFu) > 0x7C00u;
+    if (DT == KC_FP8_E4M3FN) any |= has_zero_byte((x & 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu);  // magnitude 0x7F
+    if (DT == KC_FP8_E4M3FNUZ || DT == KC_FP8_E5M2FNUZ) any |= has_zero_byte(x ^ 0x80808080u);  // byte 0x80
+    if (DT == KC_FP8_E5M2) any |= (((x & 0x7F7F7F7Fu) + 0x03030303u) & 0x80808080u) != 0u;    // magnitude > 0x7C
+    if (DT == KC_F64 && (i & 1)) {  // high word of a binary64 element
+      const uint32_t hi = x & 0x7FFFFFFFu;
+      any |= hi > 0x7FF00000u || (hi == 0x7FF00000u && w[i - 1] != 0u);
+    }
+  }
+  return any;
 }
-template <> __device__ __forceinline__ bool word_has_nan<KC_F16>(uint32_t w) {
-  return (w & 0x7FFFu) > 0x7C00u || ((w >> 16) & 0x7FFFu) > 0x7C00u;
-}
-template <> __device__ __forceinline__ bool word_has_nan<KC_FP8_E4M3FN>(uint32_t w) {
-  const uint32_t y = (w & 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;  // zero byte where magnitude is 0x7F
-  return ((y - 0x01010101u) & ~y & 0x80808080u) != 0u;
-}
-template <> __device__ __forceinline__ bool word_has_nan<KC_U8>(uint32_t) { return false; }
 
 struct Partial {
   uint32_t mis_elems, mis_bytes, nan_both, nan_c, nan_g, over, not_close;
@@ -90,26 +173,29 @@ struct Tol {
 
 __device__ __forceinline__ uint32_t ulp_bin(uint64_t d) {
   if (d <= 16u) return (uint32_t)d;
-  return 12u + (64u - (uint32_t)__clzll(d - 1ull));  // 12 + ceil(log2 d)
+  const uint32_t b = 12u + (64u - (uint32_t)__clzll(d - 1ull));  // 12 + ceil(log2 d)
+  return b < kBins - 1u ? b : kBins - 1u;
 }
 
-__device__ __forceinline__ uint32_t diff_bytes(uint32_t a, uint32_t b) {
-  const uint32_t x = a ^ b;
-  return (uint32_t)((x & 0xFFu) != 0u) + (uint32_t)((x & 0xFF00u) != 0u) + (uint32_t)((x & 0xFF0000u) != 0u) +
-         (uint32_t)((x & 0xFF000000u) != 0u);
+template <typename B> __device__ __forceinline__ uint32_t diff_bytes(B a, B b) {
+  const B x = a ^ b;
+  uint32_t n = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(B); ++i) n += (uint32_t)(((x >> (8u * i)) & 0xFFu) != 0u);
+  return n;
 }
 
 // Exact per-element path.
 template <uint32_t DT>
-__device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, const Tol& tol, Partial& p,
-                                        uint32_t* hist) {
+__device__ __forceinline__ void element(typename Fmt<DT>::B c, typename Fmt<DT>::B g, uint64_t idx, const Tol& tol,
+                                        Partial& p, uint32_t* hist) {
   using F = Fmt<DT>;
   if (c != g) {
     ++p.mis_elems;
     p.mis_bytes += diff_bytes(c, g);
     if (idx < p.first) p.first = idx;
   }
-  if (DT == KC_U8) return;
+  if constexpr (F::kind == 2) return;
   const bool nc = F::nan(c), ng = F::nan(g);
   if (nc || ng) {
     if (nc && ng) ++p.nan_both;
@@ -117,14 +203,20 @@ __device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, co
     else ++p.nan_g;
     return;
   }
-  const int64_t oc = (c & F::sign) ? -(int64_t)(c & F::mag) : (int64_t)(c & F::mag);
-  const int64_t og = (g & F::sign) ? -(int64_t)(g & F::mag) : (int64_t)(g & F::mag);
-  const uint64_t d = (uint64_t)(oc > og ? oc - og : og - oc);
+  uint64_t d;
+  if constexpr (F::kind == 1) {
+    const int64_t ci = F::sext(c), gi = F::sext(g);
+    d = ci >= gi ? (uint64_t)ci - (uint64_t)gi : (uint64_t)gi - (uint64_t)ci;  // exact below 2^64
+  } else {
+    constexpr typename F::B sb = (typename F::B)1 << (8u * F::size - 1u);
+    const uint64_t mc = (uint64_t)(c & F::mag), mg = (uint64_t)(g & F::mag);
+    d = ((c ^ g) & sb) == 0 ? (mc > mg ? mc - mg : mg - mc) : mc + mg;  // across zero: the two magnitudes
+  }
   if (d > tol.ulp) ++p.over;
   if (d != 0u) atomicAdd(&hist[ulp_bin(d)], 1u);
   if (c == g) return;
   const double vc = F::value(c), vg = F::value(g);
-  const double a = __builtin_fabs(vc - vg);
+  const double a = F::kind == 1 ? (double)d : __builtin_fabs(vc - vg);
   if (a > p.max_abs) p.max_abs = a;
   if (vg != 0.0 && !F::inf(g)) {
     const double r = a / __builtin_fabs(vg);
@@ -140,11 +232,16 @@ __device__ __forceinline__ void element(uint32_t c, uint32_t g, uint64_t idx, co
 }
 
 template <uint32_t DT>
-__device__ __forceinline__ uint32_t elem_of(const uint4& v, uint32_t e) {
-  const uint32_t w = e * Fmt<DT>::size / 4u;
+__device__ __forceinline__ typename Fmt<DT>::B elem_of(const uint4& v, uint32_t e) {
+  constexpr uint32_t sz = Fmt<DT>::size;
+  if (sz == 8) {
+    return e == 0 ? (typename Fmt<DT>::B)(((uint64_t)v.y << 32) | v.x)
+                  : (typename Fmt<DT>::B)(((uint64_t)v.w << 32) | v.z);
+  }
+  const uint32_t w = e * sz / 4u;
   const uint32_t word = w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
-  if (Fmt<DT>::size == 4) return word;
-  if (Fmt<DT>::size == 2) return (e & 1u) ? (word >> 16) : (word & 0xFFFFu);
+  if (sz == 4) return word;
+  if (sz == 2) return (e & 1u) ? (word >> 16) : (word & 0xFFFFu);
   return (word >> (8u * (e & 3u))) & 0xFFu;
 }
 
@@ -152,8 +249,7 @@ template <uint32_t DT>
 __device__ __forceinline__ void vec16(const uint4& c, const uint4& g, uint64_t e0, const Tol& tol, Partial& p,
                                       uint32_t* hist) {
   const bool eq = c.x == g.x && c.y == g.y && c.z == g.z && c.w == g.w;
-  if (eq && !(word_has_nan<DT>(g.x) || word_has_nan<DT>(g.y) || word_has_nan<DT>(g.z) || word_has_nan<DT>(g.w)))
-    return;
+  if (eq && !vec_has_nan<DT>(g)) return;
   constexpr uint32_t epv = 16u / Fmt<DT>::size;
 #pragma unroll
   for (uint32_t e = 0; e < epv; ++e) element<DT>(elem_of<DT>(c, e), elem_of<DT>(g, e), e0 + e, tol, p, hist);
@@ -161,6 +257,7 @@ __device__ __forceinline__ void vec16(const uint4& c, const uint4& g, uint64_t e
 
 template <uint32_t DT>
 __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uint64_t b1, Partial& p, uint32_t* hist) {
+  using B = typename Fmt<DT>::B;
   constexpr uint32_t es = Fmt<DT>::size;
   const uint64_t nvec = (b1 - b0) / 16u;
   const uint32_t tid = threadIdx.x;
@@ -184,10 +281,10 @@ __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uin
   // bytes past the last whole 16-byte run: element by element
   if (tid == 0) {
     for (uint64_t b = b0 + nvec * 16u; b < b1; b += es) {
-      uint32_t cv = 0, gv = 0;
+      B cv = 0, gv = 0;
       for (uint32_t i = 0; i < es; ++i) {
-        cv |= (uint32_t)pr.cand[b + i] << (8u * i);
-        gv |= (uint32_t)pr.gold[b + i] << (8u * i);
+        cv |= (B)pr.cand[b + i] << (8u * i);
+        gv |= (B)pr.gold[b + i] << (8u * i);
       }
       element<DT>(cv, gv, b / es, tol, p, hist);
     }
@@ -233,6 +330,14 @@ __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const 
         case KC_BF16: tile_body<KC_BF16>(pr, b0, b1, p, hist); break;
         case KC_F16: tile_body<KC_F16>(pr, b0, b1, p, hist); break;
         case KC_FP8_E4M3FN: tile_body<KC_FP8_E4M3FN>(pr, b0, b1, p, hist); break;
+        case KC_F64: tile_body<KC_F64>(pr, b0, b1, p, hist); break;
+        case KC_FP8_E4M3FNUZ: tile_body<KC_FP8_E4M3FNUZ>(pr, b0, b1, p, hist); break;
+        case KC_FP8_E5M2: tile_body<KC_FP8_E5M2>(pr, b0, b1, p, hist); break;
+        case KC_FP8_E5M2FNUZ: tile_body<KC_FP8_E5M2FNUZ>(pr, b0, b1, p, hist); break;
+        case KC_I8: tile_body<KC_I8>(pr, b0, b1, p, hist); break;
+        case KC_I16: tile_body<KC_I16>(pr, b0, b1, p, hist); break;
+        case KC_I32: tile_body<KC_I32>(pr, b0, b1, p, hist); break;
+        case KC_I64: tile_body<KC_I64>(pr, b0, b1, p, hist); break;
         default: tile_body<KC_U8>(pr, b0, b1, p, hist); break;
       }
     }

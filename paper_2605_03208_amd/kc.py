@@ -19,10 +19,13 @@ ABI_VERSION = 2  # layout of the structs below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
+F64, FP8_E4M3FNUZ, FP8_E5M2, FP8_E5M2FNUZ, I8, I16, I32, I64 = 5, 6, 7, 8, 9, 10, 11, 12
+TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, torch.float8_e4m3fn: FP8_E4M3FN,
+               torch.uint8: U8, torch.float64: F64, torch.float8_e4m3fnuz: FP8_E4M3FNUZ,
+               torch.float8_e5m2: FP8_E5M2, torch.float8_e5m2fnuz: FP8_E5M2FNUZ, torch.int8: I8,
+               torch.int16: I16, torch.int32: I32, torch.int64: I64}
+ELEM_SIZE = {k: torch.empty(0, dtype=t).element_size() for t, k in TORCH_TO_KC.items()}
 OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE = range(6)
-ELEM_SIZE = {F32: 4, BF16: 2, F16: 2, FP8_E4M3FN: 1, U8: 1}
-TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16,
-               torch.float8_e4m3fn: FP8_E4M3FN, torch.uint8: U8}
 
 SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "kc_default_window",
            "kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_tuning", "kc_ctx_get_tuning",

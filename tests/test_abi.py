@@ -76,3 +76,21 @@ def test_missing_library_fails_loudly(kc, monkeypatch, tmp_path):
     monkeypatch.setattr(K, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         K.lib()
+
+
+def test_binding_constants_match_header(kc):
+    """Element-type, status and op codes in the binding are the header's."""
+    text = open(os.path.join(ROOT, "include", "kc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    enum = {k: int(v) for k, v in re.findall(r"\b(KC_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    dts = [k for k in enum if k[3:] in ("F32", "BF16", "F16", "U8", "F64", "I8", "I16", "I32", "I64")
+           or k.startswith("KC_FP8")]
+    assert len(dts) == 13
+    for k in dts:
+        assert getattr(kc, k[3:]) == enum[k], k
+        assert k[3:] in {name for name in dir(kc)}
+    assert sorted(kc.TORCH_TO_KC.values()) == sorted(enum[k] for k in dts)
+    for k in ("OK", "EINVAL", "EALIGN", "EORDER", "ENOMEM", "EHIP", "EDTYPE", "ELIMIT"):
+        assert getattr(kc, k) == enum["KC_" + k]
+    for k in ("PAGE_HASH", "SNAPSHOT", "COMPACT", "RESTORE", "CLOSURE", "COMPARE"):
+        assert getattr(kc, "OP_" + k) == enum["KC_OP_" + k]

@@ -307,42 +307,84 @@ def test_compare_c1_pairs(kc, ctx):
         assert r["n_mismatch_elems"] == 1049 + 2 and r["n_nan_cand_only"] == 2 and r["pass"] == 0
 
 
+SPECIALS = {  # NaN, inf / max, -inf / -max, smallest subnormal, -0 / 0, largest finite ...
+    W.DT_F32: [0x7FC00000, 0x7F800000, 0xFF800000, 0x00000001, 0x80000000, 0x7F7FFFFF],
+    W.DT_BF16: [0x7FC0, 0x7F80, 0xFF80, 0x0001, 0x8000, 0x7F7F],
+    W.DT_F16: [0x7E00, 0x7C00, 0xFC00, 0x0001, 0x8000, 0x7BFF],
+    W.DT_FP8: [0x7F, 0xFF, 0x7E, 0x01, 0x80, 0x00],
+    W.DT_F64: [0x7FF8000000000000, 0x7FF0000000000000, 0xFFF0000000000000, 0x1, 0x8000000000000000,
+               0x7FEFFFFFFFFFFFFF, 0x7FF0000000000001],
+    W.DT_FP8_E4M3FNUZ: [0x80, 0x7F, 0xFF, 0x01, 0x00, 0x08],
+    W.DT_FP8_E5M2: [0x7E, 0x7C, 0xFC, 0x01, 0x80, 0x7B, 0xFF],
+    W.DT_FP8_E5M2FNUZ: [0x80, 0x7F, 0xFF, 0x01, 0x00, 0x04],
+}
+for _dt, _t in ((W.DT_I8, torch.int8), (W.DT_I16, torch.int16), (W.DT_I32, torch.int32), (W.DT_I64, torch.int64)):
+    _i = torch.iinfo(_t)
+    _m = (1 << (8 * W.ELEM_SIZE[_dt])) - 1
+    SPECIALS[_dt] = [_i.min & _m, _i.max, _m, 0, 1, (_i.min + 1) & _m]
+ALL_DTS = [W.DT_F32, W.DT_BF16, W.DT_F16, W.DT_FP8, W.DT_U8, W.DT_F64, W.DT_FP8_E4M3FNUZ, W.DT_FP8_E5M2,
+           W.DT_FP8_E5M2FNUZ, W.DT_I8, W.DT_I16, W.DT_I32, W.DT_I64]
+BITS_VIEW = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}
+
+
 def _special_pair(dt, n, seed):
     rng = np.random.default_rng(seed)
     gen = torch.Generator(device="cuda").manual_seed(seed)
-    gold = torch.randn(n, device="cuda", generator=gen).to(W.TORCH_DTYPE[dt]) if dt != W.DT_U8 else \
-        torch.randint(0, 256, (n,), device="cuda", dtype=torch.uint8, generator=gen)
+    t = W.TORCH_DTYPE[dt]
+    es = W.ELEM_SIZE[dt]
+    if dt == W.DT_U8:
+        gold = torch.randint(0, 256, (n,), device="cuda", dtype=torch.uint8, generator=gen)
+    elif t in W.INT_TYPES:
+        hi = 100 if es == 1 else 1 << 20
+        gold = torch.randint(-hi, hi, (n,), device="cuda", dtype=torch.int64, generator=gen).to(t)
+    else:
+        gold = torch.randn(n, device="cuda", generator=gen, dtype=torch.float64).to(t)
     cand = gold.clone()
-    gb = gold.view(torch.uint8) if dt in (W.DT_FP8, W.DT_U8) else gold.view(torch.int16 if W.ELEM_SIZE[dt] == 2 else torch.int32)
+    gb = gold.view(BITS_VIEW[es])
     cb = cand.view(gb.dtype)
     m = max(1, n // 20)
     idx = torch.from_numpy(rng.choice(n, size=min(n, m), replace=False)).cuda()
-    flips = torch.from_numpy(rng.integers(1, 1 << (8 * W.ELEM_SIZE[dt] - 1), size=len(idx))).cuda().to(cb.dtype)
+    flips = torch.from_numpy(rng.integers(1, 1 << (8 * es - 1), size=len(idx))).cuda().to(cb.dtype)
     cb[idx] ^= flips          # arbitrary bit flips: NaNs, infs, sign changes, huge ULP distances
-    if n > 8 and dt not in (W.DT_U8,):
-        special = {W.DT_F32: [0x7FC00000, 0x7F800000, 0xFF800000, 0x00000001, 0x80000000, 0x7F7FFFFF],
-                   W.DT_BF16: [0x7FC0, 0x7F80, 0xFF80, 0x0001, 0x8000, 0x7F7F],
-                   W.DT_F16: [0x7E00, 0x7C00, 0xFC00, 0x0001, 0x8000, 0x7BFF],
-                   W.DT_FP8: [0x7F, 0xFF, 0x7E, 0x01, 0x80, 0x00]}[dt]
+    if n > 8 and dt != W.DT_U8:
+        special = SPECIALS[dt]
         for j, v in enumerate(special):
-            val = v if v < (1 << (8 * W.ELEM_SIZE[dt] - 1)) else v - (1 << (8 * W.ELEM_SIZE[dt]))
+            val = v if es == 1 or v < (1 << (8 * es - 1)) else v - (1 << (8 * es))
             gb[j] = val
             cb[(j + 1) % len(special)] = val
     return cand, gold
 
 
-@pytest.mark.parametrize("dt", [W.DT_F32, W.DT_BF16, W.DT_F16, W.DT_FP8, W.DT_U8])
+@pytest.mark.parametrize("dt", ALL_DTS)
 def test_compare_dtypes_specials_and_tails(kc, ctx, dt):
     say(f"compare dtype={dt}: bit flips, specials, ragged tails, empty")
     pairs = []
     for i, n in enumerate([0, 1, 3, 7, 8, 15, 16, 17, 255, 4096 + 5, 70001, 300007]):
-        es = W.ELEM_SIZE[dt]
-        n_al = n
-        c, g = _special_pair(dt, max(n_al, 1), 100 * dt + i)
-        c, g = c[:n_al], g[:n_al]
+        c, g = _special_pair(dt, max(n, 1), 100 * dt + i)
+        c, g = c[:n], g[:n]
         pairs.append((c, g, dt, int(i % 9), (0.0, 1e-8, 1e-3)[i % 3], (0.0, 1e-5, 0.0, 1e-2)[i % 4]))
     for tb, per_item in ((None, 0), (4096, 0), (4096, 1), (1 << 20, 0)):
         cmp_vs_oracle(kc, ctx, pairs, tile_bytes=tb, per_item=per_item)
+
+
+def test_compare_mixed_dtypes_one_launch(kc, ctx):
+    say("compare: every dtype in one batched launch, 1-ULP perturbations")
+    rng = np.random.default_rng(77)
+    gen = torch.Generator().manual_seed(77)
+    pairs = []
+    for dt in ALL_DTS:
+        if dt == W.DT_U8:
+            continue
+        t = W.TORCH_DTYPE[dt]
+        for n in (1000, 65536 + 3):
+            if t in W.INT_TYPES:
+                gold = torch.randint(-100, 100, (n,), generator=gen, dtype=torch.int64).to(t)
+            else:
+                gold = (torch.randn(n, generator=gen, dtype=torch.float64) * 0.5).to(t)
+            pr = W.perturb_pair(gold.cuda(), dt, rng, n // 100, 3, n_nan=0 if t in W.INT_TYPES else 2, ulp_tol=1)
+            pairs.append((pr.cand, pr.gold, dt, 1, 1e-8, 1e-5))
+    got = cmp_vs_oracle(kc, ctx, pairs)
+    assert all(r["n_mismatch_elems"] > 0 for r in got)
 
 
 def test_compare_c3_scaled(kc, ctx):
@@ -370,7 +412,7 @@ def test_compare_errors(kc, ctx):
         kc.compare(ctx, [(a[1:33], a[1:33], W.DT_U8, 0)])
     assert ei.value.code == kc.EALIGN
     arr, n = kc.make_pairs([(a, a, W.DT_U8, 0)])
-    arr[0].dtype = 9
+    arr[0].dtype = 13
     with pytest.raises(kc.KCError) as ei:
         kc.compare(ctx, (arr, n))
     assert ei.value.code == kc.EDTYPE
