@@ -72,8 +72,9 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         path = os.environ.get("KCO_LIB") or LIB_PATH  # KCO_LIB: load another build (mutation tests)
-        if path == LIB_PATH and not os.path.exists(LIB_PATH):
-            build()
+        if path == LIB_PATH and (not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+                os.path.getmtime(f) for f in SOURCES + [os.path.join(HERE, "kco.h")])):
+            build()  # missing or older than its sources
         L = ctypes.CDLL(path)
         u64, u32, i32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
         P = ctypes.POINTER
@@ -87,10 +88,13 @@ def lib() -> ctypes.CDLL:
         L.kco_closure_scan.argtypes = [P(Range), P(vp), u32, u64, u64, P(ScanResult), P(Oob), u64]
         L.kco_compare.argtypes = [vp, vp, u64, u32, u32, ctypes.c_double, ctypes.c_double, P(CmpResult)]
         L.kco_ulp.argtypes = [u32, u64, u64, P(u64)]
+        L.kco_pointer_graph.argtypes = [P(Range), P(vp), u32, u64, u64, vp]
+        L.kco_graph_reach.argtypes = [P(Range), u32, vp, vp, u64, vp]
         L.kco_ulp_bin.argtypes = [u64]
         L.kco_ulp_bin.restype = u32
         for name in ("kco_range_check", "kco_default_window", "kco_page_hash", "kco_compact",
-                     "kco_restore", "kco_closure_scan", "kco_compare", "kco_ulp"):
+                     "kco_restore", "kco_closure_scan", "kco_compare", "kco_ulp", "kco_pointer_graph",
+                     "kco_graph_reach"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -214,6 +218,36 @@ def closure_scan(ranges, views, win_lo: int = 0, win_hi: int = 0, oob_cap: int =
                                   ctypes.byref(res), oob, oob_cap), "closure_scan")
     d = {k: int(getattr(res, k)) for k, _ in ScanResult._fields_}
     return d, [(int(oob[i].word_va), int(oob[i].value)) for i in range(d["n_written"])]
+
+
+def pointer_graph(ranges, views, win_lo: int = 0, win_hi: int = 0) -> np.ndarray:
+    """Edge bitmap: n rows of ceil(n / 64) uint64 words (row a, bit b = a -> b)."""
+    n = len(ranges)
+    rw = (n + 63) // 64
+    edge = np.zeros(max(1, n * rw), dtype=np.uint64)
+    _check(lib().kco_pointer_graph(_ranges(ranges), _hosts(views), n, win_lo, win_hi, _ptr(edge)),
+           "pointer_graph")
+    return edge[:n * rw].reshape(n, rw)
+
+
+def edges_to_bool(edge_bm: np.ndarray, n: int) -> np.ndarray:
+    """(n, ceil(n/64)) uint64 rows -> (n, n) boolean adjacency."""
+    rows = np.ascontiguousarray(edge_bm, dtype=np.uint64).reshape(n, -1)
+    bits = np.unpackbits(rows.view(np.uint8).reshape(n, -1), axis=1, bitorder="little")
+    return bits[:, :n].astype(bool)
+
+
+def graph_reach(ranges, edge_bm, root_words) -> np.ndarray:
+    """Boolean mask of the ranges reachable from the root words."""
+    n = len(ranges)
+    rw = (n + 63) // 64
+    edge = np.ascontiguousarray(edge_bm, dtype=np.uint64).reshape(-1)
+    roots = np.ascontiguousarray(root_words, dtype=np.uint64).reshape(-1)
+    reach = np.zeros(max(1, rw), dtype=np.uint64)
+    _check(lib().kco_graph_reach(_ranges(ranges), n, _ptr(edge) if edge.size else None,
+                                 _ptr(roots) if roots.size else None, roots.size, _ptr(reach)), "graph_reach")
+    bits = np.unpackbits(reach.view(np.uint8), bitorder="little")
+    return bits[:n].astype(bool)
 
 
 def compare(cand, gold, dtype: int, ulp_tol: int = 0, atol: float = 0.0, rtol: float = 0.0):

@@ -507,3 +507,68 @@ int kco_compare(const void *cand, const void *gold, uint64_t n_elems,
   res->status = 0;
   return KCO_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pointer graph between ranges and the reachable set                        */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t graph_row_words(uint32_t n) { return ((uint64_t)n + 63u) / 64u; }
+
+int kco_pointer_graph(const kco_range *ranges, const uint8_t *const *host_ptr,
+                      uint32_t n, uint64_t win_lo, uint64_t win_hi,
+                      uint64_t *edge_bm) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (n > 0 && edge_bm == NULL) return KCO_EINVAL;
+  if (win_lo == 0 && win_hi == 0)
+    kco_default_window(ranges, n, &win_lo, &win_hi);
+  else if (win_lo == 0 || win_lo >= win_hi)
+    return KCO_EINVAL;
+  uint64_t rw = graph_row_words(n);
+  memset(edge_bm, 0, (size_t)(n * rw) * sizeof(uint64_t));
+  for (uint32_t a = 0; a < n; ++a) {
+    for (uint64_t off = 0; off < ranges[a].size; off += 8) {
+      uint64_t w = read_u64_le(host_ptr[a] + off);
+      if (!(w >= win_lo && w < win_hi)) continue; /* not pointer-like */
+      int64_t b = find_range(ranges, n, w);
+      if (b >= 0) bit_set(edge_bm + (uint64_t)a * rw, (uint64_t)b);
+    }
+  }
+  return KCO_OK;
+}
+
+int kco_graph_reach(const kco_range *ranges, uint32_t n, const uint64_t *edge_bm,
+                    const uint64_t *root_words, uint64_t n_root_words,
+                    uint64_t *reach_bm) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if ((n > 0 && (edge_bm == NULL || reach_bm == NULL)) || (n_root_words > 0 && root_words == NULL))
+    return KCO_EINVAL;
+  uint64_t rw = graph_row_words(n);
+  memset(reach_bm, 0, (size_t)rw * sizeof(uint64_t));
+  uint32_t *queue = (uint32_t *)malloc(((size_t)n + 1u) * sizeof(uint32_t));
+  if (queue == NULL) return KCO_ENOMEM;
+  uint32_t head = 0, tail = 0;
+  /* the roots: every range that some root word points into */
+  for (uint64_t i = 0; i < n_root_words; ++i) {
+    int64_t r = find_range(ranges, n, root_words[i]);
+    if (r >= 0 && !bit_get(reach_bm, (uint64_t)r)) {
+      bit_set(reach_bm, (uint64_t)r);
+      queue[tail++] = (uint32_t)r;
+    }
+  }
+  /* breadth-first over the edges */
+  while (head < tail) {
+    uint32_t a = queue[head++];
+    for (uint32_t b = 0; b < n; ++b) {
+      if (bit_get(edge_bm + (uint64_t)a * rw, b) && !bit_get(reach_bm, b)) {
+        bit_set(reach_bm, b);
+        queue[tail++] = b;
+      }
+    }
+  }
+  free(queue);
+  return KCO_OK;
+}

@@ -128,6 +128,23 @@ int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
                      uint32_t n, uint64_t win_lo, uint64_t win_hi,
                      kco_scan_result *res, kco_oob *oob, uint64_t oob_cap);
 
+/* Pointer graph between ranges: edge_bm holds n rows of ceil(n / 64) u64
+ * words; bit b of row a is set iff some 8-byte-aligned word of range a is
+ * pointer-like (same window rule as kco_closure_scan) and lies inside range b.
+ * This is the graph a pointer-chasing capture would follow (paper Sec. 4.2.1,
+ * address-space closure, where the paper contrasts whole-memory capture with
+ * chasing pointers). */
+int kco_pointer_graph(const kco_range *ranges, const uint8_t *const *host_ptr,
+                      uint32_t n, uint64_t win_lo, uint64_t win_hi,
+                      uint64_t *edge_bm);
+
+/* Ranges reachable from the root words (e.g. the kernel-argument words): the
+ * ranges they point into, then everything reachable over edge_bm.  reach_bm
+ * holds ceil(n / 64) u64 words, bit r = range r reached. */
+int kco_graph_reach(const kco_range *ranges, uint32_t n, const uint64_t *edge_bm,
+                    const uint64_t *root_words, uint64_t n_root_words,
+                    uint64_t *reach_bm);
+
 /* Typed compare of one candidate / golden pair of n_elems elements.  Besides
  * the ULP report, an element pair (neither NaN) is close iff
  * |c - g| <= atol + rtol * |g| in fp64, an infinity being close only to an

@@ -250,6 +250,84 @@ def c1_snapshot(device="cpu", scale: float = 1.0, seed: int = 1) -> SnapshotCase
 
 
 # --------------------------------------------------------------------------
+# pointer graphs: a planted sparse digraph between ranges
+# --------------------------------------------------------------------------
+
+def graph_case(device="cpu", n_ranges: int = 64, seed: int = 5, mean_out: float = 1.5,
+               max_pages: int = 24) -> SnapshotCase:
+    """Ranges of 1..max_pages pages holding N(0,1) fp32 data (never
+    pointer-like), a few zero pages, and a random digraph planted as pointer
+    words: for each edge a -> b, 1..3 aligned words of range a hold addresses
+    anywhere inside range b (first and last byte included).  One range also
+    holds a whole page of pointers into three targets.  Out-of-range
+    pointer-like values (range ends, gap middles) are planted too and make no
+    edge.  ``truth['edges']`` is the planted edge set, ``truth['plants']`` the
+    planted (source, target, value) words; ``truth['root_words']``
+    imitates a kernel-argument block: addresses into two root ranges mixed with
+    scalars and one out-of-range pointer."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, max_pages + 1, size=n_ranges) * PAGE
+    lay = make_layout(rng, sizes, gap_pages=(1, 8))
+    arena = Arena(lay, device)
+    ranges = arena.ranges()
+    bases = np.array([b for b, _ in ranges], dtype=np.uint64)
+    ends = bases + lay.sizes.astype(np.uint64)
+    gen = torch.Generator().manual_seed(seed)
+    content = torch.randn(lay.total // 4, generator=gen).numpy().view(np.uint8).copy()
+    w = content.view(np.uint64)
+    cum_w = lay.cum() // 8
+    N = lay.n_pages
+    zero_pages = rng.choice(N, size=N // 10, replace=False)
+    content.reshape(N, PAGE)[zero_pages] = 0
+    taken = set()
+
+    def free_word(a):  # an unused aligned word of range a
+        while True:
+            x = int(cum_w[a] + rng.integers(0, lay.sizes[a] // 8))
+            if x not in taken:
+                taken.add(x)
+                return x
+
+    def addr_in(b):
+        off = int(rng.integers(0, lay.sizes[b]))
+        off = (0, int(lay.sizes[b]) - 1, off)[int(rng.integers(0, 3))]
+        return int(bases[b]) + off
+
+    edges, plants = set(), []
+    for a in range(n_ranges):
+        for b in rng.choice(n_ranges, size=min(n_ranges, rng.poisson(mean_out)), replace=False):
+            edges.add((a, int(b)))
+            for _ in range(int(rng.integers(1, 4))):
+                v = addr_in(int(b))
+                w[free_word(a)] = v
+                plants.append((a, int(b), v))
+    # a page-sized pointer array in one range, three targets
+    a = int(np.argmax(lay.sizes))
+    tg = rng.choice(n_ranges, size=min(3, n_ranges), replace=False)
+    p0 = int(cum_w[a])
+    for j in range(PAGE // 8):
+        if p0 + j not in taken:
+            taken.add(p0 + j)
+            b = int(tg[j % len(tg)])
+            v = addr_in(b)
+            w[p0 + j] = v
+            plants.append((a, b, v))
+            edges.add((a, b))
+    # pointer-like values outside every range: no edge
+    gaps = [int(ends[i]) + (int(bases[i + 1]) - int(ends[i])) // 2 for i in range(n_ranges - 1)]
+    oob_vals = [int(ends[-1]), int(bases[0]) - 8] + gaps[:8] + [int(ends[i]) for i in range(min(8, n_ranges))]
+    for v in oob_vals:
+        w[free_word(int(rng.integers(0, n_ranges)))] = v
+    arena.load_concat(content)
+    roots = rng.choice(n_ranges, size=min(2, n_ranges), replace=False)
+    root_words = np.array([addr_in(int(roots[0])), 42, 0x3FF0000000000000, addr_in(int(roots[-1])),
+                           int(ends[-1]) + PAGE, 0], dtype=np.uint64)
+    truth = dict(edges=edges, plants=plants, oob_vals=oob_vals, roots=[int(r) for r in roots],
+                 root_words=root_words)
+    return SnapshotCase("graph", arena, truth)
+
+
+# --------------------------------------------------------------------------
 # perturbation by k ULP (library nextafter / sorted fp8 code table)
 # --------------------------------------------------------------------------
 

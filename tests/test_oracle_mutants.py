@@ -12,7 +12,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_xxh64.py", "tests/test_oracle_snapshot.py", "tests/test_oracle_compare.py",
-             "tests/test_golden.py"]
+             "tests/test_oracle_graph.py", "tests/test_golden.py"]
 
 MUTANTS = {
     "round uses P1": ("acc = acc + lane * PRIME2;", "acc = acc + lane * PRIME1;"),
@@ -55,6 +55,12 @@ MUTANTS = {
     "tolerance inclusive": ("if (d > ulp_tol) res->n_over_tol += 1;", "if (d >= ulp_tol) res->n_over_tol += 1;"),
     "rtol scales the candidate": ("close = abs_err <= atol + rtol * fabs(vg);", "close = abs_err <= atol + rtol * fabs(vc);"),
     "infinities always close": ("close = vc == vg;", "close = 1;"),
+    "edge points back to its source": ("if (b >= 0) bit_set(edge_bm + (uint64_t)a * rw, (uint64_t)b);",
+                                       "if (b >= 0) bit_set(edge_bm + (uint64_t)a * rw, (uint64_t)a);"),
+    "graph ignores the window": ("if (!(w >= win_lo && w < win_hi)) continue; /* not pointer-like */", ""),
+    "reach follows edges backwards": ("if (bit_get(edge_bm + (uint64_t)a * rw, b) && !bit_get(reach_bm, b)) {",
+                                      "if (bit_get(edge_bm + (uint64_t)b * rw, a) && !bit_get(reach_bm, b)) {"),
+    "roots not expanded": ("queue[tail++] = (uint32_t)r;", "(void)0;"),
 }
 
 
