@@ -17,6 +17,9 @@
  *                    inside a captured range
  *   kc_compare       candidate vs golden: byte / element mismatches, first
  *                    mismatch, fp64 max abs / rel error, ULP histogram, NaNs
+ *   kc_pointer_graph which range points into which (the graph pointer
+ *                    chasing would follow), and kc_graph_reach, the ranges
+ *                    reachable from the kernel-argument words
  *
  * Conventions
  *  - Pointers suffixed _d are device pointers owned by the caller; the
@@ -52,7 +55,8 @@ extern "C" {
 #endif
 
 #define KC_PAGE_SIZE 4096u
-#define KC_ABI_VERSION 2
+#define KC_ABI_VERSION 3
+#define KC_GRAPH_MAX_RANGES 16384u /* kc_pointer_graph: at most 32 MiB of edges */
 
 /* Status codes. */
 enum {
@@ -175,7 +179,8 @@ enum {
   KC_OP_RESTORE = 3,
   KC_OP_CLOSURE = 4,
   KC_OP_COMPARE = 5,
-  KC_OP_COUNT = 6
+  KC_OP_GRAPH = 6,
+  KC_OP_COUNT = 7
 };
 
 /* ---- host-only helpers (no device needed) ---------------------------- */
@@ -274,6 +279,28 @@ int kc_restore(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
                uint64_t cap_pages, uint64_t *n_bad_d, void *stream);
 
 /* ---- validation ----------------------------------------------------------- */
+
+/* Pointer graph between ranges (Sec. 4.2.1: the paper captures all tracked
+ * memory rather than chasing pointers; this is the graph such a chase would
+ * follow, so that callers can capture the reachable ranges only).
+ * edge_bm_d: device, n_ranges rows of ceil(n_ranges / 64) u64 words, every
+ * word written by the call.  Bit b of row a is set iff some 8-byte-aligned
+ * word of range a is pointer-like (win_lo / win_hi as in kc_scan_args,
+ * (0, 0) = default window) and lies in range b (half-open).  Self edges are
+ * kept.  More than KC_GRAPH_MAX_RANGES ranges: KC_ELIMIT.  Asynchronous on
+ * `stream`, allocates nothing. */
+int kc_pointer_graph(kc_ctx *ctx, const kc_rangeset *rs, uint64_t win_lo,
+                     uint64_t win_hi, uint64_t *edge_bm_d, void *stream);
+
+/* Host-only: the ranges reachable from root_words (e.g. the words of a
+ * kernel-argument block): the ranges the root words lie in, then, over the
+ * edges of edge_bm (host copy of kc_pointer_graph's output for the same
+ * ranges), everything reachable from them.  reach_bm: host, ceil(n / 64) u64
+ * words, bit r set iff range r is reached (bits past n cleared).  Ranges are
+ * checked as in kc_range_check. */
+int kc_graph_reach(const kc_range *ranges, uint32_t n, const uint64_t *edge_bm,
+                   const uint64_t *root_words, uint64_t n_root_words,
+                   uint64_t *reach_bm);
 
 /* Closure scan (Sec. 4.2.1, address-space closure and its bounds): every
  * 8-byte-aligned word of every range is tested against the window; a

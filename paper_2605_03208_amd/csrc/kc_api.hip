@@ -468,6 +468,70 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   return KC_OK;
 }
 
+int kc_pointer_graph(kc_ctx* c, const kc_rangeset* rs, uint64_t win_lo, uint64_t win_hi, uint64_t* edge_bm_d,
+                     void* stream) {
+  if (c == nullptr || rs == nullptr || rs->ctx != c) return KC_EINVAL;
+  if (rs->n_ranges > KC_GRAPH_MAX_RANGES) return KC_ELIMIT;
+  if (rs->n_ranges == 0) return KC_OK;
+  if (edge_bm_d == nullptr) return KC_EINVAL;
+  uint64_t lo = win_lo, hi = win_hi;
+  if (lo == 0 && hi == 0) {
+    lo = rs->win_lo;
+    hi = rs->win_hi;
+  } else if (lo == 0 || lo >= hi) {
+    return KC_EINVAL;
+  }
+  DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
+  const hipStream_t s = as_stream(stream);
+  const uint32_t row_words = (rs->n_ranges + 63u) / 64u;
+  KC_HIP(launch_fill_u64(edge_bm_d, (uint64_t)rs->n_ranges * row_words, 0, s));
+  KernelTimer timer(c, KC_OP_GRAPH, s);
+  KC_HIP(launch_pointer_graph(rs->tiles, rs->n_tiles, lo, hi - lo, rs->rt, edge_bm_d, row_words,
+                              grid_for(c, KC_OP_GRAPH, 8), s));
+  return KC_OK;
+}
+
+int kc_graph_reach(const kc_range* ranges, uint32_t n, const uint64_t* edge_bm, const uint64_t* root_words,
+                   uint64_t n_root_words, uint64_t* reach_bm) {
+  const int st = range_check(ranges, n, nullptr);
+  if (st != KC_OK) return st;
+  if (n > KC_GRAPH_MAX_RANGES) return KC_ELIMIT;
+  if ((n > 0 && (edge_bm == nullptr || reach_bm == nullptr)) || (n_root_words > 0 && root_words == nullptr))
+    return KC_EINVAL;
+  if (n == 0) return KC_OK;
+  const uint32_t rw = (n + 63u) / 64u;
+  std::fill(reach_bm, reach_bm + rw, 0ull);
+  std::vector<uint32_t> stack;
+  stack.reserve(n);
+  auto visit = [&](uint32_t r) {
+    if (!((reach_bm[r >> 6] >> (r & 63u)) & 1ull)) {
+      reach_bm[r >> 6] |= 1ull << (r & 63u);
+      stack.push_back(r);
+    }
+  };
+  for (uint64_t i = 0; i < n_root_words; ++i) {  // the range each root word lies in
+    const uint64_t w = root_words[i];
+    const kc_range* it = std::upper_bound(ranges, ranges + n, w,
+                                          [](uint64_t v, const kc_range& r) { return v < r.base; });
+    if (it != ranges && w - (it - 1)->base < (it - 1)->size) visit((uint32_t)(it - 1 - ranges));
+  }
+  while (!stack.empty()) {  // depth-first over the rows, a word of targets at a time
+    const uint32_t a = stack.back();
+    stack.pop_back();
+    const uint64_t* row = edge_bm + (uint64_t)a * rw;
+    for (uint32_t k = 0; k < rw; ++k) {
+      uint64_t fresh = row[k] & ~reach_bm[k];
+      if (k == rw - 1u && (n & 63u)) fresh &= (1ull << (n & 63u)) - 1ull;  // bits past the last range
+      while (fresh) {
+        visit(k * 64u + (uint32_t)__builtin_ctzll(fresh));
+        fresh &= fresh - 1ull;
+      }
+    }
+  }
+  return KC_OK;
+}
+
 int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan, void* stream) {
   kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
   if (c == nullptr || rs == nullptr || rs->ctx != c || scan == nullptr) return KC_EINVAL;

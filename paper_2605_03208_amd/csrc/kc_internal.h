@@ -129,6 +129,9 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
                                   uint32_t grid, hipStream_t s);
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
                           const ScanDev& sd, uint32_t grid, hipStream_t s);
+hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
+                                const RangeTable& rt, uint64_t* edge_bm, uint32_t row_words, uint32_t grid,
+                                hipStream_t s);
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
                            const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
                            uint64_t cap, kc_scan_result* res, uint64_t n_words, uint32_t grid,

@@ -121,6 +121,23 @@ __device__ __forceinline__ bool in_ranges(uint64_t w, const FenceLds& f, const R
   return w < rt.end[a];
 }
 
+// Index of the range holding w, or -1.
+__device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, const RangeTable& rt) {
+  if (rt.n == 0u || w < f.base[0]) return -1;
+  uint32_t i = 0;
+#pragma unroll
+  for (uint32_t step = kFences / 2; step > 0; step >>= 1)
+    if (i + step < rt.n_fence && f.base[i + step] <= w) i += step;
+  if (rt.stride == 1u) return w < f.end[i] ? (int32_t)i : -1;
+  uint32_t a = i * rt.stride;
+  uint32_t b = min(a + rt.stride, rt.n);
+  while (b - a > 1u) {
+    const uint32_t m = (a + b) >> 1;
+    if (rt.base[m] <= w) a = m; else b = m;
+  }
+  return w < rt.end[a] ? (int32_t)a : -1;
+}
+
 // --------------------------------------------------------------- fill -----
 __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -643,6 +660,51 @@ __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_t
 }
 
 
+// Pointer graph: for every pointer-like word, set bit (source range, target
+// range).  Lanes of a wave that hit the same target share one atomicOr, and a
+// wave skips the target it set last.
+__device__ __forceinline__ void graph_emit(int32_t t, uint32_t lane, uint64_t* row, int32_t& last) {
+  uint64_t pending = __ballot(t >= 0);
+  while (pending) {
+    const int32_t leader = __ffsll((long long)pending) - 1;
+    const int32_t tb = __shfl(t, leader, 64);
+    pending &= ~__ballot(t == tb);
+    if (tb != last && (int32_t)lane == leader) atomicOr((unsigned long long*)&row[tb >> 6], 1ull << (tb & 63));
+    last = tb;
+  }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_pointer_graph(
+    const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span, RangeTable rt, uint64_t* edge_bm,
+    uint32_t row_words) {
+  __shared__ FenceLds fences;
+  const uint32_t lane = threadIdx.x;
+  load_fences(fences, rt, lane, kWave);
+  __syncthreads();
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile tile = tiles[t];
+    const int32_t src = range_index(tile.va, fences, rt);  // the tile's own range (always found)
+    uint64_t* row = edge_bm + (uint64_t)(src < 0 ? 0 : src) * row_words;
+    int32_t last = -1;
+    const uint32_t nseg = tile.npages * 4u;
+    for (uint32_t s0 = 0; s0 < nseg; s0 += 8) {
+      uint4 x[8];
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i)
+        x[i] = (s0 + i < nseg) ? ld16nt(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) {
+        const uint64_t w0 = ((uint64_t)x[i].y << 32) | x[i].x;
+        const uint64_t w1 = ((uint64_t)x[i].w << 32) | x[i].z;
+        const bool p0 = (w0 - lo) < span, p1 = (w1 - lo) < span;
+        if (__ballot(p0 || p1) == 0ull || src < 0) continue;  // no pointer-like word here
+        graph_emit(p0 ? range_index(w0, fences, rt) : -1, lane, row, last);
+        graph_emit(p1 ? range_index(w1, fences, rt) : -1, lane, row, last);
+      }
+    }
+  }
+}
+
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 }  // namespace
@@ -738,6 +800,15 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, c
   grid = grid < 1u ? 1u : grid;
   hipLaunchKernelGGL(k_restore_scatter, dim3(grid), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
                      n_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
+                                const RangeTable& rt, uint64_t* edge_bm, uint32_t row_words, uint32_t grid,
+                                hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  grid = std::max(1u, std::min(grid, n_tiles));
+  hipLaunchKernelGGL(k_pointer_graph, dim3(grid), dim3(64), 0, s, tiles, n_tiles, lo, span, rt, edge_bm, row_words);
   return hipGetLastError();
 }
 

@@ -10,12 +10,13 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
-ABI_VERSION = 2  # layout of the structs below
+ABI_VERSION = 3  # layout of the structs and the entry-point set below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
@@ -25,14 +26,15 @@ TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, tor
                torch.float8_e5m2: FP8_E5M2, torch.float8_e5m2fnuz: FP8_E5M2FNUZ, torch.int8: I8,
                torch.int16: I16, torch.int32: I32, torch.int64: I64}
 ELEM_SIZE = {k: torch.empty(0, dtype=t).element_size() for t, k in TORCH_TO_KC.items()}
-OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE = range(6)
+OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE, OP_GRAPH = range(7)
+GRAPH_MAX_RANGES = 16384
 
 SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "kc_default_window",
            "kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_tuning", "kc_ctx_get_tuning",
            "kc_ctx_enable_timing", "kc_ctx_kernel_ms",
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
-           "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load"]
+           "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach"]
 
 
 class KCError(RuntimeError):
@@ -126,6 +128,8 @@ def lib() -> ctypes.CDLL:
             "kc_snapshot_save": ([vp, vp, ctypes.c_char_p, u64, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)],
                                  i32),
             "kc_snapshot_load": ([vp, vp, ctypes.c_char_p, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)], i32),
+            "kc_pointer_graph": ([vp, vp, u64, u64, vp, vp], i32),
+            "kc_graph_reach": ([P(Range), u32, vp, vp, u64, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -324,6 +328,35 @@ def restore(ctx: Context, rs: RangeSet, zero_bm, changed_bm, packed, page_va, n_
 def closure_scan(ctx: Context, rs: RangeSet, scan: ScanOut, stream=None) -> None:
     _check(lib().kc_closure_scan(ctx.handle, rs.handle, ctypes.byref(scan.args), _stream(stream)),
            "kc_closure_scan")
+
+
+def pointer_graph(ctx: Context, rs: RangeSet, win_lo: int = 0, win_hi: int = 0,
+                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Edge bitmap on the device: (n_ranges, ceil(n_ranges / 64)) int64 words,
+    row a bit b set iff range a holds a pointer-like word inside range b."""
+    n = len(rs.ranges)
+    rw = (n + 63) // 64
+    if out is None:
+        out = torch.empty(max(1, n * rw), dtype=torch.int64, device=torch.device("cuda", ctx.device))
+    assert out.numel() * out.element_size() >= n * rw * 8
+    _check(lib().kc_pointer_graph(ctx.handle, rs.handle, win_lo, win_hi, _ptr(out), _stream(stream)),
+           "kc_pointer_graph")
+    return out[:n * rw].view(n, rw) if n else out[:0].view(0, 0)
+
+
+def graph_reach(ranges, edge_bm, root_words) -> np.ndarray:
+    """Host: boolean mask of the ranges reachable from ``root_words`` over the
+    edges of ``edge_bm`` (a host copy of ``pointer_graph``'s output)."""
+    n = len(ranges)
+    rw = (n + 63) // 64
+    edge = np.ascontiguousarray(np.asarray(edge_bm).view(np.uint64).reshape(-1))
+    assert edge.size >= n * rw
+    roots = np.ascontiguousarray(np.asarray(root_words, dtype=np.uint64).reshape(-1))
+    reach = np.zeros(max(1, rw), dtype=np.uint64)
+    _check(lib().kc_graph_reach(_ranges(ranges), n, edge.ctypes.data if edge.size else None,
+                                roots.ctypes.data if roots.size else None, roots.size, reach.ctypes.data),
+           "kc_graph_reach")
+    return np.unpackbits(reach.view(np.uint8), bitorder="little")[:n].astype(bool)
 
 
 def make_pairs(pairs) -> tuple[ctypes.Array, int]:

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(kc):
 
 
 def test_abi_version_and_strerror(kc):
-    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 2
+    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 3
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert kc.strerror(code) not in ("", "unknown status")
 
@@ -92,5 +92,27 @@ def test_binding_constants_match_header(kc):
     assert sorted(kc.TORCH_TO_KC.values()) == sorted(enum[k] for k in dts)
     for k in ("OK", "EINVAL", "EALIGN", "EORDER", "ENOMEM", "EHIP", "EDTYPE", "ELIMIT"):
         assert getattr(kc, k) == enum["KC_" + k]
-    for k in ("PAGE_HASH", "SNAPSHOT", "COMPACT", "RESTORE", "CLOSURE", "COMPARE"):
+    for k in ("PAGE_HASH", "SNAPSHOT", "COMPACT", "RESTORE", "CLOSURE", "COMPARE", "GRAPH"):
         assert getattr(kc, "OP_" + k) == enum["KC_OP_" + k]
+
+
+def test_graph_reach_agrees_with_oracle(kc, oracle_lib):
+    """kc_graph_reach is host code: compare it with the oracle on random graphs."""
+    rng = np.random.default_rng(5)
+    for n in (0, 1, 2, 63, 64, 65, 200):
+        ranges = [(0x400000 + i * 0x5000, 0x1000 * (1 + i % 3)) for i in range(n)]
+        rw = (n + 63) // 64
+        bits = np.zeros((n, rw * 64), np.uint8)
+        bits[:, :n] = rng.random((n, n)) < 1.5 / max(n, 1)
+        bits[:, n:] = 1 if n % 64 else 0        # garbage past the last range must be ignored
+        edge = np.packbits(bits, axis=1, bitorder="little").view(np.uint64).reshape(n, rw)
+        for roots in ([], [ranges[0][0]] if n else [], [r[0] + r[1] - 1 for r in ranges[::7]],
+                      [0, 1, 2**64 - 1] + ([ranges[-1][0] + ranges[-1][1]] if n else [])):
+            got = kc.graph_reach(ranges, edge, roots)
+            clean = edge.copy()
+            if n % 64:
+                clean[:, -1] &= np.uint64((1 << (n % 64)) - 1)
+            want = oracle_lib.graph_reach(ranges, clean, roots)
+            assert (got == want).all(), (n, roots)
+    with pytest.raises(kc.KCError):
+        kc.graph_reach([(0x1000, 0x1001)], np.zeros(1, np.uint64), [])

@@ -1,0 +1,123 @@
+"""Pointer graph on the GPU vs the CPU oracle, bit for bit, through the C ABI,
+and the reachable-only snapshot built on it.
+
+Every case prints its name before touching the GPU."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_03208_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PAGE = 4096
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kc():
+    from paper_2605_03208_amd import kc as K
+    K.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return K
+
+
+@pytest.fixture(scope="module")
+def ctx(kc):
+    c = kc.Context(0)
+    yield c
+    c.close()
+
+
+def graph_vs_oracle(kc, ctx, case, win=(0, 0), per_cu=None):
+    ranges = case.ranges()
+    rs = kc.RangeSet(ctx, ranges)
+    host = case.arena.host_copy()
+    views = W.host_views(case.layout, host)
+    if per_cu is not None:
+        ctx.set_tuning(kc.OP_GRAPH, grid_per_cu=per_cu)
+    edge = kc.pointer_graph(ctx, rs, win[0], win[1])
+    torch.cuda.synchronize()
+    got = edge.cpu().numpy().view(np.uint64)
+    want = oracle.pointer_graph(ranges, views, win[0], win[1])
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    if per_cu is not None:
+        ctx.set_tuning(kc.OP_GRAPH, grid_per_cu=0)
+    return rs, got
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (7, 2), (64, 3), (130, 4), (700, 5)])
+def test_planted_graph(kc, ctx, n, seed):
+    say(f"pointer graph: planted digraph n_ranges={n} seed={seed}")
+    case = W.graph_case("cuda", n_ranges=n, seed=seed)
+    rs, got = graph_vs_oracle(kc, ctx, case)
+    adj = oracle.edges_to_bool(got, n)
+    want = np.zeros((n, n), bool)
+    for a, b in case.truth["edges"]:
+        want[a, b] = True
+    assert (adj == want).all()
+    for per_cu in (1, 32):   # launch shape must not change the result
+        graph_vs_oracle(kc, ctx, case, per_cu=per_cu)
+    rs.close()
+
+
+def test_windows_and_dense_pointers(kc, ctx):
+    say("pointer graph: custom windows; c1 scaled (1 % of words are pointers)")
+    case = W.graph_case("cuda", n_ranges=40, seed=21)
+    vals = sorted(v for _, _, v in case.truth["plants"])
+    for win in ((vals[len(vals) // 3], vals[2 * len(vals) // 3]), (vals[0], vals[0] + 1), (1, 2**64 - 1)):
+        graph_vs_oracle(kc, ctx, case, win=win)[0].close()
+    c1 = W.c1_snapshot("cuda", scale=1 / 16, seed=3)
+    graph_vs_oracle(kc, ctx, c1)[0].close()
+
+
+def test_reachable_only_snapshot(kc, ctx):
+    say("pointer graph: reach from kernel-argument words, snapshot of the reachable ranges only")
+    case = W.graph_case("cuda", n_ranges=200, seed=31, mean_out=0.8)
+    ranges = case.ranges()
+    rs, got = graph_vs_oracle(kc, ctx, case)
+    reach = kc.graph_reach(ranges, got, case.truth["root_words"])
+    assert (reach == oracle.graph_reach(ranges, got, case.truth["root_words"])).all()
+    sub = [r for r, keep in zip(ranges, reach) if keep]
+    assert 0 < len(sub) <= len(ranges)
+    rs_sub = kc.RangeSet(ctx, sub)
+    out = kc.snapshot(ctx, rs_sub)
+    torch.cuda.synchronize()
+    host = case.arena.host_copy()
+    views = [v for v, keep in zip(W.host_views(case.layout, host), reach) if keep]
+    oh, oz, _ = oracle.page_hash(sub, views)
+    assert np.array_equal(out["hash"].cpu().numpy().view(np.uint64)[:rs_sub.n_pages], oh)
+    op, ova, onk = oracle.compact(sub, views, oz)
+    assert int(out["n_kept"].cpu().numpy().view(np.uint64)[0]) == onk
+    assert np.array_equal(out["page_va"].cpu().numpy().view(np.uint64)[:onk], ova)
+    assert np.array_equal(out["packed"][:onk * PAGE].cpu().numpy(), op)
+    rs_sub.close()
+    rs.close()
+
+
+def test_graph_limits_and_empty(kc, ctx):
+    say("pointer graph: empty range set, too many ranges, bad window")
+    rs = kc.RangeSet(ctx, [])
+    e = kc.pointer_graph(ctx, rs)
+    assert e.numel() == 0
+    rs.close()
+    many = [(0x7F0000000000 + i * 2 * PAGE, PAGE) for i in range(kc.GRAPH_MAX_RANGES + 1)]
+    rs = kc.RangeSet(ctx, many)   # the table only: nothing is read before the limit check
+    with pytest.raises(kc.KCError) as ei:
+        kc.pointer_graph(ctx, rs)
+    assert ei.value.code == kc.ELIMIT
+    rs.close()
+    case = W.graph_case("cuda", n_ranges=3, seed=2)
+    rs = kc.RangeSet(ctx, case.ranges())
+    with pytest.raises(kc.KCError) as ei:
+        kc.pointer_graph(ctx, rs, 0, 100)
+    assert ei.value.code == kc.EINVAL
+    rs.close()
