@@ -298,6 +298,8 @@ def main() -> int:
         log("oracle CPU baseline on a bounded sample")
         cpu = cpu_baseline(case, ranges, sample_idx)
     if not args.no_extras:
+        log("pointer graph over the same ranges")
+        line["pointer_graph"] = pointer_graph_pass(torch, kc, ctx, rs, N, args.steps)
         log("graph replay of the step")
         line["graph"] = graph_step(torch, step, res, pair_list, kc, args.steps)
         state["ps"].close()
@@ -313,6 +315,23 @@ def main() -> int:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
+
+
+def pointer_graph_pass(torch, kc, ctx, rs, n_pages: int, reps: int) -> dict:
+    """kc_pointer_graph over the step's ranges: one read of every page."""
+    import numpy as np
+    out = kc.pointer_graph(ctx, rs)
+    ctx.enable_timing(True)
+    ms = []
+    for _ in range(reps):
+        kc.pointer_graph(ctx, rs, out=out)
+        ms.append(ctx.kernel_ms(kc.OP_GRAPH))
+    ctx.enable_timing(False)
+    edges = int(np.unpackbits(out.cpu().numpy().view(np.uint8)).sum())
+    k = float(np.mean(ms))
+    gbs = n_pages * PAGE / (k / 1e3) / 1e9
+    return {"kernel": "k_pointer_graph", "kernel_ms": round(k, 4), "GBps": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "n_ranges": len(rs.ranges), "n_edges": edges}
 
 
 def graph_step(torch, step, res, pair_list, kc, reps: int) -> dict:
