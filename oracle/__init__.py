@@ -90,11 +90,12 @@ def lib() -> ctypes.CDLL:
         L.kco_ulp.argtypes = [u32, u64, u64, P(u64)]
         L.kco_pointer_graph.argtypes = [P(Range), P(vp), u32, u64, u64, vp]
         L.kco_graph_reach.argtypes = [P(Range), u32, vp, vp, u64, vp]
+        L.kco_region_diff.argtypes = [P(Range), P(vp), u32, vp, vp, vp, u64, u64, vp]
         L.kco_ulp_bin.argtypes = [u64]
         L.kco_ulp_bin.restype = u32
         for name in ("kco_range_check", "kco_default_window", "kco_page_hash", "kco_compact",
                      "kco_restore", "kco_closure_scan", "kco_compare", "kco_ulp", "kco_pointer_graph",
-                     "kco_graph_reach"):
+                     "kco_graph_reach", "kco_region_diff"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -218,6 +219,26 @@ def closure_scan(ranges, views, win_lo: int = 0, win_hi: int = 0, oob_cap: int =
                                   ctypes.byref(res), oob, oob_cap), "closure_scan")
     d = {k: int(getattr(res, k)) for k, _ in ScanResult._fields_}
     return d, [(int(oob[i].word_va), int(oob[i].value)) for i in range(d["n_written"])]
+
+
+class RegionDiff(ctypes.Structure):
+    _fields_ = [("n_diff_bytes", ctypes.c_uint64), ("n_diff_pages", ctypes.c_uint64),
+                ("first_diff_va", ctypes.c_uint64), ("n_bad_pages", ctypes.c_uint64)]
+
+
+def region_diff(ranges, views, gold_zero_bm, gold_packed, gold_page_va, gold_n_kept: int,
+                cap_pages: int | None = None) -> list[dict]:
+    """Per-range byte difference of the live bytes in ``views`` against a full snapshot."""
+    n = len(ranges)
+    zb = np.ascontiguousarray(gold_zero_bm, dtype=np.uint64)
+    pk = np.ascontiguousarray(gold_packed, dtype=np.uint8)
+    va = np.ascontiguousarray(gold_page_va, dtype=np.uint64)
+    cap = len(va) if cap_pages is None else int(cap_pages)
+    res = (RegionDiff * max(1, n))()
+    _check(lib().kco_region_diff(_ranges(ranges), _hosts(views), n, _ptr(zb) if zb.size else None,
+                                 _ptr(pk) if pk.size else None, _ptr(va) if va.size else None, int(gold_n_kept),
+                                 cap, res), "region_diff")
+    return [{k: int(getattr(res[i], k)) for k, _ in RegionDiff._fields_} for i in range(n)]
 
 
 def pointer_graph(ranges, views, win_lo: int = 0, win_hi: int = 0) -> np.ndarray:

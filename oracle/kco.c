@@ -572,3 +572,54 @@ int kco_graph_reach(const kco_range *ranges, uint32_t n, const uint64_t *edge_bm
   free(queue);
   return KCO_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Per-range byte difference against a full snapshot                         */
+/* ------------------------------------------------------------------------ */
+
+int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
+                    uint32_t n, const uint64_t *gold_zero_bm,
+                    const uint8_t *gold_packed, const uint64_t *gold_page_va,
+                    uint64_t gold_n_kept, uint64_t cap_pages,
+                    kco_region_diff_result *res) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (n > 0 && res == NULL) return KCO_EINVAL;
+  if (n_pages > 0 && gold_zero_bm == NULL) return KCO_EINVAL;
+  uint64_t n_valid = gold_n_kept < cap_pages ? gold_n_kept : cap_pages;
+  if (n_valid > 0 && (gold_packed == NULL || gold_page_va == NULL)) return KCO_EINVAL;
+  static const uint8_t zeros[PAGE];
+  uint64_t g = 0, slot = 0; /* slot = non-zero pages seen so far */
+  for (uint32_t a = 0; a < n; ++a) {
+    res[a].n_diff_bytes = 0;
+    res[a].n_diff_pages = 0;
+    res[a].first_diff_va = UINT64_MAX;
+    res[a].n_bad_pages = 0;
+    uint64_t pages = ranges[a].size / PAGE;
+    for (uint64_t p = 0; p < pages; ++p, ++g) {
+      uint64_t va = ranges[a].base + p * PAGE;
+      const uint8_t *gold;
+      if (bit_get(gold_zero_bm, g)) {
+        gold = zeros;
+      } else {
+        uint64_t s = slot++;
+        if (s >= n_valid || gold_page_va[s] != va) {
+          res[a].n_bad_pages += 1;
+          continue;
+        }
+        gold = gold_packed + s * PAGE;
+      }
+      const uint8_t *live = host_ptr[a] + p * PAGE;
+      uint64_t d = 0;
+      for (uint32_t b = 0; b < PAGE; ++b) {
+        if (live[b] == gold[b]) continue;
+        if (res[a].first_diff_va == UINT64_MAX) res[a].first_diff_va = va + b;
+        ++d;
+      }
+      res[a].n_diff_bytes += d;
+      if (d > 0) res[a].n_diff_pages += 1;
+    }
+  }
+  return KCO_OK;
+}

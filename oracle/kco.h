@@ -89,6 +89,10 @@ typedef struct {
   uint32_t pass_close, reserved;
 } kco_cmp_result;
 
+typedef struct {
+  uint64_t n_diff_bytes, n_diff_pages, first_diff_va, n_bad_pages;
+} kco_region_diff_result;
+
 /* XXH64 of len bytes at data with the given seed (public xxHash definition). */
 uint64_t kco_xxh64(const void *data, uint64_t len, uint64_t seed);
 
@@ -127,6 +131,21 @@ int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
 int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
                      uint32_t n, uint64_t win_lo, uint64_t win_hi,
                      kco_scan_result *res, kco_oob *oob, uint64_t oob_cap);
+
+/* Per-range byte difference between the live bytes of the ranges and a full
+ * snapshot of the same ranges (byte-exact comparison reported per region,
+ * paper Sec. 4.5.2).  The golden copy of page g is all zeros when its zero
+ * bit is set; otherwise packed page s, s = number of non-zero pages before g
+ * (the order kco_compact writes), accepted iff s < min(n_kept, cap_pages) and
+ * page_va[s] is the VA of page g; a non-zero page without an accepted copy is
+ * counted in n_bad_pages and not compared.  res[a] per range: differing
+ * bytes, pages with at least one differing byte, VA of the first differing
+ * byte (UINT64_MAX if none). */
+int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
+                    uint32_t n, const uint64_t *gold_zero_bm,
+                    const uint8_t *gold_packed, const uint64_t *gold_page_va,
+                    uint64_t gold_n_kept, uint64_t cap_pages,
+                    kco_region_diff_result *res);
 
 /* Pointer graph between ranges: edge_bm holds n rows of ceil(n / 64) u64
  * words; bit b of row a is set iff some 8-byte-aligned word of range a is

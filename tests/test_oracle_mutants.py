@@ -12,7 +12,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_xxh64.py", "tests/test_oracle_snapshot.py", "tests/test_oracle_compare.py",
-             "tests/test_oracle_graph.py", "tests/test_golden.py"]
+             "tests/test_oracle_graph.py", "tests/test_oracle_region.py", "tests/test_golden.py"]
 
 MUTANTS = {
     "round uses P1": ("acc = acc + lane * PRIME2;", "acc = acc + lane * PRIME1;"),
@@ -61,6 +61,9 @@ MUTANTS = {
     "reach follows edges backwards": ("if (bit_get(edge_bm + (uint64_t)a * rw, b) && !bit_get(reach_bm, b)) {",
                                       "if (bit_get(edge_bm + (uint64_t)b * rw, a) && !bit_get(reach_bm, b)) {"),
     "roots not expanded": ("queue[tail++] = (uint32_t)r;", "(void)0;"),
+    "zero pages take a snapshot slot": ("        gold = zeros;\n", "        gold = zeros;\n        ++slot;\n"),
+    "diff pages counted per byte": ("if (d > 0) res[a].n_diff_pages += 1;", "res[a].n_diff_pages += d;"),
+    "page VA not checked": ("if (s >= n_valid || gold_page_va[s] != va) {", "if (s >= n_valid) {"),
 }
 
 
