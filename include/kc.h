@@ -17,6 +17,8 @@
  *                    inside a captured range
  *   kc_compare       candidate vs golden: byte / element mismatches, first
  *                    mismatch, fp64 max abs / rel error, ULP histogram, NaNs
+ *   kc_region_diff   per-range differing bytes of live memory against a
+ *                    snapshot, comparing only pages whose hash changed
  *   kc_pointer_graph which range points into which (the graph pointer
  *                    chasing would follow), and kc_graph_reach, the ranges
  *                    reachable from the kernel-argument words
@@ -164,6 +166,15 @@ typedef struct {
   uint32_t reserved;
 } kc_cmp_result;
 
+/* Per-range byte difference against a snapshot (32 bytes). */
+typedef struct {
+  uint64_t n_diff_bytes;  /* bytes that differ from the snapshot's copy        */
+  uint64_t n_diff_pages;  /* pages with at least one differing byte            */
+  uint64_t first_diff_va; /* VA of the lowest differing byte, UINT64_MAX if none */
+  uint64_t n_bad_pages;   /* non-zero snapshot pages without an accepted copy:
+                             not compared                                      */
+} kc_region_diff_result;
+
 /* Launch shape of one operation.  Zero fields keep the built-in choice. */
 typedef struct {
   uint32_t grid_per_cu; /* persistent workgroups per compute unit          */
@@ -180,7 +191,8 @@ enum {
   KC_OP_CLOSURE = 4,
   KC_OP_COMPARE = 5,
   KC_OP_GRAPH = 6,
-  KC_OP_COUNT = 7
+  KC_OP_REGION_DIFF = 7,
+  KC_OP_COUNT = 8
 };
 
 /* ---- host-only helpers (no device needed) ---------------------------- */
@@ -279,6 +291,30 @@ int kc_restore(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
                uint64_t cap_pages, uint64_t *n_bad_d, void *stream);
 
 /* ---- validation ----------------------------------------------------------- */
+
+/* Per-range byte difference between the live bytes of the ranges and a full
+ * snapshot of them (kc_snapshot output, changed_bm NULL), hash first (Sec.
+ * 4.5.2, byte-exact comparison reported per region):
+ * 1) the live pages are hashed with `seed` against gold_hash_d (which must be
+ *    the snapshot's hash table, made with the same seed): cand_hash_d,
+ *    cand_zero_bm_d and changed_bm_d receive the live hash table, zero bitmap
+ *    and changed-page bitmap (each fully written);
+ * 2) only changed pages are compared byte by byte with the snapshot's copy:
+ *    all zeros when the page's gold zero bit is set, else packed page s,
+ *    s = number of non-zero pages before it, accepted iff
+ *    s < min(*gold_n_kept_d, cap_pages) and gold_page_va_d[s] is the page's VA.
+ *    Non-zero pages without an accepted copy are counted in n_bad_pages
+ *    (changed or not) and not compared.
+ * res_d: device, one kc_region_diff_result per range, fully written.  Equal to a full
+ * byte compare unless two different pages share an XXH64 hash.  Allocates
+ * nothing, asynchronous on `stream`. */
+int kc_region_diff(kc_ctx *ctx, const kc_rangeset *rs, uint64_t seed,
+                   const uint64_t *gold_hash_d, const uint64_t *gold_zero_bm_d,
+                   const void *gold_packed_d, const uint64_t *gold_page_va_d,
+                   const uint64_t *gold_n_kept_d, uint64_t cap_pages,
+                   uint64_t *cand_hash_d, uint64_t *cand_zero_bm_d,
+                   uint64_t *changed_bm_d, kc_region_diff_result *res_d,
+                   void *stream);
 
 /* Pointer graph between ranges (Sec. 4.2.1: the paper captures all tracked
  * memory rather than chasing pointers; this is the graph such a chase would

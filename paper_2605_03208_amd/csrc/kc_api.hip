@@ -468,6 +468,43 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   return KC_OK;
 }
 
+int kc_region_diff(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t* gold_hash_d,
+                   const uint64_t* gold_zero_bm_d, const void* gold_packed_d, const uint64_t* gold_page_va_d,
+                   const uint64_t* gold_n_kept_d, uint64_t cap_pages, uint64_t* cand_hash_d, uint64_t* cand_zero_bm_d,
+                   uint64_t* changed_bm_d, kc_region_diff_result* res_d, void* stream) {
+  kc_rangeset* rs = const_cast<kc_rangeset*>(crs);
+  if (c == nullptr || rs == nullptr || rs->ctx != c) return KC_EINVAL;
+  if (rs->n_ranges == 0) return KC_OK;
+  if (res_d == nullptr || gold_n_kept_d == nullptr) return KC_EINVAL;
+  if (rs->n_pages > 0 && (gold_hash_d == nullptr || gold_zero_bm_d == nullptr || cand_hash_d == nullptr ||
+                          cand_zero_bm_d == nullptr || changed_bm_d == nullptr))
+    return KC_EINVAL;
+  if (cap_pages > 0 && (gold_packed_d == nullptr || gold_page_va_d == nullptr)) return KC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return KC_EHIP;
+  const hipStream_t s = as_stream(stream);
+  KC_HIP(launch_region_init(res_d, rs->n_ranges, cand_zero_bm_d, changed_bm_d, rs->n_words, s));
+  HashParams hp{};
+  hp.seed = seed;
+  hp.prior = gold_hash_d;
+  hp.hash = cand_hash_d;
+  hp.zero_bm = cand_zero_bm_d;
+  hp.changed_bm = changed_bm_d;
+  int st = run_hash(rs, hp, false, true, false, KC_OP_PAGE_HASH, s);
+  if (st != KC_OK) return st;
+  ScanSrc src{};  // rank of each non-zero snapshot page: keep prefix of the gold zero bitmap
+  src.kind = kSrcKeepBits;
+  src.zero_bm = gold_zero_bm_d;
+  src.n_pages = rs->n_pages;
+  src.n_items = rs->n_words;
+  KC_HIP(launch_scan(src, rs->word_prefix, rs->block_sums, rs->n_oob, s));
+  KernelTimer timer(c, KC_OP_REGION_DIFF, s);
+  KC_HIP(launch_region_diff(rs->tiles, rs->n_tiles, rs->rt, changed_bm_d, gold_zero_bm_d, rs->word_prefix,
+                            gold_page_va_d, gold_n_kept_d, cap_pages, static_cast<const uint8_t*>(gold_packed_d),
+                            res_d, grid_for(c, KC_OP_REGION_DIFF, 8), s));
+  return KC_OK;
+}
+
 int kc_pointer_graph(kc_ctx* c, const kc_rangeset* rs, uint64_t win_lo, uint64_t win_hi, uint64_t* edge_bm_d,
                      void* stream) {
   if (c == nullptr || rs == nullptr || rs->ctx != c) return KC_EINVAL;

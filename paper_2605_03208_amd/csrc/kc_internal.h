@@ -132,6 +132,12 @@ hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
 hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
                                 const RangeTable& rt, uint64_t* edge_bm, uint32_t row_words, uint32_t grid,
                                 hipStream_t s);
+hipError_t launch_region_init(kc_region_diff_result* res, uint32_t n, uint64_t* bm_a, uint64_t* bm_b, uint64_t n_words,
+                              hipStream_t s);
+hipError_t launch_region_diff(const Tile* tiles, uint32_t n_tiles, const RangeTable& rt, const uint64_t* changed_bm,
+                              const uint64_t* gold_zero_bm, const uint64_t* rank_prefix, const uint64_t* gold_page_va,
+                              const uint64_t* gold_n_kept, uint64_t cap, const uint8_t* gold_packed,
+                              kc_region_diff_result* res, uint32_t grid, hipStream_t s);
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
                            const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
                            uint64_t cap, kc_scan_result* res, uint64_t n_words, uint32_t grid,

@@ -26,7 +26,7 @@ TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, tor
                torch.float8_e5m2: FP8_E5M2, torch.float8_e5m2fnuz: FP8_E5M2FNUZ, torch.int8: I8,
                torch.int16: I16, torch.int32: I32, torch.int64: I64}
 ELEM_SIZE = {k: torch.empty(0, dtype=t).element_size() for t, k in TORCH_TO_KC.items()}
-OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE, OP_GRAPH = range(7)
+OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE, OP_GRAPH, OP_REGION_DIFF = range(8)
 GRAPH_MAX_RANGES = 16384
 
 SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "kc_default_window",
@@ -34,7 +34,8 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_ctx_enable_timing", "kc_ctx_kernel_ms",
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
-           "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach"]
+           "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
+           "kc_region_diff"]
 
 
 class KCError(RuntimeError):
@@ -130,6 +131,7 @@ def lib() -> ctypes.CDLL:
             "kc_snapshot_load": ([vp, vp, ctypes.c_char_p, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)], i32),
             "kc_pointer_graph": ([vp, vp, u64, u64, vp, vp], i32),
             "kc_graph_reach": ([P(Range), u32, vp, vp, u64, vp], i32),
+            "kc_region_diff": ([vp, vp, u64, vp, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -328,6 +330,32 @@ def restore(ctx: Context, rs: RangeSet, zero_bm, changed_bm, packed, page_va, n_
 def closure_scan(ctx: Context, rs: RangeSet, scan: ScanOut, stream=None) -> None:
     _check(lib().kc_closure_scan(ctx.handle, rs.handle, ctypes.byref(scan.args), _stream(stream)),
            "kc_closure_scan")
+
+
+REGION_DIFF_FIELDS = ("n_diff_bytes", "n_diff_pages", "first_diff_va", "n_bad_pages")
+
+
+def region_diff(ctx: Context, rs: RangeSet, gold: dict, seed: int = 0, cap_pages: int | None = None,
+                out: dict | None = None, stream=None) -> dict:
+    """Per-range byte difference of the live ranges against the full snapshot
+    ``gold`` (as returned by ``snapshot``).  Returns device tensors: res
+    (n_ranges x 4 int64), hash, zero_bm, changed_bm of the live pages."""
+    dev = torch.device("cuda", ctx.device)
+    cap = gold["page_va"].numel() if cap_pages is None else int(cap_pages)
+    n = len(rs.ranges)
+    if out is None:
+        out = dict(res=torch.empty(max(1, n) * 4, dtype=torch.int64, device=dev), hash=_u64(rs.n_pages, dev),
+                   zero_bm=_u64(rs.n_words, dev), changed_bm=_u64(rs.n_words, dev))
+    _check(lib().kc_region_diff(ctx.handle, rs.handle, seed & (2**64 - 1), _ptr(gold["hash"]), _ptr(gold["zero_bm"]),
+                                _ptr(gold["packed"]), _ptr(gold["page_va"]), _ptr(gold["n_kept"]), cap,
+                                _ptr(out["hash"]), _ptr(out["zero_bm"]), _ptr(out["changed_bm"]), _ptr(out["res"]),
+                                _stream(stream)), "kc_region_diff")
+    return out
+
+
+def decode_region_diff(res: torch.Tensor, n: int) -> list[dict]:
+    raw = res[:n * 4].cpu().numpy().view(np.uint64).reshape(n, 4)
+    return [{k: int(v) for k, v in zip(REGION_DIFF_FIELDS, row)} for row in raw]
 
 
 def pointer_graph(ctx: Context, rs: RangeSet, win_lo: int = 0, win_hi: int = 0,

@@ -92,7 +92,7 @@ def test_binding_constants_match_header(kc):
     assert sorted(kc.TORCH_TO_KC.values()) == sorted(enum[k] for k in dts)
     for k in ("OK", "EINVAL", "EALIGN", "EORDER", "ENOMEM", "EHIP", "EDTYPE", "ELIMIT"):
         assert getattr(kc, k) == enum["KC_" + k]
-    for k in ("PAGE_HASH", "SNAPSHOT", "COMPACT", "RESTORE", "CLOSURE", "COMPARE", "GRAPH"):
+    for k in ("PAGE_HASH", "SNAPSHOT", "COMPACT", "RESTORE", "CLOSURE", "COMPARE", "GRAPH", "REGION_DIFF"):
         assert getattr(kc, "OP_" + k) == enum["KC_OP_" + k]
 
 
