@@ -95,6 +95,56 @@ def test_graph_replay_matches_eager(kc):
     ctx.close()
 
 
+def test_graph_replay_region_diff_and_pointer_graph(kc):
+    say("graph: region diff + pointer graph recorded once, replayed over clobbered outputs and changed memory")
+    ctx = kc.Context(0)
+    case = W.graph_case("cuda", n_ranges=300, seed=17, max_pages=8)
+    rs = kc.RangeSet(ctx, case.ranges())
+    n = len(case.ranges())
+    dev = torch.device("cuda", 0)
+    gold = kc.snapshot(ctx, rs)
+    torch.cuda.synchronize()
+
+    def buffers():
+        return dict(res=torch.empty(n * 4, dtype=torch.int64, device=dev),
+                    hash=torch.empty(rs.n_pages, dtype=torch.int64, device=dev),
+                    zero_bm=torch.empty(rs.n_words, dtype=torch.int64, device=dev),
+                    changed_bm=torch.empty(rs.n_words, dtype=torch.int64, device=dev),
+                    edge=torch.empty(n * ((n + 63) // 64), dtype=torch.int64, device=dev))
+
+    def step(b):
+        kc.region_diff(ctx, rs, gold, out=b)
+        kc.pointer_graph(ctx, rs, out=b["edge"])
+
+    live = buffers()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(live)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(live)
+    rng = np.random.default_rng(3)
+    for rep in range(4):
+        if rep >= 2:   # change the live memory between replays
+            idx = torch.from_numpy(rng.integers(0, case.arena.buf.numel(), size=50)).cuda()
+            case.arena.buf[idx] ^= 0x5A
+        eager = buffers()
+        step(eager)
+        torch.cuda.synchronize()
+        for t in live.values():
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in live:
+            assert torch.equal(live[k], eager[k]), (rep, k)
+    rs.close()
+    ctx.close()
+
+
 def test_autotuner_candidates_are_bit_identical(kc, tmp_path, monkeypatch):
     say("autotuner: every candidate of snapshot / compare gives the same outputs")
     from paper_2605_03208_amd import autotune
