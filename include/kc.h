@@ -19,6 +19,8 @@
  *                    mismatch, fp64 max abs / rel error, ULP histogram, NaNs
  *   kc_region_diff   per-range differing bytes of live memory against a
  *                    snapshot, comparing only pages whose hash changed
+ *   kc_vaspace_*     device memory mapped at exactly the captured VAs in a
+ *                    fresh process, for a VA-faithful restore
  *   kc_pointer_graph which range points into which (the graph pointer
  *                    chasing would follow), and kc_graph_reach, the ranges
  *                    reachable from the kernel-argument words
@@ -70,7 +72,8 @@ enum {
   KC_ENOMEM = -4,  /* device or pinned host allocation failed             */
   KC_EHIP = -5,    /* a HIP runtime call failed; see kc_last_error()       */
   KC_EDTYPE = -6,  /* unknown element type                                 */
-  KC_ELIMIT = -7   /* a documented size limit is exceeded                  */
+  KC_ELIMIT = -7,  /* a documented size limit is exceeded                  */
+  KC_ERELOC = -8   /* an address range could not be placed at its VA       */
 };
 
 /* Element types understood by kc_compare.  Floating types get the ULP
@@ -96,6 +99,7 @@ enum {
 typedef struct kc_ctx kc_ctx;
 typedef struct kc_rangeset kc_rangeset;
 typedef struct kc_pairset kc_pairset;
+typedef struct kc_vaspace kc_vaspace;
 
 typedef struct {
   uint64_t base; /* device VA of the allocation */
@@ -289,6 +293,26 @@ int kc_restore(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
                const uint64_t *changed_bm_d, const void *packed_d,
                const uint64_t *page_va_d, const uint64_t *n_kept_d,
                uint64_t cap_pages, uint64_t *n_bad_d, void *stream);
+
+/* ---- address space of a replay (Sec. 4.5.1, replay stages 3-4: reserve each
+ *      captured region at its original VA before anything else allocates,
+ *      abort on relocation) ------------------------------------------------- */
+
+/* Map device memory of `hip_device` at exactly the VAs of the ranges: each
+ * range is covered by a span aligned to the device's virtual-memory
+ * granularity (touching spans merge), every span is reserved at its own
+ * address, backed by device memory and made readable and writable.  If any
+ * span cannot be reserved at its address, everything reserved so far is
+ * released and KC_ERELOC is returned (the replay must not run relocated).
+ * Contents are undefined until restored (kc_snapshot_load + kc_restore).
+ * Call it before other device allocations of the process.  *n_spans and
+ * *mapped_bytes (either may be NULL) report the spans. */
+int kc_vaspace_create(int hip_device, const kc_range *ranges, uint32_t n,
+                      kc_vaspace **out, uint32_t *n_spans,
+                      uint64_t *mapped_bytes);
+
+/* Unmap and release everything kc_vaspace_create mapped (NULL is a no-op). */
+void kc_vaspace_destroy(kc_vaspace *vs);
 
 /* ---- validation ----------------------------------------------------------- */
 

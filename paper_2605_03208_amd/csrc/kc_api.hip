@@ -125,6 +125,7 @@ const char* kc_strerror(int code) {
     case KC_EHIP: return "HIP runtime error";
     case KC_EDTYPE: return "unknown element type";
     case KC_ELIMIT: return "size limit exceeded";
+    case KC_ERELOC: return "address range not available at its original VA";
     default: return "unknown status";
   }
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
 ABI_VERSION = 3  # layout of the structs and the entry-point set below
 
-OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT, ERELOC = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
 F64, FP8_E4M3FNUZ, FP8_E5M2, FP8_E5M2FNUZ, I8, I16, I32, I64 = 5, 6, 7, 8, 9, 10, 11, 12
 TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, torch.float8_e4m3fn: FP8_E4M3FN,
@@ -35,7 +35,7 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
            "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
-           "kc_region_diff"]
+           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy"]
 
 
 class KCError(RuntimeError):
@@ -132,6 +132,8 @@ def lib() -> ctypes.CDLL:
             "kc_pointer_graph": ([vp, vp, u64, u64, vp, vp], i32),
             "kc_graph_reach": ([P(Range), u32, vp, vp, u64, vp], i32),
             "kc_region_diff": ([vp, vp, u64, vp, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp], i32),
+            "kc_vaspace_create": ([i32, P(Range), u32, P(vp), P(u32), P(u64)], i32),
+            "kc_vaspace_destroy": ([vp], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -250,6 +252,31 @@ class RangeSet:
     def close(self) -> None:
         if self.handle:
             lib().kc_rangeset_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VaSpace:
+    """Device memory mapped at exactly the given ranges' VAs (create it before
+    other device allocations of the process); raises KCError with code ERELOC
+    when a range cannot be placed at its address."""
+
+    def __init__(self, device: int, ranges):
+        self.ranges = [(int(b), int(s)) for b, s in ranges]
+        self.handle = ctypes.c_void_p()
+        n_spans, mapped = ctypes.c_uint32(0), ctypes.c_uint64(0)
+        _check(lib().kc_vaspace_create(device, _ranges(self.ranges), len(self.ranges), ctypes.byref(self.handle),
+                                       ctypes.byref(n_spans), ctypes.byref(mapped)), "kc_vaspace_create")
+        self.n_spans, self.mapped_bytes = int(n_spans.value), int(mapped.value)
+
+    def close(self) -> None:
+        if self.handle:
+            lib().kc_vaspace_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

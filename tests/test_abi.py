@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(kc):
 
 def test_abi_version_and_strerror(kc):
     assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 3
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert kc.strerror(code) not in ("", "unknown status")
 
 
@@ -90,7 +90,7 @@ def test_binding_constants_match_header(kc):
         assert getattr(kc, k[3:]) == enum[k], k
         assert k[3:] in {name for name in dir(kc)}
     assert sorted(kc.TORCH_TO_KC.values()) == sorted(enum[k] for k in dts)
-    for k in ("OK", "EINVAL", "EALIGN", "EORDER", "ENOMEM", "EHIP", "EDTYPE", "ELIMIT"):
+    for k in ("OK", "EINVAL", "EALIGN", "EORDER", "ENOMEM", "EHIP", "EDTYPE", "ELIMIT", "ERELOC"):
         assert getattr(kc, k) == enum["KC_" + k]
     for k in ("PAGE_HASH", "SNAPSHOT", "COMPACT", "RESTORE", "CLOSURE", "COMPARE", "GRAPH", "REGION_DIFF"):
         assert getattr(kc, "OP_" + k) == enum["KC_OP_" + k]
@@ -116,3 +116,12 @@ def test_graph_reach_agrees_with_oracle(kc, oracle_lib):
             assert (got == want).all(), (n, roots)
     with pytest.raises(kc.KCError):
         kc.graph_reach([(0x1000, 0x1001)], np.zeros(1, np.uint64), [])
+
+
+def test_vaspace_rejects_bad_ranges_before_any_device_call(kc):
+    """Range validation happens on the host, before the device is touched."""
+    for ranges, code in (([(0x10001000, 0x1001)], kc.EALIGN), ([(0x20000000, 0x1000), (0x10000000, 0x1000)], kc.EORDER),
+                         ([(0, 0x1000)], kc.EINVAL)):
+        with pytest.raises(kc.KCError) as ei:
+            kc.VaSpace(0, ranges)
+        assert ei.value.code == code
