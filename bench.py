@@ -300,6 +300,8 @@ def main() -> int:
     if not args.no_extras:
         log("pointer graph over the same ranges")
         line["pointer_graph"] = pointer_graph_pass(torch, kc, ctx, rs, N, args.steps)
+        log("region diff of the live pool against the step's snapshot, 1 % of pages touched")
+        line["region_diff"] = region_diff_pass(torch, kc, ctx, rs, out, case, N, args.steps)
         log("graph replay of the step")
         line["graph"] = graph_step(torch, step, res, pair_list, kc, args.steps)
         state["ps"].close()
@@ -315,6 +317,42 @@ def main() -> int:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
+
+
+def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int) -> dict:
+    """kc_region_diff over the step's ranges against the step's snapshot, after
+    one byte of every 100th page was flipped (flipped back afterwards)."""
+    import numpy as np
+    cum = case.layout.cum()
+    pages = np.arange(0, n_pages, 100)
+    a = np.searchsorted(cum // PAGE, pages, side="right") - 1
+    offs = case.layout.offsets[a] + (pages - cum[a] // PAGE) * PAGE + 123
+    idx = torch.from_numpy(offs.astype(np.int64)).cuda()
+    buf = case.arena.buf
+    buf[idx] ^= 0x5A
+    out = kc.region_diff(ctx, rs, gold)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        kc.region_diff(ctx, rs, gold, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ctx.enable_timing(True)
+    kc.region_diff(ctx, rs, gold, out=out)
+    kms = ctx.kernel_ms(kc.OP_REGION_DIFF)
+    hms = ctx.kernel_ms(kc.OP_PAGE_HASH)
+    ctx.enable_timing(False)
+    diff = kc.decode_region_diff(out["res"], len(rs.ranges))
+    buf[idx] ^= 0x5A
+    torch.cuda.synchronize()
+    changed = len(pages)
+    alg = n_pages * PAGE + 2 * changed * PAGE
+    return {"op_ms": round(ms, 4), "GBps": round(alg / (ms / 1e3) / 1e9, 1),
+            "frac_of_peak": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "hash_kernel_ms": round(hms, 4), "diff_kernel_ms": round(kms, 4), "pages_changed": changed,
+            "diff_bytes": sum(r["n_diff_bytes"] for r in diff), "diff_pages": sum(r["n_diff_pages"] for r in diff)}
 
 
 def pointer_graph_pass(torch, kc, ctx, rs, n_pages: int, reps: int) -> dict:
