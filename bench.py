@@ -298,6 +298,8 @@ def main() -> int:
         log("oracle CPU baseline on a bounded sample")
         cpu = cpu_baseline(case, ranges, sample_idx)
     if not args.no_extras:
+        log("copy ceiling: plain 4 GiB device-to-device copy")
+        line["copy_ceiling"] = copy_ceiling(torch, dev)
         log("pointer graph over the same ranges")
         line["pointer_graph"] = pointer_graph_pass(torch, kc, ctx, rs, N, args.steps)
         log("region diff of the live pool against the step's snapshot, 1 % of pages touched")
@@ -317,6 +319,26 @@ def main() -> int:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
+
+
+def copy_ceiling(torch, dev, gib: int = 4, reps: int = 5) -> dict:
+    """A plain device copy (torch's copy kernel): what a read+write stream reaches on this part."""
+    src = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * (gib << 30) / (ms / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * (gib << 30), "ms": round(ms, 4), "GBps": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int) -> dict:
