@@ -58,10 +58,15 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# Sources the step's kernels are compiled from (kernels, their device helpers
+# and the shared definitions); the counter values below belong to one version.
+STEP_KERNEL_SOURCES = ("kc_compare.hip", "kc_device.h", "kc_internal.h", "kc_snapshot.hip")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_03208_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in STEP_KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()

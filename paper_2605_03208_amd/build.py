@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libkc.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["kc_api.hip", "kc_snapshot.hip", "kc_compare.hip", "kc_io.hip", "kc_vaspace.hip"]
+SOURCES = ["kc_api.hip", "kc_snapshot.hip", "kc_compare.hip", "kc_io.hip", "kc_vaspace.hip", "kc_graph.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         return obj
 
-    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -6,6 +6,7 @@
 // the XXH64 lanes read their words from a padded LDS stage.
 #include <algorithm>
 
+#include "kc_device.h"
 #include "kc_internal.h"
 
 namespace kc {
@@ -65,12 +66,6 @@ __device__ __forceinline__ uint64_t acc_init(uint64_t seed, uint32_t k) {
 // ------------------------------------------------------------- helpers ----
 __device__ __forceinline__ bool nz16(uint4 v) { return (v.x | v.y | v.z | v.w) != 0u; }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
-
 // OR page bits (bit i = page g0+i) into a bitmap; one lane calls this.
 __device__ __forceinline__ void or_page_bits(uint64_t* bm, uint32_t g0, uint32_t np, uint32_t bits) {
   if (bits == 0u) return;
@@ -87,55 +82,6 @@ __device__ __forceinline__ uint32_t quad_bits(uint64_t ballot) {
 #pragma unroll
   for (uint32_t q = 0; q < 16; ++q) out |= (uint32_t)((ballot >> (4u * q)) & 1ull) << q;
   return out;
-}
-
-// ---------------------------------------------------------- range search --
-struct FenceLds {
-  uint64_t base[kFences];
-  uint64_t end[kFences];
-};
-
-__device__ __forceinline__ void load_fences(FenceLds& f, const RangeTable& rt, uint32_t tid,
-                                            uint32_t nthreads) {
-  for (uint32_t i = tid; i < rt.n_fence; i += nthreads) {
-    const uint32_t r = i * rt.stride;
-    f.base[i] = rt.base[r];
-    f.end[i] = rt.end[r];
-  }
-}
-
-// True iff w lies in [base_r, end_r) for some range r.
-__device__ __forceinline__ bool in_ranges(uint64_t w, const FenceLds& f, const RangeTable& rt) {
-  if (rt.n == 0u || w < f.base[0]) return false;
-  uint32_t i = 0;
-#pragma unroll
-  for (uint32_t step = kFences / 2; step > 0; step >>= 1)
-    if (i + step < rt.n_fence && f.base[i + step] <= w) i += step;
-  if (rt.stride == 1u) return w < f.end[i];
-  uint32_t a = i * rt.stride;
-  uint32_t b = min(a + rt.stride, rt.n);
-  while (b - a > 1u) {
-    const uint32_t m = (a + b) >> 1;
-    if (rt.base[m] <= w) a = m; else b = m;
-  }
-  return w < rt.end[a];
-}
-
-// Index of the range holding w, or -1.
-__device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, const RangeTable& rt) {
-  if (rt.n == 0u || w < f.base[0]) return -1;
-  uint32_t i = 0;
-#pragma unroll
-  for (uint32_t step = kFences / 2; step > 0; step >>= 1)
-    if (i + step < rt.n_fence && f.base[i + step] <= w) i += step;
-  if (rt.stride == 1u) return w < f.end[i] ? (int32_t)i : -1;
-  uint32_t a = i * rt.stride;
-  uint32_t b = min(a + rt.stride, rt.n);
-  while (b - a > 1u) {
-    const uint32_t m = (a + b) >> 1;
-    if (rt.base[m] <= w) a = m; else b = m;
-  }
-  return w < rt.end[a] ? (int32_t)a : -1;
 }
 
 // --------------------------------------------------------------- fill -----
@@ -659,141 +605,6 @@ __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_t
   }
 }
 
-
-// Pointer graph: for every pointer-like word, set bit (source range, target
-// range).  Lanes of a wave that hit the same target share one atomicOr, and a
-// wave skips the target it set last.
-__device__ __forceinline__ void graph_emit(int32_t t, uint32_t lane, uint64_t* row, int32_t& last) {
-  uint64_t pending = __ballot(t >= 0);
-  while (pending) {
-    const int32_t leader = __ffsll((long long)pending) - 1;
-    const int32_t tb = __shfl(t, leader, 64);
-    pending &= ~__ballot(t == tb);
-    if (tb != last && (int32_t)lane == leader) atomicOr((unsigned long long*)&row[tb >> 6], 1ull << (tb & 63));
-    last = tb;
-  }
-}
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_pointer_graph(
-    const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span, RangeTable rt, uint64_t* edge_bm,
-    uint32_t row_words) {
-  __shared__ FenceLds fences;
-  const uint32_t lane = threadIdx.x;
-  load_fences(fences, rt, lane, kWave);
-  __syncthreads();
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const Tile tile = tiles[t];
-    const int32_t src = range_index(tile.va, fences, rt);  // the tile's own range (always found)
-    uint64_t* row = edge_bm + (uint64_t)(src < 0 ? 0 : src) * row_words;
-    int32_t last = -1;
-    const uint32_t nseg = tile.npages * 4u;
-    for (uint32_t s0 = 0; s0 < nseg; s0 += 8) {
-      uint4 x[8];
-#pragma unroll
-      for (uint32_t i = 0; i < 8; ++i)
-        x[i] = (s0 + i < nseg) ? ld16nt(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) {
-        const uint64_t w0 = ((uint64_t)x[i].y << 32) | x[i].x;
-        const uint64_t w1 = ((uint64_t)x[i].w << 32) | x[i].z;
-        const bool p0 = (w0 - lo) < span, p1 = (w1 - lo) < span;
-        if (__ballot(p0 || p1) == 0ull || src < 0) continue;  // no pointer-like word here
-        graph_emit(p0 ? range_index(w0, fences, rt) : -1, lane, row, last);
-        graph_emit(p1 ? range_index(w1, fences, rt) : -1, lane, row, last);
-      }
-    }
-  }
-}
-
-// Per-range byte difference against a full snapshot.  Pages are visited in
-// order inside a tile; the snapshot slot of a non-zero page is its rank among
-// the non-zero pages (prefix per bitmap word + popcount below its bit).
-__global__ void k_region_init(kc_region_diff_result* res, uint32_t n, uint64_t* bm_a, uint64_t* bm_b, uint64_t n_words) {
-  const uint64_t m = n > n_words ? n : n_words;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
-    if (i < n) {
-      res[i].n_diff_bytes = 0;
-      res[i].n_diff_pages = 0;
-      res[i].first_diff_va = ~0ull;
-      res[i].n_bad_pages = 0;
-    }
-    if (i < n_words) {
-      bm_a[i] = 0;
-      bm_b[i] = 0;
-    }
-  }
-}
-
-__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t x) {
-  return (uint32_t)((x & 0xFFu) != 0u) + (uint32_t)((x & 0xFF00u) != 0u) + (uint32_t)((x & 0xFF0000u) != 0u) +
-         (uint32_t)((x & 0xFF000000u) != 0u);
-}
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_region_diff(
-    const Tile* tiles, uint32_t n_tiles, RangeTable rt, const uint64_t* changed_bm, const uint64_t* gold_zero_bm,
-    const uint64_t* rank_prefix, const uint64_t* gold_page_va, const uint64_t* gold_n_kept, uint64_t cap,
-    const uint8_t* gold_packed, kc_region_diff_result* res) {
-  __shared__ FenceLds fences;
-  const uint32_t lane = threadIdx.x;
-  load_fences(fences, rt, lane, kWave);
-  __syncthreads();
-  const uint64_t kept = *gold_n_kept;
-  const uint64_t n_valid = kept < cap ? kept : cap;
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const Tile tile = tiles[t];
-    const int32_t a = range_index(tile.va, fences, rt);
-    uint64_t bad = 0, dbytes = 0, dpages = 0, first = ~0ull;
-    for (uint32_t j = 0; j < tile.npages; ++j) {
-      const uint64_t g = (uint64_t)tile.g + j, va = tile.va + (uint64_t)j * kPage;
-      const uint64_t zw = gold_zero_bm[g >> 6], below = (1ull << (g & 63u)) - 1ull;
-      const bool zero = (zw >> (g & 63u)) & 1ull;
-      uint64_t gp = 0;
-      if (!zero) {
-        const uint64_t s = rank_prefix[g >> 6] + (uint64_t)__popcll(~zw & below);
-        if (s >= n_valid || gold_page_va[s] != va) {
-          ++bad;
-          continue;
-        }
-        gp = (uint64_t)(gold_packed + s * kPage);
-      }
-      if (!((changed_bm[g >> 6] >> (g & 63u)) & 1ull)) continue;
-      uint32_t nd = 0, fo = ~0u;
-#pragma unroll
-      for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t off = k * 1024u + lane * 16u;
-        const uint4 c = ld16nt(va + off);
-        const uint4 d = zero ? make_uint4(0, 0, 0, 0) : ld16nt(gp + off);
-        const uint32_t x[4] = {c.x ^ d.x, c.y ^ d.y, c.z ^ d.z, c.w ^ d.w};
-#pragma unroll
-        for (uint32_t i = 0; i < 4; ++i) {
-          nd += nonzero_bytes(x[i]);
-          if (x[i] != 0u && fo == ~0u) fo = off + 4u * i + ((uint32_t)__builtin_ctz(x[i]) >> 3);
-        }
-      }
-      nd = wave_sum_u32(nd);
-#pragma unroll
-      for (int dd = 32; dd >= 1; dd >>= 1) {
-        const uint32_t y = __shfl_xor(fo, dd, 64);
-        fo = y < fo ? y : fo;
-      }
-      if (nd) {
-        dbytes += nd;
-        ++dpages;
-        if (first == ~0ull) first = va + fo;  // pages ascend inside a tile
-      }
-    }
-    if (lane == 0 && a >= 0) {
-      kc_region_diff_result* r = res + a;
-      if (dbytes) {
-        atomicAdd((unsigned long long*)&r->n_diff_bytes, (unsigned long long)dbytes);
-        atomicAdd((unsigned long long*)&r->n_diff_pages, (unsigned long long)dpages);
-        atomicMin((unsigned long long*)&r->first_diff_va, (unsigned long long)first);
-      }
-      if (bad) atomicAdd((unsigned long long*)&r->n_bad_pages, (unsigned long long)bad);
-    }
-  }
-}
-
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 }  // namespace
@@ -889,36 +700,6 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, c
   grid = grid < 1u ? 1u : grid;
   hipLaunchKernelGGL(k_restore_scatter, dim3(grid), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
                      n_bad);
-  return hipGetLastError();
-}
-
-hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
-                                const RangeTable& rt, uint64_t* edge_bm, uint32_t row_words, uint32_t grid,
-                                hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_pointer_graph, dim3(grid), dim3(64), 0, s, tiles, n_tiles, lo, span, rt, edge_bm, row_words);
-  return hipGetLastError();
-}
-
-hipError_t launch_region_init(kc_region_diff_result* res, uint32_t n, uint64_t* bm_a, uint64_t* bm_b, uint64_t n_words,
-                              hipStream_t s) {
-  const uint64_t m = std::max<uint64_t>(n, n_words);
-  if (m == 0) return hipSuccess;
-  const uint64_t nbk = blocks_for(m, 256);
-  hipLaunchKernelGGL(k_region_init, dim3((uint32_t)(nbk < 4096 ? nbk : 4096)), dim3(256), 0, s, res, n, bm_a, bm_b,
-                     n_words);
-  return hipGetLastError();
-}
-
-hipError_t launch_region_diff(const Tile* tiles, uint32_t n_tiles, const RangeTable& rt, const uint64_t* changed_bm,
-                              const uint64_t* gold_zero_bm, const uint64_t* rank_prefix, const uint64_t* gold_page_va,
-                              const uint64_t* gold_n_kept, uint64_t cap, const uint8_t* gold_packed,
-                              kc_region_diff_result* res, uint32_t grid, hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_region_diff, dim3(grid), dim3(64), 0, s, tiles, n_tiles, rt, changed_bm, gold_zero_bm,
-                     rank_prefix, gold_page_va, gold_n_kept, cap, gold_packed, res);
   return hipGetLastError();
 }
 
