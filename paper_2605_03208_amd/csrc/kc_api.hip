@@ -273,7 +273,8 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   const size_t sz_wp = align_up(8 * std::max<uint64_t>(1, rs->n_words), 256);
   const size_t sz_bs = align_up(8 * std::max<uint64_t>(1, std::max(nb_words, nb_tiles)), 256);
   const size_t sz_misc = 256;
-  const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc;
+  const size_t sz_bk = align_up(sizeof(uint16_t) * kBuckets, 256);
+  const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk;
   hipError_t e = hipMalloc(&rs->dev, total);
   if (e != hipSuccess) {
     set_error("hipMalloc(rangeset)", e);
@@ -290,6 +291,21 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->block_sums = reinterpret_cast<uint64_t*>(p); p += sz_bs;
   rs->counts = reinterpret_cast<unsigned long long*>(p);
   rs->n_oob = reinterpret_cast<uint64_t*>(p + 64);
+  p += sz_misc;
+  uint16_t* bucket_d = reinterpret_cast<uint16_t*>(p);
+  // Bucket index over [lowest base, highest end): the last fence at or below
+  // each bucket's first address.
+  const uint32_t stride = n <= kFences ? 1u : (n + kFences - 1) / kFences;
+  const uint32_t n_fence = n == 0 ? 0u : (n + stride - 1) / stride;
+  const uint64_t lo = n ? ranges[0].base : 0, span = n ? ranges[n - 1].base + ranges[n - 1].size - lo : 0;
+  uint32_t shift = 12;
+  while (span > 0 && ((span - 1) >> shift) >= kBuckets) ++shift;
+  std::vector<uint16_t> bucket(kBuckets, 0);
+  for (uint32_t b = 0, i = 0; b < kBuckets && n > 0; ++b) {
+    const uint64_t start = (uint64_t)b << shift;  // offset from lo
+    while (i + 1 < n_fence && ranges[(uint64_t)(i + 1) * stride].base - lo <= start) ++i;
+    bucket[b] = (uint16_t)i;
+  }
 
   auto fail = [&](const char* what, hipError_t err) {
     set_error(what, err);
@@ -307,11 +323,17 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
       return fail("hipMemcpy(ends)", e);
   }
   if ((e = hipMemset(rs->counts, 0, sz_misc)) != hipSuccess) return fail("hipMemset(counts)", e);
+  if ((e = hipMemcpy(bucket_d, bucket.data(), sizeof(uint16_t) * kBuckets, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("hipMemcpy(bucket index)", e);
   rs->rt.base = rs->bases;
   rs->rt.end = rs->ends;
+  rs->rt.bucket = bucket_d;
+  rs->rt.lo = lo;
+  rs->rt.span = span;
   rs->rt.n = n;
-  rs->rt.stride = n <= kFences ? 1u : (n + kFences - 1) / kFences;
-  rs->rt.n_fence = n == 0 ? 0u : (n + rs->rt.stride - 1) / rs->rt.stride;
+  rs->rt.stride = stride;
+  rs->rt.n_fence = n_fence;
+  rs->rt.shift = shift;
   *out = rs;
   if (n_pages_out) *n_pages_out = n_pages;
   return KC_OK;

@@ -16,6 +16,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
 struct FenceLds {
   uint64_t base[kFences];
   uint64_t end[kFences];
+  uint16_t bucket[kBuckets];
 };
 
 __device__ __forceinline__ void load_fences(FenceLds& f, const RangeTable& rt, uint32_t tid,
@@ -25,32 +26,27 @@ __device__ __forceinline__ void load_fences(FenceLds& f, const RangeTable& rt, u
     f.base[i] = rt.base[r];
     f.end[i] = rt.end[r];
   }
+  if (rt.n != 0u)
+    for (uint32_t i = tid; i < kBuckets; i += nthreads) f.bucket[i] = rt.bucket[i];
 }
 
-// True iff w lies in [base_r, end_r) for some range r.
-__device__ __forceinline__ bool in_ranges(uint64_t w, const FenceLds& f, const RangeTable& rt) {
-  if (rt.n == 0u || w < f.base[0]) return false;
-  uint32_t i = 0;
-#pragma unroll
-  for (uint32_t step = kFences / 2; step > 0; step >>= 1)
-    if (i + step < rt.n_fence && f.base[i + step] <= w) i += step;
-  if (rt.stride == 1u) return w < f.end[i];
-  uint32_t a = i * rt.stride;
-  uint32_t b = min(a + rt.stride, rt.n);
-  while (b - a > 1u) {
-    const uint32_t m = (a + b) >> 1;
-    if (rt.base[m] <= w) a = m; else b = m;
+// Last fence whose base is at or below w, for lo <= w < lo + span: start at the
+// bucket's entry and search only up to the next bucket's (usually no step).
+__device__ __forceinline__ uint32_t fence_of(uint64_t w, const FenceLds& f, const RangeTable& rt) {
+  const uint32_t b = (uint32_t)((w - rt.lo) >> rt.shift);
+  uint32_t i = f.bucket[b];
+  uint32_t j = b + 1u < kBuckets ? f.bucket[b + 1u] : rt.n_fence - 1u;
+  while (i < j) {
+    const uint32_t m = (i + j + 1u) >> 1;
+    if (f.base[m] <= w) i = m; else j = m - 1u;
   }
-  return w < rt.end[a];
+  return i;
 }
 
 // Index of the range holding w, or -1.
 __device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, const RangeTable& rt) {
-  if (rt.n == 0u || w < f.base[0]) return -1;
-  uint32_t i = 0;
-#pragma unroll
-  for (uint32_t step = kFences / 2; step > 0; step >>= 1)
-    if (i + step < rt.n_fence && f.base[i + step] <= w) i += step;
+  if (rt.n == 0u || w - rt.lo >= rt.span) return -1;  // below the lowest base wraps to a large offset
+  const uint32_t i = fence_of(w, f, rt);
   if (rt.stride == 1u) return w < f.end[i] ? (int32_t)i : -1;
   uint32_t a = i * rt.stride;
   uint32_t b = min(a + rt.stride, rt.n);
@@ -59,6 +55,11 @@ __device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, co
     if (rt.base[m] <= w) a = m; else b = m;
   }
   return w < rt.end[a] ? (int32_t)a : -1;
+}
+
+// True iff w lies in [base_r, end_r) for some range r.
+__device__ __forceinline__ bool in_ranges(uint64_t w, const FenceLds& f, const RangeTable& rt) {
+  return range_index(w, f, rt) >= 0;
 }
 
 }  // namespace kc

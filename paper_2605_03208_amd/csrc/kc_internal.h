@@ -17,6 +17,7 @@ constexpr uint32_t kTilePages = 16;     // pages per wave tile (one lane quad pe
 constexpr uint32_t kChunk = 512;        // bytes of each page staged per step
 constexpr uint32_t kStageStride = kChunk + 32;  // padded LDS row: quads land in distinct banks
 constexpr uint32_t kFences = 256;       // range-table entries held in LDS
+constexpr uint32_t kBuckets = 1024;     // entries of the LDS bucket index over the ranges
 
 // 16-byte global accesses.  Data that streams through once (pages, packed
 // snapshot, compared buffers) uses non-temporal loads and stores, which on
@@ -42,13 +43,19 @@ struct Tile {
 };
 static_assert(sizeof(Tile) == 16, "tile layout");
 
-// Sorted range table on the device (bases and one-past-end addresses).
+// Sorted range table on the device (bases and one-past-end addresses), with
+// a bucket index over [lo, lo + span) = [lowest base, highest end): bucket b
+// covers addresses lo + [b << shift, (b + 1) << shift) and holds the last
+// fence whose base is at or below the bucket's first address.
 struct RangeTable {
   const uint64_t* base;
   const uint64_t* end;
+  const uint16_t* bucket;  // kBuckets entries
+  uint64_t lo, span;
   uint32_t n;
   uint32_t stride;   // LDS fence stride: fence i = range i * stride
   uint32_t n_fence;  // ceil(n / stride) <= kFences
+  uint32_t shift;
 };
 
 struct ScanDev {

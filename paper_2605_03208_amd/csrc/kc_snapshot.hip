@@ -582,25 +582,32 @@ __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_t
     const Tile tile = tiles[t];
     const uint32_t nseg = tile.npages * 4u;
     uint64_t done = 0;
-    for (uint32_t s = 0; s < nseg && done < cnt && pre + done < cap; ++s) {
-      const uint64_t a = tile.va + (uint64_t)s * 1024u + lane * 16u;
-      const uint4 v = ld16(a);
-      const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
-      const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
-      const bool o0 = (w0 - sd.lo) < sd.span && !in_ranges(w0, fences, sd.rt);
-      const bool o1 = (w1 - sd.lo) < sd.span && !in_ranges(w1, fences, sd.rt);
-      const uint64_t b0 = __ballot(o0), b1 = __ballot(o1);
-      const uint64_t r0 = pre + done + (uint64_t)__popcll(b0 & below) + (uint64_t)__popcll(b1 & below);
-      const uint64_t r1 = r0 + (o0 ? 1u : 0u);
-      if (o0 && r0 < cap) {
-        oob[r0].word_va = a;
-        oob[r0].value = w0;
+    // eight 1-KiB segments per round trip; within them, segments in order
+    for (uint32_t s0 = 0; s0 < nseg && done < cnt && pre + done < cap; s0 += 8) {
+      uint4 x[8];
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i)
+        x[i] = s0 + i < nseg ? ld16(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) {  // words past the tile are zero: never pointer-like
+        const uint64_t a = tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u;
+        const uint64_t w0 = ((uint64_t)x[i].y << 32) | x[i].x;
+        const uint64_t w1 = ((uint64_t)x[i].w << 32) | x[i].z;
+        const bool o0 = (w0 - sd.lo) < sd.span && !in_ranges(w0, fences, sd.rt);
+        const bool o1 = (w1 - sd.lo) < sd.span && !in_ranges(w1, fences, sd.rt);
+        const uint64_t b0 = __ballot(o0), b1 = __ballot(o1);
+        const uint64_t r0 = pre + done + (uint64_t)__popcll(b0 & below) + (uint64_t)__popcll(b1 & below);
+        const uint64_t r1 = r0 + (o0 ? 1u : 0u);
+        if (o0 && r0 < cap) {
+          oob[r0].word_va = a;
+          oob[r0].value = w0;
+        }
+        if (o1 && r1 < cap) {
+          oob[r1].word_va = a + 8u;
+          oob[r1].value = w1;
+        }
+        done += (uint64_t)__popcll(b0) + (uint64_t)__popcll(b1);
       }
-      if (o1 && r1 < cap) {
-        oob[r1].word_va = a + 8u;
-        oob[r1].value = w1;
-      }
-      done += (uint64_t)__popcll(b0) + (uint64_t)__popcll(b1);
     }
   }
 }
