@@ -158,6 +158,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 #pragma unroll 1
     for (uint32_t c = 0; c < kPage / kChunk; ++c) {
+      uint32_t ptr_mask = 0;  // bit 2j+h: word h of this lane's 16 bytes of load j is pointer-like
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
         const uint32_t pg = 2 * j + half;
@@ -166,21 +167,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const uint64_t b = __ballot(nz16(v));
           nonzero |= ((uint32_t)((uint32_t)b != 0u) << (2 * j)) | ((uint32_t)((b >> 32) != 0ull) << (2 * j + 1));
         }
-        if (SCAN) {
+        if (SCAN) {  // pointer-like words are only marked here; the range search runs once per chunk
           const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
           const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
-          const bool p0 = (w0 - scan_lo) < scan_span;
-          const bool p1 = (w1 - scan_lo) < scan_span;
-          if (__ballot(p0 || p1)) {
-            if (p0) {
-              ++n_ptr;
-              if (in_ranges(w0, fences, p.scan.rt)) ++n_in; else ++oob;
-            }
-            if (p1) {
-              ++n_ptr;
-              if (in_ranges(w1, fences, p.scan.rt)) ++n_in; else ++oob;
-            }
-          }
+          const uint32_t p0 = (w0 - scan_lo) < scan_span ? 1u : 0u;
+          const uint32_t p1 = (w1 - scan_lo) < scan_span ? 1u : 0u;
+          ptr_mask |= (p0 << (2 * j)) | (p1 << (2 * j + 1));
         }
         if (GATHER) {
           if (((keep >> pg) & 1u) && slot_j[j] < p.cap_pages)
@@ -197,6 +189,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint32_t pg = 2 * j + half;
         cur[j] = ((more >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + cn * kChunk + off16)
                                      : make_uint4(0, 0, 0, 0);
+      }
+      if (SCAN && __ballot(ptr_mask != 0u)) {
+        // the marked words, read back from the stage: one search chain per lane per chunk
+        n_ptr += (uint32_t)__popc(ptr_mask);
+        for (uint32_t m = ptr_mask; m != 0u; m &= m - 1u) {
+          const uint32_t bit = (uint32_t)__builtin_ctz(m);
+          const uint64_t w = *reinterpret_cast<const uint64_t*>(stage + (2u * (bit >> 1) + half) * kStageStride +
+                                                                 off16 + (bit & 1u) * 8u);
+          if (in_ranges(w, fences, p.scan.rt)) ++n_in; else ++oob;
+        }
       }
       const uint8_t* row = stage + q * kStageStride + k * 8u;
 #pragma unroll
