@@ -43,14 +43,14 @@ HBM_PEAK_GBS = 8000.0
 PAGE = 4096
 
 # HBM traffic of the main kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
-# then WRITE_SIZE) of `bench.py --steps 2 --warmup 1 --no-cpu --no-extras`,
+# then WRITE_SIZE) of `bench.py --steps 2 --warmup 1 --no-cpu --no-extras --no-tune`,
 # per launch, scaled by the factors a plain 4 GiB device copy gives (fetch
 # x2.0, write x1.0).  Valid only for the kernel sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "551f9af27bb6744700457d88c11b8d6c2a7ffade63bcc57af34ad590f49174d9",
-    "snapshot": 62932939319,   # fetch 31432054094 + write 31500885225
-    "restore": 62951835019,    # fetch 31597952446 + write 31353882573
-    "compare": 64455914708,    # fetch 64455914708 + write 0
+    "source_sha256": "2c4ef7ce667798211da73185f094e5cac466ed3664931f45bb86c0d1d6c7d98c",
+    "snapshot": 62933975772,  # fetch 31432303269 + write 31501672503
+    "restore": 62952006989,   # fetch 31598330778 + write 31353676211
+    "compare": 64456598118,   # fetch 64456598118 + write 0
 }
 
 
