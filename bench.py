@@ -132,6 +132,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB three times (counter calibration) and exit")
+    ap.add_argument("--c1-only", action="store_true",
+                    help="only measure the small latency-bound case (64 MiB snapshot + restore + compare) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -158,6 +160,9 @@ def main() -> int:
     kc.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.c1_only:
+        print(json.dumps({"c1_latency": c1_latency(torch, kc, W, dev)}), flush=True)
+        return 0
     log(f"generating the MoE pool at scale {args.scale}")
     case = W.c4_snapshot("cuda", scale=args.scale)
     ranges = case.ranges()

@@ -159,7 +159,6 @@ int kc_ctx_create(kc_ctx** out, int hip_device) {
   c->device = hip_device;
   c->n_cu = cu > 0 ? (uint32_t)cu : 256u;
   std::memset(c->tune, 0, sizeof(c->tune));
-  c->tune[KC_OP_COMPARE].tile_bytes = 64u << 10;
   hipError_t e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
   if (e != hipSuccess) {
     set_error("hipEventCreateWithFlags", e);
@@ -216,7 +215,6 @@ int kc_ctx_set_tuning(kc_ctx* c, uint32_t op, const kc_tuning* t) {
   if (t->tile_bytes != 0 && (t->tile_bytes % 16u != 0 || t->tile_bytes < 4096u || t->tile_bytes > (64u << 20)))
     return KC_EINVAL;
   c->tune[op] = *t;
-  if (op == KC_OP_COMPARE && c->tune[op].tile_bytes == 0) c->tune[op].tile_bytes = 64u << 10;
   return KC_OK;
 }
 
@@ -682,7 +680,8 @@ void fill_pair_tables(const kc_pair* pairs, uint32_t n_pairs, const std::vector<
 int run_compare(kc_ctx* c, const CmpPairDev* dpairs, const CmpTileDev* dtiles, const std::vector<uint64_t>& tile_off,
                 uint32_t n_pairs, uint32_t tile_bytes, unsigned long long* dacc, uint64_t acc_words, bool* acc_dirty,
                 kc_cmp_result* res_d, hipStream_t s) {
-  const uint32_t grid = grid_for(c, KC_OP_COMPARE, 2);
+  // built-in shape: 2 workgroups per CU, 4 when there are few tiles to share
+  const uint32_t grid = grid_for(c, KC_OP_COMPARE, tile_off[n_pairs] < 16ull * c->n_cu ? 4 : 2);
   if (*acc_dirty) KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(dacc), acc_words, 0, s));
   *acc_dirty = true;
   {
@@ -700,8 +699,17 @@ int run_compare(kc_ctx* c, const CmpPairDev* dpairs, const CmpTileDev* dtiles, c
   return KC_OK;
 }
 
-uint32_t compare_tile_bytes(const kc_ctx* c) {
-  return c->tune[KC_OP_COMPARE].tile_bytes ? c->tune[KC_OP_COMPARE].tile_bytes : (64u << 10);
+// Tuned tile size, else 64 KiB halved (down to 16 KiB) while the pairs would
+// give fewer than eight tiles per compute unit: small batches still spread
+// over the whole chip.
+uint32_t compare_tile_bytes(const kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs) {
+  if (c->tune[KC_OP_COMPARE].tile_bytes) return c->tune[KC_OP_COMPARE].tile_bytes;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < n_pairs; ++i)
+    if (pairs[i].dtype <= KC_I64 && pairs[i].n_elems <= (1ull << 60)) total += pairs[i].n_elems * elem_size(pairs[i].dtype);
+  uint32_t tb = 64u << 10;
+  while (tb > (16u << 10) && total / tb < 8ull * c->n_cu) tb >>= 1;
+  return tb;
 }
 
 }  // namespace
@@ -711,7 +719,7 @@ extern "C" {
 int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result* res_d, void* stream) {
   if (c == nullptr || (n_pairs > 0 && (pairs == nullptr || res_d == nullptr))) return KC_EINVAL;
   if (n_pairs == 0) return KC_OK;
-  const uint32_t tile_bytes = compare_tile_bytes(c);
+  const uint32_t tile_bytes = compare_tile_bytes(c, pairs, n_pairs);
   std::vector<uint64_t> tile_off;
   int st = plan_pairs(pairs, n_pairs, tile_bytes, tile_off);
   if (st != KC_OK) return st;
@@ -782,7 +790,7 @@ int kc_compare(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp_result*
 int kc_pairset_create(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_pairset** out) {
   if (c == nullptr || out == nullptr || (n_pairs > 0 && pairs == nullptr)) return KC_EINVAL;
   *out = nullptr;
-  const uint32_t tile_bytes = compare_tile_bytes(c);
+  const uint32_t tile_bytes = compare_tile_bytes(c, pairs, n_pairs);
   std::vector<uint64_t> tile_off;
   int st = plan_pairs(pairs, n_pairs, tile_bytes, tile_off);
   if (st != KC_OK) return st;
