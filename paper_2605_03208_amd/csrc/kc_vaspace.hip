@@ -94,10 +94,10 @@ int kc_vaspace_create(int hip_device, const kc_range* ranges, uint32_t n, kc_vas
     hipError_t e = hipMemAddressReserve(&got, s.size, gran, want, 0);
     if (e != hipSuccess || got != want) {
       if (e == hipSuccess) (void)hipMemAddressFree(got, s.size);
-      char msg[160];
-      std::snprintf(msg, sizeof(msg), "span 0x%llx + 0x%llx not reservable at its VA (%s)",
-                    (unsigned long long)s.base, (unsigned long long)s.size,
-                    e == hipSuccess ? "placed elsewhere" : hipGetErrorName(e));
+      char msg[224];
+      std::snprintf(msg, sizeof(msg), "span 0x%llx + 0x%llx (granularity 0x%llx) not reservable at its VA: %s 0x%llx",
+                    (unsigned long long)s.base, (unsigned long long)s.size, (unsigned long long)gran,
+                    e == hipSuccess ? "placed at" : hipGetErrorName(e), (unsigned long long)(uintptr_t)got);
       release_all(vs);
       delete vs;
       kc::set_error_text(msg);

@@ -154,7 +154,7 @@ def strerror(code: int) -> str:
 
 def _check(code: int, what: str) -> None:
     if code != OK:
-        detail = lib().kc_last_error().decode() if code == EHIP else ""
+        detail = lib().kc_last_error().decode() if code in (EHIP, ERELOC) else ""
         raise KCError(code, what, detail)
 
 

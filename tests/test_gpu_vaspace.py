@@ -43,6 +43,7 @@ def test_cross_process_restore_at_the_captured_vas(kc, tmp_path):
     say("vaspace: capture in one process, replay at the same VAs in a fresh one")
     d = str(tmp_path / "snap")
     r = _child("capture", d)
+    print(r.stdout, flush=True)
     assert r.returncode == 0, r.stdout + r.stderr
     r = _child("replay", d)
     print(r.stdout, r.stderr[-2000:], flush=True)

@@ -42,7 +42,10 @@ def capture(d):
                 edges=[int(x) for x in edge.reshape(-1)])
     with open(os.path.join(d, "capture.json"), "w") as f:
         json.dump(info, f)
-    print(json.dumps({"captured": len(ranges), "n_kept": info["n_kept"], "n_in_range": res["n_in_range"]}))
+    probe = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")   # where this allocator goes next
+    print(json.dumps({"captured": len(ranges), "n_kept": info["n_kept"], "n_in_range": res["n_in_range"],
+                      "lowest": hex(ranges[0][0]), "highest_end": hex(ranges[-1][0] + ranges[-1][1]),
+                      "next_allocation": hex(probe.data_ptr())}))
     return 0
 
 
@@ -56,7 +59,8 @@ def replay(d):
         vs = kc.VaSpace(0, ranges)          # the first device allocation of this process
     except kc.KCError as e:
         if e.code == kc.ERELOC:
-            print(json.dumps({"relocated": str(e)}), flush=True)
+            probe = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+            print(json.dumps({"relocated": str(e), "first_allocation_here": hex(probe.data_ptr())}), flush=True)
             return 3
         raise
     ctx = kc.Context(0)
