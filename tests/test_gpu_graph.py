@@ -121,3 +121,39 @@ def test_graph_limits_and_empty(kc, ctx):
         kc.pointer_graph(ctx, rs, 0, 100)
     assert ei.value.code == kc.EINVAL
     rs.close()
+
+
+def test_ranges_from_far_apart_allocations(kc, ctx):
+    say("range lookups: 520 ranges in two arenas gigabytes apart, cross pointers, scan + graph + hash vs oracle")
+    a = W.graph_case("cuda", n_ranges=260, seed=41, max_pages=3)
+    spacer = torch.empty(3 << 30, dtype=torch.uint8, device="cuda")   # pushes the second arena far away
+    b = W.graph_case("cuda", n_ranges=260, seed=42, max_pages=3)
+    cases = sorted([a, b], key=lambda c: c.arena.va_base)
+    ranges = cases[0].ranges() + cases[1].ranges()
+    say(f"gap between the arenas: {(ranges[260][0] - ranges[259][0]) / 2**30:.2f} GiB")
+    # pointers from the lower arena into the upper one and back, at known words
+    rng = np.random.default_rng(3)
+    for src, dst in ((cases[0], cases[1]), (cases[1], cases[0])):
+        words = src.arena.buf.view(torch.int64)
+        dr = dst.ranges()
+        for _ in range(40):
+            base, size = dr[int(rng.integers(0, len(dr)))]
+            r0, s0 = src.ranges()[int(rng.integers(0, len(dr)))]
+            w = (r0 - src.arena.va_base) // 8 + int(rng.integers(0, s0 // 8))
+            words[w] = base + int(rng.integers(0, size))
+    torch.cuda.synchronize()
+    rs = kc.RangeSet(ctx, ranges)
+    edge = kc.pointer_graph(ctx, rs)
+    scan = kc.ScanOut("cuda", oob_cap=256)
+    h, z, _ = kc.page_hash(ctx, rs, scan=scan)
+    torch.cuda.synchronize()
+    views = W.host_views(cases[0].layout, cases[0].arena.host_copy()) + \
+        W.host_views(cases[1].layout, cases[1].arena.host_copy())
+    assert np.array_equal(edge.cpu().numpy().view(np.uint64), oracle.pointer_graph(ranges, views))
+    res, oob = scan.result()
+    o_res, o_oob = oracle.closure_scan(ranges, views, oob_cap=256)
+    assert res == o_res and oob == o_oob
+    oh, oz, _ = oracle.page_hash(ranges, views)
+    assert np.array_equal(h.cpu().numpy().view(np.uint64)[:rs.n_pages], oh)
+    rs.close()
+    del spacer
