@@ -124,35 +124,46 @@ def test_graph_limits_and_empty(kc, ctx):
 
 
 def test_ranges_from_far_apart_allocations(kc, ctx):
-    say("range lookups: 520 ranges in two arenas gigabytes apart, cross pointers, scan + graph + hash vs oracle")
+    say("range lookups: 520 small ranges plus two at the ends of a 3 GiB allocation, cross pointers, "
+        "scan + graph + hash vs oracle")
     a = W.graph_case("cuda", n_ranges=260, seed=41, max_pages=3)
-    spacer = torch.empty(3 << 30, dtype=torch.uint8, device="cuda")   # pushes the second arena far away
     b = W.graph_case("cuda", n_ranges=260, seed=42, max_pages=3)
-    cases = sorted([a, b], key=lambda c: c.arena.va_base)
-    ranges = cases[0].ranges() + cases[1].ranges()
-    say(f"gap between the arenas: {(ranges[260][0] - ranges[259][0]) / 2**30:.2f} GiB")
-    # pointers from the lower arena into the upper one and back, at known words
+    spacer = torch.zeros(3 << 30, dtype=torch.uint8, device="cuda")
+    s0 = (spacer.data_ptr() + PAGE - 1) // PAGE * PAGE
+    s1 = (spacer.data_ptr() + spacer.numel()) // PAGE * PAGE - 2 * PAGE
+    far = [(s0, 2 * PAGE), (s1, 2 * PAGE)]           # the span of the set now covers gigabytes
+    # pointers between the arenas and into the far ranges, at known words
     rng = np.random.default_rng(3)
-    for src, dst in ((cases[0], cases[1]), (cases[1], cases[0])):
+    targets = a.ranges() + b.ranges() + far
+    for src in (a, b):
         words = src.arena.buf.view(torch.int64)
-        dr = dst.ranges()
-        for _ in range(40):
-            base, size = dr[int(rng.integers(0, len(dr)))]
-            r0, s0 = src.ranges()[int(rng.integers(0, len(dr)))]
-            w = (r0 - src.arena.va_base) // 8 + int(rng.integers(0, s0 // 8))
-            words[w] = base + int(rng.integers(0, size))
+        for _ in range(60):
+            base, size = targets[int(rng.integers(0, len(targets)))]
+            r0, sz0 = src.ranges()[int(rng.integers(0, 260))]
+            words[(r0 - src.arena.va_base) // 8 + int(rng.integers(0, sz0 // 8))] = base + int(rng.integers(0, size))
+    spacer[s0 - spacer.data_ptr():s0 - spacer.data_ptr() + 8] = torch.tensor(
+        [a.ranges()[5][0] + 16], dtype=torch.int64).view(torch.uint8).cuda()
     torch.cuda.synchronize()
+    views_by_base = {}
+    for c in (a, b):
+        for (base, _), v in zip(c.ranges(), W.host_views(c.layout, c.arena.host_copy())):
+            views_by_base[base] = v
+    for base, size in far:
+        off = base - spacer.data_ptr()
+        views_by_base[base] = spacer[off:off + size].cpu().numpy()
+    ranges = sorted(targets)
+    views = [views_by_base[base] for base, _ in ranges]
+    say(f"span of the set: {(ranges[-1][0] + ranges[-1][1] - ranges[0][0]) / 2**30:.2f} GiB, {len(ranges)} ranges")
     rs = kc.RangeSet(ctx, ranges)
     edge = kc.pointer_graph(ctx, rs)
     scan = kc.ScanOut("cuda", oob_cap=256)
     h, z, _ = kc.page_hash(ctx, rs, scan=scan)
     torch.cuda.synchronize()
-    views = W.host_views(cases[0].layout, cases[0].arena.host_copy()) + \
-        W.host_views(cases[1].layout, cases[1].arena.host_copy())
     assert np.array_equal(edge.cpu().numpy().view(np.uint64), oracle.pointer_graph(ranges, views))
     res, oob = scan.result()
     o_res, o_oob = oracle.closure_scan(ranges, views, oob_cap=256)
     assert res == o_res and oob == o_oob
+    assert res["n_in_range"] >= 120
     oh, oz, _ = oracle.page_hash(ranges, views)
     assert np.array_equal(h.cpu().numpy().view(np.uint64)[:rs.n_pages], oh)
     rs.close()
