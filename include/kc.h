@@ -40,10 +40,19 @@
  *    truncated lists, rejected page addresses) are reported through outputs.
  *  - A kc_ctx, and any kc_rangeset made from it, is used by one host thread
  *    and one stream at a time: rangesets own the scratch their calls use.
- *  - Ranges: (base VA, size) with base > 0, base and size multiples of 4096,
- *    sorted by base, disjoint.  They are the pointer-to-size map of tracked
- *    allocations (Sec. 4.1.1, memory tracking).  Page g of the set numbers
- *    the pages of range 0 first, then range 1, and so on.
+ *  - Ranges: (base VA, size) with base > 0 a multiple of 4096, size > 0 any
+ *    number of bytes, sorted by base, disjoint.  They are the pointer-to-size
+ *    map of tracked allocations (Sec. 4.1.1, memory tracking).  A range spans
+ *    ceil(size / 4096) pages; page g of the set numbers the pages of range 0
+ *    first, then range 1, and so on.  When size is not a multiple of 4096 the
+ *    range's last page is partial: only its size mod 4096 bytes belong to
+ *    the range.  They alone are hashed (XXH64 of that many bytes), zero-tested
+ *    and compared; its packed slot holds them followed by zeros; a restore
+ *    writes them and nothing past the range's end; the closure scan and the
+ *    pointer graph read only 8-byte words wholly inside the range.  Loads may
+ *    touch up to 15 bytes past a range's end inside its last page (the page
+ *    is mapped: device memory is mapped in whole pages); nothing is written
+ *    there.
  *  - Bitmaps: u64 words, page g is bit (g % 64) of word (g / 64); a bitmap
  *    over N pages has ceil(N / 64) words and its bits past N are 0.
  *  - Limits: fewer than 2^32 pages per rangeset, fewer than 2^31 ranges.
@@ -59,7 +68,7 @@ extern "C" {
 #endif
 
 #define KC_PAGE_SIZE 4096u
-#define KC_ABI_VERSION 3
+#define KC_ABI_VERSION 4
 #define KC_GRAPH_MAX_RANGES 16384u /* kc_pointer_graph: at most 32 MiB of edges */
 
 /* Status codes. */
@@ -67,7 +76,7 @@ enum {
   KC_OK = 0,
   KC_EINVAL = -1,  /* null where non-null is required, empty range, base 0,
                       bad window, size overflow                            */
-  KC_EALIGN = -2,  /* range not 4096-aligned / buffer not 16-byte aligned  */
+  KC_EALIGN = -2,  /* range base not 4096-aligned / buffer not 16-byte aligned */
   KC_EORDER = -3,  /* ranges unsorted or overlapping                       */
   KC_ENOMEM = -4,  /* device or pinned host allocation failed             */
   KC_EHIP = -5,    /* a HIP runtime call failed; see kc_last_error()       */

@@ -182,7 +182,7 @@ def compact(ranges, views, zero_bm, changed_bm=None, cap_pages=None):
     """Returns (packed u8[min(n_kept,cap)*4096], page_va u64[min(n_kept,cap)], n_kept)."""
     n = _n_pages(ranges)
     cap = n if cap_pages is None else int(cap_pages)
-    packed = np.zeros(max(cap, 1) * PAGE, dtype=np.uint8)
+    packed = np.full(max(cap, 1) * PAGE, 0xEE, dtype=np.uint8)   # every byte of a slot must be written
     va = np.zeros(max(cap, 1), dtype=np.uint64)
     n_kept = ctypes.c_uint64(0)
     zero_bm = np.ascontiguousarray(zero_bm, dtype=np.uint64)

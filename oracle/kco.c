@@ -106,7 +106,9 @@ uint64_t kco_xxh64(const void *data, uint64_t len, uint64_t seed) {
 
 /* ------------------------------------------------------------------------ */
 /* Range table: the pointer-to-size map of tracked allocations               */
-/* (paper Sec. 4.1.1), as sorted, disjoint, page-aligned (base, size).       */
+/* (paper Sec. 4.1.1), as sorted, disjoint (base, size) with a page-aligned  */
+/* base.  A range spans ceil(size / 4096) pages; its last page holds the     */
+/* remaining size mod 4096 bytes when that is not zero.                      */
 /* ------------------------------------------------------------------------ */
 
 int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
@@ -117,13 +119,13 @@ int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
   for (uint32_t a = 0; a < n; ++a) {
     uint64_t base = ranges[a].base, size = ranges[a].size;
     if (base == 0 || size == 0) return KCO_EINVAL;
-    if (base % PAGE != 0 || size % PAGE != 0) return KCO_EALIGN;
+    if (base % PAGE != 0) return KCO_EALIGN;
     if (base + size < base) return KCO_EINVAL; /* wraps around 2^64 */
     if (a > 0) {
       uint64_t prev_end = ranges[a - 1].base + ranges[a - 1].size;
       if (base < prev_end) return KCO_EORDER;
     }
-    pages += size / PAGE;
+    pages += (size + PAGE - 1) / PAGE;
     if (first_page) first_page[a + 1] = pages;
   }
   if (n_pages) *n_pages = pages;
@@ -153,10 +155,18 @@ static void bit_set(uint64_t *bm, uint64_t g) {
   bm[g / 64] |= 1ULL << (g % 64);
 }
 
-static int page_is_zero(const uint8_t *page) {
-  for (uint32_t i = 0; i < PAGE; ++i)
+static int page_is_zero(const uint8_t *page, uint64_t len) {
+  for (uint64_t i = 0; i < len; ++i)
     if (page[i] != 0) return 0;
   return 1;
+}
+
+/* Pages of a range and the bytes of its page p (the last may be partial). */
+static uint64_t range_pages(const kco_range *r) { return (r->size + PAGE - 1) / PAGE; }
+
+static uint64_t page_len(const kco_range *r, uint64_t p) {
+  uint64_t rest = r->size - p * PAGE;
+  return rest < PAGE ? rest : PAGE;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -178,11 +188,12 @@ int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
   }
   uint64_t g = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    uint64_t pages = ranges[a].size / PAGE;
+    uint64_t pages = range_pages(&ranges[a]);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
       const uint8_t *page = host_ptr[a] + p * PAGE;
-      hash[g] = kco_xxh64(page, PAGE, seed);
-      if (page_is_zero(page)) bit_set(zero_bm, g);
+      uint64_t len = page_len(&ranges[a], p);
+      hash[g] = kco_xxh64(page, len, seed);
+      if (page_is_zero(page, len)) bit_set(zero_bm, g);
       if (prior && hash[g] != prior[g]) bit_set(changed_bm, g);
     }
   }
@@ -204,13 +215,15 @@ int kco_compact(const kco_range *ranges, const uint8_t *const *host_ptr,
   if (cap_pages > 0 && (packed == NULL || page_va == NULL)) return KCO_EINVAL;
   uint64_t g = 0, slot = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    uint64_t pages = ranges[a].size / PAGE;
+    uint64_t pages = range_pages(&ranges[a]);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
       int keep = !bit_get(zero_bm, g);
       if (changed_bm != NULL) keep = keep && bit_get(changed_bm, g);
       if (!keep) continue;
-      if (slot < cap_pages) {
-        memcpy(packed + slot * PAGE, host_ptr[a] + p * PAGE, PAGE);
+      if (slot < cap_pages) { /* a partial page is followed by zeros in its slot */
+        uint64_t len = page_len(&ranges[a], p);
+        memcpy(packed + slot * PAGE, host_ptr[a] + p * PAGE, len);
+        memset(packed + slot * PAGE + len, 0, PAGE - len);
         page_va[slot] = ranges[a].base + p * PAGE;
       }
       ++slot;
@@ -252,11 +265,11 @@ int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
   /* 1. zero-fill the selected zero pages */
   uint64_t g = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    uint64_t pages = ranges[a].size / PAGE;
+    uint64_t pages = range_pages(&ranges[a]);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
       int selected = changed_bm == NULL || bit_get(changed_bm, g);
       if (selected && bit_get(zero_bm, g))
-        memset(host_ptr[a] + p * PAGE, 0, PAGE);
+        memset(host_ptr[a] + p * PAGE, 0, page_len(&ranges[a], p));
     }
   }
   /* 2. scatter every packed page back to the VA the page table names */
@@ -268,7 +281,8 @@ int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
       ++bad;
       continue;
     }
-    memcpy(host_ptr[a] + (va - ranges[a].base), packed + s * PAGE, PAGE);
+    uint64_t p = (va - ranges[a].base) / PAGE; /* only the page's own bytes are written */
+    memcpy(host_ptr[a] + p * PAGE, packed + s * PAGE, page_len(&ranges[a], p));
   }
   if (n_bad) *n_bad = bad;
   return KCO_OK;
@@ -291,7 +305,7 @@ int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
     return KCO_EINVAL;
   memset(res, 0, sizeof(*res));
   for (uint32_t a = 0; a < n; ++a) {
-    for (uint64_t off = 0; off < ranges[a].size; off += 8) {
+    for (uint64_t off = 0; off + 8 <= ranges[a].size; off += 8) { /* words wholly inside */
       uint64_t w = read_u64_le(host_ptr[a] + off);
       res->n_words += 1;
       if (w < win_lo || w >= win_hi) continue;
@@ -528,7 +542,7 @@ int kco_pointer_graph(const kco_range *ranges, const uint8_t *const *host_ptr,
   uint64_t rw = graph_row_words(n);
   memset(edge_bm, 0, (size_t)(n * rw) * sizeof(uint64_t));
   for (uint32_t a = 0; a < n; ++a) {
-    for (uint64_t off = 0; off < ranges[a].size; off += 8) {
+    for (uint64_t off = 0; off + 8 <= ranges[a].size; off += 8) { /* words wholly inside */
       uint64_t w = read_u64_le(host_ptr[a] + off);
       if (!(w >= win_lo && w < win_hi)) continue; /* not pointer-like */
       int64_t b = find_range(ranges, n, w);
@@ -596,9 +610,10 @@ int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
     res[a].n_diff_pages = 0;
     res[a].first_diff_va = UINT64_MAX;
     res[a].n_bad_pages = 0;
-    uint64_t pages = ranges[a].size / PAGE;
+    uint64_t pages = range_pages(&ranges[a]);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
       uint64_t va = ranges[a].base + p * PAGE;
+      uint64_t len = page_len(&ranges[a], p);
       const uint8_t *gold;
       if (bit_get(gold_zero_bm, g)) {
         gold = zeros;
@@ -612,7 +627,7 @@ int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
       }
       const uint8_t *live = host_ptr[a] + p * PAGE;
       uint64_t d = 0;
-      for (uint32_t b = 0; b < PAGE; ++b) {
+      for (uint64_t b = 0; b < len; ++b) {
         if (live[b] == gold[b]) continue;
         if (res[a].first_diff_va == UINT64_MAX) res[a].first_diff_va = va + b;
         ++d;

@@ -26,10 +26,15 @@
  *     explicit NaN accounting (paper Sec. 4.5.2, tolerance comparison).
  *
  * Conventions shared with the product ABI (same meaning, independent code):
- * a range is (base VA, size in bytes), base and size multiples of 4096,
- * base > 0, ranges sorted by base and disjoint.  Global page index g numbers
- * the pages of range 0 first, then range 1, ...  Bitmaps are arrays of u64,
- * bit (g % 64) of word (g / 64); bits past the last page are 0.
+ * a range is (base VA, size in bytes), base a multiple of 4096 and > 0,
+ * size > 0, ranges sorted by base and disjoint.  A range spans
+ * ceil(size / 4096) pages; when size is not a multiple of 4096 its last page
+ * is partial and holds size mod 4096 bytes: its hash is the XXH64 of exactly
+ * those bytes, its zero test looks at them only, its packed slot holds them
+ * followed by zeros, a restore writes only them, and the closure scan reads
+ * only 8-byte words that lie wholly inside the range.  Global page index g
+ * numbers the pages of range 0 first, then range 1, ...  Bitmaps are arrays
+ * of u64, bit (g % 64) of word (g / 64); bits past the last page are 0.
  *
  * The data of range a is read from / written to host_ptr[a] (a host copy of
  * the bytes that live at VA base_a on the device); VAs are only used as
@@ -48,7 +53,7 @@ extern "C" {
 enum {
   KCO_OK = 0,
   KCO_EINVAL = -1, /* null pointer, empty range, zero base, bad window      */
-  KCO_EALIGN = -2, /* base or size not a multiple of 4096                   */
+  KCO_EALIGN = -2, /* base not a multiple of 4096                            */
   KCO_EORDER = -3, /* ranges unsorted or overlapping                        */
   KCO_ENOMEM = -4,
   KCO_EDTYPE = -6

@@ -36,10 +36,10 @@ int range_check(const kc_range* r, uint32_t n, uint64_t* n_pages) {
   for (uint32_t i = 0; i < n; ++i) {
     const uint64_t base = r[i].base, size = r[i].size;
     if (base == 0 || size == 0) return KC_EINVAL;
-    if ((base | size) & (KC_PAGE_SIZE - 1)) return KC_EALIGN;
+    if (base & (KC_PAGE_SIZE - 1)) return KC_EALIGN;
     if (base + size < base) return KC_EINVAL;
     if (i > 0 && base < r[i - 1].base + r[i - 1].size) return KC_EORDER;
-    pages += size / KC_PAGE_SIZE;
+    pages += (size + KC_PAGE_SIZE - 1) / KC_PAGE_SIZE;  // a partial last page counts
     if (pages > kMaxPages) return KC_ELIMIT;
   }
   if (n_pages) *n_pages = pages;
@@ -107,7 +107,7 @@ int finish_scan(kc_rangeset* rs, const kc_scan_args* sa, const ScanDev& sd, hipS
   src.n_items = rs->n_tiles;
   KC_HIP(launch_scan(src, rs->tile_prefix, rs->block_sums, rs->n_oob, s));
   KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, rs->n_oob, sa->oob_d, sa->oob_cap,
-                         sa->res_d, rs->n_pages * (KC_PAGE_SIZE / 8), grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
+                         sa->res_d, rs->n_scan_words, grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
   return KC_OK;
 }
 
@@ -244,19 +244,28 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
 
   std::vector<Tile> tiles;
   std::vector<uint64_t> bases(n), ends(n);
+  std::vector<uint32_t> ragged;
   rs->range_tile.assign(n + 1, 0);
+  rs->ragged_of.assign(n, UINT32_MAX);
   uint64_t g0 = 0;
   for (uint32_t i = 0; i < n; ++i) {
     rs->range_tile[i] = (uint32_t)tiles.size();
-    const uint64_t pages = ranges[i].size / KC_PAGE_SIZE;
+    const uint64_t pages = (ranges[i].size + KC_PAGE_SIZE - 1) / KC_PAGE_SIZE;
+    const uint32_t tail = (uint32_t)(ranges[i].size - (pages - 1) * KC_PAGE_SIZE);  // bytes of the last page
+    rs->n_scan_words += ranges[i].size / 8;
     for (uint64_t p = 0; p < pages; p += kTilePages) {
       Tile t;
       t.va = ranges[i].base + p * KC_PAGE_SIZE;
       t.g = (uint32_t)(g0 + p);
-      t.npages = (uint32_t)std::min<uint64_t>(kTilePages, pages - p);
+      t.npages = (uint16_t)std::min<uint64_t>(kTilePages, pages - p);
+      t.last_len = (uint16_t)(p + t.npages == pages ? tail : KC_PAGE_SIZE);
       tiles.push_back(t);
     }
     g0 += pages;
+    if (tail != KC_PAGE_SIZE) {  // the range's last tile holds a partial page
+      rs->ragged_of[i] = (uint32_t)ragged.size();
+      ragged.push_back((uint32_t)tiles.size() - 1u);
+    }
     bases[i] = ranges[i].base;
     ends[i] = ranges[i].base + ranges[i].size;
   }
@@ -272,7 +281,8 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   const size_t sz_bs = align_up(8 * std::max<uint64_t>(1, std::max(nb_words, nb_tiles)), 256);
   const size_t sz_misc = 256;
   const size_t sz_bk = align_up(sizeof(uint16_t) * kBuckets, 256);
-  const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk;
+  const size_t sz_rg = align_up(4 * std::max<size_t>(1, ragged.size()), 256);
+  const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
   hipError_t e = hipMalloc(&rs->dev, total);
   if (e != hipSuccess) {
     set_error("hipMalloc(rangeset)", e);
@@ -291,6 +301,9 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->n_oob = reinterpret_cast<uint64_t*>(p + 64);
   p += sz_misc;
   uint16_t* bucket_d = reinterpret_cast<uint16_t*>(p);
+  p += sz_bk;
+  rs->ragged = reinterpret_cast<uint32_t*>(p);
+  rs->n_ragged = (uint32_t)ragged.size();
   // Bucket index over [lowest base, highest end): the last fence at or below
   // each bucket's first address.
   const uint32_t stride = n <= kFences ? 1u : (n + kFences - 1) / kFences;
@@ -323,6 +336,9 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   if ((e = hipMemset(rs->counts, 0, sz_misc)) != hipSuccess) return fail("hipMemset(counts)", e);
   if ((e = hipMemcpy(bucket_d, bucket.data(), sizeof(uint16_t) * kBuckets, hipMemcpyHostToDevice)) != hipSuccess)
     return fail("hipMemcpy(bucket index)", e);
+  if (!ragged.empty() &&
+      (e = hipMemcpy(rs->ragged, ragged.data(), 4 * ragged.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("hipMemcpy(ragged tiles)", e);
   rs->rt.base = rs->bases;
   rs->rt.end = rs->ends;
   rs->rt.bucket = bucket_d;
@@ -354,6 +370,8 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     hp.tiles = rs->tiles;
     hp.n_tiles = rs->n_tiles;
     hp.tile0 = 0;
+    hp.ragged = rs->ragged;
+    hp.n_ragged = rs->n_ragged;
     KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, s));
     return KC_OK;
   }
@@ -361,6 +379,9 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     hp.tile0 = rs->range_tile[r];
     hp.tiles = rs->tiles + hp.tile0;
     hp.n_tiles = rs->range_tile[r + 1] - hp.tile0;
+    const bool rg = rs->ragged_of[r] != UINT32_MAX;
+    hp.ragged = rg ? rs->ragged + rs->ragged_of[r] : nullptr;
+    hp.n_ragged = rg ? 1u : 0u;
     KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, s));
   }
   return KC_OK;
@@ -485,7 +506,7 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, bad, grid, s));
   KernelTimer timer(c, KC_OP_RESTORE, s);
   KC_HIP(launch_restore_scatter(rs->rt, static_cast<const uint8_t*>(packed_d), page_va_d, n_kept_d, cap_pages,
-                                bad, grid, s));
+                                bad, rs->n_ragged > 0, grid, s));
   return KC_OK;
 }
 

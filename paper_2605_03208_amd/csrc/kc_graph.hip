@@ -47,8 +47,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         x[i] = (s0 + i < nseg) ? ld16nt(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i) {
-        const uint64_t w0 = ((uint64_t)x[i].y << 32) | x[i].x;
-        const uint64_t w1 = ((uint64_t)x[i].w << 32) | x[i].z;
+        const uint4 v = seg_words(tile, s0 + i, lane, x[i]);  // words wholly inside the range only
+        const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
+        const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
         const bool p0 = (w0 - lo) < span, p1 = (w1 - lo) < span;
         if (__ballot(p0 || p1) == 0ull || src < 0) continue;  // no pointer-like word here
         graph_emit(p0 ? range_index(w0, fences, rt) : -1, lane, row, last);
@@ -114,6 +115,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     bool zero = false, bad = false, need = false;
     uint64_t gp = 0;
     int32_t a = -1;
+    const uint32_t len = live ? page_bytes(tile, j) : 0u;
     if (live) {
       a = range_index(va, fences, rt);
       const uint64_t zw = gold_zero_bm[g >> 6];
@@ -140,12 +142,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const uint64_t pgp = __shfl((unsigned long long)gp, L, 64);
       const int32_t pz = __shfl((int)zero, L, 64);
       const int32_t pa = __shfl(a, L, 64);
+      const uint32_t plen = __shfl(len, L, 64);  // bytes of the page (a range's last page may be partial)
       uint32_t nd = 0, fo = ~0u;
 #pragma unroll
       for (uint32_t k = 0; k < 4; ++k) {
         const uint32_t off = k * 1024u + lane * 16u;
-        const uint4 c = ld16nt(pva + off);
-        const uint4 d = pz ? make_uint4(0, 0, 0, 0) : ld16nt(pgp + off);
+        const uint4 c = off < plen ? clip16(ld16nt(pva + off), off, plen) : make_uint4(0, 0, 0, 0);
+        const uint4 d = pz || off >= plen ? make_uint4(0, 0, 0, 0) : clip16(ld16nt(pgp + off), off, plen);
         const uint32_t x[4] = {c.x ^ d.x, c.y ^ d.y, c.z ^ d.z, c.w ^ d.w};
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) {

@@ -35,13 +35,67 @@ __device__ __forceinline__ void st16nt(uint64_t addr, uint4 v) {
   __builtin_nontemporal_store(x, reinterpret_cast<v4u*>(addr));
 }
 
-// A tile: up to 16 consecutive pages of one range.
+// A tile: up to 16 consecutive pages of one range.  Only a range's last page
+// can be partial (a range size that is not a multiple of the page); last_len
+// is the byte count of the tile's last page.
 struct Tile {
-  uint64_t va;      // VA of the first page
-  uint32_t g;       // global index of the first page
-  uint32_t npages;  // 1..16
+  uint64_t va;        // VA of the first page
+  uint32_t g;         // global index of the first page
+  uint16_t npages;    // 1..16
+  uint16_t last_len;  // 1..4096
 };
 static_assert(sizeof(Tile) == 16, "tile layout");
+
+// Bytes of page j of a tile.
+__device__ __forceinline__ uint32_t page_bytes(const Tile& t, uint32_t j) {
+  return j + 1u == t.npages ? (uint32_t)t.last_len : kPage;
+}
+
+// The 16 bytes at offset off of a page of len bytes, bytes at or past len
+// cleared.
+__device__ __forceinline__ uint4 clip16(uint4 v, uint32_t off, uint32_t len) {
+  if (off + 16u <= len) return v;
+  if (off >= len) return make_uint4(0, 0, 0, 0);
+  const uint32_t keep = len - off;  // 1..15 bytes
+  const auto cut = [&](uint32_t w, uint32_t i) -> uint32_t {
+    const uint32_t lo = i * 4u;
+    if (keep >= lo + 4u) return w;
+    if (keep <= lo) return 0u;
+    return w & ((1u << (8u * (keep - lo))) - 1u);
+  };
+  return make_uint4(cut(v.x, 0), cut(v.y, 1), cut(v.z, 2), cut(v.w, 3));
+}
+
+// The two 8-byte words of the 16 bytes at offset off of a page of len bytes,
+// each cleared unless it lies wholly inside the page (a cleared word is never
+// pointer-like: windows start at 1 or above).
+__device__ __forceinline__ uint4 words_inside(uint4 v, uint32_t off, uint32_t len) {
+  if (off + 16u <= len) return v;
+  if (off + 8u <= len) return make_uint4(v.x, v.y, 0u, 0u);
+  return make_uint4(0, 0, 0, 0);
+}
+
+// 16 bytes at tile segment s (1 KiB each, four per page) for this lane, with
+// the words that are not wholly inside the range cleared.
+__device__ __forceinline__ uint4 seg_words(const Tile& t, uint32_t s, uint32_t lane, uint4 v) {
+  const uint32_t pg = s >> 2, off = (s & 3u) * 1024u + lane * 16u;
+  return pg + 1u == t.npages ? words_inside(v, off, t.last_len) : v;
+}
+
+// Store only the first n (0..16) bytes of v at addr.
+__device__ __forceinline__ void st_bytes(uint64_t addr, uint4 v, uint32_t n) {
+  if (n >= 16u) {
+    st16nt(addr, v);
+    return;
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < 16u; ++i) {
+    if (i < n) {
+      const uint32_t w = i < 4u ? v.x : (i < 8u ? v.y : (i < 12u ? v.z : v.w));
+      *reinterpret_cast<uint8_t*>(addr + i) = (uint8_t)(w >> (8u * (i & 3u)));
+    }
+  }
+}
 
 // Sorted range table on the device (bases and one-past-end addresses), with
 // a bucket index over [lo, lo + span) = [lowest base, highest end): bucket b
@@ -69,6 +123,8 @@ struct HashParams {
   const Tile* tiles;
   uint32_t n_tiles;
   uint32_t tile0;          // index of tiles[0] in the rangeset's tile list
+  const uint32_t* ragged;  // indices (in the rangeset's list) of tiles with a partial last page
+  uint32_t n_ragged;
   uint64_t seed;
   const uint64_t* prior;   // nullable
   uint64_t* hash;
@@ -133,7 +189,7 @@ hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64
 hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
                                   const uint64_t* page_va, const uint64_t* n_kept,
                                   uint64_t cap_pages, unsigned long long* n_bad,
-                                  uint32_t grid, hipStream_t s);
+                                  bool ragged, uint32_t grid, hipStream_t s);
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
                           const ScanDev& sd, uint32_t grid, hipStream_t s);
 hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
@@ -214,6 +270,10 @@ struct kc_rangeset {
   int device = 0;  // recorded at creation: destroy never touches the context
   uint32_t n_ranges = 0, n_tiles = 0;
   uint64_t n_pages = 0, n_words = 0;
+  uint64_t n_scan_words = 0;         // 8-byte words wholly inside the ranges
+  uint32_t n_ragged = 0;             // tiles with a partial last page (at most one per range)
+  uint32_t* ragged = nullptr;        // their indices, ascending (device)
+  std::vector<uint32_t> ragged_of;   // per range: its entry in ragged, or UINT32_MAX
   std::vector<uint32_t> range_tile;  // first tile of each range (n + 1)
   uint64_t win_lo = 0, win_hi = 0;   // default pointer window
   std::vector<kc_range> host_ranges;

@@ -18,6 +18,7 @@ constexpr uint64_t kP1 = 0x9E3779B185EBCA87ull;
 constexpr uint64_t kP2 = 0xC2B2AE3D27D4EB4Full;
 constexpr uint64_t kP3 = 0x165667B19E3779F9ull;
 constexpr uint64_t kP4 = 0x85EBCA77C2B2AE63ull;
+constexpr uint64_t kP5 = 0x27D4EB2F165667C5ull;
 
 __device__ __forceinline__ uint64_t rotl64(uint64_t x, uint32_t r) {
   return (x << r) | (x >> (64u - r));
@@ -37,9 +38,10 @@ __device__ __forceinline__ uint64_t quad64(uint64_t x) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// Lane k of a quad holds accumulator k of one page after its 128 stripes.
-// Returns the page hash in every lane of the quad.
-__device__ __forceinline__ uint64_t xxh64_page_merge(uint64_t acc, uint32_t k) {
+// Lane k of a quad holds accumulator k of one page after its stripes.
+// Returns the merged accumulators (before the length is added) in every lane
+// of the quad.
+__device__ __forceinline__ uint64_t xxh64_merge4(uint64_t acc, uint32_t k) {
   const uint32_t rot = k == 0 ? 1u : (k == 1 ? 7u : (k == 2 ? 12u : 18u));
   uint64_t r = rotl64(acc, rot);
   const uint64_t m = xround(0, acc);
@@ -50,7 +52,30 @@ __device__ __forceinline__ uint64_t xxh64_page_merge(uint64_t acc, uint32_t k) {
   h = (h ^ quad64<0x55>(m)) * kP1 + kP4;
   h = (h ^ quad64<0xAA>(m)) * kP1 + kP4;
   h = (h ^ quad64<0xFF>(m)) * kP1 + kP4;
-  h += kPage;
+  return h;
+}
+
+// The bytes past the last whole 32-byte stripe (r = 1..31 of them, held
+// little-endian in t[0..3]): 8-byte lanes, then a 4-byte lane, then bytes.
+__device__ __forceinline__ uint64_t xxh64_tail(uint64_t h, const uint64_t (&t)[4], uint32_t r) {
+#pragma unroll
+  for (uint32_t i = 0; i < 3; ++i)
+    if (r >= 8u * (i + 1u)) h = rotl64(h ^ xround(0, t[i]), 27) * kP1 + kP4;
+  const uint32_t n8 = r >> 3;
+  const uint64_t rest = n8 == 0 ? t[0] : (n8 == 1 ? t[1] : (n8 == 2 ? t[2] : t[3]));
+  uint32_t rr = r & 7u, sh = 0;
+  if (rr >= 4u) {
+    h = rotl64(h ^ (uint64_t)(uint32_t)rest * kP1, 23) * kP2 + kP3;
+    sh = 32u;
+    rr -= 4u;
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < 3; ++i)
+    if (i < rr) h = rotl64(h ^ ((rest >> (sh + 8u * i)) & 0xFFull) * kP5, 11) * kP1;
+  return h;
+}
+
+__device__ __forceinline__ uint64_t xxh64_avalanche(uint64_t h) {
   h ^= h >> 33;
   h *= kP2;
   h ^= h >> 29;
@@ -113,9 +138,13 @@ __global__ void k_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
 //
 // GATHER: zero bits come from the probe, zero pages are not read (their hash
 // is computed from zeros), kept pages are also stored to their packed slot.
-template <bool GATHER, bool PRIOR, bool SCAN>
+// RAGGED = false: every tile whose pages are all whole (the hot path); RAGGED =
+// true: only the tiles listed in p.ragged, whose last page is partial (at most
+// one per range), with the bytes past the range's end masked out.
+template <bool GATHER, bool PRIOR, bool SCAN, bool RAGGED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_page_hash(HashParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kTilePages * kStageStride];
+  __shared__ uint64_t tail_lds[kTilePages][4];  // a partial page's bytes past its last whole stripe
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
   const uint32_t q = lane >> 2, k = lane & 3u;
@@ -127,10 +156,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   uint32_t n_ptr = 0, n_in = 0;
 
-  for (uint32_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+  const uint32_t n_items = RAGGED ? p.n_ragged : p.n_tiles;
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const uint32_t t = RAGGED ? p.ragged[it] - p.tile0 : it;
     const Tile tile = p.tiles[t];
+    if (!RAGGED && tile.last_len != kPage) continue;  // left to the ragged launch
     const uint32_t np = tile.npages;
     const uint64_t va = tile.va;
+    const uint32_t last_pg = np - 1u, last_len = RAGGED ? tile.last_len : kPage;  // only the last page can be partial
     uint32_t keep = (1u << np) - 1u;
     uint64_t slot_j[8];
     if (GATHER) {
@@ -154,8 +187,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
     for (uint32_t j = 0; j < 8; ++j) {
       const uint32_t pg = 2 * j + half;
-      cur[j] = ((keep >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + off16) : make_uint4(0, 0, 0, 0);
+      if (RAGGED) {
+        const uint32_t len = pg == last_pg ? last_len : kPage;
+        cur[j] = ((keep >> pg) & 1u) && off16 < len ? clip16(ld16nt(va + (uint64_t)pg * kPage + off16), off16, len)
+                                                    : make_uint4(0, 0, 0, 0);
+      } else {
+        cur[j] = ((keep >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + off16) : make_uint4(0, 0, 0, 0);
+      }
     }
+    // this lane's quad: stripes of its page, and the bytes past the last stripe
+    const uint32_t qlen = RAGGED && q == last_pg ? last_len : kPage;
+    const uint32_t lim = qlen / 32u, rem = qlen & 31u;
 #pragma unroll 1
     for (uint32_t c = 0; c < kPage / kChunk; ++c) {
       uint32_t ptr_mask = 0;  // bit 2j+h: word h of this lane's 16 bytes of load j is pointer-like
@@ -170,8 +212,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (SCAN) {  // pointer-like words are only marked here; the range search runs once per chunk
           const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
           const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
-          const uint32_t p0 = (w0 - scan_lo) < scan_span ? 1u : 0u;
-          const uint32_t p1 = (w1 - scan_lo) < scan_span ? 1u : 0u;
+          uint32_t p0 = (w0 - scan_lo) < scan_span ? 1u : 0u;
+          uint32_t p1 = (w1 - scan_lo) < scan_span ? 1u : 0u;
+          if (RAGGED) {  // words wholly inside the range only
+            const uint32_t o = c * kChunk + off16, len = pg == last_pg ? last_len : kPage;
+            p0 = o + 8u <= len ? p0 : 0u;
+            p1 = o + 16u <= len ? p1 : 0u;
+          }
           ptr_mask |= (p0 << (2 * j)) | (p1 << (2 * j + 1));
         }
         if (GATHER) {
@@ -186,9 +233,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const uint32_t more = c + 1 < kPage / kChunk ? keep : 0u;
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t pg = 2 * j + half;
-        cur[j] = ((more >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + cn * kChunk + off16)
-                                     : make_uint4(0, 0, 0, 0);
+        const uint32_t pg = 2 * j + half, o = cn * kChunk + off16;
+        if (RAGGED) {
+          const uint32_t len = pg == last_pg ? last_len : kPage;
+          cur[j] = ((more >> pg) & 1u) && o < len ? clip16(ld16nt(va + (uint64_t)pg * kPage + o), o, len)
+                                                  : make_uint4(0, 0, 0, 0);
+        } else {
+          cur[j] = ((more >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + o) : make_uint4(0, 0, 0, 0);
+        }
       }
       if (SCAN && __ballot(ptr_mask != 0u)) {
         // the marked words, read back from the stage: one search chain per lane per chunk
@@ -203,11 +255,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const uint8_t* row = stage + q * kStageStride + k * 8u;
 #pragma unroll
       for (uint32_t s = 0; s < kChunk / 32; ++s)
-        acc = xround(acc, *reinterpret_cast<const uint64_t*>(row + s * 32u));
+        if (!RAGGED || c * (kChunk / 32) + s < lim) acc = xround(acc, *reinterpret_cast<const uint64_t*>(row + s * 32u));
+      if (RAGGED && rem != 0u && c == lim / (kChunk / 32))  // the partial page's last bytes are in this chunk
+        tail_lds[q][k] = *reinterpret_cast<const uint64_t*>(stage + q * kStageStride + (lim * 32u - c * kChunk) + 8u * k);
       __syncthreads();
     }
 
-    const uint64_t h = xxh64_page_merge(acc, k);
+    const uint64_t merged = xxh64_merge4(acc, k);  // every lane of the quad takes part
+    uint64_t h = (lim > 0u ? merged : p.seed + kP5) + qlen;
+    if (RAGGED && rem != 0u) {
+      const uint64_t tail[4] = {tail_lds[q][0], tail_lds[q][1], tail_lds[q][2], tail_lds[q][3]};
+      h = xxh64_tail(h, tail, rem);
+    }
+    h = xxh64_avalanche(h);
     const bool mine = (k == 0u) && (q < np);
     if (mine) p.hash[tile.g + q] = h;
     const uint32_t valid = (1u << np) - 1u;
@@ -246,11 +306,14 @@ __global__ __launch_bounds__(64) void k_probe_zero(const Tile* tiles, uint32_t n
     Tile tile{0, 0, 0};
     if (t < n_tiles) tile = tiles[t];
     const bool valid = pl < tile.npages;
+    const uint32_t len = valid ? page_bytes(tile, pl) : 0u;  // a partial page is tested over its bytes only
     const uint64_t page_va = tile.va + (uint64_t)pl * kPage;
-    const uint4 v = valid ? ld16(page_va) : make_uint4(0, 0, 0, 0);
-    uint64_t maybe = __ballot(valid && !nz16(v));
+    const uint4 v = valid ? clip16(ld16(page_va), 0u, len) : make_uint4(0, 0, 0, 0);
+    const bool cand = valid && !nz16(v);
+    uint64_t maybe = __ballot(cand && len == kPage);
+    uint64_t maybe_part = __ballot(cand && len != kPage);
     uint64_t zero = 0;
-    while (maybe) {
+    while (maybe) {  // whole pages, four at a time
       uint32_t ln[4];
       uint64_t pva[4];
       uint32_t cnt = 0;
@@ -274,6 +337,19 @@ __global__ __launch_bounds__(64) void k_probe_zero(const Tile* tiles, uint32_t n
         const bool nzl = nz16(x[i * 4]) || nz16(x[i * 4 + 1]) || nz16(x[i * 4 + 2]) || nz16(x[i * 4 + 3]);
         if (i < cnt && __ballot(nzl) == 0ull) zero |= 1ull << ln[i];
       }
+    }
+    while (maybe_part) {  // partial last pages (one per range at most), one at a time over their bytes
+      const uint32_t L = (uint32_t)__builtin_ctzll(maybe_part);
+      maybe_part &= maybe_part - 1ull;
+      const uint64_t pva = __shfl(page_va, L, 64);
+      const uint32_t plen = __shfl(len, L, 64);
+      bool nzl = false;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t o = j * 1024u + lane * 16u;
+        if (o < plen) nzl = nzl || nz16(clip16(ld16nt(pva + o), o, plen));
+      }
+      if (__ballot(nzl) == 0ull) zero |= 1ull << L;
     }
     if (pl == 0 && t < n_tiles) or_page_bits(zero_bm, tile.g, tile.npages, (uint32_t)((zero >> (16u * sub)) & 0xFFFFull));
   }
@@ -438,8 +514,11 @@ __global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_til
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j)
-          if (i < cnt) x[i * 4 + j] = ld16nt(tile.va + (uint64_t)pg[i] * kPage + j * 1024u + lane * 16u);
+        for (uint32_t j = 0; j < 4; ++j) {
+          const uint32_t o = j * 1024u + lane * 16u, len = page_bytes(tile, pg[i]);  // a partial page: zeros after
+          if (i < cnt) x[i * 4 + j] = o < len ? clip16(ld16nt(tile.va + (uint64_t)pg[i] * kPage + o), o, len)
+                                               : make_uint4(0, 0, 0, 0);
+        }
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
@@ -469,8 +548,13 @@ __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t
     while (mask) {
       const uint32_t pg = (uint32_t)__builtin_ctz(mask);
       mask &= mask - 1u;
+      const uint32_t len = page_bytes(tile, pg);  // never past the range's end
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) st16nt(tile.va + (uint64_t)pg * kPage + j * 1024u + lane * 16u, z);
+      for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t o = j * 1024u + lane * 16u;
+        if (o + 16u <= len) st16nt(tile.va + (uint64_t)pg * kPage + o, z);
+        else if (o < len) st_bytes(tile.va + (uint64_t)pg * kPage + o, z, len - o);
+      }
     }
   }
 }
@@ -488,8 +572,13 @@ __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uin
     bool ok = false;
     if (lane < 4 && s0 + lane < n) {
       va = page_va[s0 + lane];
-      ok = (va & (kPage - 1)) == 0 && in_ranges(va, fences, rt);
-      if (!ok) atomicAdd(n_bad, 1ull);
+      const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
+      if (a >= 0) {  // a range's partial last page is left to k_restore_tail
+        const uint64_t end = rt.stride == 1u ? fences.end[a] : rt.end[a];
+        ok = va + kPage <= end;
+      } else {
+        atomicAdd(n_bad, 1ull);
+      }
     }
     const uint32_t okm = (uint32_t)__ballot(ok);
     uint64_t dst[4];
@@ -506,6 +595,40 @@ __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uin
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
         if ((okm >> i) & 1u) st16nt(dst[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
+  }
+}
+
+// Packed pages bound for a range's partial last page: only the page's own
+// bytes are written.  One lane per slot finds them; the wave copies each.
+__global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_t* packed, const uint64_t* page_va,
+                                                     const uint64_t* n_kept, uint64_t cap) {
+  __shared__ FenceLds fences;
+  const uint32_t lane = threadIdx.x;
+  load_fences(fences, rt, lane, kWave);
+  __syncthreads();
+  const uint64_t n = min(*n_kept, cap);
+  for (uint64_t s0 = (uint64_t)blockIdx.x * 64u; s0 < n; s0 += (uint64_t)gridDim.x * 64u) {
+    uint64_t va = 0;
+    uint32_t len = 0;
+    if (s0 + lane < n) {
+      va = page_va[s0 + lane];
+      const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
+      if (a >= 0) {
+        const uint64_t end = rt.stride == 1u ? fences.end[a] : rt.end[a];
+        if (va + kPage > end) len = (uint32_t)(end - va);
+      }
+    }
+    for (uint64_t m = __ballot(len != 0u); m != 0ull; m &= m - 1ull) {
+      const int32_t L = __ffsll((long long)m) - 1;
+      const uint64_t dva = __shfl((unsigned long long)va, L, 64);
+      const uint32_t dlen = __shfl(len, L, 64);
+      const uint64_t src = (uint64_t)packed + (s0 + (uint64_t)L) * kPage;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t o = j * 1024u + lane * 16u;
+        if (o < dlen) st_bytes(dva + o, ld16nt(src + o), dlen - o);  // never past the range's end
+      }
+    }
   }
 }
 
@@ -545,7 +668,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       for (uint32_t i = 0; i < 8; ++i)
         x[i] = (s0 + i < nseg) ? ld16nt(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
 #pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) closure_words(x[i], sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
+      for (uint32_t i = 0; i < 8; ++i)
+        closure_words(seg_words(tile, s0 + i, lane, x[i]), sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
     }
     const uint32_t o = wave_sum_u32(oob);
     if (lane == 0) sd.tile_oob[tile0 + t] = o;
@@ -593,8 +717,9 @@ __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_t
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i) {  // words past the tile are zero: never pointer-like
         const uint64_t a = tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u;
-        const uint64_t w0 = ((uint64_t)x[i].y << 32) | x[i].x;
-        const uint64_t w1 = ((uint64_t)x[i].w << 32) | x[i].z;
+        const uint4 v = seg_words(tile, s0 + i, lane, x[i]);  // same words as the counting pass
+        const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
+        const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
         const bool o0 = (w0 - sd.lo) < sd.span && !in_ranges(w0, fences, sd.rt);
         const bool o1 = (w1 - sd.lo) < sd.span && !in_ranges(w1, fences, sd.rt);
         const uint64_t b0 = __ballot(o0), b1 = __ballot(o1);
@@ -639,11 +764,15 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t grid,
                             hipStream_t s) {
   if (p.n_tiles == 0) return hipSuccess;
+  const uint32_t grid_r = std::max(1u, std::min(grid, p.n_ragged));
   grid = std::max(1u, std::min(grid, p.n_tiles));
-#define KC_HASH_CASE(G, P, S)                                                     \
-  if (gather == G && prior == P && scan == S) {                                  \
-    hipLaunchKernelGGL((k_page_hash<G, P, S>), dim3(grid), dim3(64), 0, s, p);   \
-    return hipGetLastError();                                                    \
+#define KC_HASH_CASE(G, P, S)                                                              \
+  if (gather == G && prior == P && scan == S) {                                           \
+    hipLaunchKernelGGL((k_page_hash<G, P, S, false>), dim3(grid), dim3(64), 0, s, p);     \
+    hipError_t e = hipGetLastError();                                                     \
+    if (e != hipSuccess || p.n_ragged == 0) return e;                                     \
+    hipLaunchKernelGGL((k_page_hash<G, P, S, true>), dim3(grid_r), dim3(64), 0, s, p);    \
+    return hipGetLastError();                                                             \
   }
   KC_HASH_CASE(false, false, false)
   KC_HASH_CASE(false, false, true)
@@ -702,13 +831,18 @@ hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64
 
 hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, const uint64_t* page_va,
                                   const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad,
-                                  uint32_t grid, hipStream_t s) {
+                                  bool ragged, uint32_t grid, hipStream_t s) {
   if (cap_pages == 0) return hipSuccess;
   const uint64_t groups = (cap_pages + 3) / 4;
   grid = (uint32_t)(groups < grid ? groups : grid);
   grid = grid < 1u ? 1u : grid;
   hipLaunchKernelGGL(k_restore_scatter, dim3(grid), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
                      n_bad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ragged) return e;
+  const uint64_t groups64 = (cap_pages + 63) / 64;
+  const uint32_t grid_t = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(groups64, 1024));
+  hipLaunchKernelGGL(k_restore_tail, dim3(grid_t), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages);
   return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
-ABI_VERSION = 3  # layout of the structs and the entry-point set below
+ABI_VERSION = 4  # layout of the structs, the entry-point set and the range rules below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT, ERELOC = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4

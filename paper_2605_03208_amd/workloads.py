@@ -118,7 +118,7 @@ class Layout:
 
     @property
     def n_pages(self) -> int:
-        return self.total // PAGE
+        return int(((self.sizes + PAGE - 1) // PAGE).sum())   # a partial last page counts
 
     def cum(self) -> np.ndarray:
         """Start of each range in range-concatenated byte space."""
@@ -134,7 +134,7 @@ def make_layout(rng: np.random.Generator, sizes: np.ndarray, gap_pages=(1, 16)) 
     pos = int(gaps[0])
     for i, s in enumerate(sizes):
         offsets[i] = pos
-        pos += int(s) + int(gaps[i + 1])
+        pos += (int(s) + PAGE - 1) // PAGE * PAGE + int(gaps[i + 1])   # every range starts on a page
     return Layout(np.asarray(sizes, dtype=np.int64), offsets, pos)
 
 
@@ -247,6 +247,49 @@ def c1_snapshot(device="cpu", scale: float = 1.0, seed: int = 1) -> SnapshotCase
     truth = dict(zero_pages=zero_pages, ptr_pos=ptr_pos, ptr_val=ptr_val, oob_pos=oob_pos,
                  oob_val=oob_val, n_pages=N)
     return SnapshotCase("c1", arena, truth)
+
+
+# --------------------------------------------------------------------------
+# ragged ranges: sizes that are not multiples of the page
+# --------------------------------------------------------------------------
+
+SENTINEL = 0xA5
+
+
+def ragged_case(device="cpu", n_ranges: int = 40, seed: int = 9, max_bytes: int = 9 * PAGE + 123) -> SnapshotCase:
+    """Ranges of arbitrary byte sizes (a few whole-page sizes, a few under
+    16 bytes) on page-aligned bases, 0-3 pages apart.  Every byte of the arena
+    outside the ranges (the rest of each partial last page, the gaps) holds
+    ``SENTINEL``; range bytes are random, with about a fifth of the pages (or
+    partial pages) zeroed and about 0.2 % of the words wholly inside a range
+    set to addresses inside some range.  ``truth['ptr']`` lists those planted
+    (range, byte offset, value) words."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, max_bytes + 1, size=n_ranges)
+    sizes[::7] = (sizes[::7] + PAGE - 1) // PAGE * PAGE
+    sizes[1::11] = rng.integers(1, 16, size=len(sizes[1::11]))
+    lay = make_layout(rng, sizes, gap_pages=(0, 3))
+    arena = Arena(lay, device)
+    arena.buf.fill_(SENTINEL)
+    ranges = arena.ranges()
+    content = rng.integers(0, 256, size=lay.total, dtype=np.uint8)
+    cum = lay.cum()
+    for a in range(n_ranges):   # zero about a fifth of each range's pages (partial ones included)
+        for p in range((int(sizes[a]) + PAGE - 1) // PAGE):
+            if rng.random() < 0.2:
+                lo = int(cum[a]) + p * PAGE
+                content[lo:min(lo + PAGE, int(cum[a + 1]))] = 0
+    ptr = []
+    for a in range(n_ranges):
+        n_words = int(sizes[a]) // 8
+        for w in np.flatnonzero(rng.random(n_words) < 0.002):
+            b = int(rng.integers(0, n_ranges))
+            v = ranges[b][0] + int(rng.integers(0, int(sizes[b])))
+            content[int(cum[a]) + 8 * int(w): int(cum[a]) + 8 * int(w) + 8] = np.frombuffer(
+                np.uint64(v).tobytes(), dtype=np.uint8)
+            ptr.append((a, 8 * int(w), v))
+    arena.load_concat(content)
+    return SnapshotCase("ragged", arena, dict(ptr=ptr, sentinel=SENTINEL))
 
 
 # --------------------------------------------------------------------------

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(kc):
 
 
 def test_abi_version_and_strerror(kc):
-    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 3
+    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 4
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert kc.strerror(code) not in ("", "unknown status")
 
@@ -115,12 +115,12 @@ def test_graph_reach_agrees_with_oracle(kc, oracle_lib):
             want = oracle_lib.graph_reach(ranges, clean, roots)
             assert (got == want).all(), (n, roots)
     with pytest.raises(kc.KCError):
-        kc.graph_reach([(0x1000, 0x1001)], np.zeros(1, np.uint64), [])
+        kc.graph_reach([(0x1010, 0x1000)], np.zeros(1, np.uint64), [])
 
 
 def test_vaspace_rejects_bad_ranges_before_any_device_call(kc):
     """Range validation happens on the host, before the device is touched."""
-    for ranges, code in (([(0x10001000, 0x1001)], kc.EALIGN), ([(0x20000000, 0x1000), (0x10000000, 0x1000)], kc.EORDER),
+    for ranges, code in (([(0x10001010, 0x1000)], kc.EALIGN), ([(0x20000000, 0x1000), (0x10000000, 0x1000)], kc.EORDER),
                          ([(0, 0x1000)], kc.EINVAL)):
         with pytest.raises(kc.KCError) as ei:
             kc.VaSpace(0, ranges)

@@ -274,7 +274,7 @@ def test_empty_rangeset(kc, ctx):
 
 def test_rangeset_errors(kc, ctx):
     say("range-set argument errors")
-    for bad, code in (([(0x10001000, 0x1001)], kc.EALIGN), ([(0x20000, 0x1000), (0x10000, 0x1000)], kc.EORDER),
+    for bad, code in (([(0x10001010, 0x1000)], kc.EALIGN), ([(0x20000, 0x1000), (0x10000, 0x1000)], kc.EORDER),
                       ([(0x10000, 0)], kc.EINVAL)):
         with pytest.raises(kc.KCError) as ei:
             kc.RangeSet(ctx, bad)

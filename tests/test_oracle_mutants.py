@@ -12,7 +12,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_xxh64.py", "tests/test_oracle_snapshot.py", "tests/test_oracle_compare.py",
-             "tests/test_oracle_graph.py", "tests/test_oracle_region.py", "tests/test_golden.py"]
+             "tests/test_oracle_graph.py", "tests/test_oracle_region.py", "tests/test_oracle_ragged.py",
+             "tests/test_golden.py"]
 
 MUTANTS = {
     "round uses P1": ("acc = acc + lane * PRIME2;", "acc = acc + lane * PRIME1;"),
@@ -20,7 +21,15 @@ MUTANTS = {
     "merge rotation": ("rotate_left(v2, 7)", "rotate_left(v2, 8)"),
     "tail lane constant": ("acc = rotate_left(acc, 27) * PRIME1 + PRIME4;", "acc = rotate_left(acc, 27) * PRIME1 + PRIME3;"),
     "avalanche shift": ("acc ^= acc >> 29;", "acc ^= acc >> 28;"),
-    "zero test skips last byte": ("for (uint32_t i = 0; i < PAGE; ++i)", "for (uint32_t i = 0; i + 1 < PAGE; ++i)"),
+    "zero test skips last byte": ("for (uint64_t i = 0; i < len; ++i)", "for (uint64_t i = 0; i + 1 < len; ++i)"),
+    "partial page hashed whole": ("hash[g] = kco_xxh64(page, len, seed);", "hash[g] = kco_xxh64(page, PAGE, seed);"),
+    "partial slot not padded": ("memset(packed + slot * PAGE + len, 0, PAGE - len);", ""),
+    "restore writes whole page": ("memcpy(host_ptr[a] + p * PAGE, packed + s * PAGE, page_len(&ranges[a], p));",
+                                  "memcpy(host_ptr[a] + p * PAGE, packed + s * PAGE, PAGE);"),
+    "scan reads a straddling word": ("for (uint64_t off = 0; off + 8 <= ranges[a].size; off += 8) { /* words wholly inside */\n"
+                                     "      uint64_t w = read_u64_le(host_ptr[a] + off);\n      res->n_words += 1;",
+                                     "for (uint64_t off = 0; off < ranges[a].size; off += 8) { /* words wholly inside */\n"
+                                     "      uint64_t w = read_u64_le(host_ptr[a] + off);\n      res->n_words += 1;"),
     "changed inverted": ("if (prior && hash[g] != prior[g])", "if (prior && hash[g] == prior[g])"),
     "page VA off by one page": ("page_va[slot] = ranges[a].base + p * PAGE;", "page_va[slot] = ranges[a].base + (p + 1) * PAGE;"),
     "delta keep uses or": ("if (changed_bm != NULL) keep = keep && bit_get(changed_bm, g);",
