@@ -131,3 +131,22 @@ def test_ragged_delta_compact_and_per_range_launches(kc, ctx):
     rs2.close()
     ctx2.close()
     rs.close()
+
+
+def test_ragged_snapshot_files_roundtrip(kc, ctx, tmp_path):
+    say("ragged ranges: snapshot saved to files, loaded, restored over clobbered ranges")
+    case = W.ragged_case("cuda", n_ranges=25, seed=13)
+    ranges = case.ranges()
+    host = case.arena.host_copy().copy()
+    rs = kc.RangeSet(ctx, ranges)
+    out = kc.snapshot(ctx, rs)
+    torch.cuda.synchronize()
+    d = str(tmp_path / "snap")
+    kc.snapshot_save(ctx, rs, d, out)
+    for (o, s) in zip(case.layout.offsets, case.layout.sizes):
+        case.arena.buf[int(o): int(o) + int(s)] = 0x3C
+    back, _ = kc.snapshot_load(ctx, rs, d)
+    kc.restore(ctx, rs, back["zero_bm"], None, back["packed"], back["page_va"], back["n_kept"])
+    torch.cuda.synchronize()
+    assert np.array_equal(case.arena.host_copy(), host)
+    rs.close()
