@@ -47,10 +47,10 @@ PAGE = 4096
 # per launch, scaled by the factors a plain 4 GiB device copy gives (fetch
 # x2.0, write x1.0).  Valid only for the kernel sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "2c4ef7ce667798211da73185f094e5cac466ed3664931f45bb86c0d1d6c7d98c",
-    "snapshot": 62933975772,  # fetch 31432303269 + write 31501672503
-    "restore": 62952006989,   # fetch 31598330778 + write 31353676211
-    "compare": 64456598118,   # fetch 64456598118 + write 0
+    "source_sha256": "8785260bab888e6de41356437000d3a32802dd881ea06275cf77ce92e028f122",
+    "snapshot": 62932579584,   # fetch 31432321664 + write 31500257920
+    "restore": 62951983744,    # fetch 31598329293 + write 31353654451
+    "compare": 64456598861,    # fetch 64456598861 + write 0
 }
 
 
