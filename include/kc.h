@@ -308,8 +308,8 @@ int kc_restore(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
  *      abort on relocation) ------------------------------------------------- */
 
 /* Map device memory of `hip_device` at exactly the VAs of the ranges: each
- * range is covered by a span aligned to the device's virtual-memory
- * granularity (touching spans merge), every span is reserved at its own
+ * range is covered by a span aligned to the device's recommended
+ * virtual-memory granularity (touching spans merge), every span is reserved at its own
  * address, backed by device memory and made readable and writable.  If any
  * span cannot be reserved at its address, everything reserved so far is
  * released and KC_ERELOC is returned (the replay must not run relocated).
@@ -322,6 +322,16 @@ int kc_vaspace_create(int hip_device, const kc_range *ranges, uint32_t n,
 
 /* Unmap and release everything kc_vaspace_create mapped (NULL is a no-op). */
 void kc_vaspace_destroy(kc_vaspace *vs);
+
+/* An address at which `size` bytes (rounded up to the virtual-memory
+ * granularity) could be reserved a moment ago, chosen away from the blocks the
+ * runtime takes for itself: a trial reservation shows where free reservations
+ * land; addresses 64 GiB, 128 GiB, ... below that are tried and the first one
+ * granted exactly is returned (every trial is released again).  A capture
+ * that maps its tracked memory there with kc_vaspace_create lets a replay
+ * process, which maps the same ranges before anything else allocates, get the
+ * same addresses. */
+int kc_vaspace_suggest(int hip_device, uint64_t size, uint64_t *base);
 
 /* ---- validation ----------------------------------------------------------- */
 

@@ -77,8 +77,13 @@ int kc_vaspace_create(int hip_device, const kc_range* ranges, uint32_t n, kc_vas
   prop.type = hipMemAllocationTypePinned;
   prop.location.type = hipMemLocationTypeDevice;
   prop.location.id = hip_device;
-  size_t gran = 0;
+  // Spans follow the recommended granularity (the runtime places reservations
+  // of that size class where larger allocations go), at least the minimum.
+  size_t gran = 0, rec = 0;
   KC_HIP(hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum));
+  if (hipMemGetAllocationGranularity(&rec, &prop, hipMemAllocationGranularityRecommended) == hipSuccess && rec > gran)
+    gran = rec;
+  (void)hipGetLastError();
   if (gran == 0 || (gran & (gran - 1)) != 0) {
     kc::set_error_text("unexpected virtual memory granularity");
     return KC_EHIP;
@@ -125,6 +130,48 @@ int kc_vaspace_create(int hip_device, const kc_range* ranges, uint32_t n, kc_vas
   if (n_spans) *n_spans = (uint32_t)vs->spans.size();
   if (mapped_bytes) *mapped_bytes = total;
   *out = vs;
+  return KC_OK;
+}
+
+int kc_vaspace_suggest(int hip_device, uint64_t size, uint64_t* base) {
+  if (base == nullptr || size == 0) return KC_EINVAL;
+  *base = 0;
+  kc::DeviceGuard g(hip_device);
+  if (!g.ok) return KC_EHIP;
+  hipMemAllocationProp prop{};
+  prop.type = hipMemAllocationTypePinned;
+  prop.location.type = hipMemLocationTypeDevice;
+  prop.location.id = hip_device;
+  size_t gran = 0, rec = 0;
+  KC_HIP(hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum));
+  if (hipMemGetAllocationGranularity(&rec, &prop, hipMemAllocationGranularityRecommended) == hipSuccess && rec > gran)
+    gran = rec;
+  (void)hipGetLastError();
+  if (gran == 0) return KC_EHIP;
+  const uint64_t span = (size + gran - 1) / gran * gran;
+  // Where an unplaced reservation lands, then addresses well below it: the
+  // runtime later claims blocks near the first placements for its own use, so
+  // the first address below them that is granted exactly is the suggestion.
+  void* p = nullptr;
+  KC_HIP(hipMemAddressReserve(&p, span, gran, nullptr, 0));
+  const uint64_t first = (uint64_t)(uintptr_t)p;
+  KC_HIP(hipMemAddressFree(p, span));
+  constexpr uint64_t kStep = 64ull << 30;
+  for (uint64_t k = 1; k <= 8; ++k) {
+    if (first < k * kStep + span) break;
+    const uint64_t want = (first - k * kStep) / gran * gran;
+    void* got = nullptr;
+    if (hipMemAddressReserve(&got, span, gran, reinterpret_cast<void*>(want), 0) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    (void)hipMemAddressFree(got, span);
+    if ((uint64_t)(uintptr_t)got == want) {
+      *base = want;
+      return KC_OK;
+    }
+  }
+  *base = first;  // nothing below was granted exactly: the first placement
   return KC_OK;
 }
 

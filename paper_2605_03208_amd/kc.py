@@ -35,7 +35,7 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
            "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
-           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy"]
+           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest"]
 
 
 class KCError(RuntimeError):
@@ -134,6 +134,7 @@ def lib() -> ctypes.CDLL:
             "kc_region_diff": ([vp, vp, u64, vp, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp], i32),
             "kc_vaspace_create": ([i32, P(Range), u32, P(vp), P(u32), P(u64)], i32),
             "kc_vaspace_destroy": ([vp], None),
+            "kc_vaspace_suggest": ([i32, u64, P(u64)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -284,6 +285,13 @@ class VaSpace:
             self.close()
         except Exception:
             pass
+
+
+def vaspace_suggest(device: int, size: int) -> int:
+    """An address where ``size`` bytes could be reserved a moment ago."""
+    base = ctypes.c_uint64(0)
+    _check(lib().kc_vaspace_suggest(device, size, ctypes.byref(base)), "kc_vaspace_suggest")
+    return int(base.value)
 
 
 class ScanOut:

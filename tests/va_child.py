@@ -1,10 +1,10 @@
 """Two processes of a VA-faithful capture and replay, run by
 ``tests/test_gpu_vaspace.py`` (not a test module itself).
 
-``capture DIR``: build seeded ranges holding data and pointers into each
-other at whatever VAs this process's allocator gives, snapshot them, save the
-snapshot to DIR with the raw bytes, the closure-scan result and the pointer
-graph.
+``capture DIR``: map the tracked memory at an address the runtime offers,
+fill seeded ranges with data and pointers into each other, snapshot them, and
+save the snapshot to DIR with the raw bytes, the closure-scan result and the
+pointer graph.
 
 ``replay DIR``: in a fresh process, map device memory at exactly the saved
 VAs before anything else allocates (exit 3 if a range cannot be placed there),
@@ -24,10 +24,34 @@ def raw_view(torch, base, size):
 
 
 def capture(d):
+    """The tracked memory is mapped at an address the runtime offers for it
+    (kc_vaspace_suggest), filled with seeded bytes and pointers between the
+    ranges, snapshotted and saved."""
     import torch
     from paper_2605_03208_amd import kc, workloads as W
-    case = W.graph_case("cuda", n_ranges=40, seed=77, max_pages=32)
-    ranges = case.ranges()
+    page = 4096
+    rng = np.random.default_rng(77)
+    sizes = rng.integers(1, 33, size=40) * page
+    sizes[::9] -= rng.integers(1, page, size=len(sizes[::9]))      # a few partial last pages
+    lay = W.make_layout(rng, sizes, gap_pages=(1, 8))
+    total = (lay.arena_bytes + page - 1) // page * page
+    base = kc.vaspace_suggest(0, total)
+    vs = kc.VaSpace(0, [(base, total)])                            # the capture's tracked memory
+    ranges = lay.ranges(base)
+    host = np.zeros(total, dtype=np.uint8)
+    n_ptr = 0
+    for (o, s) in zip(lay.offsets, lay.sizes):
+        o, s = int(o), int(s)
+        host[o:o + s] = rng.integers(0, 256, size=s, dtype=np.uint8)
+        for p in range((s + page - 1) // page):
+            if rng.random() < 0.15:
+                host[o + p * page: min(o + (p + 1) * page, o + s)] = 0
+        for w in np.flatnonzero(rng.random(s // 8) < 0.005):
+            b, bs = ranges[int(rng.integers(0, len(ranges)))]
+            host[o + 8 * int(w): o + 8 * int(w) + 8] = np.frombuffer(
+                np.uint64(b + int(rng.integers(0, bs))).tobytes(), dtype=np.uint8)
+            n_ptr += 1
+    raw_view(torch, base, total).copy_(torch.from_numpy(host).cuda())
     ctx = kc.Context(0)
     rs = kc.RangeSet(ctx, ranges)
     scan = kc.ScanOut("cuda", oob_cap=64)
@@ -35,17 +59,18 @@ def capture(d):
     torch.cuda.synchronize()
     kc.snapshot_save(ctx, rs, d, out)
     edge = kc.pointer_graph(ctx, rs).cpu().numpy().view(np.uint64)
-    host = case.arena.host_copy()
-    np.concatenate(W.host_views(case.layout, host)).tofile(os.path.join(d, "raw.bin"))
+    np.concatenate([host[int(o): int(o) + int(s)] for o, s in zip(lay.offsets, lay.sizes)]).tofile(
+        os.path.join(d, "raw.bin"))
     res, oob = scan.result()
     info = dict(ranges=ranges, scan=res, oob=oob, n_kept=int(out["n_kept"].item()),
                 edges=[int(x) for x in edge.reshape(-1)])
     with open(os.path.join(d, "capture.json"), "w") as f:
         json.dump(info, f)
-    probe = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")   # where this allocator goes next
-    print(json.dumps({"captured": len(ranges), "n_kept": info["n_kept"], "n_in_range": res["n_in_range"],
-                      "lowest": hex(ranges[0][0]), "highest_end": hex(ranges[-1][0] + ranges[-1][1]),
-                      "next_allocation": hex(probe.data_ptr())}))
+    print(json.dumps({"captured": len(ranges), "at": hex(base), "bytes": total, "n_kept": info["n_kept"],
+                      "pointers_planted": n_ptr, "n_in_range": res["n_in_range"]}))
+    rs.close()
+    ctx.close()
+    vs.close()
     return 0
 
 
