@@ -324,6 +324,7 @@ def main() -> int:
         line["graph"]["c1_latency"] = c1_latency(torch, kc, W, dev)
         line["batching"] = batching(torch, kc, W, dev)
         line["snapshot_files"] = snapshot_files(torch, kc, W, dev)
+        line["partial_pages"] = partial_pages(torch, kc, W, dev)
         line["serving"] = serving(torch, kc, W, dev, args.serve_seconds)
     if cpu is not None:
         line["cpu_baseline"] = cpu
@@ -493,6 +494,40 @@ def c1_latency(torch, kc, W, dev) -> dict:
     return {"workload": "c1: 64 MiB / 48 ranges snapshot + restore + 16 x 2^20 fp32 compare",
             "stream_us": round(stream_us, 1), "graph_us": round(graph_us, 1),
             "graph_speedup": round(stream_us / graph_us, 3), "replays_match_eager": ok}
+
+
+def partial_pages(torch, kc, W, dev) -> dict:
+    """Full snapshot of the c2 pool (4096 ranges, 2 GiB) with its page-multiple
+    sizes, then with every range 1-4095 bytes shorter (every range ends in a
+    partial page): what the partial-page path costs."""
+    import numpy as np
+    log("partial pages: c2 full snapshot, whole vs every range ending in a partial page")
+    case = W.c2_snapshot("cuda")
+    rng = np.random.default_rng(7)
+    whole = case.ranges()
+    ragged = [(b, s - int(rng.integers(1, 4096))) for b, s in whole]
+    out = {"ranges": len(whole)}
+    for name, ranges in (("whole", whole), ("ragged", ragged)):
+        ctx = kc.Context(0)
+        rs = kc.RangeSet(ctx, ranges)
+        snap = kc.snapshot(ctx, rs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            kc.snapshot(ctx, rs, out=snap)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        nbytes = sum(s for _, s in ranges)
+        out[f"{name}_ms"] = round(ms, 4)
+        out[f"{name}_GBps_read"] = round(nbytes / (ms / 1e3) / 1e9, 1)
+        rs.close()
+        ctx.close()
+    out["ragged_over_whole"] = round(out["ragged_ms"] / out["whole_ms"], 3)
+    del case
+    torch.cuda.empty_cache()
+    return out
 
 
 def batching(torch, kc, W, dev) -> dict:
