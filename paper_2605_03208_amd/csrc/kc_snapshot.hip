@@ -142,7 +142,7 @@ __global__ void k_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
 // true: only the tiles listed in p.ragged, whose last page is partial (at most
 // one per range), with the bytes past the range's end masked out.
 template <bool GATHER, bool PRIOR, bool SCAN, bool RAGGED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_page_hash(HashParams p) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 : 4))) void k_page_hash(HashParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kTilePages * kStageStride];
   __shared__ uint64_t tail_lds[kTilePages][4];  // a partial page's bytes past its last whole stripe
   __shared__ FenceLds fences;
