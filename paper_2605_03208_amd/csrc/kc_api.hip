@@ -107,7 +107,7 @@ int finish_scan(kc_rangeset* rs, const kc_scan_args* sa, const ScanDev& sd, hipS
   src.n_items = rs->n_tiles;
   KC_HIP(launch_scan(src, rs->tile_prefix, rs->block_sums, rs->n_oob, s));
   KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, rs->n_oob, sa->oob_d, sa->oob_cap,
-                         sa->res_d, rs->n_scan_words, grid_for(rs->ctx, KC_OP_CLOSURE, 8), s));
+                         sa->res_d, rs->n_scan_words, s));
   return KC_OK;
 }
 

@@ -280,11 +280,13 @@ __device__ __forceinline__ void tile_body(const CmpPairDev& pr, uint64_t b0, uin
   }
   // bytes past the last whole 16-byte run: element by element
   if (tid == 0) {
+    const KC_GLOBAL uint8_t* cb = (const KC_GLOBAL uint8_t*)pr.cand;
+    const KC_GLOBAL uint8_t* gb = (const KC_GLOBAL uint8_t*)pr.gold;
     for (uint64_t b = b0 + nvec * 16u; b < b1; b += es) {
       B cv = 0, gv = 0;
       for (uint32_t i = 0; i < es; ++i) {
-        cv |= (B)pr.cand[b + i] << (8u * i);
-        gv |= (B)pr.gold[b + i] << (8u * i);
+        cv |= (B)cb[b + i] << (8u * i);
+        gv |= (B)gb[b + i] << (8u * i);
       }
       element<DT>(cv, gv, b / es, tol, p, hist);
     }

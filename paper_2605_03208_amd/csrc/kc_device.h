@@ -52,9 +52,11 @@ __device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, co
   uint32_t b = min(a + rt.stride, rt.n);
   while (b - a > 1u) {
     const uint32_t m = (a + b) >> 1;
-    if (rt.base[m] <= w) a = m; else b = m;
+    if (ld8g(rt.base + m) <= w) a = m; else b = m;
   }
-  return w < rt.end[a] ? (int32_t)a : -1;
+  // typed global: merged with the LDS read above, the two would become one
+  // flat load, whose wait also waits for every global load in flight
+  return w < ld8g(rt.end + a) ? (int32_t)a : -1;
 }
 
 // True iff w lies in [base_r, end_r) for some range r.

@@ -23,17 +23,32 @@ constexpr uint32_t kBuckets = 1024;     // entries of the LDS bucket index over 
 // snapshot, compared buffers) uses non-temporal loads and stores, which on
 // gfx950 measured 7.2 TB/s for a read-only stream against 6.35 TB/s for
 // plain loads.
+//
+// The addresses are typed as global memory (address space 1).  A plain
+// pointer made from an integer compiles to a flat access, which counts on the
+// LDS counter as well, so the first LDS wait after it (the hash reads its
+// stage from LDS while the next chunk is in flight) would wait for the
+// global loads too.
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint4 ld16(uint64_t addr) { return *reinterpret_cast<const uint4*>(addr); }
-__device__ __forceinline__ void st16(uint64_t addr, uint4 v) { *reinterpret_cast<uint4*>(addr) = v; }
+#define KC_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ uint4 ld16(uint64_t addr) {
+  const v4u v = *(const KC_GLOBAL v4u*)addr;
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st16(uint64_t addr, uint4 v) {
+  const v4u x = {v.x, v.y, v.z, v.w};
+  *(KC_GLOBAL v4u*)addr = x;
+}
 __device__ __forceinline__ uint4 ld16nt(uint64_t addr) {
-  const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(addr));
+  const v4u v = __builtin_nontemporal_load((const KC_GLOBAL v4u*)addr);
   return make_uint4(v[0], v[1], v[2], v[3]);
 }
 __device__ __forceinline__ void st16nt(uint64_t addr, uint4 v) {
   const v4u x = {v.x, v.y, v.z, v.w};
-  __builtin_nontemporal_store(x, reinterpret_cast<v4u*>(addr));
+  __builtin_nontemporal_store(x, (KC_GLOBAL v4u*)addr);
 }
+// An 8-byte global load through a plain pointer, kept a global access.
+__device__ __forceinline__ uint64_t ld8g(const uint64_t* p) { return *(const KC_GLOBAL uint64_t*)p; }
 
 // A tile: up to 16 consecutive pages of one range.  Only a range's last page
 // can be partial (a range size that is not a multiple of the page); last_len
@@ -92,7 +107,7 @@ __device__ __forceinline__ void st_bytes(uint64_t addr, uint4 v, uint32_t n) {
   for (uint32_t i = 0; i < 16u; ++i) {
     if (i < n) {
       const uint32_t w = i < 4u ? v.x : (i < 8u ? v.y : (i < 12u ? v.z : v.w));
-      *reinterpret_cast<uint8_t*>(addr + i) = (uint8_t)(w >> (8u * (i & 3u)));
+      *(KC_GLOBAL uint8_t*)(addr + i) = (uint8_t)(w >> (8u * (i & 3u)));
     }
   }
 }
@@ -203,8 +218,7 @@ hipError_t launch_region_diff(const Tile* tiles, uint32_t n_tiles, const RangeTa
                               kc_region_diff_result* res, uint32_t grid, hipStream_t s);
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
                            const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
-                           uint64_t cap, kc_scan_result* res, uint64_t n_words, uint32_t grid,
-                           hipStream_t s);
+                           uint64_t cap, kc_scan_result* res, uint64_t n_words, hipStream_t s);
 hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
                           uint32_t tile_bytes, unsigned long long* acc, uint32_t grid, hipStream_t s);
 hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, unsigned long long* acc,

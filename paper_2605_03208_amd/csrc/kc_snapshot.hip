@@ -574,7 +574,7 @@ __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uin
       va = page_va[s0 + lane];
       const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
       if (a >= 0) {  // a range's partial last page is left to k_restore_tail
-        const uint64_t end = rt.stride == 1u ? fences.end[a] : rt.end[a];
+        const uint64_t end = rt.stride == 1u ? fences.end[a] : ld8g(rt.end + a);
         ok = va + kPage <= end;
       } else {
         atomicAdd(n_bad, 1ull);
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_
       va = page_va[s0 + lane];
       const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
       if (a >= 0) {
-        const uint64_t end = rt.stride == 1u ? fences.end[a] : rt.end[a];
+        const uint64_t end = rt.stride == 1u ? fences.end[a] : ld8g(rt.end + a);
         if (va + kPage > end) len = (uint32_t)(end - va);
       }
     }
@@ -682,14 +682,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // Writes the out-of-range words of each tile at its prefix position, in
-// ascending address order, up to the list capacity.
-__global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_tiles, ScanDev sd,
-                                                 const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
-                                                 uint64_t cap, kc_scan_result* res, uint64_t n_words) {
+// ascending address order, up to the list capacity.  A block owns a slice of
+// consecutive tiles: one parallel read of their counts lists the tiles with
+// entries below the capacity, then each listed tile is read again with one
+// wave per page (its four 1-KiB segments in one round trip), the waves'
+// entries placed by a prefix over their counts.
+constexpr uint32_t kEmitThreads = kTilePages * kWave;  // one wave per page of a tile
+constexpr uint32_t kEmitMaxSlice = kEmitThreads;       // tiles a block lists at once
+constexpr uint32_t kEmitMaxBlocks = 512;
+
+__global__ __launch_bounds__(kEmitThreads) void k_oob_emit(const Tile* tiles, uint32_t n_tiles, uint32_t slice,
+                                                           ScanDev sd, const uint64_t* tile_prefix,
+                                                           const uint64_t* n_oob, kc_oob* oob, uint64_t cap,
+                                                           kc_scan_result* res, uint64_t n_words) {
   __shared__ FenceLds fences;
-  const uint32_t lane = threadIdx.x;
+  __shared__ uint32_t listed[kEmitMaxSlice];
+  __shared__ uint32_t n_listed;
+  __shared__ uint32_t wave_cnt[kTilePages];
+  const uint32_t tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
   const uint64_t total = *n_oob;
-  if (blockIdx.x == 0 && lane == 0) {  // the result struct
+  if (blockIdx.x == 0 && tid == 0) {  // the result struct
     res->n_words = n_words;
     res->n_ptr_like = sd.counts[0];
     res->n_in_range = sd.counts[1];
@@ -698,44 +710,64 @@ __global__ __launch_bounds__(64) void k_oob_emit(const Tile* tiles, uint32_t n_t
     res->truncated = total > cap ? 1u : 0u;
   }
   if (total == 0 || cap == 0) return;  // nothing to list: no tile to revisit
-  load_fences(fences, sd.rt, lane, kWave);
-  __syncthreads();
   const uint64_t below = (1ull << lane) - 1ull;
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const uint32_t cnt = sd.tile_oob[t];
-    const uint64_t pre = tile_prefix[t];
-    if (cnt == 0u || pre >= cap) continue;
-    const Tile tile = tiles[t];
-    const uint32_t nseg = tile.npages * 4u;
-    uint64_t done = 0;
-    // eight 1-KiB segments per round trip; within them, segments in order
-    for (uint32_t s0 = 0; s0 < nseg && done < cnt && pre + done < cap; s0 += 8) {
-      uint4 x[8];
+  bool fenced = false;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * slice; t0 < n_tiles; t0 += (uint64_t)gridDim.x * slice) {
+    if (tid == 0) n_listed = 0u;
+    __syncthreads();
+    const uint64_t t = t0 + tid;
+    if (tid < slice && t < n_tiles && sd.tile_oob[t] != 0u && tile_prefix[t] < cap)
+      listed[atomicAdd(&n_listed, 1u)] = (uint32_t)t;
+    __syncthreads();
+    const uint32_t n = n_listed;  // the same in every thread
+    if (n != 0u && !fenced) {     // the range table, only for blocks with a tile to revisit
+      load_fences(fences, sd.rt, tid, kEmitThreads);
+      __syncthreads();
+      fenced = true;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint32_t tt = listed[i];
+      const Tile tile = tiles[tt];
+      const bool mine = wv < tile.npages;
+      uint4 x[4];
 #pragma unroll
-      for (uint32_t i = 0; i < 8; ++i)
-        x[i] = s0 + i < nseg ? ld16(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
+      for (uint32_t j = 0; j < 4; ++j)
+        x[j] = mine ? ld16(tile.va + (uint64_t)(wv * 4u + j) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
+      uint64_t b0[4], b1[4];
+      uint32_t cnt = 0;
 #pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) {  // words past the tile are zero: never pointer-like
-        const uint64_t a = tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u;
-        const uint4 v = seg_words(tile, s0 + i, lane, x[i]);  // same words as the counting pass
+      for (uint32_t j = 0; j < 4; ++j) {  // zero words (and pages past the tile) are never pointer-like
+        const uint4 v = seg_words(tile, wv * 4u + j, lane, x[j]);  // same words as the counting pass
         const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
         const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
-        const bool o0 = (w0 - sd.lo) < sd.span && !in_ranges(w0, fences, sd.rt);
-        const bool o1 = (w1 - sd.lo) < sd.span && !in_ranges(w1, fences, sd.rt);
-        const uint64_t b0 = __ballot(o0), b1 = __ballot(o1);
-        const uint64_t r0 = pre + done + (uint64_t)__popcll(b0 & below) + (uint64_t)__popcll(b1 & below);
+        b0[j] = __ballot((w0 - sd.lo) < sd.span && !in_ranges(w0, fences, sd.rt));
+        b1[j] = __ballot((w1 - sd.lo) < sd.span && !in_ranges(w1, fences, sd.rt));
+        cnt += (uint32_t)(__popcll(b0[j]) + __popcll(b1[j]));
+        x[j] = v;
+      }
+      if (lane == 0) wave_cnt[wv] = cnt;
+      __syncthreads();
+      uint64_t done = tile_prefix[tt];
+      for (uint32_t w = 0; w < wv; ++w) done += wave_cnt[w];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {  // segments in order, lanes in order, word 0 before word 1
+        const uint64_t a = tile.va + (uint64_t)(wv * 4u + j) * 1024u + lane * 16u;
+        const bool o0 = ((b0[j] >> lane) & 1ull) != 0ull, o1 = ((b1[j] >> lane) & 1ull) != 0ull;
+        const uint64_t r0 = done + (uint64_t)__popcll(b0[j] & below) + (uint64_t)__popcll(b1[j] & below);
         const uint64_t r1 = r0 + (o0 ? 1u : 0u);
         if (o0 && r0 < cap) {
           oob[r0].word_va = a;
-          oob[r0].value = w0;
+          oob[r0].value = ((uint64_t)x[j].y << 32) | x[j].x;
         }
         if (o1 && r1 < cap) {
           oob[r1].word_va = a + 8u;
-          oob[r1].value = w1;
+          oob[r1].value = ((uint64_t)x[j].w << 32) | x[j].z;
         }
-        done += (uint64_t)__popcll(b0) + (uint64_t)__popcll(b1);
+        done += (uint64_t)__popcll(b0[j]) + (uint64_t)__popcll(b1[j]);
       }
+      __syncthreads();  // wave_cnt is reused by the next listed tile
     }
+    __syncthreads();  // every thread has read n_listed before it is cleared again
   }
 }
 
@@ -856,10 +888,13 @@ hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, c
 
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd, const uint64_t* tile_prefix,
                            const uint64_t* n_oob, kc_oob* oob, uint64_t cap, kc_scan_result* res, uint64_t n_words,
-                           uint32_t grid, hipStream_t s) {
-  grid = std::max(1u, std::min(grid, std::max(1u, n_tiles)));
-  hipLaunchKernelGGL(k_oob_emit, dim3(grid), dim3(64), 0, s, tiles, n_tiles, sd, tile_prefix, n_oob, oob, cap, res,
-                     n_words);
+                           hipStream_t s) {
+  // slices of up to 1024 tiles, at most 512 blocks: few tiles per block on small sets, so that listed tiles are
+  // revisited in parallel
+  const uint32_t slice = std::max(1u, std::min(kEmitMaxSlice, blocks_for(n_tiles, kEmitMaxBlocks)));
+  const uint32_t blocks = std::max(1u, blocks_for(n_tiles, slice));
+  hipLaunchKernelGGL(k_oob_emit, dim3(blocks), dim3(kEmitThreads), 0, s, tiles, n_tiles, slice, sd, tile_prefix,
+                     n_oob, oob, cap, res, n_words);
   return hipGetLastError();
 }
 
