@@ -689,7 +689,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // entries placed by a prefix over their counts.
 constexpr uint32_t kEmitThreads = kTilePages * kWave;  // one wave per page of a tile
 constexpr uint32_t kEmitMaxSlice = kEmitThreads;       // tiles a block lists at once
-constexpr uint32_t kEmitMaxBlocks = 512;
+constexpr uint32_t kEmitMaxBlocks = 128;
 
 __global__ __launch_bounds__(kEmitThreads) void k_oob_emit(const Tile* tiles, uint32_t n_tiles, uint32_t slice,
                                                            ScanDev sd, const uint64_t* tile_prefix,
@@ -889,8 +889,8 @@ hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, c
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd, const uint64_t* tile_prefix,
                            const uint64_t* n_oob, kc_oob* oob, uint64_t cap, kc_scan_result* res, uint64_t n_words,
                            hipStream_t s) {
-  // slices of up to 1024 tiles, at most 512 blocks: few tiles per block on small sets, so that listed tiles are
-  // revisited in parallel
+  // slices of up to 1024 tiles, at most 128 blocks unless the slices are full: few tiles per block on small sets,
+  // so that listed tiles are revisited in parallel
   const uint32_t slice = std::max(1u, std::min(kEmitMaxSlice, blocks_for(n_tiles, kEmitMaxBlocks)));
   const uint32_t blocks = std::max(1u, blocks_for(n_tiles, slice));
   hipLaunchKernelGGL(k_oob_emit, dim3(blocks), dim3(kEmitThreads), 0, s, tiles, n_tiles, slice, sd, tile_prefix,
