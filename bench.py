@@ -352,9 +352,9 @@ def main() -> int:
         log("copy ceiling: plain 4 GiB device-to-device copy")
         line["copy_ceiling"] = copy_ceiling(torch, dev)
         log("pointer graph over the same ranges")
-        line["pointer_graph"] = pointer_graph_pass(torch, kc, ctx, rs, N, args.steps)
+        line["pointer_graph"] = pointer_graph_pass(torch, kc, ctx, rs, N, args.steps, tune=not args.no_tune)
         log("region diff of the live pool against the step's snapshot, 1 % of pages touched")
-        line["region_diff"] = region_diff_pass(torch, kc, ctx, rs, out, case, N, args.steps)
+        line["region_diff"] = region_diff_pass(torch, kc, ctx, rs, out, case, N, args.steps, tune=not args.no_tune)
         log("graph replay of the step")
         line["graph"] = graph_step(torch, step, res, pair_list, kc, args.steps)
         state["ps"].close()
@@ -393,10 +393,11 @@ def copy_ceiling(torch, dev, gib: int = 4, reps: int = 5) -> dict:
             "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int) -> dict:
+def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int, tune: bool = True) -> dict:
     """kc_region_diff over the step's ranges against the step's snapshot, after
     one byte of every 100th page was flipped (flipped back afterwards)."""
     import numpy as np
+    shape = None
     cum = case.layout.cum()
     pages = np.arange(0, n_pages, 100)
     a = np.searchsorted(cum // PAGE, pages, side="right") - 1
@@ -405,6 +406,11 @@ def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int) ->
     buf = case.arena.buf
     buf[idx] ^= 0x5A
     out = kc.region_diff(ctx, rs, gold)
+    if tune:
+        from paper_2605_03208_amd import autotune
+        r = autotune.tune(ctx, kc.OP_REGION_DIFF, lambda: kc.region_diff(ctx, rs, gold, out=out),
+                          lambda: autotune.digest_tensors(out["res"], out["changed_bm"]), f"c4-moe-pool-pages{n_pages}")
+        shape = r["best"]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -426,13 +432,20 @@ def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int) ->
     return {"op_ms": round(ms, 4), "GBps": round(alg / (ms / 1e3) / 1e9, 1),
             "frac_of_peak": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "hash_kernel_ms": round(hms, 4), "diff_kernel_ms": round(kms, 4), "pages_changed": changed,
-            "diff_bytes": sum(r["n_diff_bytes"] for r in diff), "diff_pages": sum(r["n_diff_pages"] for r in diff)}
+            "diff_bytes": sum(r["n_diff_bytes"] for r in diff), "diff_pages": sum(r["n_diff_pages"] for r in diff),
+            "diff_shape": shape}
 
 
-def pointer_graph_pass(torch, kc, ctx, rs, n_pages: int, reps: int) -> dict:
+def pointer_graph_pass(torch, kc, ctx, rs, n_pages: int, reps: int, tune: bool = True) -> dict:
     """kc_pointer_graph over the step's ranges: one read of every page."""
     import numpy as np
     out = kc.pointer_graph(ctx, rs)
+    shape = None
+    if tune:
+        from paper_2605_03208_amd import autotune
+        r = autotune.tune(ctx, kc.OP_GRAPH, lambda: kc.pointer_graph(ctx, rs, out=out),
+                          lambda: autotune.digest_tensors(out), f"c4-moe-pool-pages{n_pages}")
+        shape = r["best"]
     ctx.enable_timing(True)
     ms = []
     for _ in range(reps):
@@ -443,7 +456,8 @@ def pointer_graph_pass(torch, kc, ctx, rs, n_pages: int, reps: int) -> dict:
     k = float(np.mean(ms))
     gbs = n_pages * PAGE / (k / 1e3) / 1e9
     return {"kernel": "k_pointer_graph", "kernel_ms": round(k, 4), "GBps": round(gbs, 1),
-            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "n_ranges": len(rs.ranges), "n_edges": edges}
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "n_ranges": len(rs.ranges), "n_edges": edges,
+            "shape": shape}
 
 
 def graph_step(torch, step, res, pair_list, kc, reps: int) -> dict:

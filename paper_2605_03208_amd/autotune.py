@@ -32,10 +32,13 @@ CANDIDATES = {
     kc.OP_CLOSURE: [dict(grid_per_cu=g) for g in (4, 8, 16)],
     kc.OP_COMPARE: [dict(grid_per_cu=g, tile_bytes=t) for g in (1, 2, 3, 4)
                     for t in (32 << 10, 64 << 10, 128 << 10, 256 << 10)],
+    kc.OP_GRAPH: [dict(grid_per_cu=g) for g in (4, 8, 12, 16)],
+    kc.OP_REGION_DIFF: [dict(grid_per_cu=g) for g in (8, 12, 16, 20, 32)],
 }
 
 OP_NAMES = {kc.OP_PAGE_HASH: "page_hash", kc.OP_SNAPSHOT: "snapshot", kc.OP_COMPACT: "compact",
-            kc.OP_RESTORE: "restore", kc.OP_CLOSURE: "closure_scan", kc.OP_COMPARE: "compare"}
+            kc.OP_RESTORE: "restore", kc.OP_CLOSURE: "closure_scan", kc.OP_COMPARE: "compare",
+            kc.OP_GRAPH: "pointer_graph", kc.OP_REGION_DIFF: "region_diff"}
 
 
 class TuningChangedResult(RuntimeError):

@@ -279,7 +279,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   const size_t sz_tp = align_up(8 * std::max<size_t>(1, rs->n_tiles), 256);
   const size_t sz_wp = align_up(8 * std::max<uint64_t>(1, rs->n_words), 256);
   const size_t sz_bs = align_up(8 * std::max<uint64_t>(1, std::max(nb_words, nb_tiles)), 256);
-  const size_t sz_misc = 256;
+  const size_t sz_misc = 256 + align_up(8 * kScanCountWords, 256);
   const size_t sz_bk = align_up(sizeof(uint16_t) * kBuckets, 256);
   const size_t sz_rg = align_up(4 * std::max<size_t>(1, ragged.size()), 256);
   const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
@@ -297,8 +297,9 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->tile_prefix = reinterpret_cast<uint64_t*>(p); p += sz_tp;
   rs->word_prefix = reinterpret_cast<uint64_t*>(p); p += sz_wp;
   rs->block_sums = reinterpret_cast<uint64_t*>(p); p += sz_bs;
-  rs->counts = reinterpret_cast<unsigned long long*>(p);
+  rs->n_bad = reinterpret_cast<unsigned long long*>(p);
   rs->n_oob = reinterpret_cast<uint64_t*>(p + 64);
+  rs->counts = reinterpret_cast<unsigned long long*>(p + 256);
   p += sz_misc;
   uint16_t* bucket_d = reinterpret_cast<uint16_t*>(p);
   p += sz_bk;
@@ -333,7 +334,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
     if ((e = hipMemcpy(rs->ends, ends.data(), 8 * n, hipMemcpyHostToDevice)) != hipSuccess)
       return fail("hipMemcpy(ends)", e);
   }
-  if ((e = hipMemset(rs->counts, 0, sz_misc)) != hipSuccess) return fail("hipMemset(counts)", e);
+  if ((e = hipMemset(rs->n_bad, 0, sz_misc)) != hipSuccess) return fail("hipMemset(counts)", e);
   if ((e = hipMemcpy(bucket_d, bucket.data(), sizeof(uint16_t) * kBuckets, hipMemcpyHostToDevice)) != hipSuccess)
     return fail("hipMemcpy(bucket index)", e);
   if (!ragged.empty() &&
@@ -402,7 +403,7 @@ int kc_page_hash(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   KC_HIP(launch_zero3(zero_bm_d, rs->n_words, changed_bm_d, prior_hash_d ? rs->n_words : 0,
-                      reinterpret_cast<uint64_t*>(rs->counts), scan ? 2 : 0, s));
+                      reinterpret_cast<uint64_t*>(rs->counts), scan ? kScanCountWords : 0, s));
   HashParams hp{};
   hp.seed = seed;
   hp.prior = prior_hash_d;
@@ -467,8 +468,8 @@ int kc_snapshot(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
-  KC_HIP(launch_zero3(zero_bm_d, rs->n_words, nullptr, 0, reinterpret_cast<uint64_t*>(rs->counts), scan ? 2 : 0,
-                      s));
+  KC_HIP(launch_zero3(zero_bm_d, rs->n_words, nullptr, 0, reinterpret_cast<uint64_t*>(rs->counts),
+                      scan ? kScanCountWords : 0, s));
   KC_HIP(launch_probe_zero(rs->tiles, rs->n_tiles, zero_bm_d, grid_for(c, KC_OP_SNAPSHOT, 8), s));
   ScanSrc src{};
   src.kind = kSrcKeepBits;
@@ -501,7 +502,7 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
-  unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->counts + 2;
+  unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->n_bad;
   const uint32_t grid = grid_for(c, KC_OP_RESTORE, 16);
   KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, bad, grid, s));
   KernelTimer timer(c, KC_OP_RESTORE, s);
@@ -620,7 +621,7 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
   DeviceGuard g(c->device);
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
-  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), 2, 0, s));
+  KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), kScanCountWords, 0, s));
   const uint32_t grid = grid_for(c, KC_OP_CLOSURE, 8);
   {
     KernelTimer timer(c, KC_OP_CLOSURE, s);

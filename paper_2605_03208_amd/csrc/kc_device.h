@@ -12,6 +12,20 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   return x;
 }
 
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Adds a wave's closure-scan counts into its slot (lane 0 only).
+__device__ __forceinline__ void add_scan_counts(unsigned long long* counts, uint32_t slot, uint32_t n_ptr,
+                                                uint32_t n_in) {
+  unsigned long long* c = counts + (size_t)(slot % kScanSlots) * kScanSlotStride;
+  if (n_ptr) atomicAdd(c, (unsigned long long)n_ptr);
+  if (n_in) atomicAdd(c + 1, (unsigned long long)n_in);
+}
+
 // ---------------------------------------------------------- range search --
 struct FenceLds {
   uint64_t base[kFences];

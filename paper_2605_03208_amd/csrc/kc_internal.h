@@ -127,11 +127,18 @@ struct RangeTable {
   uint32_t shift;
 };
 
+// The closure-scan totals are accumulated in kScanSlots slot pairs, each on
+// its own 256-byte line: every wave adds its counts once at its end, and
+// waves that finish together would otherwise queue on one address.
+constexpr uint32_t kScanSlots = 64;
+constexpr uint32_t kScanSlotStride = 32;  // u64 words between slots
+constexpr uint32_t kScanCountWords = kScanSlots * kScanSlotStride;
+
 struct ScanDev {
   uint64_t lo, span;                 // pointer-like iff (w - lo) < span
   RangeTable rt;
   uint32_t* tile_oob;                // per-tile out-of-range count
-  unsigned long long* counts;        // [0] n_ptr_like, [1] n_in_range (accumulated)
+  unsigned long long* counts;        // slot s: [s * kScanSlotStride] n_ptr_like, [+1] n_in_range (accumulated)
 };
 
 struct HashParams {
@@ -299,7 +306,8 @@ struct kc_rangeset {
   uint64_t* tile_prefix = nullptr;
   uint64_t* word_prefix = nullptr;
   uint64_t* block_sums = nullptr;
-  unsigned long long* counts = nullptr;  // [0] ptr-like, [1] in-range, [2] rejected page VAs
+  unsigned long long* counts = nullptr;  // closure-scan slots (kScanCountWords)
+  unsigned long long* n_bad = nullptr;   // rejected page VAs of a restore given no counter
   uint64_t* n_oob = nullptr;
   kc::RangeTable rt{};
 };

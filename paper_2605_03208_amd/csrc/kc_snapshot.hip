@@ -288,8 +288,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 :
   if (SCAN) {
     const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
     if (lane == 0) {
-      if (a) atomicAdd(&p.scan.counts[0], (unsigned long long)a);
-      if (b) atomicAdd(&p.scan.counts[1], (unsigned long long)b);
+      add_scan_counts(p.scan.counts, blockIdx.x, a, b);
     }
   }
 }
@@ -676,8 +675,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
   if (lane == 0) {
-    if (a) atomicAdd(&sd.counts[0], (unsigned long long)a);
-    if (b) atomicAdd(&sd.counts[1], (unsigned long long)b);
+    add_scan_counts(sd.counts, blockIdx.x, a, b);
   }
 }
 
@@ -701,13 +699,18 @@ __global__ __launch_bounds__(kEmitThreads) void k_oob_emit(const Tile* tiles, ui
   __shared__ uint32_t wave_cnt[kTilePages];
   const uint32_t tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
   const uint64_t total = *n_oob;
-  if (blockIdx.x == 0 && tid == 0) {  // the result struct
-    res->n_words = n_words;
-    res->n_ptr_like = sd.counts[0];
-    res->n_in_range = sd.counts[1];
-    res->n_oob = total;
-    res->n_written = (uint32_t)(total < cap ? total : cap);
-    res->truncated = total > cap ? 1u : 0u;
+  if (blockIdx.x == 0 && wv == 0) {  // the result struct, from the slot totals
+    static_assert(kScanSlots == kWave, "one slot per lane");
+    const unsigned long long* c = sd.counts + (size_t)lane * kScanSlotStride;
+    const unsigned long long a = wave_sum_u64(c[0]), b = wave_sum_u64(c[1]);
+    if (lane == 0) {
+      res->n_words = n_words;
+      res->n_ptr_like = a;
+      res->n_in_range = b;
+      res->n_oob = total;
+      res->n_written = (uint32_t)(total < cap ? total : cap);
+      res->truncated = total > cap ? 1u : 0u;
+    }
   }
   if (total == 0 || cap == 0) return;  // nothing to list: no tile to revisit
   const uint64_t below = (1ull << lane) - 1ull;
