@@ -47,10 +47,10 @@ PAGE = 4096
 # per launch, scaled by the factors a plain 4 GiB device copy gives (fetch
 # x2.0, write x1.0).  Valid only for the kernel sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "043154fe07a1261f446304ca4aa798954fd19e2c8293fb182469509bb1cf32f7",
-    "snapshot": 62932794473,   # fetch 31432308206 + write 31500486267
-    "restore": 62952072089,    # fetch 31598331315 + write 31353740774
-    "compare": 64456598426,    # fetch 64456598426 + write 0
+    "source_sha256": "adaf817fcac9c57fafdb89e7685e7efdd9cafa4bc632d7e699f87aa7c35c062e",
+    "snapshot": 62932999758,   # fetch 31432312485 + write 31500687273
+    "restore": 62955229081,    # fetch 31598348134 + write 31356880947
+    "compare": 64456630554,    # fetch 64456630554 + write 0
 }
 
 
@@ -363,7 +363,7 @@ def main() -> int:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         line["graph"]["c1_latency"] = c1_latency(torch, kc, W, dev)
-        line["batching"] = batching(torch, kc, W, dev)
+        line["batching"] = batching(torch, kc, W, dev, tune=not args.no_tune)
         line["snapshot_files"] = snapshot_files(torch, kc, W, dev)
         line["partial_pages"] = partial_pages(torch, kc, W, dev)
         line["serving"] = serving(torch, kc, W, dev, args.serve_seconds)
@@ -585,8 +585,10 @@ def partial_pages(torch, kc, W, dev) -> dict:
     return out
 
 
-def batching(torch, kc, W, dev) -> dict:
-    """Batched persistent launches vs one launch per buffer on uneven sizes."""
+def batching(torch, kc, W, dev, tune: bool = True) -> dict:
+    """Batched persistent launches (autotuned shapes unless ``tune`` is off) vs one launch per buffer on uneven
+    sizes."""
+    from paper_2605_03208_amd import autotune
     out = {}
     log("batching: c3 compare, 10,000 pairs / 8 GiB per side")
     ps = W.c3_pairs("cuda", n_pairs=10000)
@@ -598,6 +600,10 @@ def batching(torch, kc, W, dev) -> dict:
     for mode in ("batched", "per_buffer"):
         c2 = kc.Context(0)
         c2.set_tuning(kc.OP_COMPARE, per_item=1 if mode == "per_buffer" else 0)
+        if mode == "batched" and tune:
+            r = autotune.tune(c2, kc.OP_COMPARE, lambda: kc.compare(c2, arr, res=res),
+                              lambda: autotune.digest_tensors(res), "c3-10000-pairs")
+            out["c3_batched_shape"] = r["best"]
         kc.compare(c2, arr, res=res)
         torch.cuda.synchronize()
         results[mode] = res.clone()
@@ -630,6 +636,13 @@ def batching(torch, kc, W, dev) -> dict:
             c2.set_tuning(op, per_item=1 if mode == "per_buffer" else 0)
         rs = kc.RangeSet(c2, rngs)
         s2 = kc.snapshot(c2, rs, seed=2, prior=prior)
+        if mode == "batched" and tune:
+            run = lambda: kc.snapshot(c2, rs, seed=2, prior=prior, out=s2)
+            dig = lambda: autotune.digest_tensors(s2["hash"], s2["changed_bm"], s2["n_kept"], s2["page_va"])
+            out["c2_batched_shape"] = {kc_name: autotune.tune(c2, op, run, dig, "c2-delta-4096-ranges")["best"]
+                                       for op, kc_name in ((kc.OP_PAGE_HASH, "page_hash"),
+                                                           (kc.OP_COMPACT, "compact"))}
+            run()
         torch.cuda.synchronize()
         nk = int(s2["n_kept"].item())
         digests[mode] = (s2["hash"].cpu(), s2["changed_bm"].cpu(), s2["packed"][: nk * PAGE].cpu())
