@@ -280,7 +280,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   const size_t sz_wp = align_up(8 * std::max<uint64_t>(1, rs->n_words), 256);
   const size_t sz_bs = align_up(8 * std::max<uint64_t>(1, std::max(nb_words, nb_tiles)), 256);
   const size_t sz_misc = 256 + align_up(8 * kScanCountWords, 256);
-  const size_t sz_bk = align_up(sizeof(uint16_t) * kBuckets, 256);
+  const size_t sz_bk = 2 * align_up(sizeof(uint16_t) * kBuckets, 256);  // bucket index of each fence table
   const size_t sz_rg = align_up(4 * std::max<size_t>(1, ragged.size()), 256);
   const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
   hipError_t e = hipMalloc(&rs->dev, total);
@@ -302,22 +302,29 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->counts = reinterpret_cast<unsigned long long*>(p + 256);
   p += sz_misc;
   uint16_t* bucket_d = reinterpret_cast<uint16_t*>(p);
+  uint16_t* bucket_w_d = reinterpret_cast<uint16_t*>(p + sz_bk / 2);
   p += sz_bk;
   rs->ragged = reinterpret_cast<uint32_t*>(p);
   rs->n_ragged = (uint32_t)ragged.size();
   // Bucket index over [lowest base, highest end): the last fence at or below
-  // each bucket's first address.
-  const uint32_t stride = n <= kFences ? 1u : (n + kFences - 1) / kFences;
-  const uint32_t n_fence = n == 0 ? 0u : (n + stride - 1) / stride;
+  // each bucket's first address, for a table of every stride-th range.
   const uint64_t lo = n ? ranges[0].base : 0, span = n ? ranges[n - 1].base + ranges[n - 1].size - lo : 0;
   uint32_t shift = 12;
   while (span > 0 && ((span - 1) >> shift) >= kBuckets) ++shift;
-  std::vector<uint16_t> bucket(kBuckets, 0);
-  for (uint32_t b = 0, i = 0; b < kBuckets && n > 0; ++b) {
-    const uint64_t start = (uint64_t)b << shift;  // offset from lo
-    while (i + 1 < n_fence && ranges[(uint64_t)(i + 1) * stride].base - lo <= start) ++i;
-    bucket[b] = (uint16_t)i;
-  }
+  auto fence_stride = [&](uint32_t cap) { return n <= cap ? 1u : (n + cap - 1) / cap; };
+  auto bucket_index = [&](uint32_t stride, uint32_t n_fence) {
+    std::vector<uint16_t> bucket(kBuckets, 0);
+    for (uint32_t b = 0, i = 0; b < kBuckets && n > 0; ++b) {
+      const uint64_t start = (uint64_t)b << shift;  // offset from lo
+      while (i + 1 < n_fence && ranges[(uint64_t)(i + 1) * stride].base - lo <= start) ++i;
+      bucket[b] = (uint16_t)i;
+    }
+    return bucket;
+  };
+  const uint32_t stride = fence_stride(kFences), stride_w = fence_stride(kWideFences);
+  const uint32_t n_fence = n == 0 ? 0u : (n + stride - 1) / stride;
+  const uint32_t n_fence_w = n == 0 ? 0u : (n + stride_w - 1) / stride_w;
+  const std::vector<uint16_t> bucket = bucket_index(stride, n_fence), bucket_w = bucket_index(stride_w, n_fence_w);
 
   auto fail = [&](const char* what, hipError_t err) {
     set_error(what, err);
@@ -337,6 +344,9 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   if ((e = hipMemset(rs->n_bad, 0, sz_misc)) != hipSuccess) return fail("hipMemset(counts)", e);
   if ((e = hipMemcpy(bucket_d, bucket.data(), sizeof(uint16_t) * kBuckets, hipMemcpyHostToDevice)) != hipSuccess)
     return fail("hipMemcpy(bucket index)", e);
+  if ((e = hipMemcpy(bucket_w_d, bucket_w.data(), sizeof(uint16_t) * kBuckets, hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return fail("hipMemcpy(bucket index)", e);
   if (!ragged.empty() &&
       (e = hipMemcpy(rs->ragged, ragged.data(), 4 * ragged.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return fail("hipMemcpy(ragged tiles)", e);
@@ -349,6 +359,9 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->rt.stride = stride;
   rs->rt.n_fence = n_fence;
   rs->rt.shift = shift;
+  rs->rt.bucket_w = bucket_w_d;
+  rs->rt.stride_w = stride_w;
+  rs->rt.n_fence_w = n_fence_w;
   *out = rs;
   if (n_pages_out) *n_pages_out = n_pages;
   return KC_OK;
@@ -568,7 +581,7 @@ int kc_pointer_graph(kc_ctx* c, const kc_rangeset* rs, uint64_t win_lo, uint64_t
   KC_HIP(launch_fill_u64(edge_bm_d, (uint64_t)rs->n_ranges * row_words, 0, s));
   KernelTimer timer(c, KC_OP_GRAPH, s);
   KC_HIP(launch_pointer_graph(rs->tiles, rs->n_tiles, lo, hi - lo, rs->rt, edge_bm_d, row_words,
-                              grid_for(c, KC_OP_GRAPH, 8), s));
+                              grid_for(c, KC_OP_GRAPH, 8), c->n_cu, s));
   return KC_OK;
 }
 
@@ -626,11 +639,11 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
   {
     KernelTimer timer(c, KC_OP_CLOSURE, s);
     if (!c->tune[KC_OP_CLOSURE].per_item) {
-      KC_HIP(launch_closure(rs->tiles, rs->n_tiles, 0, sd, grid, s));
+      KC_HIP(launch_closure(rs->tiles, rs->n_tiles, 0, sd, grid, c->n_cu, s));
     } else {
       for (uint32_t r = 0; r < rs->n_ranges; ++r) {
         const uint32_t t0 = rs->range_tile[r];
-        KC_HIP(launch_closure(rs->tiles + t0, rs->range_tile[r + 1] - t0, t0, sd, grid, s));
+        KC_HIP(launch_closure(rs->tiles + t0, rs->range_tile[r + 1] - t0, t0, sd, grid, c->n_cu, s));
       }
     }
   }

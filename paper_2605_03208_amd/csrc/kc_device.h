@@ -44,26 +44,25 @@ __device__ __forceinline__ void load_fences(FenceLds& f, const RangeTable& rt, u
     for (uint32_t i = tid; i < kBuckets; i += nthreads) f.bucket[i] = rt.bucket[i];
 }
 
-// Last fence whose base is at or below w, for lo <= w < lo + span: start at the
-// bucket's entry and search only up to the next bucket's (usually no step).
-__device__ __forceinline__ uint32_t fence_of(uint64_t w, const FenceLds& f, const RangeTable& rt) {
-  const uint32_t b = (uint32_t)((w - rt.lo) >> rt.shift);
-  uint32_t i = f.bucket[b];
-  uint32_t j = b + 1u < kBuckets ? f.bucket[b + 1u] : rt.n_fence - 1u;
+// The search over fences held in LDS (base, end and bucket arrays of a fence
+// table with the given stride): index of the range holding w, or -1.  The
+// last fence whose base is at or below w starts at the bucket's entry and is
+// searched only up to the next bucket's (usually no step); with a stride above
+// one, the ranges of that fence are searched in global memory.
+__device__ __forceinline__ int32_t search_fences(uint64_t w, const uint64_t* fbase, const uint64_t* fend,
+                                                 const uint16_t* fbucket, uint32_t stride, uint32_t n_fence,
+                                                 const RangeTable& rt) {
+  if (rt.n == 0u || w - rt.lo >= rt.span) return -1;  // below the lowest base wraps to a large offset
+  const uint32_t bk = (uint32_t)((w - rt.lo) >> rt.shift);
+  uint32_t i = fbucket[bk];
+  uint32_t j = bk + 1u < kBuckets ? fbucket[bk + 1u] : n_fence - 1u;
   while (i < j) {
     const uint32_t m = (i + j + 1u) >> 1;
-    if (f.base[m] <= w) i = m; else j = m - 1u;
+    if (fbase[m] <= w) i = m; else j = m - 1u;
   }
-  return i;
-}
-
-// Index of the range holding w, or -1.
-__device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, const RangeTable& rt) {
-  if (rt.n == 0u || w - rt.lo >= rt.span) return -1;  // below the lowest base wraps to a large offset
-  const uint32_t i = fence_of(w, f, rt);
-  if (rt.stride == 1u) return w < f.end[i] ? (int32_t)i : -1;
-  uint32_t a = i * rt.stride;
-  uint32_t b = min(a + rt.stride, rt.n);
+  if (stride == 1u) return w < fend[i] ? (int32_t)i : -1;
+  uint32_t a = i * stride;
+  uint32_t b = min(a + stride, rt.n);
   while (b - a > 1u) {
     const uint32_t m = (a + b) >> 1;
     if (ld8g(rt.base + m) <= w) a = m; else b = m;
@@ -73,9 +72,53 @@ __device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, co
   return w < ld8g(rt.end + a) ? (int32_t)a : -1;
 }
 
+// Index of the range holding w, or -1 (table of up to kFences fences).
+__device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, const RangeTable& rt) {
+  return search_fences(w, f.base, f.end, f.bucket, rt.stride, rt.n_fence, rt);
+}
+
 // True iff w lies in [base_r, end_r) for some range r.
 __device__ __forceinline__ bool in_ranges(uint64_t w, const FenceLds& f, const RangeTable& rt) {
   return range_index(w, f, rt) >= 0;
+}
+
+// ------------------------------------------------------------ wide table --
+// Kernels whose workgroups hold several independent waves share one copy of
+// up to kWideFences fences in dynamic LDS: n_fence_w bases, n_fence_w ends,
+// then the kBuckets-entry bucket index.
+extern __shared__ __attribute__((aligned(16))) uint64_t kc_wide_lds[];
+constexpr uint32_t kWideWaves = 8;  // most waves per workgroup of the kernels that use it
+
+// Workgroups for a grid of `waves` waves: up to kWideWaves waves each, but
+// about one workgroup per CU when the grid is small (spread over the CUs
+// rather than packed onto a few).
+inline void wide_shape(uint32_t waves, uint32_t n_cu, uint32_t* blocks, uint32_t* waves_per_block) {
+  waves = waves < 1u ? 1u : waves;
+  uint32_t b = (waves + kWideWaves - 1) / kWideWaves;
+  if (b < n_cu) b = waves < n_cu ? waves : n_cu;
+  *waves_per_block = (waves + b - 1) / b;
+  *blocks = (waves + *waves_per_block - 1) / *waves_per_block;
+}
+
+inline size_t wide_lds_bytes(const RangeTable& rt) { return 16u * (size_t)rt.n_fence_w + 2u * kBuckets; }
+
+__device__ __forceinline__ void load_wide_fences(const RangeTable& rt, uint32_t tid, uint32_t nthreads) {
+  const uint32_t nf = rt.n_fence_w;
+  for (uint32_t i = tid; i < nf; i += nthreads) {
+    const uint32_t r = i * rt.stride_w;
+    kc_wide_lds[i] = rt.base[r];
+    kc_wide_lds[nf + i] = rt.end[r];
+  }
+  if (rt.n != 0u) {
+    uint16_t* bucket = reinterpret_cast<uint16_t*>(kc_wide_lds + 2u * nf);
+    for (uint32_t i = tid; i < kBuckets; i += nthreads) bucket[i] = rt.bucket_w[i];
+  }
+}
+
+__device__ __forceinline__ int32_t wide_range_index(uint64_t w, const RangeTable& rt) {
+  const uint32_t nf = rt.n_fence_w;
+  return search_fences(w, kc_wide_lds, kc_wide_lds + nf, reinterpret_cast<const uint16_t*>(kc_wide_lds + 2u * nf),
+                       rt.stride_w, nf, rt);
 }
 
 }  // namespace kc

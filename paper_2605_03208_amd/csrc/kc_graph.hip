@@ -27,16 +27,17 @@ __device__ __forceinline__ void graph_emit(int32_t t, uint32_t lane, uint64_t* r
   }
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_pointer_graph(
+// Workgroups of kWideWaves independent waves share the wide range table.
+__global__ __launch_bounds__(kWideWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_pointer_graph(
     const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span, RangeTable rt, uint64_t* edge_bm,
     uint32_t row_words) {
-  __shared__ FenceLds fences;
-  const uint32_t lane = threadIdx.x;
-  load_fences(fences, rt, lane, kWave);
+  const uint32_t lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+  const uint32_t wave = blockIdx.x * wpb + threadIdx.x / kWave, n_waves = gridDim.x * wpb;
+  load_wide_fences(rt, threadIdx.x, blockDim.x);
   __syncthreads();
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  for (uint32_t t = wave; t < n_tiles; t += n_waves) {
     const Tile tile = tiles[t];
-    const int32_t src = range_index(tile.va, fences, rt);  // the tile's own range (always found)
+    const int32_t src = wide_range_index(tile.va, rt);  // the tile's own range (always found)
     uint64_t* row = edge_bm + (uint64_t)(src < 0 ? 0 : src) * row_words;
     int32_t last = -1;
     const uint32_t nseg = tile.npages * 4u;
@@ -52,8 +53,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
         const bool p0 = (w0 - lo) < span, p1 = (w1 - lo) < span;
         if (__ballot(p0 || p1) == 0ull || src < 0) continue;  // no pointer-like word here
-        graph_emit(p0 ? range_index(w0, fences, rt) : -1, lane, row, last);
-        graph_emit(p1 ? range_index(w1, fences, rt) : -1, lane, row, last);
+        graph_emit(p0 ? wide_range_index(w0, rt) : -1, lane, row, last);
+        graph_emit(p1 ? wide_range_index(w1, rt) : -1, lane, row, last);
       }
     }
   }
@@ -182,10 +183,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
                                 const RangeTable& rt, uint64_t* edge_bm, uint32_t row_words, uint32_t grid,
-                                hipStream_t s) {
+                                uint32_t n_cu, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
-  grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_pointer_graph, dim3(grid), dim3(64), 0, s, tiles, n_tiles, lo, span, rt, edge_bm, row_words);
+  uint32_t blocks = 1, wpb = 1;
+  wide_shape(std::min(grid, n_tiles), n_cu, &blocks, &wpb);  // grid counts waves
+  hipLaunchKernelGGL(k_pointer_graph, dim3(blocks), dim3(wpb * kWave), wide_lds_bytes(rt), s, tiles, n_tiles, lo,
+                     span, rt, edge_bm, row_words);
   return hipGetLastError();
 }
 

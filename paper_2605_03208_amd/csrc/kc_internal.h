@@ -16,7 +16,8 @@ constexpr uint32_t kWave = 64;
 constexpr uint32_t kTilePages = 16;     // pages per wave tile (one lane quad per page)
 constexpr uint32_t kChunk = 512;        // bytes of each page staged per step
 constexpr uint32_t kStageStride = kChunk + 32;  // padded LDS row: quads land in distinct banks
-constexpr uint32_t kFences = 256;       // range-table entries held in LDS
+constexpr uint32_t kFences = 256;       // range-table entries held in LDS by one-wave workgroups
+constexpr uint32_t kWideFences = 4096;  // the same, shared by the waves of a multi-wave workgroup
 constexpr uint32_t kBuckets = 1024;     // entries of the LDS bucket index over the ranges
 
 // 16-byte global accesses.  Data that streams through once (pages, packed
@@ -125,6 +126,10 @@ struct RangeTable {
   uint32_t stride;   // LDS fence stride: fence i = range i * stride
   uint32_t n_fence;  // ceil(n / stride) <= kFences
   uint32_t shift;
+  // The wide table (up to kWideFences fences, in dynamic LDS shared by the
+  // waves of a workgroup): its stride, fence count and bucket index.
+  const uint16_t* bucket_w;
+  uint32_t stride_w, n_fence_w;
 };
 
 // The closure-scan totals are accumulated in kScanSlots slot pairs, each on
@@ -213,10 +218,10 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
                                   uint64_t cap_pages, unsigned long long* n_bad,
                                   bool ragged, uint32_t grid, hipStream_t s);
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
-                          const ScanDev& sd, uint32_t grid, hipStream_t s);
+                          const ScanDev& sd, uint32_t grid, uint32_t n_cu, hipStream_t s);
 hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
                                 const RangeTable& rt, uint64_t* edge_bm, uint32_t row_words, uint32_t grid,
-                                hipStream_t s);
+                                uint32_t n_cu, hipStream_t s);
 hipError_t launch_region_init(kc_region_diff_result* res, uint32_t n, uint64_t* bm_a, uint64_t* bm_b, uint64_t n_words,
                               hipStream_t s);
 hipError_t launch_region_diff(const Tile* tiles, uint32_t n_tiles, const RangeTable& rt, const uint64_t* changed_bm,

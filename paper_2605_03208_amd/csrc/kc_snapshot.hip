@@ -633,32 +633,33 @@ __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_
 }
 
 // --------------------------------------------------------- closure scan ---
-__device__ __forceinline__ void closure_words(uint4 v, uint64_t lo, uint64_t span, const FenceLds& f,
-                                              const RangeTable& rt, uint32_t& n_ptr, uint32_t& n_in,
-                                              uint32_t& oob) {
+__device__ __forceinline__ void closure_words(uint4 v, uint64_t lo, uint64_t span, const RangeTable& rt,
+                                              uint32_t& n_ptr, uint32_t& n_in, uint32_t& oob) {
   const uint64_t w0 = ((uint64_t)v.y << 32) | v.x;
   const uint64_t w1 = ((uint64_t)v.w << 32) | v.z;
   const bool p0 = (w0 - lo) < span, p1 = (w1 - lo) < span;
   if (__ballot(p0 || p1)) {
     if (p0) {
       ++n_ptr;
-      if (in_ranges(w0, f, rt)) ++n_in; else ++oob;
+      if (wide_range_index(w0, rt) >= 0) ++n_in; else ++oob;
     }
     if (p1) {
       ++n_ptr;
-      if (in_ranges(w1, f, rt)) ++n_in; else ++oob;
+      if (wide_range_index(w1, rt) >= 0) ++n_in; else ++oob;
     }
   }
 }
 
 // Standalone scan: a tile's 16 pages are read as 64 contiguous 1-KiB runs.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, ScanDev sd) {
-  __shared__ FenceLds fences;
-  const uint32_t lane = threadIdx.x;
-  load_fences(fences, sd.rt, lane, kWave);
+// Workgroups of kWideWaves independent waves share the wide range table.
+__global__ __launch_bounds__(kWideWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_closure(
+    const Tile* tiles, uint32_t n_tiles, uint32_t tile0, ScanDev sd) {
+  const uint32_t lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+  const uint32_t wave = blockIdx.x * wpb + threadIdx.x / kWave, n_waves = gridDim.x * wpb;
+  load_wide_fences(sd.rt, threadIdx.x, blockDim.x);
   __syncthreads();
   uint32_t n_ptr = 0, n_in = 0;
-  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  for (uint32_t t = wave; t < n_tiles; t += n_waves) {
     const Tile tile = tiles[t];
     const uint32_t nseg = tile.npages * 4u;
     uint32_t oob = 0;
@@ -669,14 +670,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         x[i] = (s0 + i < nseg) ? ld16nt(tile.va + (uint64_t)(s0 + i) * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i)
-        closure_words(seg_words(tile, s0 + i, lane, x[i]), sd.lo, sd.span, fences, sd.rt, n_ptr, n_in, oob);
+        closure_words(seg_words(tile, s0 + i, lane, x[i]), sd.lo, sd.span, sd.rt, n_ptr, n_in, oob);
     }
     const uint32_t o = wave_sum_u32(oob);
     if (lane == 0) sd.tile_oob[tile0 + t] = o;
   }
   const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
   if (lane == 0) {
-    add_scan_counts(sd.counts, blockIdx.x, a, b);
+    add_scan_counts(sd.counts, wave, a, b);
   }
 }
 
@@ -883,10 +884,12 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, c
 }
 
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0, const ScanDev& sd,
-                          uint32_t grid, hipStream_t s) {
+                          uint32_t grid, uint32_t n_cu, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
-  grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_closure, dim3(grid), dim3(64), 0, s, tiles, n_tiles, tile0, sd);
+  uint32_t blocks = 1, wpb = 1;
+  wide_shape(std::min(grid, n_tiles), n_cu, &blocks, &wpb);  // grid counts waves
+  hipLaunchKernelGGL(k_closure, dim3(blocks), dim3(wpb * kWave), wide_lds_bytes(sd.rt), s, tiles, n_tiles, tile0,
+                     sd);
   return hipGetLastError();
 }
 

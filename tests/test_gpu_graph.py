@@ -69,6 +69,34 @@ def test_planted_graph(kc, ctx, n, seed):
     rs.close()
 
 
+@pytest.mark.parametrize("n,seed", [(4096, 6), (5000, 7)])
+def test_many_ranges_graph_and_scans(kc, ctx, n, seed):
+    """The graph and the standalone scan keep up to 4096 ranges in one LDS
+    table per workgroup; past that the table strides and the search finishes
+    in global memory.  The fused scan keeps 256."""
+    say(f"pointer graph and closure scans over {n} ranges")
+    case = W.graph_case("cuda", n_ranges=n, seed=seed, max_pages=3)
+    rs, got = graph_vs_oracle(kc, ctx, case)
+    want = np.zeros((n, n), bool)
+    for a, b in case.truth["edges"]:
+        want[a, b] = True
+    assert (oracle.edges_to_bool(got, n) == want).all()
+    ranges = case.ranges()
+    host = case.arena.host_copy()
+    views = W.host_views(case.layout, host)
+    o_res, o_oob = oracle.closure_scan(ranges, views, oob_cap=64)
+    assert o_res["n_oob"] > 0 and o_res["n_in_range"] > 0
+    say(f"closure scans over {n} ranges: standalone and fused vs oracle")
+    scan = kc.ScanOut("cuda", oob_cap=64)
+    kc.closure_scan(ctx, rs, scan)
+    scan2 = kc.ScanOut("cuda", oob_cap=64)
+    kc.snapshot(ctx, rs, scan=scan2)
+    torch.cuda.synchronize()
+    assert scan.result() == (o_res, o_oob)
+    assert scan2.result() == (o_res, o_oob)
+    rs.close()
+
+
 def test_windows_and_dense_pointers(kc, ctx):
     say("pointer graph: custom windows; c1 scaled (1 % of words are pointers)")
     case = W.graph_case("cuda", n_ranges=40, seed=21)
