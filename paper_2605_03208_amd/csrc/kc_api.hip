@@ -386,7 +386,7 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     hp.tile0 = 0;
     hp.ragged = rs->ragged;
     hp.n_ragged = rs->n_ragged;
-    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, s));
+    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, c->n_cu, s));
     return KC_OK;
   }
   for (uint32_t r = 0; r < rs->n_ranges; ++r) {
@@ -396,7 +396,7 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     const bool rg = rs->ragged_of[r] != UINT32_MAX;
     hp.ragged = rg ? rs->ragged + rs->ragged_of[r] : nullptr;
     hp.n_ragged = rg ? 1u : 0u;
-    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, s));
+    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, c->n_cu, s));
   }
   return KC_OK;
 }

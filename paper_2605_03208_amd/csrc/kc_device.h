@@ -92,9 +92,10 @@ constexpr uint32_t kWideWaves = 8;  // most waves per workgroup of the kernels t
 // Workgroups for a grid of `waves` waves: up to kWideWaves waves each, but
 // about one workgroup per CU when the grid is small (spread over the CUs
 // rather than packed onto a few).
-inline void wide_shape(uint32_t waves, uint32_t n_cu, uint32_t* blocks, uint32_t* waves_per_block) {
+inline void wide_shape(uint32_t waves, uint32_t n_cu, uint32_t* blocks, uint32_t* waves_per_block,
+                       uint32_t max_waves = kWideWaves) {
   waves = waves < 1u ? 1u : waves;
-  uint32_t b = (waves + kWideWaves - 1) / kWideWaves;
+  uint32_t b = (waves + max_waves - 1) / max_waves;
   if (b < n_cu) b = waves < n_cu ? waves : n_cu;
   *waves_per_block = (waves + b - 1) / b;
   *blocks = (waves + *waves_per_block - 1) / *waves_per_block;
@@ -114,6 +115,10 @@ __device__ __forceinline__ void load_wide_fences(const RangeTable& rt, uint32_t 
     for (uint32_t i = tid; i < kBuckets; i += nthreads) bucket[i] = rt.bucket_w[i];
   }
 }
+
+// Orders a wave's own LDS accesses across lanes: the LDS executes one wave's
+// operations in program order, so only the compiler must not move them.
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
 
 __device__ __forceinline__ int32_t wide_range_index(uint64_t w, const RangeTable& rt) {
   const uint32_t nf = rt.n_fence_w;

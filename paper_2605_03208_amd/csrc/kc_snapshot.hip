@@ -129,6 +129,7 @@ __global__ void k_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
 }
 
 // ---------------------------------------------------------- page hash -----
+constexpr uint32_t kHashWaves = 4;  // most waves per workgroup of the hash pass
 // One wave hashes a tile of up to 16 pages: lane quad q owns page q, lane k of
 // the quad runs XXH64 accumulator k over the words 8k + 32s of each stripe s.
 // The wave streams the tile in 8 chunks of 512 bytes per page: 8 loads of
@@ -142,23 +143,29 @@ __global__ void k_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
 // RAGGED = false: every tile whose pages are all whole (the hot path); RAGGED =
 // true: only the tiles listed in p.ragged, whose last page is partial (at most
 // one per range), with the bytes past the range's end masked out.
+//
+// A workgroup holds up to kHashWaves independent waves, each with its own
+// stage; with the closure scan they share one wide range table in dynamic LDS.
 template <bool GATHER, bool PRIOR, bool SCAN, bool RAGGED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 : 4))) void k_page_hash(HashParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t stage[kTilePages * kStageStride];
-  __shared__ uint64_t tail_lds[kTilePages][4];  // a partial page's bytes past its last whole stripe
-  __shared__ FenceLds fences;
-  const uint32_t lane = threadIdx.x;
+__global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 : (SCAN ? 3 : 4)))) void k_page_hash(
+    HashParams p) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage_all[kHashWaves][kTilePages * kStageStride];
+  __shared__ uint64_t tail_all[kHashWaves][kTilePages][4];  // a partial page's bytes past its last whole stripe
+  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+  uint8_t* const stage = stage_all[wv];
+  uint64_t(*const tail_lds)[4] = tail_all[wv];
   const uint32_t q = lane >> 2, k = lane & 3u;
   const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
   const uint64_t scan_lo = p.scan.lo, scan_span = p.scan.span;
   if (SCAN) {
-    load_fences(fences, p.scan.rt, lane, kWave);
-    __syncthreads();
+    load_wide_fences(p.scan.rt, threadIdx.x, blockDim.x);
+    __syncthreads();  // the only workgroup barrier: the waves share nothing else
   }
   uint32_t n_ptr = 0, n_in = 0;
 
+  const uint32_t wave = blockIdx.x * wpb + wv, n_waves = gridDim.x * wpb;
   const uint32_t n_items = RAGGED ? p.n_ragged : p.n_tiles;
-  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+  for (uint32_t it = wave; it < n_items; it += n_waves) {
     const uint32_t t = RAGGED ? p.ragged[it] - p.tile0 : it;
     const Tile tile = p.tiles[t];
     if (!RAGGED && tile.last_len != kPage) continue;  // left to the ragged launch
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 :
         }
         *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
       }
-      __syncthreads();
+      wave_lds_order();
       // loads of the next chunk overlap the hashing of this one
       const uint32_t cn = c + 1 < kPage / kChunk ? c + 1 : c;
       const uint32_t more = c + 1 < kPage / kChunk ? keep : 0u;
@@ -250,7 +257,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 :
           const uint32_t bit = (uint32_t)__builtin_ctz(m);
           const uint64_t w = *reinterpret_cast<const uint64_t*>(stage + (2u * (bit >> 1) + half) * kStageStride +
                                                                  off16 + (bit & 1u) * 8u);
-          if (in_ranges(w, fences, p.scan.rt)) ++n_in; else ++oob;
+          if (wide_range_index(w, p.scan.rt) >= 0) ++n_in; else ++oob;
         }
       }
       const uint8_t* row = stage + q * kStageStride + k * 8u;
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 :
         if (!RAGGED || c * (kChunk / 32) + s < lim) acc = xround(acc, *reinterpret_cast<const uint64_t*>(row + s * 32u));
       if (RAGGED && rem != 0u && c == lim / (kChunk / 32))  // the partial page's last bytes are in this chunk
         tail_lds[q][k] = *reinterpret_cast<const uint64_t*>(stage + q * kStageStride + (lim * 32u - c * kChunk) + 8u * k);
-      __syncthreads();
+      wave_lds_order();
     }
 
     const uint64_t merged = xxh64_merge4(acc, k);  // every lane of the quad takes part
@@ -289,7 +296,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RAGGED ? 1 :
   if (SCAN) {
     const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
     if (lane == 0) {
-      add_scan_counts(p.scan.counts, blockIdx.x, a, b);
+      add_scan_counts(p.scan.counts, wave, a, b);
     }
   }
 }
@@ -799,17 +806,19 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 }
 
 hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t grid,
-                            hipStream_t s) {
+                            uint32_t n_cu, hipStream_t s) {
   if (p.n_tiles == 0) return hipSuccess;
-  const uint32_t grid_r = std::max(1u, std::min(grid, p.n_ragged));
-  grid = std::max(1u, std::min(grid, p.n_tiles));
-#define KC_HASH_CASE(G, P, S)                                                              \
-  if (gather == G && prior == P && scan == S) {                                           \
-    hipLaunchKernelGGL((k_page_hash<G, P, S, false>), dim3(grid), dim3(64), 0, s, p);     \
-    hipError_t e = hipGetLastError();                                                     \
-    if (e != hipSuccess || p.n_ragged == 0) return e;                                     \
-    hipLaunchKernelGGL((k_page_hash<G, P, S, true>), dim3(grid_r), dim3(64), 0, s, p);    \
-    return hipGetLastError();                                                             \
+  uint32_t blocks = 1, wpb = 1, blocks_r = 1, wpb_r = 1;  // grid counts waves
+  wide_shape(std::min(grid, p.n_tiles), n_cu, &blocks, &wpb, kHashWaves);
+  wide_shape(std::min(grid, std::max(1u, p.n_ragged)), n_cu, &blocks_r, &wpb_r, kHashWaves);
+  const size_t lds = scan ? wide_lds_bytes(p.scan.rt) : 0;
+#define KC_HASH_CASE(G, P, S)                                                                              \
+  if (gather == G && prior == P && scan == S) {                                                           \
+    hipLaunchKernelGGL((k_page_hash<G, P, S, false>), dim3(blocks), dim3(wpb * kWave), lds, s, p);        \
+    hipError_t e = hipGetLastError();                                                                     \
+    if (e != hipSuccess || p.n_ragged == 0) return e;                                                     \
+    hipLaunchKernelGGL((k_page_hash<G, P, S, true>), dim3(blocks_r), dim3(wpb_r * kWave), lds, s, p);     \
+    return hipGetLastError();                                                                             \
   }
   KC_HASH_CASE(false, false, false)
   KC_HASH_CASE(false, false, true)
