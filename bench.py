@@ -47,10 +47,10 @@ PAGE = 4096
 # per launch, scaled by the factors a plain 4 GiB device copy gives (fetch
 # x2.0, write x1.0).  Valid only for the kernel sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "8d4437ac9b966799510dc311e4ec8711b2323fe10f1c27347a9126485a542e86",
-    "snapshot": 62932999758,   # fetch 31432312485 + write 31500687273
-    "restore": 62955229081,    # fetch 31598348134 + write 31356880947
-    "compare": 64456630554,    # fetch 64456630554 + write 0
+    "source_sha256": "4be9976e1bda75246a64f3be37f53a0b2d4ad225e572b5ff7233df10c0187253",
+    "snapshot": 62869163698,   # fetch 31385134299 + write 31484029399
+    "restore": 62955240909,    # fetch 31598339200 + write 31356901709
+    "compare": 64456637517,    # fetch 64456637517 + write 0
 }
 
 
