@@ -638,8 +638,10 @@ def batching(torch, kc, W, dev, tune: bool = True) -> dict:
     rngs = case.ranges()
     c0 = kc.Context(0)
     rs0 = kc.RangeSet(c0, rngs)
-    prior = kc.snapshot(c0, rs0, seed=2)["hash"].clone()
+    s1 = kc.snapshot(c0, rs0, seed=2)  # the base image P1 (full snapshot)
+    prior = s1["hash"].clone()
     W.c2_rewrite(case)
+    torch.cuda.synchronize()
     rs0.close()
     c0.close()
     digests = {}
@@ -670,11 +672,38 @@ def batching(torch, kc, W, dev, tune: bool = True) -> dict:
         out[f"c2_delta_{mode}_ms"] = round(dt * 1e3, 3)
         out[f"c2_delta_{mode}_GBps"] = round(b / dt / 1e9, 1)
         out["c2_delta_kept_pages"] = nk
+        if mode == "batched":  # restore chain: the base image P1, then the delta D on top of it
+            nk1 = int(s1["n_kept"].item())
+            full = lambda: kc.restore(c2, rs, s1["zero_bm"], None, s1["packed"], s1["page_va"], s1["n_kept"])
+            delta = lambda: kc.restore(c2, rs, s2["zero_bm"], s2["changed_bm"], s2["packed"], s2["page_va"],
+                                       s2["n_kept"])
+            full()
+            delta()
+            h, _, _ = kc.page_hash(c2, rs, seed=2)
+            torch.cuda.synchronize()
+            out["c2_restore_chain_matches_delta_hashes"] = bool(torch.equal(h[:n], s2["hash"][:n]))
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            tf = td = 0.0
+            for _ in range(reps):
+                ev[0].record()
+                full()
+                ev[1].record()
+                delta()
+                ev[2].record()
+                torch.cuda.synchronize()
+                tf += ev[0].elapsed_time(ev[1]) / reps
+                td += ev[1].elapsed_time(ev[2]) / reps
+            bf = 4104 * nk1 + 4096 * n          # packed read + page writes (kept and zero) + VA reads
+            bd = 8200 * nk                       # changed non-zero pages: packed read + page write + VA
+            out["c2_restore_full_ms"] = round(tf, 3)
+            out["c2_restore_full_GBps"] = round(bf / (tf / 1e3) / 1e9, 1)
+            out["c2_restore_delta_ms"] = round(td, 3)
+            out["c2_restore_delta_GBps"] = round(bd / (td / 1e3) / 1e9, 1)
         rs.close()
         c2.close()
     out["c2_results_identical"] = all(torch.equal(a, b) for a, b in zip(digests["batched"], digests["per_buffer"]))
     out["c2_batched_speedup"] = round(out["c2_delta_per_buffer_ms"] / out["c2_delta_batched_ms"], 2)
-    del case
+    del case, s1
     torch.cuda.empty_cache()
     return out
 
