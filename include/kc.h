@@ -190,7 +190,8 @@ typedef struct {
 
 /* Launch shape of one operation.  Zero fields keep the built-in choice. */
 typedef struct {
-  uint32_t grid_per_cu; /* persistent workgroups per compute unit          */
+  uint32_t grid_per_cu; /* persistent waves per compute unit (the compare:
+                           four-wave workgroups per compute unit)           */
   uint32_t tile_bytes;  /* compare: bytes of each side per work item        */
   uint32_t per_item;    /* 1 = one launch per range / pair (no batching)    */
   uint32_t reserved;

@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the kc operations.
 
 For one operation on the caller's real inputs, every candidate launch shape
-(persistent workgroups per CU, and for compare the bytes per tile) is run,
+(persistent waves per CU, and for compare workgroups per CU and the bytes per tile) is run,
 timed with the library's kernel events, and its outputs are digested; a
 candidate whose outputs differ from the first one's raises, so tuning can
 never change a result.  The fastest candidate is applied to the context and
