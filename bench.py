@@ -421,9 +421,10 @@ def region_diff_pass(torch, kc, ctx, rs, gold, case, n_pages: int, reps: int, tu
     out = kc.region_diff(ctx, rs, gold)
     if tune:
         from paper_2605_03208_amd import autotune
-        r = autotune.tune(ctx, kc.OP_REGION_DIFF, lambda: kc.region_diff(ctx, rs, gold, out=out),
-                          lambda: autotune.digest_tensors(out["res"], out["changed_bm"]), f"c4-moe-pool-pages{n_pages}")
-        shape = r["best"]
+        run = lambda: kc.region_diff(ctx, rs, gold, out=out)
+        dig = lambda: autotune.digest_tensors(out["res"], out["changed_bm"], out["hash"])
+        shape = {name: autotune.tune(ctx, op, run, dig, f"c4-moe-pool-pages{n_pages}")["best"]
+                 for op, name in ((kc.OP_PAGE_HASH, "hash"), (kc.OP_REGION_DIFF, "diff"))}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()

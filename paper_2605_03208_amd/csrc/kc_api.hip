@@ -379,7 +379,8 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
                     hipStream_t s) {
   kc_ctx* c = rs->ctx;
   KernelTimer timer(c, op, s);
-  const uint32_t grid = grid_for(c, op, 4);
+  // read-only hashing runs best with twice the waves of the fused snapshot (which also writes and scans)
+  const uint32_t grid = grid_for(c, op, op == KC_OP_PAGE_HASH ? 8 : 4);
   if (!c->tune[op].per_item) {
     hp.tiles = rs->tiles;
     hp.n_tiles = rs->n_tiles;
