@@ -95,8 +95,10 @@ __device__ __forceinline__ void flush_region(kc_region_diff_result* res, int32_t
 
 // A wave takes four consecutive tiles at a time, one lane per page: each lane
 // resolves its page's snapshot copy and changed bit, then the whole wave
-// compares the changed pages one after another (ascending), folding runs of
-// pages of one range before touching the per-range counters.
+// compares the changed pages one after another (ascending).  Each wave owns a
+// contiguous run of tile groups and folds its pages per range, touching a
+// range's counters only when it moves to the next range or ends: waves that
+// all add into one range's counters as they go queue on those addresses.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_region_diff(
     const Tile* tiles, uint32_t n_tiles, RangeTable rt, const uint64_t* changed_bm, const uint64_t* gold_zero_bm,
     const uint64_t* rank_prefix, const uint64_t* gold_page_va, const uint64_t* gold_n_kept, uint64_t cap,
@@ -107,8 +109,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __syncthreads();
   const uint64_t kept = *gold_n_kept;
   const uint64_t n_valid = kept < cap ? kept : cap;
-  for (uint32_t t0 = blockIdx.x * 4u; t0 < n_tiles; t0 += gridDim.x * 4u) {
-    const uint32_t t = t0 + sub;
+  const uint32_t n_groups = (n_tiles + 3u) / 4u;
+  const uint32_t per_wave = (n_groups + gridDim.x - 1u) / gridDim.x;
+  const uint32_t gbeg = min(blockIdx.x * per_wave, n_groups), gend = min(gbeg + per_wave, n_groups);
+  int32_t cur = -1;  // the range being folded, and its totals so far
+  uint64_t dbytes = 0, dpages = 0, first = ~0ull;
+  for (uint32_t gi = gbeg; gi < gend; ++gi) {
+    const uint32_t t = gi * 4u + sub;
     Tile tile{0, 0, 0};
     if (t < n_tiles) tile = tiles[t];
     const bool live = j < tile.npages;
@@ -134,8 +141,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (nb) atomicAdd((unsigned long long*)&res[a].n_bad_pages, (unsigned long long)nb);
     }
     uint64_t need_mask = __ballot(need);
-    int32_t cur = -1;
-    uint64_t dbytes = 0, dpages = 0, first = ~0ull;
     while (need_mask) {
       const int32_t L = __ffsll((long long)need_mask) - 1;
       need_mask &= need_mask - 1ull;
@@ -175,8 +180,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (first == ~0ull) first = pva + fo;  // pages ascend within a range
       }
     }
-    if (lane == 0) flush_region(res, cur, dbytes, dpages, first);
   }
+  if (lane == 0) flush_region(res, cur, dbytes, dpages, first);
 }
 
 }  // namespace
