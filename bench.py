@@ -379,6 +379,7 @@ def main() -> int:
         line["batching"] = batching(torch, kc, W, dev, tune=not args.no_tune)
         line["snapshot_files"] = snapshot_files(torch, kc, W, dev)
         line["partial_pages"] = partial_pages(torch, kc, W, dev)
+        line["scan_many_ranges"] = scan_many_ranges(torch, kc, W, dev)
         line["serving"] = serving(torch, kc, W, dev, args.serve_seconds)
     if cpu is not None:
         line["cpu_baseline"] = cpu
@@ -597,6 +598,53 @@ def partial_pages(torch, kc, W, dev) -> dict:
     del case
     torch.cuda.empty_cache()
     return out
+
+
+def scan_many_ranges(torch, kc, W, dev, reps: int = 5) -> dict:
+    """Closure scan over the 4096-range, 2 GiB set with 1 % of every range's
+    words set to addresses inside random ranges: the fused snapshot and the
+    standalone scan, against the same set without planted pointers."""
+    log("closure scan over 4096 ranges, with and without 1 % pointer words")
+    case = W.c2_snapshot("cuda")
+    ranges = case.ranges()
+    ctx = kc.Context(0)
+    rs = kc.RangeSet(ctx, ranges)
+    out = kc.snapshot(ctx, rs, seed=0)
+    scan = kc.ScanOut(dev, oob_cap=16)
+    nbytes = sum(s for _, s in ranges)
+
+    def timed():
+        ctx.enable_timing(True)
+        snap, cl = [], []
+        for _ in range(reps):
+            kc.snapshot(ctx, rs, scan=scan, out=out)
+            snap.append(ctx.kernel_ms(kc.OP_SNAPSHOT))
+            kc.closure_scan(ctx, rs, scan)
+            cl.append(ctx.kernel_ms(kc.OP_CLOSURE))
+        ctx.enable_timing(False)
+        return min(snap), min(cl)
+
+    res = {"ranges": len(ranges), "bytes": nbytes}
+    res["fused_ms_no_pointers"], res["standalone_ms_no_pointers"] = (round(x, 4) for x in timed())
+    gen = torch.Generator(device=dev).manual_seed(7)
+    bases = torch.tensor([b for b, _ in ranges], dtype=torch.int64, device=dev)
+    sizes = torch.tensor([s for _, s in ranges], dtype=torch.int64, device=dev)
+    for i in range(len(ranges)):
+        w = case.arena.view(i).view(torch.int64)
+        k = max(1, w.numel() // 100)
+        pos = torch.randint(0, w.numel(), (k,), device=dev, generator=gen)
+        tgt = torch.randint(0, len(ranges), (k,), device=dev, generator=gen)
+        off = (torch.rand(k, device=dev, generator=gen, dtype=torch.float64) * sizes[tgt].double()).long()
+        w[pos] = bases[tgt] + off
+    res["fused_ms"], res["standalone_ms"] = (round(x, 4) for x in timed())
+    r, _ = scan.result()
+    res["n_ptr_like"], res["n_in_range"] = r["n_ptr_like"], r["n_in_range"]
+    res["standalone_GBps"] = round(nbytes / (res["standalone_ms"] / 1e3) / 1e9, 1)
+    rs.close()
+    ctx.close()
+    del case, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def batching(torch, kc, W, dev, tune: bool = True) -> dict:
