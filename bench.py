@@ -112,25 +112,37 @@ def cpu_baseline(case, ranges, sample_idx) -> dict:
     gold = [v.copy() for v in views]
     nb = sum(s for _, s in sub)
     n_pages = nb // PAGE
+    dtypes = [oracle.BF16 if ri < 192 else (oracle.U8 if ri == 192 else (oracle.F32 if ri == 193 else oracle.F16))
+              for ri in sample_idx]
+    secs = {}
     t0 = time.perf_counter()
     h, z, _ = oracle.page_hash(sub, views)
+    secs["page_hash"] = time.perf_counter() - t0
+    t1 = time.perf_counter()
     oracle.closure_scan(sub, views, oob_cap=16)
+    secs["closure_scan"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
     packed, va, n_kept = oracle.compact(sub, views, z)
+    secs["compact"] = time.perf_counter() - t1
     work = [np.empty_like(v) for v in views]
+    t1 = time.perf_counter()
     oracle.restore(sub, work, z, None, packed, va, n_kept)
-    for w, g, ri in zip(work, gold, sample_idx):
-        dt = oracle.BF16 if ri < 192 else (oracle.U8 if ri == 192 else (oracle.F32 if ri == 193 else oracle.F16))
+    secs["restore"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    for w, g, dt in zip(work, gold, dtypes):
         oracle.compare(w, g, dt, 0)
+    secs["compare"] = time.perf_counter() - t1
     t = time.perf_counter() - t0
     b = step_bytes(n_pages, n_kept, nb)
     total = sum(b.values())
-    dtypes = [oracle.BF16 if ri < 192 else (oracle.U8 if ri == 192 else (oracle.F32 if ri == 193 else oracle.F16))
-              for ri in sample_idx]
+    op_bytes = {"page_hash": nb + 8 * n_pages, "closure_scan": nb, "compact": 4104 * n_kept + 4096 * n_kept,
+                "restore": b["restore"], "compare": b["compare"]}
+    ops = {k: {"s": round(v, 3), "GBps": round(op_bytes[k] / v / 1e9, 3)} for k, v in secs.items()}
     return {"value": round(total / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sample_idx)} of the 200 ranges ({nb / 2**30:.2f} GiB: 8 experts, the pointer table, "
                       f"the workspace, one activation buffer) through page hash + closure scan + compact + "
                       f"restore + compare, {t:.1f} s single-threaded",
-            "seconds": round(t, 2),
+            "seconds": round(t, 2), "ops": ops,
             "threads": cpu_threads(sub, gold, dtypes, total)}
 
 
