@@ -142,8 +142,23 @@ def cpu_baseline(case, ranges, sample_idx) -> dict:
             "sample": f"{len(sample_idx)} of the 200 ranges ({nb / 2**30:.2f} GiB: 8 experts, the pointer table, "
                       f"the workspace, one activation buffer) through page hash + closure scan + compact + "
                       f"restore + compare, {t:.1f} s single-threaded",
-            "seconds": round(t, 2), "ops": ops,
+            "seconds": round(t, 2), "ops": ops, "host": host_cpu(),
             "threads": cpu_threads(sub, gold, dtypes, total)}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and logical CPU count (what this process may use)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable": usable}
 
 
 def cpu_threads(sub, views, dtypes, total_bytes: int, chunk: int = 64 << 20) -> dict:
