@@ -1,8 +1,9 @@
 // kc_graph.hip -- gfx950 kernels over the ranges beyond the snapshot itself:
 // the pointer graph between ranges and the per-range byte difference against
-// a snapshot.  Same execution model as the snapshot kernels: one 64-lane wave
-// per workgroup, persistent grids over the 16-page tile list, range fences in
-// LDS.
+// a snapshot.  Same execution model as the snapshot kernels: persistent grids
+// of 64-lane waves over the 16-page tile list, range fences in LDS (the graph:
+// up to eight waves per workgroup sharing the wide table; the region diff:
+// one wave per workgroup).
 #include <algorithm>
 
 #include "kc_device.h"

@@ -1,10 +1,12 @@
 // kc_snapshot.hip -- gfx950 kernels of the snapshot, restore and closure scan.
 //
-// Memory-bound streaming kernels, one 64-lane wave per workgroup (the
-// out-of-range emission: one wave per page of a tile), persistent grids
-// striding over a tile list (16 pages of one range per tile).  Global traffic
-// is 16-byte loads / stores that cover whole 512-byte or 1-KiB runs; the
-// XXH64 lanes read their words from a padded LDS stage.
+// Memory-bound streaming kernels: persistent grids of 64-lane waves striding
+// over a tile list (16 pages of one range per tile).  Most workgroups are one
+// wave; the hash pass and the standalone scan put several independent waves in
+// a workgroup to share one range table, and the out-of-range emission uses one
+// wave per page of a tile.  Global traffic is 16-byte loads / stores that
+// cover whole 512-byte or 1-KiB runs; the XXH64 lanes read their words from a
+// padded LDS stage.
 #include <algorithm>
 
 #include "kc_device.h"
