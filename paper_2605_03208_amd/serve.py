@@ -49,6 +49,8 @@ class Completed:
     done_s: float
     nbytes: int
     results: list = field(default_factory=list)
+    materialize_s: float = 0.0   # device time of the batch's candidate materialisation
+    compare_s: float = 0.0       # device time of the batch's compare
 
     @property
     def latency_s(self) -> float:
@@ -147,7 +149,9 @@ class DeviceExecutor:
         torch, kc, W = self.torch, self.kc, self.W
         s = self.streams[stream]
         entries = [(r, int(gid)) for r in reqs for gid in r.golden_ids]
+        ev0, ev_mat, ev = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         with torch.cuda.stream(s):
+            ev0.record(s)
             views = [None] * len(entries)
             arenas = []
             for dt in sorted({self.dtypes[g] for _, g in entries}):
@@ -170,16 +174,20 @@ class DeviceExecutor:
                     views[i] = arena[int(o): int(o) + n]
             pairs = [(views[i], self.goldens[g], self.dtypes[g], r.ulp_tol, *DEFAULT_CLOSE)
                      for i, (r, g) in enumerate(entries)]
+            ev_mat.record(s)
             res = kc.compare(self.ctxs[stream], pairs)
-            ev = torch.cuda.Event()
             ev.record(s)
-        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, arenas=arenas, n=len(pairs),
+        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, ev0=ev0, ev_mat=ev_mat, arenas=arenas, n=len(pairs),
                  owners=[r.rid for r, _ in entries])
         self.busy[stream] = h
         return h
 
     def done(self, h, now: float) -> bool:
         return h["ev"].query()
+
+    def split(self, h) -> tuple:
+        """(materialise, compare) device seconds of a finished batch."""
+        return h["ev0"].elapsed_time(h["ev_mat"]) / 1e3, h["ev_mat"].elapsed_time(h["ev"]) / 1e3
 
     def finish(self, h):
         out = self.kc.decode_cmp(h["res"], h["n"])
@@ -235,10 +243,11 @@ class Server:
                 if self.ex.done(h, now):
                     results = self.ex.finish(h)
                     t_done = self.clock() - t0 if real_time else now
+                    mat_s, cmp_s = self.ex.split(h) if hasattr(self.ex, "split") else (0.0, 0.0)
                     for (r, t_adm), res in zip(batch, results):
                         self.budget.give(self.ex.request_bytes(r))
                         done.append(Completed(r.rid, r.arrival_s, t_adm, t_launch, t_done,
-                                              self.ex.request_bytes(r), res))
+                                              self.ex.request_bytes(r), res, mat_s, cmp_s))
                     progressed = True
                 else:
                     still.append((h, batch, t_launch))
@@ -257,11 +266,20 @@ class Server:
 
 
 def summarize(done, wall_s: float) -> dict:
-    lat = np.array([d.latency_s for d in done]) if done else np.zeros(1)
-    q = np.array([d.admit_s - d.arrival_s for d in done]) if done else np.zeros(1)
+    """Latency percentiles, split into queue (arrival to admission), and the
+    device time of the materialisation and the compare of each request's
+    batch; aggregate compared bytes (both sides) per second."""
+    def pct(values, p):
+        return round(float(np.percentile(np.array(values) if values else np.zeros(1), p)) * 1e3, 3)
+
+    lat = [d.latency_s for d in done]
+    q = [d.admit_s - d.arrival_s for d in done]
+    mat = [d.materialize_s for d in done]
+    cmp_ = [d.compare_s for d in done]
     nbytes = sum(2 * d.nbytes for d in done)
-    return dict(requests=len(done), p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
-                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3),
-                queue_p99_ms=round(float(np.percentile(q, 99)) * 1e3, 3),
+    return dict(requests=len(done), p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
+                queue_p50_ms=pct(q, 50), queue_p99_ms=pct(q, 99),
+                materialize_p50_ms=pct(mat, 50), materialize_p99_ms=pct(mat, 99),
+                compare_p50_ms=pct(cmp_, 50), compare_p99_ms=pct(cmp_, 99),
                 aggregate_GBps=round(nbytes / max(wall_s, 1e-9) / 1e9, 1), compared_bytes=nbytes,
                 wall_s=round(wall_s, 3))

@@ -744,24 +744,29 @@ def perturb_many(arena: torch.Tensor, dtype: int, offsets, lengths, seeds, p_per
     element ``offsets`` with element ``lengths``.  In buffer b, element
     j * B + (h mod B) of each block j of B = round(1/p_pert) elements moves by
     1..kmax ULP in a direction, where h and the step come from a hash of
-    (seeds[b], j): a buffer's perturbation depends only on its own seed."""
+    (seeds[b], j): a buffer's perturbation depends only on its own seed.  A
+    float moves in sign-magnitude order of its bits (the order the compare's
+    ULP distance counts), stopping at an infinity; NaNs stay; integers and fp8
+    codes move by k and k ranks, clamped."""
     block = max(1, int(round(1.0 / p_pert)))
-    offsets = np.asarray(offsets, dtype=np.int64)
     lengths = np.asarray(lengths, dtype=np.int64)
-    seeds = np.asarray(seeds, dtype=np.int64) & 0x7FFFFFFF
     m = lengths // block
     total = int(m.sum())
     if total == 0:
         return
-    starts = np.concatenate([[0], np.cumsum(m)[:-1]])
-    j = np.arange(total, dtype=np.int64) - np.repeat(starts, m)
-    base = np.repeat(offsets, m)
-    sd = np.repeat(seeds, m)
     dev = arena.device
-    host = torch.from_numpy(np.stack([j, sd, base]))
-    if dev.type == "cuda":
-        host = host.pin_memory()
-    j_t, sd_t, base_t = host.to(dev, non_blocking=True)
+    keep = m > 0
+    per = torch.from_numpy(np.stack([np.asarray(offsets, dtype=np.int64)[keep], m[keep],
+                                     np.asarray(seeds, dtype=np.int64)[keep] & 0x7FFFFFFF]))
+    if dev.type == "cuda":  # a pageable upload would wait for the other streams' work
+        per = per.pin_memory()
+    off_t, m_t, seed_t = per.to(dev, non_blocking=True)
+    ends = torch.cumsum(m_t, 0)
+    i_t = torch.arange(total, device=dev)
+    b_t = torch.searchsorted(ends, i_t, right=True)  # buffer of each perturbation (no host read-back)
+    j_t = i_t - (ends - m_t)[b_t]
+    sd_t = seed_t[b_t]
+    base_t = off_t[b_t]
     h1 = _hash32(sd_t * 0x9E37 + j_t * 0x85EB + 1)
     h2 = _hash32(h1 + sd_t + 0x27D4EB2F)
     pos = base_t + j_t * block + (h1 % block)
@@ -777,10 +782,27 @@ def perturb_many(arena: torch.Tensor, dtype: int, offsets, lengths, seeds, p_per
         info = torch.iinfo(arena.dtype)
         arena[pos] = (vals.to(torch.int64) + k).clamp(info.min, info.max).to(arena.dtype)
         return
-    target = torch.where(k > 0, torch.full_like(vals, float("inf")), torch.full_like(vals, float("-inf")))
-    for i in range(kmax):
-        vals = torch.where(k.abs() > i, torch.nextafter(vals, target), vals)
-    arena[pos] = vals
+    nbits = 8 * arena.element_size()
+    exp_bits = {torch.float64: 11, torch.float32: 8, torch.bfloat16: 8, torch.float16: 5}[arena.dtype]
+    ibits = {8: torch.int8, 16: torch.int16, 32: torch.int32, 64: torch.int64}[nbits]
+    sign = 1 << (nbits - 1)
+    inf = ((1 << exp_bits) - 1) << (nbits - 1 - exp_bits)
+    if nbits == 64:  # the int64 view holds the bits; work in it directly (no wider type)
+        b = vals.view(torch.int64)
+        mag = b & (sign - 1)
+        neg = b < 0
+    else:
+        b = vals.view(ibits).to(torch.int64) & ((1 << nbits) - 1)
+        mag = b & (sign - 1)
+        neg = (b & sign) != 0
+    o = torch.where(neg, -mag, mag) + k                    # sign-magnitude order, +0 and -0 both 0
+    o = o.clamp(-inf, inf)
+    out = torch.where(o < 0, (-o) | sign, o) if nbits < 64 else torch.where(o < 0, (-o) | (-(1 << 63)), o)
+    out = torch.where(mag > inf, b, out)                   # NaNs unchanged
+    if nbits == 64:
+        arena[pos] = out.view(arena.dtype)
+    else:
+        arena[pos] = (out - ((out & sign) << 1)).to(ibits).view(arena.dtype)  # back to the signed view
 
 
 def perturb_device(cand: torch.Tensor, dtype: int, seed: int, p_pert: float = 1e-4, kmax: int = 16) -> None:
