@@ -1,4 +1,5 @@
 """The seeded generators produce the shapes and tallies their workloads declare."""
+import pytest
 import numpy as np
 import torch
 
@@ -80,3 +81,42 @@ def test_c5_schedule():
     assert 300 < len(reqs) < 500
     assert all(1 <= len(r.golden_ids) <= 64 and 0 <= r.ulp_tol <= 8 for r in reqs)
     assert all(a.arrival_s < b.arrival_s for a, b in zip(reqs, reqs[1:]))
+
+
+@pytest.mark.parametrize("t,dt", [(torch.float32, W.DT_F32), (torch.float64, W.DT_F64), (torch.bfloat16, W.DT_BF16),
+                                  (torch.float16, W.DT_F16)])
+def test_perturbation_steps_equal_nextafter(t, dt):
+    """perturb_many moves a float k ULP in one integer step; it must equal k
+    nextafter steps towards +-inf, including at zero, subnormals, the largest
+    finite value, infinities and NaNs."""
+    fi = torch.finfo(t)
+    iv = {2: torch.int16, 4: torch.int32, 8: torch.int64}[torch.tensor(0, dtype=t).element_size()]
+    base = [0.0, -0.0, float("inf"), float("-inf"), float("nan"), fi.max, -fi.max, fi.tiny, -fi.tiny, fi.eps,
+            -fi.eps, 1.0, -1.0]
+    sub = torch.tensor([1, 2, 3], dtype=iv).view(t)
+    vals = torch.cat([torch.tensor(base * 300, dtype=torch.float64).to(t), sub, -sub,
+                      torch.randn(2000, generator=torch.Generator().manual_seed(3), dtype=torch.float64).to(t)])
+    n = vals.numel()
+    got = vals.clone()
+    W.perturb_many(got, dt, [0], [n], [777], p_pert=1.0, kmax=16)  # every element moves
+    j, sd = torch.arange(n), torch.full((n,), 777)
+    h1 = W._hash32(sd * 0x9E37 + j * 0x85EB + 1)
+    h2 = W._hash32(h1 + sd + 0x27D4EB2F)
+    k = 1 + (h2 % 16)
+    k = torch.where(((h2 >> 20) & 1) == 1, -k, k)
+    want = vals.clone()
+    target = torch.where(k > 0, torch.full_like(want, float("inf")), torch.full_like(want, float("-inf")))
+    for i in range(16):
+        want = torch.where(k.abs() > i, torch.nextafter(want, target), want)
+    same = (got.view(iv) == want.view(iv)) | (torch.isnan(got) & torch.isnan(want))
+    assert bool(same.all())
+
+
+def test_batched_perturbation_equals_each_buffer_alone():
+    a = torch.randn(300000, generator=torch.Generator().manual_seed(4), dtype=torch.float32)
+    b = a.clone()
+    spans = ((0, 100000, 11), (100000, 150000, 22), (250000, 50000, 33))
+    W.perturb_many(a, W.DT_F32, [o for o, _, _ in spans], [n for _, n, _ in spans], [s for _, _, s in spans], 1e-3)
+    for o, n, s in spans:
+        W.perturb_device(b[o:o + n], W.DT_F32, s, 1e-3)
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32)) and not torch.equal(a, a.clone().fill_(0))
