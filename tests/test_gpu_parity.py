@@ -140,9 +140,36 @@ def test_restore_roundtrip_c1(kc, ctx):
     assert all(np.array_equal(a, b) for a, b in zip(views2, o_views))
 
 
+def _tuned_context(kc, signature, ops):
+    """A context in the launch shapes the benchmark tunes for ``signature``
+    (built-in shapes where the shipped table has none)."""
+    from paper_2605_03208_amd import autotune
+    c = kc.Context(0)
+    shapes = {}
+    for op in ops:
+        hit = autotune.lookup(autotune.cache_key(op, signature))
+        if hit:
+            c.set_tuning(op, **hit["best"])
+            shapes[autotune.OP_NAMES[op]] = hit["best"]
+    return c, shapes
+
+
 def test_delta_c2_scaled(kc, ctx):
-    say("delta snapshot c2 scale 1/32: full, rewrite 5 %, delta, restore chain")
-    case = W.c2_snapshot("cuda", scale=1 / 32)
+    _delta_c2(kc, ctx, 1 / 32)
+
+
+def test_delta_c2_full_in_bench_shapes(kc):
+    """The 4096-range, 2 GiB set at full size, in the shapes the benchmark's
+    batched delta snapshot runs."""
+    c, shapes = _tuned_context(kc, "c2-delta-4096-ranges", (kc.OP_PAGE_HASH, kc.OP_COMPACT))
+    say(f"delta snapshot c2 full size, shapes {shapes or 'built-in'}")
+    _delta_c2(kc, c, 1.0)
+    c.close()
+
+
+def _delta_c2(kc, ctx, scale):
+    say(f"delta snapshot c2 scale {scale}: full, rewrite 5 %, delta, restore chain")
+    case = W.c2_snapshot("cuda", scale=scale)
     ranges = case.ranges()
     rs = kc.RangeSet(ctx, ranges)
     s1 = kc.snapshot(ctx, rs, seed=3)
@@ -405,6 +432,32 @@ def test_compare_c3_scaled(kc, ctx):
         c2.close()
 
 
+def test_compare_c3_full_in_bench_shapes(kc):
+    """10,000 pairs, 8 GiB a side, in the shape the benchmark's batched compare
+    runs: every pair against the generator's record of what it perturbed, and
+    a sample of small and large pairs against the oracle."""
+    c, shapes = _tuned_context(kc, "c3-10000-pairs", (kc.OP_COMPARE,))
+    say(f"compare c3 full size (10,000 pairs, 8 GiB a side), shape {shapes or 'built-in'}")
+    ps = W.c3_pairs("cuda")
+    pairs = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i]), 1e-8, 1e-5) for i in range(len(ps))]
+    res = kc.compare(c, pairs)
+    torch.cuda.synchronize()
+    got = kc.decode_cmp(res, len(pairs))
+    for i, r in enumerate(got):
+        assert r["n_elems"] == ps.n_elems(i)
+        assert r["n_mismatch_elems"] == len(ps.pos[i])
+        assert r["n_over_tol"] == int((np.abs(ps.k[i]) > ps.tols[i]).sum())
+    say("compare c3 full size: sampled pairs vs oracle")
+    order = np.argsort(ps.nbytes)
+    sample = np.unique(np.concatenate([order[:10], order[-6:], np.random.default_rng(33).choice(len(ps), 14)]))
+    for i in sample:
+        cnd, gld, dt, tol, atol, rtol = pairs[int(i)]
+        o = oracle.compare(cnd.cpu().view(torch.uint8).numpy(), gld.cpu().view(torch.uint8).numpy(), dt, tol, atol,
+                           rtol)
+        assert got[int(i)] == o, int(i)
+    c.close()
+
+
 def test_compare_errors(kc, ctx):
     say("compare argument errors")
     a = torch.zeros(64, dtype=torch.uint8, device="cuda")
@@ -421,14 +474,8 @@ def test_compare_errors(kc, ctx):
 # --------------------------------------------------- c4 at full size (30 GiB) --
 
 def test_c4_full_sampled(kc):
-    from paper_2605_03208_amd import autotune
-    ctx = kc.Context(0)
-    shapes = {}
-    for op in (kc.OP_SNAPSHOT, kc.OP_RESTORE, kc.OP_COMPARE):  # the shapes the benchmark times, when tabled
-        hit = autotune.lookup(autotune.cache_key(op, "c4-moe-pool-scale1.0"))
-        if hit:
-            ctx.set_tuning(op, **hit["best"])
-            shapes[autotune.OP_NAMES[op]] = hit["best"]
+    # the shapes the benchmark times, when tabled
+    ctx, shapes = _tuned_context(kc, "c4-moe-pool-scale1.0", (kc.OP_SNAPSHOT, kc.OP_RESTORE, kc.OP_COMPARE))
     say(f"c4 full: launch shapes {shapes or 'built-in'}; generate 30 GiB MoE pool on device")
     case = W.c4_snapshot("cuda")
     ranges = case.ranges()
