@@ -51,6 +51,7 @@ class Completed:
     results: list = field(default_factory=list)
     materialize_s: float = 0.0   # device time of the batch's candidate materialisation
     compare_s: float = 0.0       # device time of the batch's compare
+    host_launch_s: float = 0.0   # host time spent issuing the batch (materialisation and compare calls)
 
     @property
     def latency_s(self) -> float:
@@ -217,7 +218,7 @@ class Server:
         pending = collections.deque(reqs)
         queue = collections.deque()
         admitted = []          # (req, admit_s)
-        running = []           # (handle, [(req, admit_s)], launch_s)
+        running = []           # (handle, [(req, admit_s)], launch_s, host_launch_s)
         done = []
         t0 = self.clock()
         now = 0.0
@@ -235,11 +236,12 @@ class Server:
                 if st is None:
                     break
                 batch, admitted = admitted[: self.max_batch], admitted[self.max_batch:]
+                t_issue = self.clock()
                 h = self.ex.launch(st, [r for r, _ in batch], now)
-                running.append((h, batch, now))
+                running.append((h, batch, now, self.clock() - t_issue if real_time else 0.0))
                 progressed = True
             still = []
-            for h, batch, t_launch in running:
+            for h, batch, t_launch, host_s in running:
                 if self.ex.done(h, now):
                     results = self.ex.finish(h)
                     t_done = self.clock() - t0 if real_time else now
@@ -247,10 +249,10 @@ class Server:
                     for (r, t_adm), res in zip(batch, results):
                         self.budget.give(self.ex.request_bytes(r))
                         done.append(Completed(r.rid, r.arrival_s, t_adm, t_launch, t_done,
-                                              self.ex.request_bytes(r), res, mat_s, cmp_s))
+                                              self.ex.request_bytes(r), res, mat_s, cmp_s, host_s))
                     progressed = True
                 else:
-                    still.append((h, batch, t_launch))
+                    still.append((h, batch, t_launch, host_s))
             running = still
             if not progressed:
                 if real_time:
@@ -259,26 +261,31 @@ class Server:
                 else:
                     # simulated time: jump to the next event
                     cands = [pending[0].arrival_s] if pending else []
-                    cands += [h[2] for h, _, _ in running if isinstance(h, tuple)]
+                    cands += [h[2] for h, _, _, _ in running if isinstance(h, tuple)]
                     nxt = min([c for c in cands if c > now], default=now + poll_s)
                     now = nxt
         return done
 
 
 def summarize(done, wall_s: float) -> dict:
-    """Latency percentiles, split into queue (arrival to admission), and the
-    device time of the materialisation and the compare of each request's
-    batch; aggregate compared bytes (both sides) per second."""
+    """Latency percentiles, split into queue (arrival to admission), wait
+    (arrival to the start of its batch's launch), the host time of issuing
+    the batch, and the device time of the materialisation and the compare of
+    each request's batch; aggregate compared bytes (both sides) per second."""
     def pct(values, p):
         return round(float(np.percentile(np.array(values) if values else np.zeros(1), p)) * 1e3, 3)
 
     lat = [d.latency_s for d in done]
     q = [d.admit_s - d.arrival_s for d in done]
+    wait = [d.launch_s - d.arrival_s for d in done]
+    host = [d.host_launch_s for d in done]
     mat = [d.materialize_s for d in done]
     cmp_ = [d.compare_s for d in done]
     nbytes = sum(2 * d.nbytes for d in done)
     return dict(requests=len(done), p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
                 queue_p50_ms=pct(q, 50), queue_p99_ms=pct(q, 99),
+                wait_p50_ms=pct(wait, 50), wait_p99_ms=pct(wait, 99),
+                host_launch_p50_ms=pct(host, 50), host_launch_p99_ms=pct(host, 99),
                 materialize_p50_ms=pct(mat, 50), materialize_p99_ms=pct(mat, 99),
                 compare_p50_ms=pct(cmp_, 50), compare_p99_ms=pct(cmp_, 99),
                 aggregate_GBps=round(nbytes / max(wall_s, 1e-9) / 1e9, 1), compared_bytes=nbytes,

@@ -66,3 +66,10 @@ def test_summary_fields():
     d = [serve.Completed(i, 0.0, 0.001, 0.001, 0.002 + i * 1e-4, 100) for i in range(100)]
     s = serve.summarize(d, 1.0)
     assert s["requests"] == 100 and s["p50_ms"] <= s["p99_ms"] and s["compared_bytes"] == 20000
+
+
+def test_summary_wait_and_host_split():
+    d = [serve.Completed(i, 0.0, 0.001, 0.003, 0.004, 100, [], 0.0005, 0.0002, 0.0001 * (i % 3)) for i in range(10)]
+    s = serve.summarize(d, 1.0)
+    assert s["queue_p50_ms"] == 1.0 and s["wait_p50_ms"] == 3.0 and s["wait_p99_ms"] == 3.0
+    assert s["host_launch_p99_ms"] <= 0.2 and s["materialize_p50_ms"] == 0.5 and s["compare_p99_ms"] == 0.2
