@@ -68,7 +68,7 @@ extern "C" {
 #endif
 
 #define KC_PAGE_SIZE 4096u
-#define KC_ABI_VERSION 4
+#define KC_ABI_VERSION 5
 #define KC_GRAPH_MAX_RANGES 16384u /* kc_pointer_graph: at most 32 MiB of edges */
 
 /* Status codes. */
@@ -414,6 +414,36 @@ void kc_pairset_destroy(kc_pairset *ps);
  * to kc_compare on the same pairs.  One stream at a time per set. */
 int kc_compare_pairset(kc_ctx *ctx, const kc_pairset *ps, kc_cmp_result *res_d,
                        void *stream);
+
+/* ---- candidate materialisation for the validation server (a request names
+ *      a golden buffer, a tolerance and a seed; the candidate is the golden
+ *      moved by the seeded perturbation: Sec. 4.5.2's validation of a
+ *      reproducer's outputs, reproducers feeding tuning agents, Sec. 1) ----- */
+
+/* One buffer of a typed arena: element offset and length, and its seed (the
+ * low 31 bits are used). */
+typedef struct {
+  uint64_t offset, length;
+  uint32_t seed, reserved;
+} kc_perturb_buf;
+
+/* In place on arena_d (device, arena_elems elements of `dtype`, aligned to
+ * the element size): in each buffer, block j < floor(length / block) moves
+ * one element, offset + j*block + (h1 mod block), by 1 + (h2 mod kmax)
+ * steps, towards -inf when bit 20 of h2 is set, with
+ *   h1 = mix32(seed*0x9E37 + j*0x85EB + 1), h2 = mix32(h1 + seed + 0x27D4EB2F),
+ *   mix32(x) = two rounds of x = ((x >> 16) ^ x) * 0x45D9F3B mod 2^32, then
+ *              (x >> 16) ^ x.
+ * A float steps in the sign-magnitude order of its bits (+0 and -0 both 0),
+ * clamped at +-inf, or at the largest finite code where the format has no
+ * inf; NaN codes stay.  Integers move by the step, clamped to their range.
+ * Buffers may not overlap.  Asynchronous on `stream`; the buffer list is
+ * passed in kernel arguments (no allocation, no staging, no host sync).
+ * Errors: KC_EINVAL (a buffer past arena_elems, block or kmax 0), KC_EDTYPE
+ * (KC_U8), KC_EALIGN. */
+int kc_perturb(kc_ctx *ctx, void *arena_d, uint64_t arena_elems, uint32_t dtype,
+               const kc_perturb_buf *bufs, uint32_t n_bufs, uint64_t block,
+               uint32_t kmax, void *stream);
 
 /* ---- snapshot files (Sec. 4.2.1: every region streamed to files in
  *      fixed-size chunks, metadata written before the data) ------------------ */

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libkc.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["kc_api.hip", "kc_snapshot.hip", "kc_compare.hip", "kc_io.hip", "kc_vaspace.hip", "kc_graph.hip"]
+SOURCES = ["kc_api.hip", "kc_snapshot.hip", "kc_compare.hip", "kc_io.hip", "kc_vaspace.hip", "kc_graph.hip",
+           "kc_perturb.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
-ABI_VERSION = 4  # layout of the structs, the entry-point set and the range rules below
+ABI_VERSION = 5  # layout of the structs, the entry-point set and the range rules below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT, ERELOC = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
@@ -35,7 +35,7 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
            "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
-           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest"]
+           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest", "kc_perturb"]
 
 
 class KCError(RuntimeError):
@@ -66,6 +66,11 @@ class Pair(ctypes.Structure):
     _fields_ = [("cand_d", ctypes.c_void_p), ("gold_d", ctypes.c_void_p), ("n_elems", ctypes.c_uint64),
                 ("dtype", ctypes.c_uint32), ("ulp_tol", ctypes.c_uint32), ("atol", ctypes.c_double),
                 ("rtol", ctypes.c_double)]
+
+
+class PerturbBuf(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_uint64), ("length", ctypes.c_uint64), ("seed", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class CmpResult(ctypes.Structure):
@@ -135,6 +140,7 @@ def lib() -> ctypes.CDLL:
             "kc_vaspace_create": ([i32, P(Range), u32, P(vp), P(u32), P(u64)], i32),
             "kc_vaspace_destroy": ([vp], None),
             "kc_vaspace_suggest": ([i32, u64, P(u64)], i32),
+            "kc_perturb": ([vp, vp, u64, u32, P(PerturbBuf), u32, u64, u32, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -448,6 +454,22 @@ def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -
         res = torch.empty(max(1, n) * RESULT_BYTES, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
     _check(lib().kc_compare(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare")
     return res
+
+
+def perturb(ctx: Context, arena: torch.Tensor, offsets, lengths, seeds, block: int, kmax: int,
+            stream=None) -> None:
+    """kc_perturb: in place on the 1-D typed ``arena``, buffer b at element
+    ``offsets[b]`` of ``lengths[b]`` elements moved by the perturbation of
+    ``seeds[b]`` (one moved element per ``block``, 1..``kmax`` steps)."""
+    dt = TORCH_TO_KC.get(arena.dtype)
+    if dt is None:
+        raise KCError(EDTYPE, "kc_perturb")
+    n = len(offsets)
+    arr = (PerturbBuf * max(1, n))()
+    for i, (o, m, sd) in enumerate(zip(offsets, lengths, seeds)):
+        arr[i].offset, arr[i].length, arr[i].seed = int(o), int(m), int(sd) & 0xFFFFFFFF
+    _check(lib().kc_perturb(ctx.handle, _ptr(arena), arena.numel(), dt, arr, n, int(block), int(kmax),
+                            _stream(stream)), "kc_perturb")
 
 
 def snapshot_save(ctx: Context, rs: RangeSet, directory: str, out: dict, seed: int = 0, cap_pages=None,

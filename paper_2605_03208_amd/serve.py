@@ -23,6 +23,7 @@ runs the same admission / batching logic on the CPU for tests.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -130,6 +131,7 @@ class DeviceExecutor:
         self.ctxs = [kc.Context(device) for _ in range(n_streams)]
         self.busy = [None] * n_streams
         self.p_pert, self.kmax = p_pert, kmax
+        self.block = max(1, int(round(1.0 / p_pert)))  # one moved element per block, as in W.perturb_many
 
     def request_bytes(self, req: Request) -> int:
         return int(self.sizes[req.golden_ids].sum())
@@ -145,8 +147,8 @@ class DeviceExecutor:
 
     def launch(self, stream: int, reqs, now: float):
         """Materialise the batch's candidates (per element type: one copy of
-        the goldens into a fresh arena, one vectorised perturbation) and run
-        all its pairs in one kc_compare launch."""
+        the goldens into a fresh arena, one kc_perturb launch) and run all
+        its pairs in one kc_compare launch."""
         torch, kc, W = self.torch, self.kc, self.W
         s = self.streams[stream]
         entries = [(r, int(gid)) for r in reqs for gid in r.golden_ids]
@@ -168,8 +170,8 @@ class DeviceExecutor:
                 else:
                     for g, o, n in zip(golds, offs, lens):
                         arena[int(o): int(o) + n].copy_(g)
-                W.perturb_many(arena, dt, offs, lens, [self.candidate_seed(*entries[i]) for i in idx],
-                               self.p_pert, self.kmax)
+                kc.perturb(self.ctxs[stream], arena, offs, lens, [self.candidate_seed(*entries[i]) for i in idx],
+                           self.block, self.kmax, stream=s)
                 arenas.append(arena)
                 for i, o, n in zip(idx, offs, lens):
                     views[i] = arena[int(o): int(o) + n]
@@ -210,7 +212,19 @@ class Server:
 
     def run(self, requests, real_time: bool = True, poll_s: float = 50e-6):
         """Serve ``requests`` (sorted by arrival).  Returns Completed records
-        in completion order."""
+        in completion order.  Python's cyclic garbage collector is paused
+        while the loop runs (a full collection over the results of earlier
+        runs stalls the loop for tens of milliseconds); reference counting
+        still frees every batch's buffers as it completes."""
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, real_time, poll_s)
+        finally:
+            if was_enabled:
+                gc.enable()
+
+    def _run(self, requests, real_time: bool, poll_s: float):
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         for r in reqs:
             if self.ex.request_bytes(r) > self.budget.limit:

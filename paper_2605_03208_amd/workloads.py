@@ -747,7 +747,7 @@ def perturb_many(arena: torch.Tensor, dtype: int, offsets, lengths, seeds, p_per
     (seeds[b], j): a buffer's perturbation depends only on its own seed.  A
     float moves in sign-magnitude order of its bits (the order the compare's
     ULP distance counts), stopping at an infinity; NaNs stay; integers and fp8
-    codes move by k and k ranks, clamped."""
+    codes move by k and k ranks, clamped (fp8 NaN codes stay too)."""
     block = max(1, int(round(1.0 / p_pert)))
     lengths = np.asarray(lengths, dtype=np.int64)
     m = lengths // block
@@ -775,12 +775,18 @@ def perturb_many(arena: torch.Tensor, dtype: int, offsets, lengths, seeds, p_per
     vals = arena[pos]
     if arena.dtype in FP8_TYPES:
         code_of_rank, rank_of_code = _fp8_tables_on(dev, arena.dtype)
-        r = (rank_of_code[vals.view(torch.uint8).to(torch.int64)] + k).clamp(0, len(code_of_rank) - 1)
-        arena[pos] = code_of_rank[r].view(arena.dtype)
+        codes = vals.view(torch.uint8)
+        rank = rank_of_code[codes.to(torch.int64)]
+        r = (rank + k).clamp(0, len(code_of_rank) - 1)
+        arena[pos] = torch.where(rank < 0, codes, code_of_rank[r]).view(arena.dtype)
         return
     if arena.dtype in INT_TYPES:
         info = torch.iinfo(arena.dtype)
-        arena[pos] = (vals.to(torch.int64) + k).clamp(info.min, info.max).to(arena.dtype)
+        v = vals.to(torch.int64)
+        o = v + k
+        if arena.dtype == torch.int64:  # saturate instead of wrapping
+            o = torch.where((k > 0) & (o < v), info.max, torch.where((k < 0) & (o > v), info.min, o))
+        arena[pos] = o.clamp(info.min, info.max).to(arena.dtype)
         return
     nbits = 8 * arena.element_size()
     exp_bits = {torch.float64: 11, torch.float32: 8, torch.bfloat16: 8, torch.float16: 5}[arena.dtype]

@@ -200,6 +200,76 @@ def test_serving_alone_equals_mix_and_oracle(kc):
             assert got == want
 
 
+def _perturb_inputs(dt, n, seed):
+    """Every code of an 8-bit type, or a type's specials (zeros, infinities,
+    NaNs, extremes, subnormals, integer bounds) repeated, then random values."""
+    t = W.TORCH_DTYPE[dt]
+    width = W.ELEM_SIZE[dt]
+    iv = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}[width]
+    g = torch.Generator().manual_seed(seed)
+    if width == 1:
+        bits = torch.arange(256, dtype=torch.int64).repeat(n // 256 + 1)[:n].to(torch.uint8)
+        return bits.view(t)
+    if t.is_floating_point:
+        fi = torch.finfo(t)
+        sub = torch.tensor([1, 2, 3], dtype=iv).view(t)
+        base = torch.cat([torch.tensor([0.0, -0.0, float("inf"), float("-inf"), float("nan"), fi.max, -fi.max,
+                                        fi.tiny, -fi.tiny, 1.0, -1.0], dtype=torch.float64).to(t), sub, -sub])
+        rnd = torch.randn(n, generator=g, dtype=torch.float64).to(t)
+    else:
+        ii = torch.iinfo(t)
+        base = torch.tensor([ii.min, ii.min + 1, ii.max, ii.max - 1, -1, 0, 1], dtype=torch.int64).to(t)
+        rnd = torch.randint(ii.min, ii.max, (n,), generator=g, dtype=torch.int64).to(t)
+    head = base.repeat(40)
+    return torch.cat([head, rnd])[:n]
+
+
+@pytest.mark.parametrize("dt", [W.DT_F32, W.DT_BF16, W.DT_F16, W.DT_F64, W.DT_FP8, W.DT_FP8_E4M3FNUZ,
+                                W.DT_FP8_E5M2, W.DT_FP8_E5M2FNUZ, W.DT_I8, W.DT_I16, W.DT_I32, W.DT_I64])
+def test_kc_perturb_equals_generator(kc, dt):
+    """The server's candidate kernel moves exactly the elements, by exactly
+    the steps, that the seeded generator moves on the CPU: specials, every
+    code of the 8-bit types, ragged buffers, and more buffers than one launch
+    carries."""
+    say(f"kc_perturb vs the generator, dtype {dt}")
+    ctx = kc.Context(0)
+    n = 70000
+    host = _perturb_inputs(dt, n, 7 + dt)
+    rng = np.random.default_rng(dt)
+    cuts = np.sort(rng.choice(np.arange(1, n), size=130, replace=False))
+    offs = np.concatenate([[0], cuts])
+    lens = np.diff(np.concatenate([offs, [n]]))
+    lens[5] = 0                                     # an empty buffer
+    seeds = rng.integers(0, 2**31, size=len(offs))
+    for p_pert, kmax in ((1.0, 16), (1 / 3, 5), (1e-2, 16)):
+        want = host.clone()
+        W.perturb_many(want, dt, offs, lens, seeds, p_pert, kmax)
+        got = host.to("cuda")
+        kc.perturb(ctx, got, offs, lens, seeds, max(1, int(round(1.0 / p_pert))), kmax)
+        torch.cuda.synchronize()
+        iv = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}[W.ELEM_SIZE[dt]]
+        assert torch.equal(got.cpu().view(iv), want.view(iv)), p_pert
+        assert not torch.equal(want.view(iv), host.view(iv))
+    ctx.close()
+
+
+def test_kc_perturb_errors(kc):
+    say("kc_perturb argument errors")
+    ctx = kc.Context(0)
+    a = torch.zeros(100, dtype=torch.float32, device="cuda")
+    for args, code in (((a, [0], [101], [1], 1, 16), kc.EINVAL), ((a, [90], [11], [1], 1, 16), kc.EINVAL),
+                       ((a, [0], [10], [1], 0, 16), kc.EINVAL), ((a, [0], [10], [1], 1, 0), kc.EINVAL),
+                       ((a.view(torch.uint8), [0], [10], [1], 1, 16), kc.EDTYPE)):
+        with pytest.raises(kc.KCError) as ei:
+            kc.perturb(ctx, *args)
+        assert ei.value.code == code
+    kc.perturb(ctx, a, [], [], [], 1, 16)                  # nothing to move
+    kc.perturb(ctx, a, [0, 50], [7, 9], [1, 2], 10, 16)    # buffers shorter than a block
+    torch.cuda.synchronize()
+    assert bool((a == 0).all())                            # rejected and empty calls wrote nothing
+    ctx.close()
+
+
 def test_sets_may_outlive_their_context(kc):
     say("context destroyed before its range set and pair set; caller's HIP state stays clean")
     ctx = kc.Context(0)

@@ -73,3 +73,18 @@ def test_summary_wait_and_host_split():
     s = serve.summarize(d, 1.0)
     assert s["queue_p50_ms"] == 1.0 and s["wait_p50_ms"] == 3.0 and s["wait_p99_ms"] == 3.0
     assert s["host_launch_p99_ms"] <= 0.2 and s["materialize_p50_ms"] == 0.5 and s["compare_p99_ms"] == 0.2
+
+
+def test_run_pauses_and_restores_the_cycle_collector():
+    import gc
+    ex = serve.MockExecutor(np.array([100, 200]), n_streams=1)
+    reqs = [serve.Request(i, i * 1e-3, np.array([i % 2]), 0, i) for i in range(4)]
+    assert gc.isenabled()
+    assert len(serve.Server(ex, 1 << 20).run(reqs, real_time=False)) == 4
+    assert gc.isenabled()
+    gc.disable()
+    try:
+        serve.Server(serve.MockExecutor(np.array([100, 200]), n_streams=1), 1 << 20).run(reqs, real_time=False)
+        assert not gc.isenabled()
+    finally:
+        gc.enable()

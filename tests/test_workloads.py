@@ -120,3 +120,20 @@ def test_batched_perturbation_equals_each_buffer_alone():
     for o, n, s in spans:
         W.perturb_device(b[o:o + n], W.DT_F32, s, 1e-3)
     assert torch.equal(a.view(torch.int32), b.view(torch.int32)) and not torch.equal(a, a.clone().fill_(0))
+
+
+def test_perturbation_keeps_fp8_nans_and_saturates_int64():
+    for t in (torch.float8_e4m3fn, torch.float8_e4m3fnuz, torch.float8_e5m2, torch.float8_e5m2fnuz):
+        dt = {v: k for k, v in W.TORCH_DTYPE.items()}[t]
+        codes = torch.arange(256, dtype=torch.int64).to(torch.uint8)
+        got = codes.clone().view(t)
+        W.perturb_many(got, dt, [0], [256], [9], p_pert=1.0, kmax=16)
+        nan = torch.isnan(codes.view(t).to(torch.float32))
+        assert bool(nan.any()) and torch.equal(got.view(torch.uint8)[nan], codes[nan])
+        assert not torch.equal(got.view(torch.uint8)[~nan], codes[~nan])
+    ii = torch.iinfo(torch.int64)
+    v = torch.tensor([ii.max, ii.min] * 200, dtype=torch.int64)
+    got = v.clone()
+    W.perturb_many(got, W.DT_I64, [0], [400], [5], p_pert=1.0, kmax=16)
+    assert bool(((got == ii.max) | (got == ii.min) | ((got - v).abs() <= 16)).all())
+    assert bool(((v == ii.max) & (got < 0)).logical_not().all()) and bool(((v == ii.min) & (got > 0)).logical_not().all())
