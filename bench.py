@@ -556,8 +556,10 @@ def c1_latency(torch, kc, W, dev) -> dict:
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
+    t0 = time.perf_counter()
     for _ in range(reps):
         step()
+    stream_host_us = (time.perf_counter() - t0) / reps * 1e6  # host time to issue one step
     e1.record(stream)
     torch.cuda.synchronize()
     stream_us = e0.elapsed_time(e1) / reps * 1e3
@@ -579,8 +581,10 @@ def c1_latency(torch, kc, W, dev) -> dict:
         res.zero_()
         torch.cuda.synchronize()
     e0.record(stream)
+    t0 = time.perf_counter()
     for _ in range(reps):
         g.replay()
+    graph_host_us = (time.perf_counter() - t0) / reps * 1e6
     e1.record(stream)
     torch.cuda.synchronize()
     graph_us = e0.elapsed_time(e1) / reps * 1e3
@@ -590,7 +594,9 @@ def c1_latency(torch, kc, W, dev) -> dict:
     ctx.close()
     return {"workload": "c1: 64 MiB / 48 ranges snapshot + restore + 16 x 2^20 fp32 compare",
             "stream_us": round(stream_us, 1), "graph_us": round(graph_us, 1),
-            "graph_speedup": round(stream_us / graph_us, 3), "replays_match_eager": ok}
+            "graph_speedup": round(stream_us / graph_us, 3),
+            "stream_host_issue_us": round(stream_host_us, 1), "graph_host_issue_us": round(graph_host_us, 1),
+            "replays_match_eager": ok}
 
 
 def partial_pages(torch, kc, W, dev) -> dict:

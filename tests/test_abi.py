@@ -1,5 +1,6 @@
 """The C-ABI library loads and exports every function ``include/kc.h``
 declares; its host-only checks agree with the oracle (no device needed)."""
+import ctypes
 import os
 import re
 
@@ -125,3 +126,19 @@ def test_vaspace_rejects_bad_ranges_before_any_device_call(kc):
         with pytest.raises(kc.KCError) as ei:
             kc.VaSpace(0, ranges)
         assert ei.value.code == code
+
+
+def test_perturb_rejects_bad_arguments_before_any_device_call(kc):
+    """kc_perturb validates its arguments on the host: no context, an unknown
+    element type, a buffer past the arena, block or kmax 0."""
+    L = kc.lib()
+    bufs = (kc.PerturbBuf * 1)()
+    bufs[0].offset, bufs[0].length, bufs[0].seed = 0, 10, 1
+    assert L.kc_perturb(None, 0x1000, 10, kc.F32, bufs, 1, 1, 16, None) == kc.EINVAL
+    # a context pointer is only dereferenced after validation; a dummy non-null one exercises the host checks
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.kc_perturb(dummy, 0x1000, 10, kc.U8, bufs, 1, 1, 16, None) == kc.EDTYPE
+    assert L.kc_perturb(dummy, 0x1000, 9, kc.F32, bufs, 1, 1, 16, None) == kc.EINVAL
+    assert L.kc_perturb(dummy, 0x1000, 10, kc.F32, bufs, 1, 0, 16, None) == kc.EINVAL
+    assert L.kc_perturb(dummy, 0x1000, 10, kc.F32, bufs, 1, 1, 0, None) == kc.EINVAL
+    assert L.kc_perturb(dummy, 0x1002, 10, kc.F32, bufs, 1, 1, 16, None) == kc.EALIGN
