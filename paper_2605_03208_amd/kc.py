@@ -73,6 +73,10 @@ class PerturbBuf(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+_PERTURB_NP = np.dtype([("offset", "<u8"), ("length", "<u8"), ("seed", "<u4"), ("reserved", "<u4")])
+assert _PERTURB_NP.itemsize == ctypes.sizeof(PerturbBuf)
+
+
 class CmpResult(ctypes.Structure):
     _fields_ = [("n_elems", ctypes.c_uint64), ("n_mismatch_elems", ctypes.c_uint64),
                 ("n_mismatch_bytes", ctypes.c_uint64), ("first_mismatch", ctypes.c_uint64),
@@ -447,6 +451,22 @@ def make_pairs(pairs) -> tuple[ctypes.Array, int]:
     return arr, len(pairs)
 
 
+_PAIR_NP = np.dtype([("cand_d", "<u8"), ("gold_d", "<u8"), ("n_elems", "<u8"), ("dtype", "<u4"),
+                     ("ulp_tol", "<u4"), ("atol", "<f8"), ("rtol", "<f8")])
+assert _PAIR_NP.itemsize == ctypes.sizeof(Pair)
+
+
+def pairs_from_arrays(cand_ptr, gold_ptr, n_elems, dtype, ulp_tol, atol=0.0, rtol=0.0) -> tuple[ctypes.Array, int]:
+    """A kc_pair list from per-pair arrays of device addresses, element
+    counts, element types and tolerances (no tensor per pair); the result
+    goes to ``compare`` in place of a pair list."""
+    n = len(cand_ptr)
+    a = np.zeros(max(1, n), dtype=_PAIR_NP)
+    a["cand_d"][:n], a["gold_d"][:n], a["n_elems"][:n] = cand_ptr, gold_ptr, n_elems
+    a["dtype"][:n], a["ulp_tol"][:n], a["atol"][:n], a["rtol"][:n] = dtype, ulp_tol, atol, rtol
+    return (Pair * max(1, n)).from_buffer(a), n
+
+
 def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Returns the device buffer of kc_cmp_result structs (decode with ``decode_cmp``)."""
     arr, n = pairs if isinstance(pairs, tuple) else make_pairs(pairs)
@@ -465,9 +485,10 @@ def perturb(ctx: Context, arena: torch.Tensor, offsets, lengths, seeds, block: i
     if dt is None:
         raise KCError(EDTYPE, "kc_perturb")
     n = len(offsets)
-    arr = (PerturbBuf * max(1, n))()
-    for i, (o, m, sd) in enumerate(zip(offsets, lengths, seeds)):
-        arr[i].offset, arr[i].length, arr[i].seed = int(o), int(m), int(sd) & 0xFFFFFFFF
+    a = np.zeros(max(1, n), dtype=_PERTURB_NP)
+    a["offset"][:n], a["length"][:n] = np.asarray(offsets, dtype=np.int64), np.asarray(lengths, dtype=np.int64)
+    a["seed"][:n] = np.asarray(seeds, dtype=np.int64) & 0xFFFFFFFF
+    arr = (PerturbBuf * max(1, n)).from_buffer(a)
     _check(lib().kc_perturb(ctx.handle, _ptr(arena), arena.numel(), dt, arr, n, int(block), int(kmax),
                             _stream(stream)), "kc_perturb")
 

@@ -126,6 +126,13 @@ class DeviceExecutor:
         self.goldens = goldens
         self.dtypes = [int(d) for d in dtypes]
         self.sizes = np.array([g.numel() * g.element_size() for g in goldens], dtype=np.int64)
+        for g in goldens:
+            assert g.is_cuda and g.is_contiguous(), "goldens must be contiguous device tensors"
+        self.dtype_arr = np.array(self.dtypes, dtype=np.int64)
+        self.numel_arr = np.array([g.numel() for g in goldens], dtype=np.int64)
+        self.gold_ptr = np.array([g.data_ptr() for g in goldens], dtype=np.uint64)
+        self.flat = [g.reshape(-1) for g in goldens]
+        self.n_elems_arr = self.sizes // np.array([kc.ELEM_SIZE[d] for d in self.dtypes], dtype=np.int64)
         self.n_streams = n_streams
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self.ctxs = [kc.Context(device) for _ in range(n_streams)]
@@ -148,40 +155,45 @@ class DeviceExecutor:
     def launch(self, stream: int, reqs, now: float):
         """Materialise the batch's candidates (per element type: one copy of
         the goldens into a fresh arena, one kc_perturb launch) and run all
-        its pairs in one kc_compare launch."""
-        torch, kc, W = self.torch, self.kc, self.W
+        its pairs in one kc_compare launch.  The pair list is built from
+        arrays of addresses (no tensor per pair), in request order."""
+        torch, kc = self.torch, self.kc
         s = self.streams[stream]
-        entries = [(r, int(gid)) for r in reqs for gid in r.golden_ids]
+        counts = np.array([len(r.golden_ids) for r in reqs], dtype=np.int64)
+        gids = np.concatenate([np.asarray(r.golden_ids, dtype=np.int64) for r in reqs])
+        # candidate_seed, vectorised: (seed * 1000003 + gid) mod 2^31 with the product reduced first
+        base = np.array([(int(r.seed) * 1000003) & 0x7FFFFFFF for r in reqs], dtype=np.int64)
+        seeds = (np.repeat(base, counts) + gids) & 0x7FFFFFFF
+        dts = self.dtype_arr[gids]
+        cand_ptr = np.zeros(len(gids), dtype=np.uint64)
         ev0, ev_mat, ev = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        arenas = []
         with torch.cuda.stream(s):
             ev0.record(s)
-            views = [None] * len(entries)
-            arenas = []
-            for dt in sorted({self.dtypes[g] for _, g in entries}):
-                idx = [i for i, (_, g) in enumerate(entries) if self.dtypes[g] == dt]
-                golds = [self.goldens[entries[i][1]] for i in idx]
-                lens = [g.numel() for g in golds]
-                align = max(1, 16 // golds[0].element_size())   # keep every candidate 16-byte aligned
-                padded = [-(-n // align) * align for n in lens]
+            for dt in np.unique(dts):
+                sel = np.nonzero(dts == dt)[0]
+                golds = [self.flat[g] for g in gids[sel].tolist()]
+                lens = self.numel_arr[gids[sel]]
+                esz = golds[0].element_size()
+                align = max(1, 16 // esz)   # keep every candidate 16-byte aligned
+                padded = -(-lens // align) * align
                 offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
-                arena = torch.empty(int(sum(padded)), dtype=golds[0].dtype, device=s.device)
-                if padded == lens:
+                arena = torch.empty(int(padded.sum()), dtype=golds[0].dtype, device=s.device)
+                if np.array_equal(padded, lens):
                     torch.cat(golds, out=arena)
                 else:
-                    for g, o, n in zip(golds, offs, lens):
-                        arena[int(o): int(o) + n].copy_(g)
-                kc.perturb(self.ctxs[stream], arena, offs, lens, [self.candidate_seed(*entries[i]) for i in idx],
-                           self.block, self.kmax, stream=s)
+                    for g, o, n in zip(golds, offs.tolist(), lens.tolist()):
+                        arena[o: o + n].copy_(g)
+                kc.perturb(self.ctxs[stream], arena, offs, lens, seeds[sel], self.block, self.kmax, stream=s)
                 arenas.append(arena)
-                for i, o, n in zip(idx, offs, lens):
-                    views[i] = arena[int(o): int(o) + n]
-            pairs = [(views[i], self.goldens[g], self.dtypes[g], r.ulp_tol, *DEFAULT_CLOSE)
-                     for i, (r, g) in enumerate(entries)]
+                cand_ptr[sel] = np.uint64(arena.data_ptr()) + offs.astype(np.uint64) * np.uint64(esz)
+            pairs = kc.pairs_from_arrays(cand_ptr, self.gold_ptr[gids], self.n_elems_arr[gids], dts,
+                                         np.repeat([int(r.ulp_tol) for r in reqs], counts), *DEFAULT_CLOSE)
             ev_mat.record(s)
             res = kc.compare(self.ctxs[stream], pairs)
             ev.record(s)
-        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, ev0=ev0, ev_mat=ev_mat, arenas=arenas, n=len(pairs),
-                 owners=[r.rid for r, _ in entries])
+        h = dict(stream=stream, reqs=reqs, res=res, ev=ev, ev0=ev0, ev_mat=ev_mat, arenas=arenas, n=len(gids),
+                 owners=np.repeat([r.rid for r in reqs], counts).tolist())
         self.busy[stream] = h
         return h
 

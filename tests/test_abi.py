@@ -142,3 +142,16 @@ def test_perturb_rejects_bad_arguments_before_any_device_call(kc):
     assert L.kc_perturb(dummy, 0x1000, 10, kc.F32, bufs, 1, 0, 16, None) == kc.EINVAL
     assert L.kc_perturb(dummy, 0x1000, 10, kc.F32, bufs, 1, 1, 0, None) == kc.EINVAL
     assert L.kc_perturb(dummy, 0x1002, 10, kc.F32, bufs, 1, 1, 16, None) == kc.EALIGN
+
+
+def test_pair_arrays_marshal_like_pair_structs(kc):
+    """The array form of a pair list (used by the server) lays out kc_pair
+    exactly as the per-pair constructor does."""
+    arr, n = kc.pairs_from_arrays(np.array([0x1000, 0x2000], dtype=np.uint64),
+                                  np.array([0x3000, 2**63 + 0x4000], dtype=np.uint64), np.array([5, 2**40]),
+                                  np.array([0, 12]), np.array([2, 9]), 1e-8, 1e-5)
+    want = [kc.Pair(0x1000, 0x3000, 5, 0, 2, 1e-8, 1e-5), kc.Pair(0x2000, 2**63 + 0x4000, 2**40, 12, 9, 1e-8, 1e-5)]
+    assert n == 2
+    assert [bytes(p) for p in arr] == [bytes(p) for p in want]
+    arr, n = kc.pairs_from_arrays([], [], [], [], [])
+    assert n == 0 and len(arr) == 1
