@@ -253,6 +253,24 @@ def test_kc_perturb_equals_generator(kc, dt):
     ctx.close()
 
 
+def test_kc_perturb_offsets_past_4g_elements(kc):
+    """Element offsets and moved-element indices past 2^32: a 4.5 GiB int8
+    arena whose second buffer starts below 2^32 and ends above it."""
+    say("kc_perturb: 4.5 GiB int8 arena, a buffer across element 2^32")
+    ctx = kc.Context(0)
+    n = (9 << 29)
+    offs, lens, seeds = [0, (1 << 32) - 12345], [1 << 30, n - ((1 << 32) - 12345)], [3, 4]
+    got = torch.zeros(n, dtype=torch.int8, device="cuda")
+    kc.perturb(ctx, got, offs, lens, seeds, 1000, 16)
+    torch.cuda.synchronize()
+    want = torch.zeros(n, dtype=torch.int8)
+    W.perturb_many(want, W.DT_I8, offs, lens, seeds, p_pert=1e-3, kmax=16)
+    assert torch.equal(got.cpu(), want)
+    assert int((want[(1 << 32):] != 0).sum()) > 0
+    del got
+    ctx.close()
+
+
 def test_kc_perturb_errors(kc):
     say("kc_perturb argument errors")
     ctx = kc.Context(0)
