@@ -439,8 +439,10 @@ typedef struct {
  * inf; NaN codes stay.  Integers move by the step, clamped to their range.
  * Buffers may not overlap.  Asynchronous on `stream`; the buffer list is
  * passed in kernel arguments (no allocation, no staging, no host sync).
- * Errors: KC_EINVAL (a buffer past arena_elems, block or kmax 0), KC_EDTYPE
- * (KC_U8), KC_EALIGN. */
+ * Errors, all detected before any launch except the last: KC_EINVAL (no
+ * context, a buffer past arena_elems, block or kmax 0), KC_EDTYPE (KC_U8),
+ * KC_EALIGN (arena_d not aligned to the element size), KC_EHIP (a launch
+ * failed; kc_last_error names it). */
 int kc_perturb(kc_ctx *ctx, void *arena_d, uint64_t arena_elems, uint32_t dtype,
                const kc_perturb_buf *bufs, uint32_t n_bufs, uint64_t block,
                uint32_t kmax, void *stream);
