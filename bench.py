@@ -215,6 +215,8 @@ def main() -> int:
                     help="only run a plain device copy of GIB GiB three times (counter calibration) and exit")
     ap.add_argument("--c1-only", action="store_true",
                     help="only measure the small latency-bound case (64 MiB snapshot + restore + compare) and exit")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving measurement (c5 and the overload burst) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -243,6 +245,9 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.c1_only:
         print(json.dumps({"c1_latency": c1_latency(torch, kc, W, dev)}), flush=True)
+        return 0
+    if args.serve_only:
+        print(json.dumps({"serving": serving(torch, kc, W, dev, args.serve_seconds)}), flush=True)
         return 0
     log(f"generating the MoE pool at scale {args.scale}")
     case = W.c4_snapshot("cuda", scale=args.scale)
