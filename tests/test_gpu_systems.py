@@ -200,6 +200,25 @@ def test_serving_alone_equals_mix_and_oracle(kc):
             assert got == want
 
 
+def test_serving_batch_past_2g_elements_equals_alone(kc):
+    """A batch whose fp8 candidate arena holds more than 2^31 elements (the
+    overload regime) gives every request the results it gets alone."""
+    say("serving: one batch with an fp8 arena past 2^31 elements vs each request alone")
+    from paper_2605_03208_amd import serve
+    golds, dtypes = W.c5_pool("cuda")
+    fp8 = np.nonzero(np.asarray(dtypes) == W.DT_FP8)[0]
+    assert sum(golds[int(g)].numel() for g in fp8) * 2 > 2**31
+    reqs = [serve.Request(i, 0.0, fp8[i::2] if i < 2 else fp8, tol, 100 + i) for i, tol in enumerate((0, 3, 8))]
+    ex = serve.DeviceExecutor(golds, dtypes, n_streams=1)
+    srv = serve.Server(ex, 64 << 30, max_batch=3)
+    mix = {d.rid: d for d in srv.run(reqs)}
+    assert len({d.launch_s for d in mix.values()}) == 1           # one batch
+    for r in reqs:
+        alone = serve.Server(ex, 64 << 30).run([serve.Request(r.rid, 0.0, r.golden_ids, r.ulp_tol, r.seed)])
+        assert alone[0].results == mix[r.rid].results, r.rid
+        assert sum(x["n_mismatch_elems"] for x in mix[r.rid].results) > 0
+
+
 def _perturb_inputs(dt, n, seed):
     """Every code of an 8-bit type, or a type's specials (zeros, infinities,
     NaNs, extremes, subnormals, integer bounds) repeated, then random values."""
