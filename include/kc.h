@@ -437,7 +437,8 @@ typedef struct {
  * A float steps in the sign-magnitude order of its bits (+0 and -0 both 0),
  * clamped at +-inf, or at the largest finite code where the format has no
  * inf; NaN codes stay.  Integers move by the step, clamped to their range.
- * Buffers may not overlap.  Asynchronous on `stream`; the buffer list is
+ * Buffers may not overlap.  The caller owns arena_d; bufs (host) is read
+ * during the call only.  Asynchronous on `stream`; the buffer list is
  * passed in kernel arguments (no allocation, no staging, no host sync).
  * Errors, all detected before any launch except the last: KC_EINVAL (no
  * context, a buffer past arena_elems, block or kmax 0), KC_EDTYPE (KC_U8),
