@@ -24,6 +24,8 @@
  *   kc_pointer_graph which range points into which (the graph pointer
  *                    chasing would follow), and kc_graph_reach, the ranges
  *                    reachable from the kernel-argument words
+ *   kc_perturb       the validation server's candidates: goldens moved by a
+ *                    seeded perturbation, in place on the device
  *
  * Conventions
  *  - Pointers suffixed _d are device pointers owned by the caller; the
