@@ -83,9 +83,15 @@ def lib() -> ctypes.CDLL:
         L.kco_range_check.argtypes = [P(Range), u32, P(u64), P(u64)]
         L.kco_default_window.argtypes = [P(Range), u32, P(u64), P(u64)]
         L.kco_page_hash.argtypes = [P(Range), P(vp), u32, u64, vp, vp, vp, vp]
+        L.kco_range_check_unit.argtypes = [P(Range), u32, u64, P(u64), P(u64)]
+        L.kco_page_hash_unit.argtypes = [P(Range), P(vp), u32, u64, u64, vp, vp, vp, vp]
+        L.kco_compact_unit.argtypes = [P(Range), P(vp), u32, u64, vp, vp, vp, vp, u64, P(u64)]
+        L.kco_restore_unit.argtypes = [P(Range), P(vp), u32, u64, vp, vp, vp, vp, u64, u64, P(u64)]
+        L.kco_region_diff_unit.argtypes = [P(Range), P(vp), u32, u64, vp, vp, vp, u64, u64, vp]
         L.kco_compact.argtypes = [P(Range), P(vp), u32, vp, vp, vp, vp, u64, P(u64)]
         L.kco_restore.argtypes = [P(Range), P(vp), u32, vp, vp, vp, vp, u64, u64, P(u64)]
         L.kco_closure_scan.argtypes = [P(Range), P(vp), u32, u64, u64, P(ScanResult), P(Oob), u64]
+        L.kco_closure_scan_range.argtypes = [P(Range), u32, u32, vp, u64, u64, P(ScanResult), P(Oob), u64]
         L.kco_compare.argtypes = [vp, vp, u64, u32, u32, ctypes.c_double, ctypes.c_double, P(CmpResult)]
         L.kco_ulp.argtypes = [u32, u64, u64, P(u64)]
         L.kco_pointer_graph.argtypes = [P(Range), P(vp), u32, u64, u64, vp]
@@ -93,8 +99,11 @@ def lib() -> ctypes.CDLL:
         L.kco_region_diff.argtypes = [P(Range), P(vp), u32, vp, vp, vp, u64, u64, vp]
         L.kco_ulp_bin.argtypes = [u64]
         L.kco_ulp_bin.restype = u32
+        for name in ("kco_range_check_unit", "kco_page_hash_unit", "kco_compact_unit", "kco_restore_unit",
+                     "kco_region_diff_unit"):
+            getattr(L, name).restype = i32
         for name in ("kco_range_check", "kco_default_window", "kco_page_hash", "kco_compact",
-                     "kco_restore", "kco_closure_scan", "kco_compare", "kco_ulp", "kco_pointer_graph",
+                     "kco_restore", "kco_closure_scan", "kco_closure_scan_range", "kco_compare", "kco_ulp", "kco_pointer_graph",
                      "kco_graph_reach", "kco_region_diff"):
             getattr(L, name).restype = i32
         _lib = L
@@ -140,13 +149,14 @@ def xxh64(data, seed: int = 0) -> int:
     return int(lib().kco_xxh64(buf.ctypes.data if buf.size else None, buf.nbytes, seed & (2**64 - 1)))
 
 
-def range_check(ranges):
-    """Returns (status, n_pages, first_page[n+1])."""
+def range_check(ranges, unit: int = PAGE):
+    """Returns (status, n_pages, first_page[n+1]); pages are hash units of
+    ``unit`` bytes."""
     fp = np.zeros(len(ranges) + 1, dtype=np.uint64)
     n_pages = ctypes.c_uint64(0)
-    st = lib().kco_range_check(_ranges(ranges), len(ranges),
-                               fp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
-                               ctypes.byref(n_pages))
+    st = lib().kco_range_check_unit(_ranges(ranges), len(ranges), unit,
+                                    fp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    ctypes.byref(n_pages))
     return st, int(n_pages.value), fp
 
 
@@ -157,15 +167,16 @@ def default_window(ranges):
     return int(lo.value), int(hi.value)
 
 
-def _n_pages(ranges) -> int:
-    st, n, _ = range_check(ranges)
+def _n_pages(ranges, unit: int = PAGE) -> int:
+    st, n, _ = range_check(ranges, unit)
     _check(st, "range_check")
     return n
 
 
-def page_hash(ranges, views, seed: int = 0, prior=None):
-    """Returns (hash u64[N], zero_bm u64[W], changed_bm u64[W] or None)."""
-    n = _n_pages(ranges)
+def page_hash(ranges, views, seed: int = 0, prior=None, unit: int = PAGE):
+    """Returns (hash u64[N], zero_bm u64[W], changed_bm u64[W] or None) over
+    hash units of ``unit`` bytes."""
+    n = _n_pages(ranges, unit)
     w = (n + 63) // 64
     h = np.zeros(n, dtype=np.uint64)
     z = np.zeros(w, dtype=np.uint64)
@@ -173,29 +184,29 @@ def page_hash(ranges, views, seed: int = 0, prior=None):
     if prior is not None:
         prior = np.ascontiguousarray(prior, dtype=np.uint64)
         assert prior.size == n
-    _check(lib().kco_page_hash(_ranges(ranges), _hosts(views), len(ranges), seed & (2**64 - 1),
-                               _ptr(prior), _ptr(h), _ptr(z), _ptr(c)), "page_hash")
+    _check(lib().kco_page_hash_unit(_ranges(ranges), _hosts(views), len(ranges), unit, seed & (2**64 - 1),
+                                    _ptr(prior), _ptr(h), _ptr(z), _ptr(c)), "page_hash")
     return h, z, c
 
 
-def compact(ranges, views, zero_bm, changed_bm=None, cap_pages=None):
-    """Returns (packed u8[min(n_kept,cap)*4096], page_va u64[min(n_kept,cap)], n_kept)."""
-    n = _n_pages(ranges)
+def compact(ranges, views, zero_bm, changed_bm=None, cap_pages=None, unit: int = PAGE):
+    """Returns (packed u8[min(n_kept,cap)*unit], page_va u64[min(n_kept,cap)], n_kept)."""
+    n = _n_pages(ranges, unit)
     cap = n if cap_pages is None else int(cap_pages)
-    packed = np.full(max(cap, 1) * PAGE, 0xEE, dtype=np.uint8)   # every byte of a slot must be written
+    packed = np.full(max(cap, 1) * unit, 0xEE, dtype=np.uint8)   # every byte of a slot must be written
     va = np.zeros(max(cap, 1), dtype=np.uint64)
     n_kept = ctypes.c_uint64(0)
     zero_bm = np.ascontiguousarray(zero_bm, dtype=np.uint64)
     if changed_bm is not None:
         changed_bm = np.ascontiguousarray(changed_bm, dtype=np.uint64)
-    _check(lib().kco_compact(_ranges(ranges), _hosts(views), len(ranges), _ptr(zero_bm),
-                             _ptr(changed_bm), _ptr(packed), _ptr(va), cap,
-                             ctypes.byref(n_kept)), "compact")
+    _check(lib().kco_compact_unit(_ranges(ranges), _hosts(views), len(ranges), unit, _ptr(zero_bm),
+                                  _ptr(changed_bm), _ptr(packed), _ptr(va), cap,
+                                  ctypes.byref(n_kept)), "compact")
     k = min(int(n_kept.value), cap)
-    return packed[: k * PAGE], va[:k], int(n_kept.value)
+    return packed[: k * unit], va[:k], int(n_kept.value)
 
 
-def restore(ranges, views, zero_bm, changed_bm, packed, page_va, n_kept, cap_pages=None):
+def restore(ranges, views, zero_bm, changed_bm, packed, page_va, n_kept, cap_pages=None, unit: int = PAGE):
     """Writes into ``views`` in place; returns the number of rejected page VAs."""
     cap = len(page_va) if cap_pages is None else int(cap_pages)
     n_bad = ctypes.c_uint64(0)
@@ -204,10 +215,10 @@ def restore(ranges, views, zero_bm, changed_bm, packed, page_va, n_kept, cap_pag
         changed_bm = np.ascontiguousarray(changed_bm, dtype=np.uint64)
     packed = np.ascontiguousarray(packed, dtype=np.uint8)
     page_va = np.ascontiguousarray(page_va, dtype=np.uint64)
-    _check(lib().kco_restore(_ranges(ranges), _hosts(views), len(ranges), _ptr(zero_bm),
-                             _ptr(changed_bm), _ptr(packed) if packed.size else None,
-                             _ptr(page_va) if page_va.size else None, int(n_kept), cap,
-                             ctypes.byref(n_bad)), "restore")
+    _check(lib().kco_restore_unit(_ranges(ranges), _hosts(views), len(ranges), unit, _ptr(zero_bm),
+                                  _ptr(changed_bm), _ptr(packed) if packed.size else None,
+                                  _ptr(page_va) if page_va.size else None, int(n_kept), cap,
+                                  ctypes.byref(n_bad)), "restore")
     return int(n_bad.value)
 
 
@@ -221,13 +232,26 @@ def closure_scan(ranges, views, win_lo: int = 0, win_hi: int = 0, oob_cap: int =
     return d, [(int(oob[i].word_va), int(oob[i].value)) for i in range(d["n_written"])]
 
 
+def closure_scan_range(ranges, a: int, view, win_lo: int = 0, win_hi: int = 0, oob_cap: int = 64):
+    """The closure scan of range ``a``'s words (host bytes ``view``) against
+    every range: returns (result dict, oob list of (word_va, value))."""
+    res = ScanResult()
+    oob = (Oob * max(1, oob_cap))()
+    v = np.ascontiguousarray(view).view(np.uint8)
+    assert not 0 <= a < len(ranges) or v.nbytes >= ranges[a][1]
+    _check(lib().kco_closure_scan_range(_ranges(ranges), len(ranges), a, _ptr(v), win_lo, win_hi,
+                                        ctypes.byref(res), oob, oob_cap), "closure_scan_range")
+    d = {k: int(getattr(res, k)) for k, _ in ScanResult._fields_}
+    return d, [(int(oob[i].word_va), int(oob[i].value)) for i in range(d["n_written"])]
+
+
 class RegionDiff(ctypes.Structure):
     _fields_ = [("n_diff_bytes", ctypes.c_uint64), ("n_diff_pages", ctypes.c_uint64),
                 ("first_diff_va", ctypes.c_uint64), ("n_bad_pages", ctypes.c_uint64)]
 
 
 def region_diff(ranges, views, gold_zero_bm, gold_packed, gold_page_va, gold_n_kept: int,
-                cap_pages: int | None = None) -> list[dict]:
+                cap_pages: int | None = None, unit: int = PAGE) -> list[dict]:
     """Per-range byte difference of the live bytes in ``views`` against a full snapshot."""
     n = len(ranges)
     zb = np.ascontiguousarray(gold_zero_bm, dtype=np.uint64)
@@ -235,9 +259,9 @@ def region_diff(ranges, views, gold_zero_bm, gold_packed, gold_page_va, gold_n_k
     va = np.ascontiguousarray(gold_page_va, dtype=np.uint64)
     cap = len(va) if cap_pages is None else int(cap_pages)
     res = (RegionDiff * max(1, n))()
-    _check(lib().kco_region_diff(_ranges(ranges), _hosts(views), n, _ptr(zb) if zb.size else None,
-                                 _ptr(pk) if pk.size else None, _ptr(va) if va.size else None, int(gold_n_kept),
-                                 cap, res), "region_diff")
+    _check(lib().kco_region_diff_unit(_ranges(ranges), _hosts(views), n, unit, _ptr(zb) if zb.size else None,
+                                      _ptr(pk) if pk.size else None, _ptr(va) if va.size else None,
+                                      int(gold_n_kept), cap, res), "region_diff")
     return [{k: int(getattr(res[i], k)) for k, _ in RegionDiff._fields_} for i in range(n)]
 
 

@@ -111,9 +111,15 @@ uint64_t kco_xxh64(const void *data, uint64_t len, uint64_t seed) {
 /* remaining size mod 4096 bytes when that is not zero.                      */
 /* ------------------------------------------------------------------------ */
 
-int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
-                    uint64_t *n_pages) {
+/* The hash unit: a power of two from 4 KiB to 2 MiB. */
+static int unit_ok(uint64_t unit) {
+  return unit >= PAGE && unit <= (2u << 20) && (unit & (unit - 1)) == 0;
+}
+
+int kco_range_check_unit(const kco_range *ranges, uint32_t n, uint64_t unit,
+                         uint64_t *first_page, uint64_t *n_pages) {
   uint64_t pages = 0;
+  if (!unit_ok(unit)) return KCO_EINVAL;
   if (n > 0 && ranges == NULL) return KCO_EINVAL;
   if (first_page) first_page[0] = 0;
   for (uint32_t a = 0; a < n; ++a) {
@@ -125,11 +131,16 @@ int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
       uint64_t prev_end = ranges[a - 1].base + ranges[a - 1].size;
       if (base < prev_end) return KCO_EORDER;
     }
-    pages += (size + PAGE - 1) / PAGE;
+    pages += (size + unit - 1) / unit;
     if (first_page) first_page[a + 1] = pages;
   }
   if (n_pages) *n_pages = pages;
   return KCO_OK;
+}
+
+int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
+                    uint64_t *n_pages) {
+  return kco_range_check_unit(ranges, n, PAGE, first_page, n_pages);
 }
 
 int kco_default_window(const kco_range *ranges, uint32_t n, uint64_t *lo,
@@ -161,23 +172,23 @@ static int page_is_zero(const uint8_t *page, uint64_t len) {
   return 1;
 }
 
-/* Pages of a range and the bytes of its page p (the last may be partial). */
-static uint64_t range_pages(const kco_range *r) { return (r->size + PAGE - 1) / PAGE; }
+/* Units of a range and the bytes of its unit p (the last may be partial). */
+static uint64_t range_pages(const kco_range *r, uint64_t unit) { return (r->size + unit - 1) / unit; }
 
-static uint64_t page_len(const kco_range *r, uint64_t p) {
-  uint64_t rest = r->size - p * PAGE;
-  return rest < PAGE ? rest : PAGE;
+static uint64_t page_len(const kco_range *r, uint64_t p, uint64_t unit) {
+  uint64_t rest = r->size - p * unit;
+  return rest < unit ? rest : unit;
 }
 
 /* ------------------------------------------------------------------------ */
 /* Snapshot: page hash + zero + changed                                      */
 /* ------------------------------------------------------------------------ */
 
-int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
-                  uint32_t n, uint64_t seed, const uint64_t *prior,
-                  uint64_t *hash, uint64_t *zero_bm, uint64_t *changed_bm) {
+int kco_page_hash_unit(const kco_range *ranges, const uint8_t *const *host_ptr,
+                       uint32_t n, uint64_t unit, uint64_t seed, const uint64_t *prior,
+                       uint64_t *hash, uint64_t *zero_bm, uint64_t *changed_bm) {
   uint64_t n_pages = 0;
-  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  int st = kco_range_check_unit(ranges, n, unit, NULL, &n_pages);
   if (st != KCO_OK) return st;
   if (n_pages > 0 && (hash == NULL || zero_bm == NULL)) return KCO_EINVAL;
   if (prior != NULL && changed_bm == NULL) return KCO_EINVAL;
@@ -188,10 +199,10 @@ int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
   }
   uint64_t g = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    uint64_t pages = range_pages(&ranges[a]);
+    uint64_t pages = range_pages(&ranges[a], unit);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
-      const uint8_t *page = host_ptr[a] + p * PAGE;
-      uint64_t len = page_len(&ranges[a], p);
+      const uint8_t *page = host_ptr[a] + p * unit;
+      uint64_t len = page_len(&ranges[a], p, unit);
       hash[g] = kco_xxh64(page, len, seed);
       if (page_is_zero(page, len)) bit_set(zero_bm, g);
       if (prior && hash[g] != prior[g]) bit_set(changed_bm, g);
@@ -200,37 +211,51 @@ int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
   return KCO_OK;
 }
 
+int kco_page_hash(const kco_range *ranges, const uint8_t *const *host_ptr,
+                  uint32_t n, uint64_t seed, const uint64_t *prior,
+                  uint64_t *hash, uint64_t *zero_bm, uint64_t *changed_bm) {
+  return kco_page_hash_unit(ranges, host_ptr, n, PAGE, seed, prior, hash, zero_bm, changed_bm);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Snapshot: compaction of the kept pages, ascending g                       */
 /* ------------------------------------------------------------------------ */
 
-int kco_compact(const kco_range *ranges, const uint8_t *const *host_ptr,
-                uint32_t n, const uint64_t *zero_bm, const uint64_t *changed_bm,
-                uint8_t *packed, uint64_t *page_va, uint64_t cap_pages,
-                uint64_t *n_kept) {
+int kco_compact_unit(const kco_range *ranges, const uint8_t *const *host_ptr,
+                     uint32_t n, uint64_t unit, const uint64_t *zero_bm,
+                     const uint64_t *changed_bm, uint8_t *packed, uint64_t *page_va,
+                     uint64_t cap_pages, uint64_t *n_kept) {
   uint64_t n_pages = 0;
-  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  int st = kco_range_check_unit(ranges, n, unit, NULL, &n_pages);
   if (st != KCO_OK) return st;
   if (n_kept == NULL || (n_pages > 0 && zero_bm == NULL)) return KCO_EINVAL;
   if (cap_pages > 0 && (packed == NULL || page_va == NULL)) return KCO_EINVAL;
   uint64_t g = 0, slot = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    uint64_t pages = range_pages(&ranges[a]);
+    uint64_t pages = range_pages(&ranges[a], unit);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
       int keep = !bit_get(zero_bm, g);
       if (changed_bm != NULL) keep = keep && bit_get(changed_bm, g);
       if (!keep) continue;
-      if (slot < cap_pages) { /* a partial page is followed by zeros in its slot */
-        uint64_t len = page_len(&ranges[a], p);
-        memcpy(packed + slot * PAGE, host_ptr[a] + p * PAGE, len);
-        memset(packed + slot * PAGE + len, 0, PAGE - len);
-        page_va[slot] = ranges[a].base + p * PAGE;
+      if (slot < cap_pages) { /* a partial unit is followed by zeros in its slot */
+        uint64_t len = page_len(&ranges[a], p, unit);
+        memcpy(packed + slot * unit, host_ptr[a] + p * unit, len);
+        memset(packed + slot * unit + len, 0, unit - len);
+        page_va[slot] = ranges[a].base + p * unit;
       }
       ++slot;
     }
   }
   *n_kept = slot;
   return KCO_OK;
+}
+
+int kco_compact(const kco_range *ranges, const uint8_t *const *host_ptr,
+                uint32_t n, const uint64_t *zero_bm, const uint64_t *changed_bm,
+                uint8_t *packed, uint64_t *page_va, uint64_t cap_pages,
+                uint64_t *n_kept) {
+  return kco_compact_unit(ranges, host_ptr, n, PAGE, zero_bm, changed_bm, packed, page_va,
+                          cap_pages, n_kept);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -252,12 +277,12 @@ static int64_t find_range(const kco_range *ranges, uint32_t n, uint64_t va) {
   return -1;
 }
 
-int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
-                const uint64_t *zero_bm, const uint64_t *changed_bm,
-                const uint8_t *packed, const uint64_t *page_va,
-                uint64_t n_kept, uint64_t cap_pages, uint64_t *n_bad) {
+int kco_restore_unit(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
+                     uint64_t unit, const uint64_t *zero_bm, const uint64_t *changed_bm,
+                     const uint8_t *packed, const uint64_t *page_va,
+                     uint64_t n_kept, uint64_t cap_pages, uint64_t *n_bad) {
   uint64_t n_pages = 0;
-  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  int st = kco_range_check_unit(ranges, n, unit, NULL, &n_pages);
   if (st != KCO_OK) return st;
   if (n_pages > 0 && zero_bm == NULL) return KCO_EINVAL;
   uint64_t n_copy = n_kept < cap_pages ? n_kept : cap_pages;
@@ -265,27 +290,36 @@ int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
   /* 1. zero-fill the selected zero pages */
   uint64_t g = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    uint64_t pages = range_pages(&ranges[a]);
+    uint64_t pages = range_pages(&ranges[a], unit);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
       int selected = changed_bm == NULL || bit_get(changed_bm, g);
       if (selected && bit_get(zero_bm, g))
-        memset(host_ptr[a] + p * PAGE, 0, page_len(&ranges[a], p));
+        memset(host_ptr[a] + p * unit, 0, page_len(&ranges[a], p, unit));
     }
   }
-  /* 2. scatter every packed page back to the VA the page table names */
+  /* 2. scatter every packed unit back to the VA the page table names: the
+   * start of a unit of some range */
   uint64_t bad = 0;
   for (uint64_t s = 0; s < n_copy; ++s) {
     uint64_t va = page_va[s];
-    int64_t a = (va % PAGE == 0) ? find_range(ranges, n, va) : -1;
-    if (a < 0) {
+    int64_t a = find_range(ranges, n, va);
+    if (a < 0 || (va - ranges[a].base) % unit != 0) {
       ++bad;
       continue;
     }
-    uint64_t p = (va - ranges[a].base) / PAGE; /* only the page's own bytes are written */
-    memcpy(host_ptr[a] + p * PAGE, packed + s * PAGE, page_len(&ranges[a], p));
+    uint64_t p = (va - ranges[a].base) / unit; /* only the unit's own bytes are written */
+    memcpy(host_ptr[a] + p * unit, packed + s * unit, page_len(&ranges[a], p, unit));
   }
   if (n_bad) *n_bad = bad;
   return KCO_OK;
+}
+
+int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
+                const uint64_t *zero_bm, const uint64_t *changed_bm,
+                const uint8_t *packed, const uint64_t *page_va,
+                uint64_t n_kept, uint64_t cap_pages, uint64_t *n_bad) {
+  return kco_restore_unit(ranges, host_ptr, n, PAGE, zero_bm, changed_bm, packed, page_va,
+                          n_kept, cap_pages, n_bad);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -319,6 +353,40 @@ int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
         }
         res->n_oob += 1;
       }
+    }
+  }
+  res->n_written = (uint32_t)(res->n_oob < oob_cap ? res->n_oob : oob_cap);
+  res->truncated = res->n_oob > oob_cap ? 1u : 0u;
+  return KCO_OK;
+}
+
+int kco_closure_scan_range(const kco_range *ranges, uint32_t n, uint32_t a,
+                           const uint8_t *host, uint64_t win_lo, uint64_t win_hi,
+                           kco_scan_result *res, kco_oob *oob, uint64_t oob_cap) {
+  uint64_t n_pages = 0;
+  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  if (st != KCO_OK) return st;
+  if (a >= n || host == NULL || res == NULL || (oob_cap > 0 && oob == NULL))
+    return KCO_EINVAL;
+  if (win_lo == 0 && win_hi == 0)
+    kco_default_window(ranges, n, &win_lo, &win_hi);
+  else if (win_lo == 0 || win_lo >= win_hi)
+    return KCO_EINVAL;
+  memset(res, 0, sizeof(*res));
+  /* the words of range a only, each tested against every range */
+  for (uint64_t off = 0; off + 8 <= ranges[a].size; off += 8) {
+    uint64_t w = read_u64_le(host + off);
+    res->n_words += 1;
+    if (w < win_lo || w >= win_hi) continue;
+    res->n_ptr_like += 1;
+    if (find_range(ranges, n, w) >= 0) {
+      res->n_in_range += 1;
+    } else {
+      if (res->n_oob < oob_cap) {
+        oob[res->n_oob].word_va = ranges[a].base + off;
+        oob[res->n_oob].value = w;
+      }
+      res->n_oob += 1;
     }
   }
   res->n_written = (uint32_t)(res->n_oob < oob_cap ? res->n_oob : oob_cap);
@@ -591,44 +659,41 @@ int kco_graph_reach(const kco_range *ranges, uint32_t n, const uint64_t *edge_bm
 /* Per-range byte difference against a full snapshot                         */
 /* ------------------------------------------------------------------------ */
 
-int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
-                    uint32_t n, const uint64_t *gold_zero_bm,
-                    const uint8_t *gold_packed, const uint64_t *gold_page_va,
-                    uint64_t gold_n_kept, uint64_t cap_pages,
-                    kco_region_diff_result *res) {
+int kco_region_diff_unit(const kco_range *ranges, const uint8_t *const *host_ptr,
+                         uint32_t n, uint64_t unit, const uint64_t *gold_zero_bm,
+                         const uint8_t *gold_packed, const uint64_t *gold_page_va,
+                         uint64_t gold_n_kept, uint64_t cap_pages,
+                         kco_region_diff_result *res) {
   uint64_t n_pages = 0;
-  int st = kco_range_check(ranges, n, NULL, &n_pages);
+  int st = kco_range_check_unit(ranges, n, unit, NULL, &n_pages);
   if (st != KCO_OK) return st;
   if (n > 0 && res == NULL) return KCO_EINVAL;
   if (n_pages > 0 && gold_zero_bm == NULL) return KCO_EINVAL;
   uint64_t n_valid = gold_n_kept < cap_pages ? gold_n_kept : cap_pages;
   if (n_valid > 0 && (gold_packed == NULL || gold_page_va == NULL)) return KCO_EINVAL;
-  static const uint8_t zeros[PAGE];
-  uint64_t g = 0, slot = 0; /* slot = non-zero pages seen so far */
+  uint64_t g = 0, slot = 0; /* slot = non-zero units seen so far */
   for (uint32_t a = 0; a < n; ++a) {
     res[a].n_diff_bytes = 0;
     res[a].n_diff_pages = 0;
     res[a].first_diff_va = UINT64_MAX;
     res[a].n_bad_pages = 0;
-    uint64_t pages = range_pages(&ranges[a]);
+    uint64_t pages = range_pages(&ranges[a], unit);
     for (uint64_t p = 0; p < pages; ++p, ++g) {
-      uint64_t va = ranges[a].base + p * PAGE;
-      uint64_t len = page_len(&ranges[a], p);
-      const uint8_t *gold;
-      if (bit_get(gold_zero_bm, g)) {
-        gold = zeros;
-      } else {
+      uint64_t va = ranges[a].base + p * unit;
+      uint64_t len = page_len(&ranges[a], p, unit);
+      const uint8_t *gold = NULL; /* NULL: the golden unit is all zeros */
+      if (!bit_get(gold_zero_bm, g)) {
         uint64_t s = slot++;
         if (s >= n_valid || gold_page_va[s] != va) {
           res[a].n_bad_pages += 1;
           continue;
         }
-        gold = gold_packed + s * PAGE;
+        gold = gold_packed + s * unit;
       }
-      const uint8_t *live = host_ptr[a] + p * PAGE;
+      const uint8_t *live = host_ptr[a] + p * unit;
       uint64_t d = 0;
       for (uint64_t b = 0; b < len; ++b) {
-        if (live[b] == gold[b]) continue;
+        if (live[b] == (gold ? gold[b] : 0)) continue;
         if (res[a].first_diff_va == UINT64_MAX) res[a].first_diff_va = va + b;
         ++d;
       }
@@ -637,4 +702,13 @@ int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
     }
   }
   return KCO_OK;
+}
+
+int kco_region_diff(const kco_range *ranges, const uint8_t *const *host_ptr,
+                    uint32_t n, const uint64_t *gold_zero_bm,
+                    const uint8_t *gold_packed, const uint64_t *gold_page_va,
+                    uint64_t gold_n_kept, uint64_t cap_pages,
+                    kco_region_diff_result *res) {
+  return kco_region_diff_unit(ranges, host_ptr, n, PAGE, gold_zero_bm, gold_packed, gold_page_va,
+                              gold_n_kept, cap_pages, res);
 }

@@ -106,6 +106,35 @@ uint64_t kco_xxh64(const void *data, uint64_t len, uint64_t seed);
 int kco_range_check(const kco_range *ranges, uint32_t n, uint64_t *first_page,
                     uint64_t *n_pages);
 
+/* Hash units larger than the 4 KiB page (paper Sec. 4.2.1: whole-allocation
+ * capture of large tensors, where a table entry per 4 KiB is more than a
+ * snapshot needs).  The *_unit entry points below take the unit in bytes, a
+ * power of two from 4096 to 2 MiB (else KCO_EINVAL), and mean by "page" one
+ * unit: a range spans ceil(size / unit) units, unit p of range a starts at
+ * base_a + p * unit (the base stays a multiple of 4096 only), its last unit
+ * holds size mod unit bytes when that is not zero, packed slots are unit
+ * bytes apart, and a restore accepts a page-table VA only if it is the start
+ * of a unit of some range.  The entry points without the suffix are these
+ * with unit = 4096. */
+int kco_range_check_unit(const kco_range *ranges, uint32_t n, uint64_t unit,
+                         uint64_t *first_page, uint64_t *n_pages);
+int kco_page_hash_unit(const kco_range *ranges, const uint8_t *const *host_ptr,
+                       uint32_t n, uint64_t unit, uint64_t seed, const uint64_t *prior,
+                       uint64_t *hash, uint64_t *zero_bm, uint64_t *changed_bm);
+int kco_compact_unit(const kco_range *ranges, const uint8_t *const *host_ptr,
+                     uint32_t n, uint64_t unit, const uint64_t *zero_bm,
+                     const uint64_t *changed_bm, uint8_t *packed, uint64_t *page_va,
+                     uint64_t cap_pages, uint64_t *n_kept);
+int kco_restore_unit(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
+                     uint64_t unit, const uint64_t *zero_bm, const uint64_t *changed_bm,
+                     const uint8_t *packed, const uint64_t *page_va,
+                     uint64_t n_kept, uint64_t cap_pages, uint64_t *n_bad);
+int kco_region_diff_unit(const kco_range *ranges, const uint8_t *const *host_ptr,
+                         uint32_t n, uint64_t unit, const uint64_t *gold_zero_bm,
+                         const uint8_t *gold_packed, const uint64_t *gold_page_va,
+                         uint64_t gold_n_kept, uint64_t cap_pages,
+                         kco_region_diff_result *res);
+
 /* Pointer window used by the closure scan when the caller passes (0, 0). */
 int kco_default_window(const kco_range *ranges, uint32_t n, uint64_t *lo,
                        uint64_t *hi);
@@ -136,6 +165,16 @@ int kco_restore(const kco_range *ranges, uint8_t *const *host_ptr, uint32_t n,
 int kco_closure_scan(const kco_range *ranges, const uint8_t *const *host_ptr,
                      uint32_t n, uint64_t win_lo, uint64_t win_hi,
                      kco_scan_result *res, kco_oob *oob, uint64_t oob_cap);
+
+/* The closure scan of one range's words (range a, bytes at host), each word
+ * tested against the whole range table with the same rules as
+ * kco_closure_scan.  Summed over a = 0 .. n-1 the counts equal
+ * kco_closure_scan's, and the lists, concatenated in range order, its list:
+ * the form a scan of a pool too large for host memory takes, one range at a
+ * time. */
+int kco_closure_scan_range(const kco_range *ranges, uint32_t n, uint32_t a,
+                           const uint8_t *host, uint64_t win_lo, uint64_t win_hi,
+                           kco_scan_result *res, kco_oob *oob, uint64_t oob_cap);
 
 /* Per-range byte difference between the live bytes of the ranges and a full
  * snapshot of the same ranges (byte-exact comparison reported per region,

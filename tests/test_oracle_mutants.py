@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_xxh64.py", "tests/test_oracle_snapshot.py", "tests/test_oracle_compare.py",
              "tests/test_oracle_graph.py", "tests/test_oracle_region.py", "tests/test_oracle_ragged.py",
-             "tests/test_golden.py"]
+             "tests/test_oracle_units.py", "tests/test_golden.py"]
 
 MUTANTS = {
     "round uses P1": ("acc = acc + lane * PRIME2;", "acc = acc + lane * PRIME1;"),
@@ -22,19 +22,30 @@ MUTANTS = {
     "tail lane constant": ("acc = rotate_left(acc, 27) * PRIME1 + PRIME4;", "acc = rotate_left(acc, 27) * PRIME1 + PRIME3;"),
     "avalanche shift": ("acc ^= acc >> 29;", "acc ^= acc >> 28;"),
     "zero test skips last byte": ("for (uint64_t i = 0; i < len; ++i)", "for (uint64_t i = 0; i + 1 < len; ++i)"),
-    "partial page hashed whole": ("hash[g] = kco_xxh64(page, len, seed);", "hash[g] = kco_xxh64(page, PAGE, seed);"),
-    "partial slot not padded": ("memset(packed + slot * PAGE + len, 0, PAGE - len);", ""),
-    "restore writes whole page": ("memcpy(host_ptr[a] + p * PAGE, packed + s * PAGE, page_len(&ranges[a], p));",
-                                  "memcpy(host_ptr[a] + p * PAGE, packed + s * PAGE, PAGE);"),
+    "partial page hashed whole": ("hash[g] = kco_xxh64(page, len, seed);", "hash[g] = kco_xxh64(page, unit, seed);"),
+    "partial slot not padded": ("memset(packed + slot * unit + len, 0, unit - len);", ""),
+    "restore writes whole page": ("memcpy(host_ptr[a] + p * unit, packed + s * unit, page_len(&ranges[a], p, unit));",
+                                  "memcpy(host_ptr[a] + p * unit, packed + s * unit, unit);"),
+    "units counted as pages": ("pages += (size + unit - 1) / unit;", "pages += (size + PAGE - 1) / PAGE;"),
+    "unit stride taken as the page": ("const uint8_t *page = host_ptr[a] + p * unit;",
+                                      "const uint8_t *page = host_ptr[a] + p * PAGE;"),
+    "restore accepts a VA inside a unit": ("if (a < 0 || (va - ranges[a].base) % unit != 0) {", "if (a < 0) {"),
+    "range scan skips its first word": ("for (uint64_t off = 0; off + 8 <= ranges[a].size; off += 8) {\n"
+                                        "    uint64_t w = read_u64_le(host + off);",
+                                        "for (uint64_t off = 8; off + 8 <= ranges[a].size; off += 8) {\n"
+                                        "    uint64_t w = read_u64_le(host + off);"),
     "scan reads a straddling word": ("for (uint64_t off = 0; off + 8 <= ranges[a].size; off += 8) { /* words wholly inside */\n"
                                      "      uint64_t w = read_u64_le(host_ptr[a] + off);\n      res->n_words += 1;",
                                      "for (uint64_t off = 0; off < ranges[a].size; off += 8) { /* words wholly inside */\n"
                                      "      uint64_t w = read_u64_le(host_ptr[a] + off);\n      res->n_words += 1;"),
     "changed inverted": ("if (prior && hash[g] != prior[g])", "if (prior && hash[g] == prior[g])"),
-    "page VA off by one page": ("page_va[slot] = ranges[a].base + p * PAGE;", "page_va[slot] = ranges[a].base + (p + 1) * PAGE;"),
+    "page VA off by one page": ("page_va[slot] = ranges[a].base + p * unit;", "page_va[slot] = ranges[a].base + (p + 1) * unit;"),
     "delta keep uses or": ("if (changed_bm != NULL) keep = keep && bit_get(changed_bm, g);",
                            "if (changed_bm != NULL) keep = keep || bit_get(changed_bm, g);"),
-    "window upper edge inclusive": ("if (w < win_lo || w >= win_hi) continue;", "if (w < win_lo || w > win_hi) continue;"),
+    "window upper edge inclusive": ("      if (w < win_lo || w >= win_hi) continue;",
+                                    "      if (w < win_lo || w > win_hi) continue;"),
+    "range scan window lower edge exclusive": ("    if (w < win_lo || w >= win_hi) continue;\n    res->n_ptr_like",
+                                               "    if (w <= win_lo || w >= win_hi) continue;\n    res->n_ptr_like"),
     "range end inclusive": ("if (va - ranges[lo].base < ranges[lo].size) return (int64_t)lo;",
                             "if (va - ranges[lo].base <= ranges[lo].size) return (int64_t)lo;"),
     "adjacent ranges rejected": ("if (base < prev_end) return KCO_EORDER;", "if (base <= prev_end) return KCO_EORDER;"),
@@ -70,7 +81,9 @@ MUTANTS = {
     "reach follows edges backwards": ("if (bit_get(edge_bm + (uint64_t)a * rw, b) && !bit_get(reach_bm, b)) {",
                                       "if (bit_get(edge_bm + (uint64_t)b * rw, a) && !bit_get(reach_bm, b)) {"),
     "roots not expanded": ("queue[tail++] = (uint32_t)r;", "(void)0;"),
-    "zero pages take a snapshot slot": ("        gold = zeros;\n", "        gold = zeros;\n        ++slot;\n"),
+    "zero pages take a snapshot slot": ("      const uint8_t *gold = NULL; /* NULL: the golden unit is all zeros */\n",
+                                        "      const uint8_t *gold = NULL; /* NULL: the golden unit is all zeros */\n"
+                                        "      if (bit_get(gold_zero_bm, g)) ++slot;\n"),
     "diff pages counted per byte": ("if (d > 0) res[a].n_diff_pages += 1;", "res[a].n_diff_pages += d;"),
     "page VA not checked": ("if (s >= n_valid || gold_page_va[s] != va) {", "if (s >= n_valid) {"),
 }

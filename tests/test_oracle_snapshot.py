@@ -217,6 +217,54 @@ def test_closure_scan_brute_force_tiny(oracle_lib):
     assert (res["n_ptr_like"], res["n_in_range"], res["n_oob"]) == (n_ptr, n_in, len(exp_oob))
     assert oob == exp_oob
     assert res["n_words"] == 4 * 512
+    # the per-range scan over the same edge words: the pieces add up to the linear scan
+    parts = [oracle_lib.closure_scan_range(rngs, a, views[a], lo, hi, oob_cap=64) for a in range(len(rngs))]
+    assert sum(r["n_ptr_like"] for r, _ in parts) == n_ptr and sum(r["n_in_range"] for r, _ in parts) == n_in
+    assert [e for _, o in parts for e in o] == exp_oob
+
+
+def test_closure_scan_range_pieces_make_the_whole(oracle_lib):
+    """The per-range scan: each range's words against the numpy searchsorted
+    formulation over the whole table (the range alone as the word source), and
+    over all ranges the counts sum to, and the lists concatenate into, the
+    whole-set scan, with and without truncation and under explicit windows."""
+    for scale, win in ((1 / 8, (0, 0)), (1 / 32, (0, 0)), (1 / 32, None)):
+        case, host, views = _case(scale=scale)
+        rngs = case.ranges()
+        if win is None:  # a window that cuts through the ranges
+            win = (rngs[3][0] + 4096, rngs[-5][0] + 12345)
+        lo, hi = win if win != (0, 0) else oracle_lib.default_window(rngs)
+        whole, whole_oob = oracle_lib.closure_scan(rngs, views, win[0], win[1], oob_cap=10**6)
+        tot = dict(n_words=0, n_ptr_like=0, n_in_range=0, n_oob=0)
+        cat = []
+        for a in range(len(rngs)):
+            res, oob = oracle_lib.closure_scan_range(rngs, a, views[a], win[0], win[1], oob_cap=10**6)
+            want, want_oob = _numpy_closure_of_range(rngs, a, views[a], lo, hi)
+            assert {k: res[k] for k in want} == want and oob == want_oob, a
+            for k in tot:
+                tot[k] += res[k]
+            cat += oob
+            short, short_oob = oracle_lib.closure_scan_range(rngs, a, views[a], win[0], win[1], oob_cap=1)
+            assert short["n_oob"] == res["n_oob"] and short_oob == oob[:1]
+            assert short["truncated"] == (1 if res["n_oob"] > 1 else 0)
+        assert all(whole[k] == v for k, v in tot.items()) and cat == whole_oob
+        assert whole["n_oob"] >= (3 if win == (0, 0) else 1)
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.closure_scan_range(rngs, len(rngs), views[0])
+
+
+def _numpy_closure_of_range(ranges, a, view, lo, hi):
+    bases = np.array([b for b, _ in ranges], dtype=np.uint64)
+    ends = np.array([b + s for b, s in ranges], dtype=np.uint64)
+    w = np.ascontiguousarray(view[: ranges[a][1] // 8 * 8]).view("<u8")
+    ptr = (w >= np.uint64(lo)) & (w < np.uint64(hi))
+    idx = np.searchsorted(bases, w, side="right").astype(np.int64) - 1
+    inr = np.zeros(len(w), dtype=bool)
+    ok = idx >= 0
+    inr[ok] = w[ok] < ends[idx[ok]]
+    bad = np.nonzero(ptr & ~inr)[0]
+    counts = dict(n_words=len(w), n_ptr_like=int(ptr.sum()), n_in_range=int((ptr & inr).sum()), n_oob=len(bad))
+    return counts, [(ranges[a][0] + 8 * int(i), int(w[i])) for i in bad]
 
 
 def test_empty_rangeset(oracle_lib):
