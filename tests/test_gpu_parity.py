@@ -432,32 +432,6 @@ def test_compare_c3_scaled(kc, ctx):
         c2.close()
 
 
-def test_compare_c3_full_in_bench_shapes(kc):
-    """10,000 pairs, 8 GiB a side, in the shape the benchmark's batched compare
-    runs: every pair against the generator's record of what it perturbed, and
-    a sample of small and large pairs against the oracle."""
-    c, shapes = _tuned_context(kc, "c3-10000-pairs", (kc.OP_COMPARE,))
-    say(f"compare c3 full size (10,000 pairs, 8 GiB a side), shape {shapes or 'built-in'}")
-    ps = W.c3_pairs("cuda")
-    pairs = [(ps.cand(i), ps.gold(i), int(ps.dtypes[i]), int(ps.tols[i]), 1e-8, 1e-5) for i in range(len(ps))]
-    res = kc.compare(c, pairs)
-    torch.cuda.synchronize()
-    got = kc.decode_cmp(res, len(pairs))
-    for i, r in enumerate(got):
-        assert r["n_elems"] == ps.n_elems(i)
-        assert r["n_mismatch_elems"] == len(ps.pos[i])
-        assert r["n_over_tol"] == int((np.abs(ps.k[i]) > ps.tols[i]).sum())
-    say("compare c3 full size: sampled pairs vs oracle")
-    order = np.argsort(ps.nbytes)
-    sample = np.unique(np.concatenate([order[:10], order[-6:], np.random.default_rng(33).choice(len(ps), 14)]))
-    for i in sample:
-        cnd, gld, dt, tol, atol, rtol = pairs[int(i)]
-        o = oracle.compare(cnd.cpu().view(torch.uint8).numpy(), gld.cpu().view(torch.uint8).numpy(), dt, tol, atol,
-                           rtol)
-        assert got[int(i)] == o, int(i)
-    c.close()
-
-
 def test_compare_errors(kc, ctx):
     say("compare argument errors")
     a = torch.zeros(64, dtype=torch.uint8, device="cuda")
@@ -469,118 +443,3 @@ def test_compare_errors(kc, ctx):
     with pytest.raises(kc.KCError) as ei:
         kc.compare(ctx, (arr, n))
     assert ei.value.code == kc.EDTYPE
-
-
-# --------------------------------------------------- c4 at full size (30 GiB) --
-
-def test_c4_full_sampled(kc):
-    # the shapes the benchmark times, when tabled
-    ctx, shapes = _tuned_context(kc, "c4-moe-pool-scale1.0", (kc.OP_SNAPSHOT, kc.OP_RESTORE, kc.OP_COMPARE))
-    say(f"c4 full: launch shapes {shapes or 'built-in'}; generate 30 GiB MoE pool on device")
-    case = W.c4_snapshot("cuda")
-    ranges = case.ranges()
-    rs = kc.RangeSet(ctx, ranges)
-    N = rs.n_pages
-    say("c4 full: fused snapshot + closure scan")
-    scan = kc.ScanOut("cuda", oob_cap=16)
-    out = kc.snapshot(ctx, rs, seed=0, scan=scan)
-    torch.cuda.synchronize()
-    n_kept = int(u64(out["n_kept"])[0])
-    assert N == 7864320 and n_kept == N - 209715 == 7654605
-    res, oob = scan.result()
-    assert res["n_words"] == N * 512 and res["n_oob"] == 0 and res["n_in_range"] >= 65536
-    say("c4 full: sampled pages vs oracle (hash, zero bit, packed bytes, page VA)")
-    rng = np.random.default_rng(44)
-    fp = np.concatenate([[0], np.cumsum(case.layout.sizes // PAGE)])
-    sample = np.unique(np.concatenate([rng.choice(N, 3000, replace=False), case.truth["zero_pages"][:50],
-                                       np.arange(fp[192], fp[193])]))
-    a_idx = np.searchsorted(fp, sample, side="right") - 1
-    page_va = np.array([ranges[a][0] for a in a_idx], dtype=np.uint64) + (sample - fp[a_idx]).astype(np.uint64) * PAGE
-    hv = u64(out["hash"])
-    zb = u64(out["zero_bm"])
-    vas = u64(out["page_va"])
-    buf = case.arena.buf
-    for g, a, va in zip(sample, a_idx, page_va):
-        off = int(case.layout.offsets[a]) + (int(g) - int(fp[a])) * PAGE
-        page = buf[off: off + PAGE].cpu().numpy()
-        assert int(hv[g]) == oracle.xxh64(page, 0)
-        assert bool((zb[g // 64] >> np.uint64(g % 64)) & np.uint64(1)) == (not page.any())
-    # packed slots: the slot of page g is g minus the zero pages before it
-    zero_sorted = case.truth["zero_pages"]
-    for g, a, va in list(zip(sample, a_idx, page_va))[::7]:
-        if np.isin(g, zero_sorted):
-            continue
-        slot = int(g) - int(np.searchsorted(zero_sorted, g))
-        assert int(vas[slot]) == int(va)
-        off = int(case.layout.offsets[a]) + (int(g) - int(fp[a])) * PAGE
-        assert torch.equal(out["packed"][slot * PAGE:(slot + 1) * PAGE], buf[off: off + PAGE])
-    say("c4 full: closure scan of a sub-set (table + 8 experts + workspace) vs oracle")
-    sub_idx = list(range(0, 8)) + [192, 193]
-    sub = [ranges[i] for i in sub_idx]
-    rs_sub = kc.RangeSet(ctx, sub)
-    scan_sub = kc.ScanOut("cuda", oob_cap=64)
-    kc.closure_scan(ctx, rs_sub, scan_sub)
-    torch.cuda.synchronize()
-    sub_views = [case.arena.view(i).cpu().numpy() for i in sub_idx]
-    check_scan(kc, scan_sub, sub, sub_views)
-    del sub_views
-    say("c4 full: injected out-of-range pointer is reported")
-    tab = case.arena.view(192).view(torch.int64)
-    slot = 12345
-    saved = int(tab[slot].item())
-    max_end = ranges[-1][0] + ranges[-1][1]
-    tab[slot] = max_end
-    scan2 = kc.ScanOut("cuda", oob_cap=16)
-    kc.closure_scan(ctx, rs, scan2)
-    torch.cuda.synchronize()
-    r2, o2 = scan2.result()
-    assert r2["n_oob"] == 1 and o2 == [(ranges[192][0] + 8 * slot, max_end)]
-    tab[slot] = saved
-    say("c4 full: clobber, restore, re-hash")
-    ref_hash = out["hash"].clone()
-    for i in (0, 100, 192, 193, 199):
-        case.arena.view(i).fill_(0xA5)
-    n_bad = torch.zeros(1, dtype=torch.int64, device="cuda")
-    kc.restore(ctx, rs, out["zero_bm"], None, out["packed"], out["page_va"], out["n_kept"], n_bad=n_bad)
-    h2, _, _ = kc.page_hash(ctx, rs)
-    torch.cuda.synchronize()
-    assert int(n_bad.item()) == 0
-    assert torch.equal(h2[:N], ref_hash[:N])
-    del out, h2, ref_hash
-    say("c4 full: compare of all 200 ranges with a golden copy; differences planted in four, vs oracle")
-    golden = case.arena.buf.clone()
-    kinds = [W.DT_BF16] * 192 + [W.DT_U8, W.DT_F32] + [W.DT_F16] * 6
-    planted = {5: (W.DT_BF16, 2, 0.0, 0.0), 192: (W.DT_U8, 0, 0.0, 0.0), 193: (W.DT_F32, 1, 1e-6, 1e-3),
-               197: (W.DT_F16, 4, 0.0, 1e-2)}
-    gen = torch.Generator(device="cuda").manual_seed(45)
-    for i, (dt, _, _, _) in planted.items():
-        es = W.ELEM_SIZE[dt]
-        bits = case.arena.view(i).view(BITS_VIEW[es])
-        n = bits.numel()
-        idx = torch.randint(0, n, (4000,), device="cuda", generator=gen)
-        step = torch.randint(1, 6, (4000,), device="cuda", generator=gen).to(bits.dtype)
-        bits[idx[:3000]] += step[:3000]                               # a few ULPs (or byte values) away
-        bits[idx[3000:]] ^= (step[3000:] << (8 * es - 4)).to(bits.dtype)  # high bits: signs, NaNs, infs
-        if dt != W.DT_U8:
-            bits[idx[:2]] = SPECIALS[dt][0]                           # NaN in the candidate only
-    pairs = []
-    for i in range(len(ranges)):
-        o, sz = int(case.layout.offsets[i]), int(case.layout.sizes[i])
-        dt, tol, atol, rtol = planted.get(i, (kinds[i], 0, 0.0, 0.0))
-        pairs.append((case.arena.buf[o:o + sz], golden[o:o + sz], dt, tol, atol, rtol))
-    ps = kc.PairSet(ctx, pairs)
-    res = kc.compare_pairset(ctx, ps)
-    torch.cuda.synchronize()
-    got = kc.decode_cmp(res, len(pairs))
-    for i, r in enumerate(got):
-        if i in planted:
-            c, g, dt, tol, atol, rtol = pairs[i]
-            o = oracle.compare(c.cpu().numpy(), g.cpu().numpy(), dt, tol, atol, rtol)
-            assert r == o, i
-            assert r["n_mismatch_elems"] > 0 and r["pass"] == 0
-        else:
-            assert r["n_mismatch_bytes"] == 0 and r["pass"] == 1 and r["n_elems"] == pairs[i][0].numel() // \
-                W.ELEM_SIZE[pairs[i][2]], i
-    ps.close()
-    rs.close()
-    ctx.close()
