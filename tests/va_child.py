@@ -8,8 +8,10 @@ pointer graph.
 
 ``replay DIR``: in a fresh process, map device memory at exactly the saved
 VAs before anything else allocates (exit 3 if a range cannot be placed there),
-load the snapshot, restore it, and check the restored state byte for byte and
-by its hashes, closure scan and pointer graph.  Prints one JSON line."""
+load the snapshot, restore it, read the restored bytes back, and snapshot,
+scan and graph the restored state again.  Everything the replay computed is
+written to DIR (``replay.npz``, ``replay.json``), so the test can hold it
+against the oracle run on the generator's raw bytes.  Prints one JSON line."""
 import json
 import os
 import sys
@@ -21,6 +23,19 @@ def raw_view(torch, base, size):
     class Mem:   # a device address range as a torch tensor, without copying
         __cuda_array_interface__ = {"shape": (size,), "typestr": "|u1", "data": (base, False), "version": 2}
     return torch.as_tensor(Mem(), device="cuda")
+
+
+def read_device(base, size):
+    """Host copy of ``size`` bytes at device address ``base`` through the HIP
+    runtime's own synchronous copy (no torch wrapping of a foreign pointer)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.empty(size, dtype=np.uint8)
+    rc = hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(base), size, 2)   # 2 = device to host
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed with {rc}")
+    return out
 
 
 def capture(d):
@@ -99,24 +114,24 @@ def replay(d):
     torch.cuda.synchronize()
     res, oob = scan.result()
     raw = np.fromfile(os.path.join(d, "raw.bin"), dtype=np.uint8)
-    try:
-        live = np.concatenate([raw_view(torch, b, s).cpu().numpy() for b, s in ranges])
-        bytes_equal = bool(np.array_equal(live, raw))
-    except (TypeError, RuntimeError, ValueError) as e:   # no foreign-pointer import in this torch
-        print(json.dumps({"bytes_check_unavailable": str(e)}), flush=True)
-        bytes_equal = None
+    live = np.concatenate([read_device(b, s) for b, s in ranges])
+    n_kept = int(again["n_kept"].item())
+    u64 = lambda t: t.detach().cpu().numpy().view(np.uint64)
+    np.savez(os.path.join(d, "replay.npz"), live=live, hash=u64(again["hash"])[: rs.n_pages],
+             zero_bm=u64(again["zero_bm"])[: rs.n_words], page_va=u64(again["page_va"])[:n_kept],
+             packed=again["packed"][: n_kept * 4096].cpu().numpy(), n_kept=np.array([n_kept], dtype=np.uint64),
+             edges=edge.reshape(-1))
+    with open(os.path.join(d, "replay.json"), "w") as f:
+        json.dump({"scan": res, "oob": [list(x) for x in oob]}, f)
     checks = {
-        "bytes_equal": bytes_equal,
+        "bytes_equal": bool(np.array_equal(live, raw)),
         "no_region_diff": all(r["n_diff_bytes"] == 0 and r["n_bad_pages"] == 0 for r in diff),
-        "hash_equal": bool(torch.equal(again["hash"], gold["hash"])),
-        "scan_equal": res == info["scan"] and [list(x) for x in oob] == info["oob"],
-        "graph_equal": [int(x) for x in edge.reshape(-1)] == info["edges"],
     }
     rs.close()
     ctx.close()
     vs.close()
     print(json.dumps({"spans": vs.n_spans, "mapped_bytes": vs.mapped_bytes, **checks}), flush=True)
-    return 0 if all(v is not False for v in checks.values()) else 1
+    return 0 if all(checks.values()) else 1
 
 
 if __name__ == "__main__":
