@@ -478,8 +478,13 @@ int kc_snapshot_save(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
  * ranges must equal the range set's (same VAs and sizes: the restore is
  * VA-faithful), else KC_EINVAL.  hash_d may be NULL (not loaded); a delta
  * snapshot needs changed_bm_d; more packed pages than cap_pages is
- * KC_ELIMIT.  Host-to-device copies are chunked and double-buffered like the
- * save.  Synchronous. */
+ * KC_ELIMIT.  A header whose kept count exceeds its page count, or whose
+ * packed count exceeds its kept count, is KC_EINVAL.  A snapshot saved
+ * truncated (cap_pages below its kept count at save time, so fewer packed
+ * pages than kept pages) is refused with KC_ELIMIT: a restore from it would
+ * leave the missing pages unwritten.  On success *n_kept_d equals the number
+ * of packed pages loaded.  Host-to-device copies are chunked and
+ * double-buffered like the save.  Synchronous. */
 int kc_snapshot_load(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
                      uint64_t *hash_d, uint64_t *zero_bm_d,
                      uint64_t *changed_bm_d, void *packed_d,

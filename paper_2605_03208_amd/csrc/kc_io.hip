@@ -324,7 +324,18 @@ int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
     set_error_text("snapshot ranges differ from the range set");
     return KC_EINVAL;
   }
-  if (h.n_packed > cap_pages) return KC_ELIMIT;
+  if (h.n_kept > h.n_pages || h.n_packed > h.n_kept) {
+    set_error_text("inconsistent snapshot header: kept or packed page count out of range");
+    return KC_EINVAL;
+  }
+  if (h.n_packed < h.n_kept) {  // saved with a capacity below its kept count: pages would stay unrestored
+    set_error_text("the snapshot was saved truncated (fewer packed pages than kept pages)");
+    return KC_ELIMIT;
+  }
+  if (h.n_packed > cap_pages) {
+    set_error_text("more packed pages than cap_pages");
+    return KC_ELIMIT;
+  }
   if (h.n_packed > 0 && (packed_d == nullptr || page_va_d == nullptr)) return KC_EINVAL;
   if (h.delta && changed_bm_d == nullptr) return KC_EINVAL;
   Pinned pin;

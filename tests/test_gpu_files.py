@@ -2,6 +2,7 @@
 byte for byte; kc_snapshot_load + kc_restore brings the original bytes back
 at the same VAs (full and delta snapshots)."""
 import json
+import struct
 import os
 import sys
 
@@ -112,6 +113,29 @@ def test_delta_files_and_errors(kc, tmp_path):
     assert ei.value.code == kc.ELIMIT
     with pytest.raises(kc.KCError) as ei:
         kc.snapshot_load(ctx, rs, d2)          # delta needs a changed bitmap buffer
+    assert ei.value.code == kc.EINVAL
+    say("snapshot files: a snapshot saved below its kept count is refused on load")
+    d3 = str(tmp_path / "truncated")
+    nk1 = int(s1["n_kept"].item())
+    kc.snapshot_save(ctx, rs, d3, s1, seed=2, cap_pages=nk1 // 2)
+    man = json.load(open(os.path.join(d3, "manifest.json")))
+    assert man["n_kept"] == nk1 and man["n_packed"] == nk1 // 2
+    assert np.array_equal(_file(d3, "page_va.bin", "<u8"), _file(d1, "page_va.bin", "<u8")[: nk1 // 2])
+    with pytest.raises(kc.KCError) as ei:
+        kc.snapshot_load(ctx, rs, d3)
+    assert ei.value.code == kc.ELIMIT
+    say("snapshot files: a header whose packed count exceeds its kept count is refused")
+    hdr = bytearray(open(os.path.join(d1, "header.bin"), "rb").read())
+    d4 = str(tmp_path / "bad_header")
+    os.makedirs(d4)
+    for name in os.listdir(d1):
+        with open(os.path.join(d1, name), "rb") as fi, open(os.path.join(d4, name), "wb") as fo:
+            fo.write(fi.read())
+    fields = list(struct.unpack("<8s2I5Q2I", bytes(hdr[:64])))   # magic, version, page size, seed, ranges,
+    fields[7] = fields[6] + 1                                    # pages, kept, packed, delta: packed = kept + 1
+    open(os.path.join(d4, "header.bin"), "wb").write(struct.pack("<8s2I5Q2I", *fields))
+    with pytest.raises(kc.KCError) as ei:
+        kc.snapshot_load(ctx, rs, d4)
     assert ei.value.code == kc.EINVAL
     other.close()
     rs.close()
