@@ -187,6 +187,14 @@ def test_serving_alone_equals_mix_and_oracle(kc):
     srv = serve.Server(ex, budget, max_batch=5)
     mix = {d.rid: d for d in srv.run(reqs)}
     assert len(mix) == len(reqs) and srv.budget.peak <= budget
+    # the mix really mixed: some batch held several requests, and some batch
+    # was launched while an earlier one was still in flight
+    batches = {}
+    for d in mix.values():
+        batches.setdefault(d.launch_s, []).append(d)
+    assert max(len(v) for v in batches.values()) >= 2
+    spans = sorted((k, max(x.done_s for x in v)) for k, v in batches.items())
+    assert any(spans[i + 1][0] < max(e for _, e in spans[: i + 1]) for i in range(len(spans) - 1))
     for r in reqs:
         alone = serve.Server(ex, budget).run([serve.Request(r.rid, 0.0, r.golden_ids, r.ulp_tol, r.seed)])
         assert alone[0].results == mix[r.rid].results, r.rid
