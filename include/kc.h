@@ -283,7 +283,7 @@ int kc_compact(kc_ctx *ctx, const kc_rangeset *rs, const uint64_t *zero_bm_d,
 
 /* kc_page_hash followed by kc_compact with identical outputs.  Without a
  * prior (full snapshot) the data is read once: a probe of each page's first
- * 64 bytes (the whole page only when those are zero) fixes the zero bitmap
+ * 16 bytes (the whole page only when those are zero) fixes the zero bitmap
  * and the slots, then one pass hashes, scans and writes the packed pages.
  * With a prior (delta snapshot) the kept set depends on the hashes, so the
  * changed pages are read a second time. */

@@ -193,7 +193,7 @@ constexpr uint32_t kAccWords = 64;  // per-pair accumulator words
 // accumulator word map
 enum : uint32_t {
   kAccMisElems = 0, kAccMisBytes, kAccNanBoth, kAccNanCand, kAccNanGold, kAccOverTol,
-  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccNotClose, kAccHist = 16  // 45 bins: 16..60
+  kAccMaxAbs, kAccMaxRel, kAccFirstInv, kAccNotClose, kAccHist = 16  // 48 bins: words 16..63
 };
 
 // ---- launchers (kc_kernels.hip) ------------------------------------------

@@ -398,15 +398,11 @@ def region_diff(ctx: Context, rs: RangeSet, gold: dict, seed: int = 0, cap_pages
     return out
 
 
-def decode_region_diff(res: torch.Tensor, n: int, sizes=None) -> list[dict]:
-    """Per-range dicts; with the range sizes, also the differing-byte percentage
-    of each range (the per-region report of the byte-exact comparison)."""
+def decode_region_diff(res: torch.Tensor, n: int) -> list[dict]:
+    """Per-range dicts of the kc_region_diff_result fields, as the library
+    wrote them (a host copy; no field is derived here)."""
     raw = res[:n * 4].cpu().numpy().view(np.uint64).reshape(n, 4)
-    out = [{k: int(v) for k, v in zip(REGION_DIFF_FIELDS, row)} for row in raw]
-    if sizes is not None:
-        for d, size in zip(out, sizes):
-            d["diff_pct"] = 100.0 * d["n_diff_bytes"] / int(size)
-    return out
+    return [{k: int(v) for k, v in zip(REGION_DIFF_FIELDS, row)} for row in raw]
 
 
 def pointer_graph(ctx: Context, rs: RangeSet, win_lo: int = 0, win_hi: int = 0,
