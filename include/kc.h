@@ -72,6 +72,7 @@ extern "C" {
 #define KC_PAGE_SIZE 4096u
 #define KC_ABI_VERSION 5
 #define KC_GRAPH_MAX_RANGES 16384u /* kc_pointer_graph: at most 32 MiB of edges */
+#define KC_NOALLOC_MAX_PAIRS 4096u /* kc_compare_noalloc: pairs per call (2 MiB of static scratch) */
 
 /* Status codes. */
 enum {
@@ -416,6 +417,25 @@ void kc_pairset_destroy(kc_pairset *ps);
  * to kc_compare on the same pairs.  One stream at a time per set. */
 int kc_compare_pairset(kc_ctx *ctx, const kc_pairset *ps, kc_cmp_result *res_d,
                        void *stream);
+
+/* For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  kc_compare with the same
+ * arguments, checks, error codes and reports (bit-identical), but nothing is
+ * allocated, on the device or on the host: the pair records travel in the
+ * kernel arguments (48 pairs per launch) and the per-pair accumulators live
+ * in a static device array of KC_NOALLOC_MAX_PAIRS x 512 bytes (2 MiB), one
+ * copy per device, bound when the first context is created on that device and
+ * held until the process ends.  More than KC_NOALLOC_MAX_PAIRS pairs:
+ * KC_ELIMIT, nothing launched.  Every call on a device shares that device's
+ * array, so calls that overlap on one device (two streams, or two threads)
+ * race and their reports are undefined: serialize them.  Each call first
+ * clears the accumulators it uses with a fill kernel (no memset node), so
+ * whatever an earlier or failed call left there does not matter.  Launch
+ * shape from the context's compare tuning (grid and tile size; per_item does
+ * not apply).  Asynchronous on `stream`: res_d[0 .. n_pairs) is written by
+ * the last kernels of the call. */
+int kc_compare_noalloc(kc_ctx *ctx, const kc_pair *pairs, uint32_t n_pairs,
+                       kc_cmp_result *res_d, void *stream);
 
 /* ---- candidate materialisation for the validation server (a request names
  *      a golden buffer, a tolerance and a seed; the candidate is the golden

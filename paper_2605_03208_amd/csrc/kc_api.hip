@@ -57,10 +57,16 @@ void default_window(const kc_range* r, uint32_t n, uint64_t* lo, uint64_t* hi) {
   *hi = max_end <= UINT64_MAX - margin ? max_end + margin : UINT64_MAX;
 }
 
+}  // namespace
+
+namespace kc {
 uint32_t grid_for(const kc_ctx* c, uint32_t op, uint32_t fallback_per_cu) {
   const uint32_t per = c->tune[op].grid_per_cu ? c->tune[op].grid_per_cu : fallback_per_cu;
   return std::max(1u, c->n_cu * per);
 }
+}  // namespace kc
+
+namespace {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -164,6 +170,12 @@ int kc_ctx_create(kc_ctx** out, int hip_device) {
     set_error("hipEventCreateWithFlags", e);
     delete c;
     return KC_EHIP;
+  }
+  const int bound = noalloc_bind(hip_device);  // device address of the static compare scratch, once per device
+  if (bound != KC_OK) {
+    (void)hipEventDestroy(c->staged);
+    delete c;
+    return bound;
   }
   *out = c;
   return KC_OK;
@@ -654,7 +666,7 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
 }  // extern "C"
 
 
-namespace {
+namespace kc {
 
 uint32_t elem_size(uint32_t dtype) {
   switch (dtype) {
@@ -664,6 +676,23 @@ uint32_t elem_size(uint32_t dtype) {
     default: return 1u;
   }
 }
+
+// Tuned tile size, else 64 KiB halved (down to 16 KiB) while the pairs would
+// give fewer than eight tiles per compute unit: small batches still spread
+// over the whole chip.
+uint32_t compare_tile_bytes(const kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs) {
+  if (c->tune[KC_OP_COMPARE].tile_bytes) return c->tune[KC_OP_COMPARE].tile_bytes;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < n_pairs; ++i)
+    if (pairs[i].dtype <= KC_I64 && pairs[i].n_elems <= (1ull << 60)) total += pairs[i].n_elems * elem_size(pairs[i].dtype);
+  uint32_t tb = 64u << 10;
+  while (tb > (16u << 10) && total / tb < 8ull * c->n_cu) tb >>= 1;
+  return tb;
+}
+
+}  // namespace kc
+
+namespace {
 
 // Validate a pair list and count its tiles.
 int plan_pairs(const kc_pair* pairs, uint32_t n_pairs, uint32_t tile_bytes, std::vector<uint64_t>& tile_off) {
@@ -733,19 +762,6 @@ int run_compare(kc_ctx* c, const CmpPairDev* dpairs, const CmpTileDev* dtiles, c
   KC_HIP(launch_compare_finalize(dpairs, n_pairs, dacc, res_d, s));
   *acc_dirty = false;
   return KC_OK;
-}
-
-// Tuned tile size, else 64 KiB halved (down to 16 KiB) while the pairs would
-// give fewer than eight tiles per compute unit: small batches still spread
-// over the whole chip.
-uint32_t compare_tile_bytes(const kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs) {
-  if (c->tune[KC_OP_COMPARE].tile_bytes) return c->tune[KC_OP_COMPARE].tile_bytes;
-  uint64_t total = 0;
-  for (uint32_t i = 0; i < n_pairs; ++i)
-    if (pairs[i].dtype <= KC_I64 && pairs[i].n_elems <= (1ull << 60)) total += pairs[i].n_elems * elem_size(pairs[i].dtype);
-  uint32_t tb = 64u << 10;
-  while (tb > (16u << 10) && total / tb < 8ull * c->n_cu) tb >>= 1;
-  return tb;
 }
 
 }  // namespace

@@ -311,92 +311,111 @@ __device__ __forceinline__ uint64_t wave_reduce_max_u64(uint64_t x) {
   return x;
 }
 
+// One tile of one pair: the workgroup streams its bytes, then flushes what it
+// found into the pair's accumulators (nothing when every element was equal).
+// hist (48 bins) is zero on entry and left zero; red is a 4 x 10 exchange area.
+__device__ __forceinline__ void compare_tile(const CmpPairDev& pr, uint64_t tile_idx, uint32_t tile_bytes,
+                                             unsigned long long* acc, uint32_t* hist, uint64_t (*red)[10]) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  Partial p{0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, ~0ull};
+  const uint64_t nbytes = pr.n_elems * pr.esize;
+  const uint64_t b0 = tile_idx * tile_bytes;
+  const uint64_t b1 = b0 + tile_bytes < nbytes ? b0 + tile_bytes : nbytes;
+  if (b0 < b1) {
+    switch (pr.dtype) {
+      case KC_F32: tile_body<KC_F32>(pr, b0, b1, p, hist); break;
+      case KC_BF16: tile_body<KC_BF16>(pr, b0, b1, p, hist); break;
+      case KC_F16: tile_body<KC_F16>(pr, b0, b1, p, hist); break;
+      case KC_FP8_E4M3FN: tile_body<KC_FP8_E4M3FN>(pr, b0, b1, p, hist); break;
+      case KC_F64: tile_body<KC_F64>(pr, b0, b1, p, hist); break;
+      case KC_FP8_E4M3FNUZ: tile_body<KC_FP8_E4M3FNUZ>(pr, b0, b1, p, hist); break;
+      case KC_FP8_E5M2: tile_body<KC_FP8_E5M2>(pr, b0, b1, p, hist); break;
+      case KC_FP8_E5M2FNUZ: tile_body<KC_FP8_E5M2FNUZ>(pr, b0, b1, p, hist); break;
+      case KC_I8: tile_body<KC_I8>(pr, b0, b1, p, hist); break;
+      case KC_I16: tile_body<KC_I16>(pr, b0, b1, p, hist); break;
+      case KC_I32: tile_body<KC_I32>(pr, b0, b1, p, hist); break;
+      case KC_I64: tile_body<KC_I64>(pr, b0, b1, p, hist); break;
+      default: tile_body<KC_U8>(pr, b0, b1, p, hist); break;
+    }
+  }
+  // Every non-equal element bumps mis_elems or a NaN class, so a tile with
+  // all of these zero contributed nothing but equal elements.
+  const bool any = (p.mis_elems | p.nan_both | p.nan_c | p.nan_g) != 0u;
+  if (!__syncthreads_or(any)) return;
+  const uint64_t v0 = wave_reduce_sum<uint32_t>(p.mis_elems);
+  const uint64_t v1 = wave_reduce_sum<uint32_t>(p.mis_bytes);
+  const uint64_t v2 = wave_reduce_sum<uint32_t>(p.nan_both);
+  const uint64_t v3 = wave_reduce_sum<uint32_t>(p.nan_c);
+  const uint64_t v4 = wave_reduce_sum<uint32_t>(p.nan_g);
+  const uint64_t v5 = wave_reduce_sum<uint32_t>(p.over);
+  const uint64_t v6 = wave_reduce_max_u64(dbl_bits(p.max_abs));
+  const uint64_t v7 = wave_reduce_max_u64(dbl_bits(p.max_rel));
+  const uint64_t v8 = wave_reduce_max_u64(~p.first);
+  const uint64_t v9 = wave_reduce_sum<uint32_t>(p.not_close);
+  if (lane == 0) {
+    red[wave][0] = v0; red[wave][1] = v1; red[wave][2] = v2; red[wave][3] = v3; red[wave][4] = v4;
+    red[wave][5] = v5; red[wave][6] = v6; red[wave][7] = v7; red[wave][8] = v8; red[wave][9] = v9;
+  }
+  __syncthreads();
+  if (tid < 10) {  // thread i folds slot i over the four waves and flushes it
+    const uint32_t i = tid;
+    const bool is_sum = i < 6 || i == 9;
+    uint64_t x = red[0][i];
+#pragma unroll
+    for (uint32_t w = 1; w < 4; ++w) {
+      const uint64_t y = red[w][i];
+      x = is_sum ? x + y : (y > x ? y : x);
+    }
+    if (x) {
+      if (i < 6) atomicAdd(&acc[kAccMisElems + i], (unsigned long long)x);
+      else if (i == 9) atomicAdd(&acc[kAccNotClose], (unsigned long long)x);
+      else atomicMax(&acc[kAccMaxAbs + (i - 6)], (unsigned long long)x);
+    }
+  }
+  if (tid < kBins) {
+    const uint32_t h = hist[tid];
+    if (h) {
+      atomicAdd(&acc[kAccHist + tid], (unsigned long long)h);
+      hist[tid] = 0u;
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_compare(const CmpPairDev* pairs, const CmpTileDev* tiles,
                                                  uint32_t n_tiles, uint32_t tile_bytes,
                                                  unsigned long long* acc_all) {
   __shared__ uint32_t hist[48];
   __shared__ uint64_t red[4][10];
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-  if (tid < 48) hist[tid] = 0u;  // stays zero between tiles: flushed bins are reset
+  if (threadIdx.x < 48) hist[threadIdx.x] = 0u;  // stays zero between tiles: flushed bins are reset
   __syncthreads();
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const CmpTileDev tl = tiles[t];
-    const CmpPairDev pr = pairs[tl.pair];
-    Partial p{0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, ~0ull};
-    const uint64_t nbytes = pr.n_elems * pr.esize;
-    const uint64_t b0 = (uint64_t)tl.idx * tile_bytes;
-    const uint64_t b1 = b0 + tile_bytes < nbytes ? b0 + tile_bytes : nbytes;
-    if (b0 < b1) {
-      switch (pr.dtype) {
-        case KC_F32: tile_body<KC_F32>(pr, b0, b1, p, hist); break;
-        case KC_BF16: tile_body<KC_BF16>(pr, b0, b1, p, hist); break;
-        case KC_F16: tile_body<KC_F16>(pr, b0, b1, p, hist); break;
-        case KC_FP8_E4M3FN: tile_body<KC_FP8_E4M3FN>(pr, b0, b1, p, hist); break;
-        case KC_F64: tile_body<KC_F64>(pr, b0, b1, p, hist); break;
-        case KC_FP8_E4M3FNUZ: tile_body<KC_FP8_E4M3FNUZ>(pr, b0, b1, p, hist); break;
-        case KC_FP8_E5M2: tile_body<KC_FP8_E5M2>(pr, b0, b1, p, hist); break;
-        case KC_FP8_E5M2FNUZ: tile_body<KC_FP8_E5M2FNUZ>(pr, b0, b1, p, hist); break;
-        case KC_I8: tile_body<KC_I8>(pr, b0, b1, p, hist); break;
-        case KC_I16: tile_body<KC_I16>(pr, b0, b1, p, hist); break;
-        case KC_I32: tile_body<KC_I32>(pr, b0, b1, p, hist); break;
-        case KC_I64: tile_body<KC_I64>(pr, b0, b1, p, hist); break;
-        default: tile_body<KC_U8>(pr, b0, b1, p, hist); break;
-      }
-    }
-    // Every non-equal element bumps mis_elems or a NaN class, so a tile with
-    // all of these zero contributed nothing but equal elements.
-    const bool any = (p.mis_elems | p.nan_both | p.nan_c | p.nan_g) != 0u;
-    if (!__syncthreads_or(any)) continue;
-    const uint64_t v0 = wave_reduce_sum<uint32_t>(p.mis_elems);
-    const uint64_t v1 = wave_reduce_sum<uint32_t>(p.mis_bytes);
-    const uint64_t v2 = wave_reduce_sum<uint32_t>(p.nan_both);
-    const uint64_t v3 = wave_reduce_sum<uint32_t>(p.nan_c);
-    const uint64_t v4 = wave_reduce_sum<uint32_t>(p.nan_g);
-    const uint64_t v5 = wave_reduce_sum<uint32_t>(p.over);
-    const uint64_t v6 = wave_reduce_max_u64(dbl_bits(p.max_abs));
-    const uint64_t v7 = wave_reduce_max_u64(dbl_bits(p.max_rel));
-    const uint64_t v8 = wave_reduce_max_u64(~p.first);
-    const uint64_t v9 = wave_reduce_sum<uint32_t>(p.not_close);
-    if (lane == 0) {
-      red[wave][0] = v0; red[wave][1] = v1; red[wave][2] = v2; red[wave][3] = v3; red[wave][4] = v4;
-      red[wave][5] = v5; red[wave][6] = v6; red[wave][7] = v7; red[wave][8] = v8; red[wave][9] = v9;
-    }
-    __syncthreads();
-    unsigned long long* acc = acc_all + (uint64_t)tl.pair * kAccWords;
-    if (tid < 10) {  // thread i folds slot i over the four waves and flushes it
-      const uint32_t i = tid;
-      const bool is_sum = i < 6 || i == 9;
-      uint64_t x = red[0][i];
-#pragma unroll
-      for (uint32_t w = 1; w < 4; ++w) {
-        const uint64_t y = red[w][i];
-        x = is_sum ? x + y : (y > x ? y : x);
-      }
-      if (x) {
-        if (i < 6) atomicAdd(&acc[kAccMisElems + i], (unsigned long long)x);
-        else if (i == 9) atomicAdd(&acc[kAccNotClose], (unsigned long long)x);
-        else atomicMax(&acc[kAccMaxAbs + (i - 6)], (unsigned long long)x);
-      }
-    }
-    if (tid < kBins) {
-      const uint32_t h = hist[tid];
-      if (h) {
-        atomicAdd(&acc[kAccHist + tid], (unsigned long long)h);
-        hist[tid] = 0u;
-      }
-    }
-    __syncthreads();
+    compare_tile(pairs[tl.pair], tl.idx, tile_bytes, acc_all + (uint64_t)tl.pair * kAccWords, hist, red);
   }
 }
 
-// One thread per pair turns the accumulators into the report and zeroes them.
-__global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs,
-                                                          unsigned long long* acc_all, kc_cmp_result* res) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pairs) return;
-  const CmpPairDev pr = pairs[i];
-  unsigned long long* acc = acc_all + (uint64_t)i * kAccWords;
-  kc_cmp_result* r = res + i;
+// The same pass over the pairs carried in the kernel arguments: tile t
+// belongs to the first pair whose inclusive tile prefix exceeds t.
+__global__ __launch_bounds__(256) void k_compare_args(CmpArgPairs a, uint32_t tile_bytes,
+                                                      unsigned long long* acc_all) {
+  __shared__ uint32_t hist[48];
+  __shared__ uint64_t red[4][10];
+  if (threadIdx.x < 48) hist[threadIdx.x] = 0u;
+  __syncthreads();
+  for (uint32_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    uint32_t lo = 0, hi = a.n - 1u;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (a.tile_end[mid] > t) hi = mid; else lo = mid + 1u;
+    }
+    const uint32_t start = lo == 0u ? 0u : a.tile_end[lo - 1u];
+    compare_tile(a.pair[lo], t - start, tile_bytes, acc_all + (uint64_t)lo * kAccWords, hist, red);
+  }
+}
+
+// One pair's report from its accumulators, which are zeroed again.
+__device__ __forceinline__ void finalize_pair(const CmpPairDev& pr, unsigned long long* acc, kc_cmp_result* r) {
   const uint64_t nb = acc[kAccNanBoth], ncand = acc[kAccNanCand], ngold = acc[kAccNanGold], over = acc[kAccOverTol];
   r->n_elems = pr.n_elems;
   r->n_mismatch_elems = acc[kAccMisElems];
@@ -430,6 +449,21 @@ __global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pair
   for (uint32_t w = 0; w < kAccWords; ++w) acc[w] = 0ull;  // ready for the next call
 }
 
+// One thread per pair turns the accumulators into the report and zeroes them.
+__global__ __launch_bounds__(256) void k_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs,
+                                                          unsigned long long* acc_all, kc_cmp_result* res) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pairs) return;
+  finalize_pair(pairs[i], acc_all + (uint64_t)i * kAccWords, res + i);
+}
+
+__global__ __launch_bounds__(64) void k_compare_args_finalize(CmpArgPairs a, unsigned long long* acc_all,
+                                                              kc_cmp_result* res) {
+  const uint32_t i = threadIdx.x;
+  if (i >= a.n) return;
+  finalize_pair(a.pair[i], acc_all + (uint64_t)i * kAccWords, res + i);
+}
+
 }  // namespace
 
 hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint32_t n_tiles,
@@ -444,6 +478,18 @@ hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, un
                                    kc_cmp_result* res, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_compare_finalize, dim3((n_pairs + 255) / 256), dim3(256), 0, s, pairs, n_pairs, acc, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_compare_args(const CmpArgPairs& a, uint32_t tile_bytes, unsigned long long* acc,
+                               kc_cmp_result* res, uint32_t grid, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  grid = grid < 1u ? 1u : (grid > a.n_tiles ? a.n_tiles : grid);
+  hipLaunchKernelGGL(k_compare_args, dim3(grid), dim3(kThreads), 0, s, a, tile_bytes, acc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  static_assert(kArgPairs <= 64, "one finalize thread per pair");
+  hipLaunchKernelGGL(k_compare_args_finalize, dim3(1), dim3(64), 0, s, a, acc, res);
   return hipGetLastError();
 }
 

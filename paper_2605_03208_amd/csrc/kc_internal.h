@@ -189,6 +189,18 @@ struct CmpTileDev {
   uint32_t pair, idx;
 };
 
+// Pairs carried in the kernel arguments of one compare launch (the variant
+// that allocates nothing): pair records and the inclusive prefix of their
+// tile counts, under the 4 KiB kernel-argument limit.
+constexpr uint32_t kArgPairs = 48;
+struct CmpArgPairs {
+  CmpPairDev pair[kArgPairs];
+  uint32_t tile_end[kArgPairs];
+  uint32_t n;        // pairs in this launch
+  uint32_t n_tiles;  // = tile_end[n - 1]
+};
+static_assert(sizeof(CmpArgPairs) <= 3072, "kernel arguments");
+
 constexpr uint32_t kAccWords = 64;  // per-pair accumulator words
 // accumulator word map
 enum : uint32_t {
@@ -235,6 +247,20 @@ hipError_t launch_compare(const CmpPairDev* pairs, const CmpTileDev* tiles, uint
                           uint32_t tile_bytes, unsigned long long* acc, uint32_t grid, hipStream_t s);
 hipError_t launch_compare_finalize(const CmpPairDev* pairs, uint32_t n_pairs, unsigned long long* acc,
                                    kc_cmp_result* res, hipStream_t s);
+// The pass and the reports of the pairs in `a` (accumulators acc[pair * kAccWords ...], zero on entry and
+// zeroed again; reports res[0 .. a.n)).
+hipError_t launch_compare_args(const CmpArgPairs& a, uint32_t tile_bytes, unsigned long long* acc,
+                               kc_cmp_result* res, uint32_t grid, hipStream_t s);
+
+// ---- shared host helpers (kc_api.hip) ----------------------------------------
+uint32_t grid_for(const kc_ctx* c, uint32_t op, uint32_t fallback_per_cu);  // persistent grid of an op
+uint32_t elem_size(uint32_t dtype);                                         // bytes of one element
+uint32_t compare_tile_bytes(const kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs);
+
+// ---- the compare that allocates nothing (kc_noalloc.hip) ---------------------
+// Looks up, once per device, the device address of the static scratch array
+// (the device must be current); KC_EHIP if the lookup fails.
+int noalloc_bind(int device);
 
 // ---- errors and device selection (kc_api.hip) ------------------------------
 void set_error_text(const char* text);

@@ -28,6 +28,7 @@ TORCH_TO_KC = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, tor
 ELEM_SIZE = {k: torch.empty(0, dtype=t).element_size() for t, k in TORCH_TO_KC.items()}
 OP_PAGE_HASH, OP_SNAPSHOT, OP_COMPACT, OP_RESTORE, OP_CLOSURE, OP_COMPARE, OP_GRAPH, OP_REGION_DIFF = range(8)
 GRAPH_MAX_RANGES = 16384
+NOALLOC_MAX_PAIRS = 4096
 
 SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "kc_default_window",
            "kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_tuning", "kc_ctx_get_tuning",
@@ -35,7 +36,8 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_rangeset_create", "kc_rangeset_destroy", "kc_page_hash", "kc_compact", "kc_snapshot",
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
            "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
-           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest", "kc_perturb"]
+           "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest", "kc_perturb",
+           "kc_compare_noalloc"]
 
 
 class KCError(RuntimeError):
@@ -135,6 +137,7 @@ def lib() -> ctypes.CDLL:
             "kc_pairset_create": ([vp, P(Pair), u32, P(vp)], i32),
             "kc_pairset_destroy": ([vp], None),
             "kc_compare_pairset": ([vp, vp, vp, vp], i32),
+            "kc_compare_noalloc": ([vp, P(Pair), u32, vp, vp], i32),
             "kc_snapshot_save": ([vp, vp, ctypes.c_char_p, u64, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)],
                                  i32),
             "kc_snapshot_load": ([vp, vp, ctypes.c_char_p, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)], i32),
@@ -469,6 +472,14 @@ def compare(ctx: Context, pairs, res: torch.Tensor | None = None, stream=None) -
     if res is None:
         res = torch.empty(max(1, n) * RESULT_BYTES, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
     _check(lib().kc_compare(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare")
+    return res
+
+
+def compare_noalloc(ctx: Context, pairs, res: torch.Tensor, stream=None) -> torch.Tensor:
+    """kc_compare_noalloc: the compare with nothing allocated by the library;
+    ``res`` (at least n * RESULT_BYTES bytes of device memory) is the caller's."""
+    arr, n = pairs if isinstance(pairs, tuple) else make_pairs(pairs)
+    _check(lib().kc_compare_noalloc(ctx.handle, arr, n, _ptr(res), _stream(stream)), "kc_compare_noalloc")
     return res
 
 
