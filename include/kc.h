@@ -258,6 +258,26 @@ int kc_ctx_kernel_ms(kc_ctx *ctx, uint32_t op, float *ms);
  * KC_ENOMEM, KC_EHIP.  *n_pages (if non-NULL) receives the page count. */
 int kc_rangeset_create(kc_ctx *ctx, const kc_range *ranges, uint32_t n,
                        kc_rangeset **out, uint64_t *n_pages);
+
+/* The same with a hash unit larger than the 4 KiB page, for whole-allocation
+ * capture of large tensors (Sec. 4.2.1: the snapshot covers whole tracked
+ * allocations; a table entry per 4 KiB is more than such tensors need).
+ * `unit` is a power of two from 4096 to 2 MiB (2097152), else KC_EINVAL.
+ * Every call on the set then means by "page" one unit: a range spans
+ * ceil(size / unit) units, unit p of range a starts at base_a + p * unit
+ * (bases stay 4096-aligned only), a range's last unit holds size mod unit
+ * bytes when that is not zero (hashed, zero-tested, packed and restored over
+ * those bytes only; its packed slot is padded with zeros), hash tables,
+ * bitmaps, page-VA tables and kept counts count units, packed slots are
+ * `unit` bytes apart, a restore accepts a page-VA entry only if it is the
+ * start of a unit of some range, snapshot files record the unit and load
+ * only into a set of the same unit.  The closure scan and the pointer graph
+ * are unchanged (they read every word); with a unit above 4096 a scan asked
+ * of kc_page_hash / kc_snapshot runs as its own pass over the ranges after
+ * the hashing pass (same results).  *n_units (if non-NULL) receives the unit
+ * count.  kc_rangeset_create is this call with unit = 4096. */
+int kc_rangeset_create_unit(kc_ctx *ctx, const kc_range *ranges, uint32_t n,
+                            uint64_t unit, kc_rangeset **out, uint64_t *n_units);
 void kc_rangeset_destroy(kc_rangeset *rs);
 
 /* ---- snapshot (Sec. 4.2.1: snapshot of all tracked memory) ------------- */

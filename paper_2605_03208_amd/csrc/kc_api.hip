@@ -110,9 +110,9 @@ int finish_scan(kc_rangeset* rs, const kc_scan_args* sa, const ScanDev& sd, hipS
   ScanSrc src{};
   src.kind = kSrcCounts;
   src.counts = rs->tile_oob;
-  src.n_items = rs->n_tiles;
+  src.n_items = rs->n_scan_tiles;
   KC_HIP(launch_scan(src, rs->tile_prefix, rs->block_sums, rs->n_oob, s));
-  KC_HIP(launch_oob_emit(rs->tiles, rs->n_tiles, sd, rs->tile_prefix, rs->n_oob, sa->oob_d, sa->oob_cap,
+  KC_HIP(launch_oob_emit(rs->scan_tiles, rs->n_scan_tiles, sd, rs->tile_prefix, rs->n_oob, sa->oob_d, sa->oob_cap,
                          sa->res_d, rs->n_scan_words, s));
   return KC_OK;
 }
@@ -237,8 +237,16 @@ int kc_ctx_get_tuning(const kc_ctx* c, uint32_t op, kc_tuning* t) {
 }
 
 int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangeset** out, uint64_t* n_pages_out) {
+  return kc_rangeset_create_unit(c, ranges, n, KC_PAGE_SIZE, out, n_pages_out);
+}
+
+int kc_rangeset_create_unit(kc_ctx* c, const kc_range* ranges, uint32_t n, uint64_t unit, kc_rangeset** out,
+                            uint64_t* n_units_out) {
   if (c == nullptr || out == nullptr) return KC_EINVAL;
   *out = nullptr;
+  uint32_t ushift = kMinUnitShift;
+  while (ushift < kMaxUnitShift && (1ull << ushift) < unit) ++ushift;
+  if ((1ull << ushift) != unit) return KC_EINVAL;  // a power of two from 4 KiB to 2 MiB
   uint64_t n_pages = 0;
   int st = range_check(ranges, n, &n_pages);
   if (st != KC_OK) return st;
@@ -249,52 +257,67 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->ctx = c;
   rs->device = c->device;
   rs->n_ranges = n;
-  rs->n_pages = n_pages;
-  rs->n_words = (n_pages + 63) / 64;
+  rs->ushift = ushift;
   rs->host_ranges.assign(ranges, ranges + n);
   default_window(ranges, n, &rs->win_lo, &rs->win_hi);
 
-  std::vector<Tile> tiles;
-  std::vector<uint64_t> bases(n), ends(n);
+  // Tiles of up to 16 units of one range; a range's last unit holds what is
+  // left of its size.  Returns the number of units.
+  auto build_tiles = [&](uint32_t shift, std::vector<Tile>& tiles, std::vector<uint32_t>& range_tile,
+                         std::vector<uint32_t>* ragged, std::vector<uint32_t>* ragged_of) {
+    const uint64_t u = 1ull << shift;
+    range_tile.assign(n + 1, 0);
+    if (ragged_of) ragged_of->assign(n, UINT32_MAX);
+    uint64_t g0 = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      range_tile[i] = (uint32_t)tiles.size();
+      const uint64_t units = (ranges[i].size + u - 1) / u;
+      const uint32_t tail = (uint32_t)(ranges[i].size - (units - 1) * u);  // bytes of the last unit
+      for (uint64_t p = 0; p < units; p += kTilePages) {
+        Tile t;
+        t.va = ranges[i].base + (p << shift);
+        t.g = (uint32_t)(g0 + p);
+        t.npages = (uint32_t)std::min<uint64_t>(kTilePages, units - p);
+        t.last_len = p + t.npages == units ? tail : (uint32_t)u;
+        tiles.push_back(t);
+      }
+      g0 += units;
+      if (ragged && tail != u) {  // the range's last tile holds a partial unit
+        (*ragged_of)[i] = (uint32_t)ragged->size();
+        ragged->push_back((uint32_t)tiles.size() - 1u);
+      }
+    }
+    range_tile[n] = (uint32_t)tiles.size();
+    return g0;
+  };
+  std::vector<Tile> tiles, scan_tiles;
   std::vector<uint32_t> ragged;
-  rs->range_tile.assign(n + 1, 0);
-  rs->ragged_of.assign(n, UINT32_MAX);
-  uint64_t g0 = 0;
+  const uint64_t n_units = build_tiles(ushift, tiles, rs->range_tile, &ragged, &rs->ragged_of);
+  if (ushift != kMinUnitShift) build_tiles(kMinUnitShift, scan_tiles, rs->scan_range_tile, nullptr, nullptr);
+  else rs->scan_range_tile = rs->range_tile;
+  std::vector<uint64_t> bases(n), ends(n);
   for (uint32_t i = 0; i < n; ++i) {
-    rs->range_tile[i] = (uint32_t)tiles.size();
-    const uint64_t pages = (ranges[i].size + KC_PAGE_SIZE - 1) / KC_PAGE_SIZE;
-    const uint32_t tail = (uint32_t)(ranges[i].size - (pages - 1) * KC_PAGE_SIZE);  // bytes of the last page
     rs->n_scan_words += ranges[i].size / 8;
-    for (uint64_t p = 0; p < pages; p += kTilePages) {
-      Tile t;
-      t.va = ranges[i].base + p * KC_PAGE_SIZE;
-      t.g = (uint32_t)(g0 + p);
-      t.npages = (uint16_t)std::min<uint64_t>(kTilePages, pages - p);
-      t.last_len = (uint16_t)(p + t.npages == pages ? tail : KC_PAGE_SIZE);
-      tiles.push_back(t);
-    }
-    g0 += pages;
-    if (tail != KC_PAGE_SIZE) {  // the range's last tile holds a partial page
-      rs->ragged_of[i] = (uint32_t)ragged.size();
-      ragged.push_back((uint32_t)tiles.size() - 1u);
-    }
     bases[i] = ranges[i].base;
     ends[i] = ranges[i].base + ranges[i].size;
   }
-  rs->range_tile[n] = (uint32_t)tiles.size();
+  rs->n_pages = n_units;
+  rs->n_words = (n_units + 63) / 64;
   rs->n_tiles = (uint32_t)tiles.size();
+  rs->n_scan_tiles = ushift != kMinUnitShift ? (uint32_t)scan_tiles.size() : rs->n_tiles;
 
-  const uint64_t nb_words = (rs->n_words + 2047) / 2048, nb_tiles = ((uint64_t)rs->n_tiles + 2047) / 2048;
+  const uint64_t nb_words = (rs->n_words + 2047) / 2048, nb_tiles = ((uint64_t)rs->n_scan_tiles + 2047) / 2048;
   const size_t sz_tiles = align_up(sizeof(Tile) * std::max<size_t>(1, tiles.size()), 256);
+  const size_t sz_st = align_up(sizeof(Tile) * scan_tiles.size(), 256);  // 4 KiB page tiles of the scans
   const size_t sz_r = align_up(8 * std::max<size_t>(1, n), 256);
-  const size_t sz_oob = align_up(4 * std::max<size_t>(1, rs->n_tiles), 256);
-  const size_t sz_tp = align_up(8 * std::max<size_t>(1, rs->n_tiles), 256);
+  const size_t sz_oob = align_up(4 * std::max<size_t>(1, rs->n_scan_tiles), 256);
+  const size_t sz_tp = align_up(8 * std::max<size_t>(1, rs->n_scan_tiles), 256);
   const size_t sz_wp = align_up(8 * std::max<uint64_t>(1, rs->n_words), 256);
   const size_t sz_bs = align_up(8 * std::max<uint64_t>(1, std::max(nb_words, nb_tiles)), 256);
   const size_t sz_misc = 256 + align_up(8 * kScanCountWords, 256);
   const size_t sz_bk = 2 * align_up(sizeof(uint16_t) * kBuckets, 256);  // bucket index of each fence table
   const size_t sz_rg = align_up(4 * std::max<size_t>(1, ragged.size()), 256);
-  const size_t total = sz_tiles + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
+  const size_t total = sz_tiles + sz_st + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
   hipError_t e = hipMalloc(&rs->dev, total);
   if (e != hipSuccess) {
     set_error("hipMalloc(rangeset)", e);
@@ -303,6 +326,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   }
   uint8_t* p = static_cast<uint8_t*>(rs->dev);
   rs->tiles = reinterpret_cast<Tile*>(p); p += sz_tiles;
+  rs->scan_tiles = ushift != kMinUnitShift ? reinterpret_cast<Tile*>(p) : rs->tiles; p += sz_st;
   rs->bases = reinterpret_cast<uint64_t*>(p); p += sz_r;
   rs->ends = reinterpret_cast<uint64_t*>(p); p += sz_r;
   rs->tile_oob = reinterpret_cast<uint32_t*>(p); p += sz_oob;
@@ -347,6 +371,9 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   if (!tiles.empty() && (e = hipMemcpy(rs->tiles, tiles.data(), sizeof(Tile) * tiles.size(),
                                        hipMemcpyHostToDevice)) != hipSuccess)
     return fail("hipMemcpy(tiles)", e);
+  if (!scan_tiles.empty() && (e = hipMemcpy(rs->scan_tiles, scan_tiles.data(), sizeof(Tile) * scan_tiles.size(),
+                                            hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("hipMemcpy(scan tiles)", e);
   if (n > 0) {
     if ((e = hipMemcpy(rs->bases, bases.data(), 8 * n, hipMemcpyHostToDevice)) != hipSuccess)
       return fail("hipMemcpy(bases)", e);
@@ -375,7 +402,7 @@ int kc_rangeset_create(kc_ctx* c, const kc_range* ranges, uint32_t n, kc_rangese
   rs->rt.stride_w = stride_w;
   rs->rt.n_fence_w = n_fence_w;
   *out = rs;
-  if (n_pages_out) *n_pages_out = n_pages;
+  if (n_units_out) *n_units_out = n_units;
   return KC_OK;
 }
 
@@ -386,13 +413,33 @@ void kc_rangeset_destroy(kc_rangeset* rs) {
   delete rs;
 }
 
+// The standalone closure scan over the 4 KiB page tiles (one launch, or one
+// per range); the caller has cleared the scan totals.
+static int run_closure(kc_rangeset* rs, const ScanDev& sd, hipStream_t s) {
+  kc_ctx* c = rs->ctx;
+  const uint32_t grid = grid_for(c, KC_OP_CLOSURE, 8);
+  KernelTimer timer(c, KC_OP_CLOSURE, s);
+  if (!c->tune[KC_OP_CLOSURE].per_item) {
+    KC_HIP(launch_closure(rs->scan_tiles, rs->n_scan_tiles, 0, sd, grid, c->n_cu, s));
+  } else {
+    for (uint32_t r = 0; r < rs->n_ranges; ++r) {
+      const uint32_t t0 = rs->scan_range_tile[r];
+      KC_HIP(launch_closure(rs->scan_tiles + t0, rs->scan_range_tile[r + 1] - t0, t0, sd, grid, c->n_cu, s));
+    }
+  }
+  return KC_OK;
+}
+
 // Launch the page-hash kernel over all tiles, or once per range.
 static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, bool scan, uint32_t op,
                     hipStream_t s) {
   kc_ctx* c = rs->ctx;
   KernelTimer timer(c, op, s);
   // read-only hashing runs best with twice the waves of the fused snapshot (which also writes and scans)
-  const uint32_t grid = grid_for(c, op, op == KC_OP_PAGE_HASH ? 8 : 4);
+  uint32_t grid = grid_for(c, op, op == KC_OP_PAGE_HASH ? 8 : 4);
+  // large units give few tiles, each a long serial chain: one wave per tile rather than two tiles on some waves
+  if (rs->ushift > kMinUnitShift) grid = std::max(grid, std::min(rs->n_tiles, 16u * c->n_cu));
+  hp.ushift = rs->ushift;
   if (!c->tune[op].per_item) {
     hp.tiles = rs->tiles;
     hp.n_tiles = rs->n_tiles;
@@ -437,8 +484,10 @@ int kc_page_hash(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_
   hp.zero_bm = zero_bm_d;
   hp.changed_bm = changed_bm_d;
   hp.scan = sd;
-  int st = run_hash(rs, hp, false, prior_hash_d != nullptr, scan != nullptr, KC_OP_PAGE_HASH, s);
+  const bool fused = scan != nullptr && rs->ushift == kMinUnitShift;  // the scan rides on 4 KiB page tiles
+  int st = run_hash(rs, hp, false, prior_hash_d != nullptr, fused, KC_OP_PAGE_HASH, s);
   if (st != KC_OK) return st;
+  if (scan && !fused && (st = run_closure(rs, sd, s)) != KC_OK) return st;
   if (scan) return finish_scan(rs, scan, sd, s);
   return KC_OK;
 }
@@ -463,12 +512,13 @@ int kc_compact(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   KernelTimer timer(c, KC_OP_COMPACT, s);
   if (!c->tune[KC_OP_COMPACT].per_item) {
     KC_HIP(launch_gather(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, rs->word_prefix,
-                         static_cast<uint8_t*>(packed_d), page_va_d, cap_pages, grid, s));
+                         static_cast<uint8_t*>(packed_d), page_va_d, cap_pages, rs->ushift, grid, s));
   } else {
     for (uint32_t r = 0; r < rs->n_ranges; ++r) {
       const uint32_t t0 = rs->range_tile[r];
       KC_HIP(launch_gather(rs->tiles + t0, rs->range_tile[r + 1] - t0, zero_bm_d, changed_bm_d,
-                           rs->word_prefix, static_cast<uint8_t*>(packed_d), page_va_d, cap_pages, grid, s));
+                           rs->word_prefix, static_cast<uint8_t*>(packed_d), page_va_d, cap_pages, rs->ushift,
+                           grid, s));
     }
   }
   return KC_OK;
@@ -496,7 +546,7 @@ int kc_snapshot(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t
   const hipStream_t s = as_stream(stream);
   KC_HIP(launch_zero3(zero_bm_d, rs->n_words, nullptr, 0, reinterpret_cast<uint64_t*>(rs->counts),
                       scan ? kScanCountWords : 0, s));
-  KC_HIP(launch_probe_zero(rs->tiles, rs->n_tiles, zero_bm_d, grid_for(c, KC_OP_SNAPSHOT, 8), s));
+  KC_HIP(launch_probe_zero(rs->tiles, rs->n_tiles, zero_bm_d, rs->ushift, grid_for(c, KC_OP_SNAPSHOT, 8), s));
   ScanSrc src{};
   src.kind = kSrcKeepBits;
   src.zero_bm = zero_bm_d;
@@ -512,8 +562,10 @@ int kc_snapshot(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint64_t
   hp.page_va = page_va_d;
   hp.cap_pages = cap_pages;
   hp.scan = sd;
-  const int st = run_hash(rs, hp, true, false, scan != nullptr, KC_OP_SNAPSHOT, s);
+  const bool fused = scan != nullptr && rs->ushift == kMinUnitShift;  // the scan rides on 4 KiB page tiles
+  int st = run_hash(rs, hp, true, false, fused, KC_OP_SNAPSHOT, s);
   if (st != KC_OK) return st;
+  if (scan && !fused && (st = run_closure(rs, sd, s)) != KC_OK) return st;
   if (scan) return finish_scan(rs, scan, sd, s);
   return KC_OK;
 }
@@ -530,10 +582,10 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   const hipStream_t s = as_stream(stream);
   unsigned long long* bad = n_bad_d ? reinterpret_cast<unsigned long long*>(n_bad_d) : rs->n_bad;
   const uint32_t grid = grid_for(c, KC_OP_RESTORE, 16);
-  KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, bad, grid, s));
+  KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, bad, rs->ushift, grid, s));
   KernelTimer timer(c, KC_OP_RESTORE, s);
   KC_HIP(launch_restore_scatter(rs->rt, static_cast<const uint8_t*>(packed_d), page_va_d, n_kept_d, cap_pages,
-                                bad, rs->n_ragged > 0, grid, s));
+                                bad, rs->n_ragged > 0, rs->ushift, grid, s));
   return KC_OK;
 }
 
@@ -570,7 +622,7 @@ int kc_region_diff(kc_ctx* c, const kc_rangeset* crs, uint64_t seed, const uint6
   KernelTimer timer(c, KC_OP_REGION_DIFF, s);
   KC_HIP(launch_region_diff(rs->tiles, rs->n_tiles, rs->rt, changed_bm_d, gold_zero_bm_d, rs->word_prefix,
                             gold_page_va_d, gold_n_kept_d, cap_pages, static_cast<const uint8_t*>(gold_packed_d),
-                            res_d, grid_for(c, KC_OP_REGION_DIFF, 8), s));
+                            res_d, rs->ushift, grid_for(c, KC_OP_REGION_DIFF, 8), s));
   return KC_OK;
 }
 
@@ -593,7 +645,7 @@ int kc_pointer_graph(kc_ctx* c, const kc_rangeset* rs, uint64_t win_lo, uint64_t
   const uint32_t row_words = (rs->n_ranges + 63u) / 64u;
   KC_HIP(launch_fill_u64(edge_bm_d, (uint64_t)rs->n_ranges * row_words, 0, s));
   KernelTimer timer(c, KC_OP_GRAPH, s);
-  KC_HIP(launch_pointer_graph(rs->tiles, rs->n_tiles, lo, hi - lo, rs->rt, edge_bm_d, row_words,
+  KC_HIP(launch_pointer_graph(rs->scan_tiles, rs->n_scan_tiles, lo, hi - lo, rs->rt, edge_bm_d, row_words,
                               grid_for(c, KC_OP_GRAPH, 8), c->n_cu, s));
   return KC_OK;
 }
@@ -648,18 +700,8 @@ int kc_closure_scan(kc_ctx* c, const kc_rangeset* crs, const kc_scan_args* scan,
   if (!g.ok) return KC_EHIP;
   const hipStream_t s = as_stream(stream);
   KC_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(rs->counts), kScanCountWords, 0, s));
-  const uint32_t grid = grid_for(c, KC_OP_CLOSURE, 8);
-  {
-    KernelTimer timer(c, KC_OP_CLOSURE, s);
-    if (!c->tune[KC_OP_CLOSURE].per_item) {
-      KC_HIP(launch_closure(rs->tiles, rs->n_tiles, 0, sd, grid, c->n_cu, s));
-    } else {
-      for (uint32_t r = 0; r < rs->n_ranges; ++r) {
-        const uint32_t t0 = rs->range_tile[r];
-        KC_HIP(launch_closure(rs->tiles + t0, rs->range_tile[r + 1] - t0, t0, sd, grid, c->n_cu, s));
-      }
-    }
-  }
+  const int rc = run_closure(rs, sd, s);
+  if (rc != KC_OK) return rc;
   return finish_scan(rs, scan, sd, s);
 }
 

@@ -103,9 +103,10 @@ __device__ __forceinline__ void flush_region(kc_region_diff_result* res, int32_t
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_region_diff(
     const Tile* tiles, uint32_t n_tiles, RangeTable rt, const uint64_t* changed_bm, const uint64_t* gold_zero_bm,
     const uint64_t* rank_prefix, const uint64_t* gold_page_va, const uint64_t* gold_n_kept, uint64_t cap,
-    const uint8_t* gold_packed, kc_region_diff_result* res) {
+    const uint8_t* gold_packed, kc_region_diff_result* res, uint32_t ushift) {
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x, sub = lane >> 4, j = lane & 15u;
+  const uint32_t unit = 1u << ushift;
   load_fences(fences, rt, lane, kWave);
   __syncthreads();
   const uint64_t kept = *gold_n_kept;
@@ -120,11 +121,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     Tile tile{0, 0, 0};
     if (t < n_tiles) tile = tiles[t];
     const bool live = j < tile.npages;
-    const uint64_t g = (uint64_t)tile.g + j, va = tile.va + (uint64_t)j * kPage;
+    const uint64_t g = (uint64_t)tile.g + j, va = tile.va + ((uint64_t)j << ushift);
     bool zero = false, bad = false, need = false;
     uint64_t gp = 0;
     int32_t a = -1;
-    const uint32_t len = live ? page_bytes(tile, j) : 0u;
+    const uint32_t len = live ? unit_bytes(tile, j, unit) : 0u;
     if (live) {
       a = range_index(va, fences, rt);
       const uint64_t zw = gold_zero_bm[g >> 6];
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (!zero) {
         const uint64_t slot = rank_prefix[g >> 6] + (uint64_t)__popcll(~zw & ((1ull << (g & 63u)) - 1ull));
         bad = slot >= n_valid || gold_page_va[slot] != va;
-        gp = (uint64_t)(gold_packed + slot * kPage);
+        gp = (uint64_t)gold_packed + (slot << ushift);
       }
       need = !bad && ((changed_bm[g >> 6] >> (g & 63u)) & 1ull);
     }
@@ -149,18 +150,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const uint64_t pgp = __shfl((unsigned long long)gp, L, 64);
       const int32_t pz = __shfl((int)zero, L, 64);
       const int32_t pa = __shfl(a, L, 64);
-      const uint32_t plen = __shfl(len, L, 64);  // bytes of the page (a range's last page may be partial)
+      const uint32_t plen = __shfl(len, L, 64);  // bytes of the unit (a range's last unit may be partial)
       uint32_t nd = 0, fo = ~0u;
+      for (uint32_t o0 = 0; o0 < plen; o0 += kPage) {  // 4 KiB of the unit per round, in address order
 #pragma unroll
-      for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t off = k * 1024u + lane * 16u;
-        const uint4 c = off < plen ? clip16(ld16nt(pva + off), off, plen) : make_uint4(0, 0, 0, 0);
-        const uint4 d = pz || off >= plen ? make_uint4(0, 0, 0, 0) : clip16(ld16nt(pgp + off), off, plen);
-        const uint32_t x[4] = {c.x ^ d.x, c.y ^ d.y, c.z ^ d.z, c.w ^ d.w};
+        for (uint32_t k = 0; k < 4; ++k) {
+          const uint32_t off = o0 + k * 1024u + lane * 16u;
+          const uint4 c = off < plen ? clip16(ld16nt(pva + off), off, plen) : make_uint4(0, 0, 0, 0);
+          const uint4 d = pz || off >= plen ? make_uint4(0, 0, 0, 0) : clip16(ld16nt(pgp + off), off, plen);
+          const uint32_t x[4] = {c.x ^ d.x, c.y ^ d.y, c.z ^ d.z, c.w ^ d.w};
 #pragma unroll
-        for (uint32_t i = 0; i < 4; ++i) {
-          nd += nonzero_bytes(x[i]);
-          if (x[i] != 0u && fo == ~0u) fo = off + 4u * i + ((uint32_t)__builtin_ctz(x[i]) >> 3);
+          for (uint32_t i = 0; i < 4; ++i) {
+            nd += nonzero_bytes(x[i]);
+            if (x[i] != 0u && fo == ~0u) fo = off + 4u * i + ((uint32_t)__builtin_ctz(x[i]) >> 3);
+          }
         }
       }
       nd = wave_sum_u32(nd);
@@ -211,11 +214,11 @@ hipError_t launch_region_init(kc_region_diff_result* res, uint32_t n, uint64_t* 
 hipError_t launch_region_diff(const Tile* tiles, uint32_t n_tiles, const RangeTable& rt, const uint64_t* changed_bm,
                               const uint64_t* gold_zero_bm, const uint64_t* rank_prefix, const uint64_t* gold_page_va,
                               const uint64_t* gold_n_kept, uint64_t cap, const uint8_t* gold_packed,
-                              kc_region_diff_result* res, uint32_t grid, hipStream_t s) {
+                              kc_region_diff_result* res, uint32_t ushift, uint32_t grid, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   grid = std::max(1u, std::min(grid, n_tiles));
   hipLaunchKernelGGL(k_region_diff, dim3(grid), dim3(64), 0, s, tiles, n_tiles, rt, changed_bm, gold_zero_bm,
-                     rank_prefix, gold_page_va, gold_n_kept, cap, gold_packed, res);
+                     rank_prefix, gold_page_va, gold_n_kept, cap, gold_packed, res, ushift);
   return hipGetLastError();
 }
 

@@ -51,20 +51,30 @@ __device__ __forceinline__ void st16nt(uint64_t addr, uint4 v) {
 // An 8-byte global load through a plain pointer, kept a global access.
 __device__ __forceinline__ uint64_t ld8g(const uint64_t* p) { return *(const KC_GLOBAL uint64_t*)p; }
 
-// A tile: up to 16 consecutive pages of one range.  Only a range's last page
-// can be partial (a range size that is not a multiple of the page); last_len
-// is the byte count of the tile's last page.
+// Hash units: a range is cut into units of 2^ushift bytes (4 KiB pages by
+// default, up to 2 MiB for whole-allocation capture of large tensors); the
+// hash table, bitmaps and packed slots count units.  The closure scan and the
+// pointer graph always walk 4 KiB page tiles.
+constexpr uint32_t kMinUnitShift = 12, kMaxUnitShift = 21;
+
+// A tile: up to 16 consecutive units of one range.  Only a range's last unit
+// can be partial (a range size that is not a multiple of the unit); last_len
+// is the byte count of the tile's last unit.
 struct Tile {
-  uint64_t va;        // VA of the first page
-  uint32_t g;         // global index of the first page
-  uint16_t npages;    // 1..16
-  uint16_t last_len;  // 1..4096
+  uint64_t va;              // VA of the first unit
+  uint32_t g;               // global index of the first unit
+  uint32_t npages : 8;      // 1..16 units
+  uint32_t last_len : 24;   // 1..unit bytes
 };
 static_assert(sizeof(Tile) == 16, "tile layout");
 
-// Bytes of page j of a tile.
+// Bytes of page j of a 4 KiB page tile.
 __device__ __forceinline__ uint32_t page_bytes(const Tile& t, uint32_t j) {
   return j + 1u == t.npages ? (uint32_t)t.last_len : kPage;
+}
+// Bytes of unit j of a tile of units of `unit` bytes.
+__device__ __forceinline__ uint32_t unit_bytes(const Tile& t, uint32_t j, uint32_t unit) {
+  return j + 1u == t.npages ? (uint32_t)t.last_len : unit;
 }
 
 // The 16 bytes at offset off of a page of len bytes, bytes at or past len
@@ -161,6 +171,7 @@ struct HashParams {
   uint8_t* packed;
   uint64_t* page_va;
   uint64_t cap_pages;
+  uint32_t ushift;         // log2 of the hash unit (12: 4 KiB pages)
   ScanDev scan;
 };
 
@@ -214,21 +225,21 @@ hipError_t launch_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
                         hipStream_t s);
 hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan,
                             uint32_t grid, uint32_t n_cu, hipStream_t s);
-hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm,
+hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t ushift,
                              uint32_t grid, hipStream_t s);
 hipError_t launch_scan(const ScanSrc& src, uint64_t* out, uint64_t* block_sums,
                        uint64_t* total_out, hipStream_t s);
 hipError_t launch_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
                          const uint64_t* changed_bm, const uint64_t* word_prefix,
-                         uint8_t* packed, uint64_t* page_va, uint64_t cap_pages,
+                         uint8_t* packed, uint64_t* page_va, uint64_t cap_pages, uint32_t ushift,
                          uint32_t grid, hipStream_t s);
 hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
-                               const uint64_t* changed_bm, unsigned long long* n_bad, uint32_t grid,
-                               hipStream_t s);
+                               const uint64_t* changed_bm, unsigned long long* n_bad, uint32_t ushift,
+                               uint32_t grid, hipStream_t s);
 hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
                                   const uint64_t* page_va, const uint64_t* n_kept,
                                   uint64_t cap_pages, unsigned long long* n_bad,
-                                  bool ragged, uint32_t grid, hipStream_t s);
+                                  bool ragged, uint32_t ushift, uint32_t grid, hipStream_t s);
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
                           const ScanDev& sd, uint32_t grid, uint32_t n_cu, hipStream_t s);
 hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,
@@ -239,7 +250,7 @@ hipError_t launch_region_init(kc_region_diff_result* res, uint32_t n, uint64_t* 
 hipError_t launch_region_diff(const Tile* tiles, uint32_t n_tiles, const RangeTable& rt, const uint64_t* changed_bm,
                               const uint64_t* gold_zero_bm, const uint64_t* rank_prefix, const uint64_t* gold_page_va,
                               const uint64_t* gold_n_kept, uint64_t cap, const uint8_t* gold_packed,
-                              kc_region_diff_result* res, uint32_t grid, hipStream_t s);
+                              kc_region_diff_result* res, uint32_t ushift, uint32_t grid, hipStream_t s);
 hipError_t launch_oob_emit(const Tile* tiles, uint32_t n_tiles, const ScanDev& sd,
                            const uint64_t* tile_prefix, const uint64_t* n_oob, kc_oob* oob,
                            uint64_t cap, kc_scan_result* res, uint64_t n_words, hipStream_t s);
@@ -321,6 +332,7 @@ struct kc_rangeset {
   kc_ctx* ctx = nullptr;
   int device = 0;  // recorded at creation: destroy never touches the context
   uint32_t n_ranges = 0, n_tiles = 0;
+  uint32_t ushift = 12;              // log2 of the hash unit; n_pages, n_words and the tiles count units
   uint64_t n_pages = 0, n_words = 0;
   uint64_t n_scan_words = 0;         // 8-byte words wholly inside the ranges
   uint32_t n_ragged = 0;             // tiles with a partial last page (at most one per range)
@@ -329,6 +341,11 @@ struct kc_rangeset {
   std::vector<uint32_t> range_tile;  // first tile of each range (n + 1)
   uint64_t win_lo = 0, win_hi = 0;   // default pointer window
   std::vector<kc_range> host_ranges;
+  // 4 KiB page tiles walked by the closure scan, its list emission and the
+  // pointer graph (the same list as `tiles` when the unit is the page)
+  uint32_t n_scan_tiles = 0;
+  std::vector<uint32_t> scan_range_tile;
+  kc::Tile* scan_tiles = nullptr;
   void* dev = nullptr;
   kc::Tile* tiles = nullptr;
   uint64_t* bases = nullptr;

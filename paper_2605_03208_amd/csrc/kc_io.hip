@@ -235,15 +235,17 @@ int kc_snapshot_save(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   FileHeader h{};
   std::memcpy(h.magic, "KCSNAP01", 8);
   h.version = 1;
-  h.page_size = KC_PAGE_SIZE;
+  h.page_size = 1u << rs->ushift;  // the hash unit: 4 KiB pages unless the range set was made with another
   h.seed = seed;
   h.n_ranges = rs->n_ranges;
   h.n_pages = rs->n_pages;
   h.n_kept = n_kept;
   h.n_packed = n_packed;
   h.delta = changed_bm_d != nullptr ? 1u : 0u;
-  std::string js = "{\n  \"format\": \"kc-snapshot\",\n  \"version\": 1,\n  \"page_size\": 4096,\n";
+  std::string js = "{\n  \"format\": \"kc-snapshot\",\n  \"version\": 1,\n";
   char buf[256];
+  std::snprintf(buf, sizeof(buf), "  \"page_size\": %u,\n", h.page_size);
+  js += buf;
   std::snprintf(buf, sizeof(buf),
                 "  \"seed\": %llu,\n  \"n_ranges\": %llu,\n  \"n_pages\": %llu,\n  \"n_kept\": %llu,\n"
                 "  \"n_packed\": %llu,\n  \"delta\": %s,\n  \"chunk_bytes\": %llu,\n  \"regions\": [\n",
@@ -277,7 +279,7 @@ int kc_snapshot_save(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
                {"zero_bm.bin", zero_bm_d, 8 * rs->n_words},
                {"changed_bm.bin", changed_bm_d, changed_bm_d ? 8 * rs->n_words : 0},
                {"page_va.bin", page_va_d, 8 * n_packed},
-               {"packed.bin", packed_d, KC_PAGE_SIZE * n_packed}};
+               {"packed.bin", packed_d, (n_packed << rs->ushift)}};
   uint64_t total = 0;
   for (const Part& p : parts) {
     if (p.src == nullptr && std::strcmp(p.name, "changed_bm.bin") == 0) continue;
@@ -313,8 +315,12 @@ int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   }
   FileHeader h;
   std::memcpy(&h, hb.data(), sizeof(h));
-  if (std::memcmp(h.magic, "KCSNAP01", 8) != 0 || h.version != 1 || h.page_size != KC_PAGE_SIZE) {
+  if (std::memcmp(h.magic, "KCSNAP01", 8) != 0 || h.version != 1) {
     set_error_text("not a snapshot directory of this format");
+    return KC_EINVAL;
+  }
+  if (h.page_size != (1u << rs->ushift)) {
+    set_error_text("the snapshot's hash unit differs from the range set's");
     return KC_EINVAL;
   }
   // the snapshot must describe exactly this range set (same VAs, same sizes)
@@ -349,7 +355,7 @@ int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
                {"zero_bm.bin", zero_bm_d, 8 * rs->n_words},
                {"changed_bm.bin", h.delta ? changed_bm_d : nullptr, 8 * rs->n_words},
                {"page_va.bin", page_va_d, 8 * h.n_packed},
-               {"packed.bin", packed_d, KC_PAGE_SIZE * h.n_packed}};
+               {"packed.bin", packed_d, (h.n_packed << rs->ushift)}};
   uint64_t total = 0;
   for (const Part& p : parts) {
     if (p.dst == nullptr || p.bytes == 0) continue;

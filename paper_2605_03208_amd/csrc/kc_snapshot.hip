@@ -159,6 +159,8 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
   const uint32_t q = lane >> 2, k = lane & 3u;
   const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
   const uint64_t scan_lo = p.scan.lo, scan_span = p.scan.span;
+  const uint32_t ushift = p.ushift, unit = 1u << ushift;  // hash unit: 4 KiB .. 2 MiB
+  const uint32_t n_chunks = unit / kChunk;
   if (SCAN) {
     load_wide_fences(p.scan.rt, threadIdx.x, blockDim.x);
     __syncthreads();  // the only workgroup barrier: the waves share nothing else
@@ -170,10 +172,10 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
   for (uint32_t it = wave; it < n_items; it += n_waves) {
     const uint32_t t = RAGGED ? p.ragged[it] - p.tile0 : it;
     const Tile tile = p.tiles[t];
-    if (!RAGGED && tile.last_len != kPage) continue;  // left to the ragged launch
+    if (!RAGGED && tile.last_len != unit) continue;  // left to the ragged launch
     const uint32_t np = tile.npages;
     const uint64_t va = tile.va;
-    const uint32_t last_pg = np - 1u, last_len = RAGGED ? tile.last_len : kPage;  // only the last page can be partial
+    const uint32_t last_pg = np - 1u, last_len = RAGGED ? (uint32_t)tile.last_len : unit;  // only the last unit can be partial
     uint32_t keep = (1u << np) - 1u;
     uint64_t slot_j[8];
     if (GATHER) {
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
       keep = (uint32_t)__ballot(kept);
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) slot_j[j] = __shfl(slot, 2 * j + half, 64);
-      if (kept && slot < p.cap_pages) p.page_va[slot] = va + (uint64_t)lane * kPage;
+      if (kept && slot < p.cap_pages) p.page_va[slot] = va + ((uint64_t)lane << ushift);
     }
     uint32_t nonzero = 0, oob = 0;
     uint64_t acc = acc_init(p.seed, k);
@@ -198,18 +200,19 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
     for (uint32_t j = 0; j < 8; ++j) {
       const uint32_t pg = 2 * j + half;
       if (RAGGED) {
-        const uint32_t len = pg == last_pg ? last_len : kPage;
-        cur[j] = ((keep >> pg) & 1u) && off16 < len ? clip16(ld16nt(va + (uint64_t)pg * kPage + off16), off16, len)
-                                                    : make_uint4(0, 0, 0, 0);
+        const uint32_t len = pg == last_pg ? last_len : unit;
+        cur[j] = ((keep >> pg) & 1u) && off16 < len
+                     ? clip16(ld16nt(va + ((uint64_t)pg << ushift) + off16), off16, len)
+                     : make_uint4(0, 0, 0, 0);
       } else {
-        cur[j] = ((keep >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + off16) : make_uint4(0, 0, 0, 0);
+        cur[j] = ((keep >> pg) & 1u) ? ld16nt(va + ((uint64_t)pg << ushift) + off16) : make_uint4(0, 0, 0, 0);
       }
     }
-    // this lane's quad: stripes of its page, and the bytes past the last stripe
-    const uint32_t qlen = RAGGED && q == last_pg ? last_len : kPage;
+    // this lane's quad: stripes of its unit, and the bytes past the last stripe
+    const uint32_t qlen = RAGGED && q == last_pg ? last_len : unit;
     const uint32_t lim = qlen / 32u, rem = qlen & 31u;
 #pragma unroll 1
-    for (uint32_t c = 0; c < kPage / kChunk; ++c) {
+    for (uint32_t c = 0; c < n_chunks; ++c) {
       uint32_t ptr_mask = 0;  // bit 2j+h: word h of this lane's 16 bytes of load j is pointer-like
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
           uint32_t p0 = (w0 - scan_lo) < scan_span ? 1u : 0u;
           uint32_t p1 = (w1 - scan_lo) < scan_span ? 1u : 0u;
           if (RAGGED) {  // words wholly inside the range only
-            const uint32_t o = c * kChunk + off16, len = pg == last_pg ? last_len : kPage;
+            const uint32_t o = c * kChunk + off16, len = pg == last_pg ? last_len : unit;
             p0 = o + 8u <= len ? p0 : 0u;
             p1 = o + 16u <= len ? p1 : 0u;
           }
@@ -233,23 +236,23 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
         }
         if (GATHER) {
           if (((keep >> pg) & 1u) && slot_j[j] < p.cap_pages)
-            st16nt((uint64_t)p.packed + slot_j[j] * kPage + c * kChunk + off16, v);
+            st16nt((uint64_t)p.packed + (slot_j[j] << ushift) + c * kChunk + off16, v);
         }
         *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
       }
       wave_lds_order();
       // loads of the next chunk overlap the hashing of this one
-      const uint32_t cn = c + 1 < kPage / kChunk ? c + 1 : c;
-      const uint32_t more = c + 1 < kPage / kChunk ? keep : 0u;
+      const uint32_t cn = c + 1 < n_chunks ? c + 1 : c;
+      const uint32_t more = c + 1 < n_chunks ? keep : 0u;
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
         const uint32_t pg = 2 * j + half, o = cn * kChunk + off16;
         if (RAGGED) {
-          const uint32_t len = pg == last_pg ? last_len : kPage;
-          cur[j] = ((more >> pg) & 1u) && o < len ? clip16(ld16nt(va + (uint64_t)pg * kPage + o), o, len)
+          const uint32_t len = pg == last_pg ? last_len : unit;
+          cur[j] = ((more >> pg) & 1u) && o < len ? clip16(ld16nt(va + ((uint64_t)pg << ushift) + o), o, len)
                                                   : make_uint4(0, 0, 0, 0);
         } else {
-          cur[j] = ((more >> pg) & 1u) ? ld16nt(va + (uint64_t)pg * kPage + o) : make_uint4(0, 0, 0, 0);
+          cur[j] = ((more >> pg) & 1u) ? ld16nt(va + ((uint64_t)pg << ushift) + o) : make_uint4(0, 0, 0, 0);
         }
       }
       if (SCAN && __ballot(ptr_mask != 0u)) {
@@ -304,61 +307,74 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
 }
 
 // ------------------------------------------------------------ zero probe --
-// Exact zero bitmap.  A wave takes four tiles at a time, one lane per page:
-// each lane reads the first 16 bytes of its page; a page whose first 16 bytes
-// are zero is then read in full by the whole wave (four such pages at a time).
+// Exact zero bitmap.  A wave takes four tiles at a time, one lane per unit:
+// each lane reads the first 16 bytes of its unit; a unit whose first 16 bytes
+// are zero is then read by the whole wave (four such units at a time, 4 KiB of
+// each per round) until a non-zero byte shows or the unit ends.
 __global__ __launch_bounds__(64) void k_probe_zero(const Tile* tiles, uint32_t n_tiles,
-                                                   uint64_t* zero_bm) {
+                                                   uint64_t* zero_bm, uint32_t ushift) {
   const uint32_t lane = threadIdx.x, sub = lane >> 4, pl = lane & 15u;
+  const uint32_t unit = 1u << ushift, nsub = unit / kPage;
   for (uint32_t t0 = blockIdx.x * 4u; t0 < n_tiles; t0 += gridDim.x * 4u) {
     const uint32_t t = t0 + sub;
     Tile tile{0, 0, 0};
     if (t < n_tiles) tile = tiles[t];
     const bool valid = pl < tile.npages;
-    const uint32_t len = valid ? page_bytes(tile, pl) : 0u;  // a partial page is tested over its bytes only
-    const uint64_t page_va = tile.va + (uint64_t)pl * kPage;
-    const uint4 v = valid ? clip16(ld16(page_va), 0u, len) : make_uint4(0, 0, 0, 0);
+    const uint32_t len = valid ? unit_bytes(tile, pl, unit) : 0u;  // a partial unit is tested over its bytes only
+    const uint64_t unit_va = tile.va + ((uint64_t)pl << ushift);
+    const uint4 v = valid ? clip16(ld16(unit_va), 0u, len) : make_uint4(0, 0, 0, 0);
     const bool cand = valid && !nz16(v);
-    uint64_t maybe = __ballot(cand && len == kPage);
-    uint64_t maybe_part = __ballot(cand && len != kPage);
+    uint64_t maybe = __ballot(cand && len == unit);
+    uint64_t maybe_part = __ballot(cand && len != unit);
     uint64_t zero = 0;
-    while (maybe) {  // whole pages, four at a time
+    while (maybe) {  // whole units, four at a time
       uint32_t ln[4];
       uint64_t pva[4];
       uint32_t cnt = 0;
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i) {
         ln[i] = maybe ? (uint32_t)__builtin_ctzll(maybe) : 0u;
-        pva[i] = __shfl(page_va, ln[i], 64);
+        pva[i] = __shfl(unit_va, ln[i], 64);
         if (maybe) {
           maybe &= maybe - 1ull;
           ++cnt;
         }
       }
-      uint4 x[16];
+      uint32_t alive = (1u << cnt) - 1u;  // units with no non-zero byte seen yet
+      for (uint32_t b = 0; b < nsub && alive != 0u; ++b) {
+        uint4 x[16];
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+          for (uint32_t j = 0; j < 4; ++j)
+            x[i * 4 + j] = ((alive >> i) & 1u) ? ld16nt(pva[i] + (uint64_t)b * kPage + j * 1024u + lane * 16u)
+                                               : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+          const bool nzl = nz16(x[i * 4]) || nz16(x[i * 4 + 1]) || nz16(x[i * 4 + 2]) || nz16(x[i * 4 + 3]);
+          if (__ballot(nzl) != 0ull) alive &= ~(1u << i);
+        }
+      }
 #pragma unroll
       for (uint32_t i = 0; i < 4; ++i)
-#pragma unroll
-        for (uint32_t j = 0; j < 4; ++j)
-          x[i * 4 + j] = (i < cnt) ? ld16nt(pva[i] + j * 1024u + lane * 16u) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-      for (uint32_t i = 0; i < 4; ++i) {
-        const bool nzl = nz16(x[i * 4]) || nz16(x[i * 4 + 1]) || nz16(x[i * 4 + 2]) || nz16(x[i * 4 + 3]);
-        if (i < cnt && __ballot(nzl) == 0ull) zero |= 1ull << ln[i];
-      }
+        if ((alive >> i) & 1u) zero |= 1ull << ln[i];
     }
-    while (maybe_part) {  // partial last pages (one per range at most), one at a time over their bytes
+    while (maybe_part) {  // partial last units (one per range at most), one at a time over their bytes
       const uint32_t L = (uint32_t)__builtin_ctzll(maybe_part);
       maybe_part &= maybe_part - 1ull;
-      const uint64_t pva = __shfl(page_va, L, 64);
+      const uint64_t pva = __shfl(unit_va, L, 64);
       const uint32_t plen = __shfl(len, L, 64);
-      bool nzl = false;
+      bool nzw = false;
+      for (uint32_t o0 = 0; o0 < plen && !nzw; o0 += kPage) {
+        bool nzl = false;
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) {
-        const uint32_t o = j * 1024u + lane * 16u;
-        if (o < plen) nzl = nzl || nz16(clip16(ld16nt(pva + o), o, plen));
+        for (uint32_t j = 0; j < 4; ++j) {
+          const uint32_t o = o0 + j * 1024u + lane * 16u;
+          if (o < plen) nzl = nzl || nz16(clip16(ld16nt(pva + o), o, plen));
+        }
+        nzw = __ballot(nzl) != 0ull;
       }
-      if (__ballot(nzl) == 0ull) zero |= 1ull << L;
+      if (!nzw) zero |= 1ull << L;
     }
     if (pl == 0 && t < n_tiles) or_page_bits(zero_bm, tile.g, tile.npages, (uint32_t)((zero >> (16u * sub)) & 0xFFFFull));
   }
@@ -494,17 +510,20 @@ __device__ __forceinline__ void tile_slots(const Tile& tile, const uint64_t* zer
 }
 
 // --------------------------------------------------------------- gather ---
+// Kept units of a tile, four at a time, copied to their packed slots 4 KiB of
+// each per round; a partial unit's slot is filled up with zeros.
 __global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
                                                const uint64_t* changed_bm, const uint64_t* word_prefix,
-                                               uint8_t* packed, uint64_t* page_va, uint64_t cap) {
+                                               uint8_t* packed, uint64_t* page_va, uint64_t cap, uint32_t ushift) {
   const uint32_t lane = threadIdx.x;
+  const uint32_t unit = 1u << ushift, nsub = unit / kPage;
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const Tile tile = tiles[t];
     bool kept;
     uint64_t slot;
     tile_slots(tile, zero_bm, changed_bm, word_prefix, lane, kept, slot);
     const bool go = kept && slot < cap;
-    if (go) page_va[slot] = tile.va + (uint64_t)lane * kPage;
+    if (go) page_va[slot] = tile.va + ((uint64_t)lane << ushift);
     uint32_t mask = (uint32_t)__ballot(go);
     while (mask) {
       uint32_t pg[4];
@@ -519,20 +538,24 @@ __global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_til
           ++cnt;
         }
       }
-      uint4 x[16];
+      for (uint32_t b = 0; b < nsub; ++b) {
+        uint4 x[16];
 #pragma unroll
-      for (uint32_t i = 0; i < 4; ++i)
+        for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) {
-          const uint32_t o = j * 1024u + lane * 16u, len = page_bytes(tile, pg[i]);  // a partial page: zeros after
-          if (i < cnt) x[i * 4 + j] = o < len ? clip16(ld16nt(tile.va + (uint64_t)pg[i] * kPage + o), o, len)
-                                               : make_uint4(0, 0, 0, 0);
-        }
+          for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t o = b * kPage + j * 1024u + lane * 16u, len = unit_bytes(tile, pg[i], unit);
+            if (i < cnt)
+              x[i * 4 + j] = o < len ? clip16(ld16nt(tile.va + ((uint64_t)pg[i] << ushift) + o), o, len)
+                                     : make_uint4(0, 0, 0, 0);  // a partial unit: zeros after its bytes
+          }
 #pragma unroll
-      for (uint32_t i = 0; i < 4; ++i)
+        for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j)
-          if (i < cnt) st16nt((uint64_t)packed + dst[i] * kPage + j * 1024u + lane * 16u, x[i * 4 + j]);
+          for (uint32_t j = 0; j < 4; ++j)
+            if (i < cnt)
+              st16nt((uint64_t)packed + (dst[i] << ushift) + b * kPage + j * 1024u + lane * 16u, x[i * 4 + j]);
+      }
     }
   }
 }
@@ -540,8 +563,8 @@ __global__ __launch_bounds__(64) void k_gather(const Tile* tiles, uint32_t n_til
 // -------------------------------------------------------------- restore ---
 __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t n_tiles,
                                                      const uint64_t* zero_bm, const uint64_t* changed_bm,
-                                                     unsigned long long* n_bad) {
-  const uint32_t lane = threadIdx.x;
+                                                     unsigned long long* n_bad, uint32_t ushift) {
+  const uint32_t lane = threadIdx.x, unit = 1u << ushift;
   if (blockIdx.x == 0 && lane == 0) *n_bad = 0ull;  // the scatter that follows counts into it
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const Tile tile = tiles[t];
@@ -557,44 +580,58 @@ __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t
     while (mask) {
       const uint32_t pg = (uint32_t)__builtin_ctz(mask);
       mask &= mask - 1u;
-      const uint32_t len = page_bytes(tile, pg);  // never past the range's end
+      const uint32_t len = unit_bytes(tile, pg, unit);  // never past the range's end
+      const uint64_t uva = tile.va + ((uint64_t)pg << ushift);
+      for (uint32_t o0 = 0; o0 < len; o0 += kPage) {
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) {
-        const uint32_t o = j * 1024u + lane * 16u;
-        if (o + 16u <= len) st16nt(tile.va + (uint64_t)pg * kPage + o, z);
-        else if (o < len) st_bytes(tile.va + (uint64_t)pg * kPage + o, z, len - o);
+        for (uint32_t j = 0; j < 4; ++j) {
+          const uint32_t o = o0 + j * 1024u + lane * 16u;
+          if (o + 16u <= len) st16nt(uva + o, z);
+          else if (o < len) st_bytes(uva + o, z, len - o);
+        }
       }
     }
   }
 }
 
+// Packed units back to their VAs in 4 KiB blocks, four blocks per wave round:
+// lanes 0..3 read the page-VA entry of their block's slot and validate it
+// (4 KiB aligned, inside a range, the start of a unit of that range); the
+// whole wave then copies the four blocks.
 __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uint8_t* packed,
                                                         const uint64_t* page_va, const uint64_t* n_kept,
-                                                        uint64_t cap, unsigned long long* n_bad) {
+                                                        uint64_t cap, unsigned long long* n_bad, uint32_t ushift) {
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
+  const uint32_t bshift = ushift - 12u;  // 4 KiB blocks per unit: 1 << bshift
+  const uint64_t unit = 1ull << ushift;
   load_fences(fences, rt, lane, kWave);
   __syncthreads();
   const uint64_t n = min(*n_kept, cap);
-  for (uint64_t s0 = (uint64_t)blockIdx.x * 4; s0 < n; s0 += (uint64_t)gridDim.x * 4) {
-    uint64_t va = 0;
+  const uint64_t nblk = n << bshift;
+  for (uint64_t s0 = (uint64_t)blockIdx.x * 4; s0 < nblk; s0 += (uint64_t)gridDim.x * 4) {
+    uint64_t dst = 0;
     bool ok = false;
-    if (lane < 4 && s0 + lane < n) {
-      va = page_va[s0 + lane];
+    if (lane < 4 && s0 + lane < nblk) {
+      const uint64_t blk = s0 + lane, sub = blk & ((1ull << bshift) - 1ull);
+      const uint64_t va = page_va[blk >> bshift];
       const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
-      if (a >= 0) {  // a range's partial last page is left to k_restore_tail
+      bool good = false;
+      if (a >= 0) {  // a range's partial last unit is left to k_restore_tail
+        const uint64_t base = rt.stride == 1u ? fences.base[a] : ld8g(rt.base + a);
         const uint64_t end = rt.stride == 1u ? fences.end[a] : ld8g(rt.end + a);
-        ok = va + kPage <= end;
-      } else {
-        atomicAdd(n_bad, 1ull);
+        good = ((va - base) & (unit - 1ull)) == 0ull;
+        ok = good && va + unit <= end;
       }
+      if (!good && sub == 0) atomicAdd(n_bad, 1ull);  // counted once per slot
+      dst = va + (sub << 12);
     }
     const uint32_t okm = (uint32_t)__ballot(ok);
-    uint64_t dst[4];
+    uint64_t d[4];
     uint4 x[16];
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i) {
-      dst[i] = __shfl(va, i, 64);
+      d[i] = __shfl(dst, i, 64);
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
         if ((okm >> i) & 1u) x[i * 4 + j] = ld16nt((uint64_t)packed + (s0 + i) * kPage + j * 1024u + lane * 16u);
@@ -603,16 +640,17 @@ __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uin
     for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
-        if ((okm >> i) & 1u) st16nt(dst[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
+        if ((okm >> i) & 1u) st16nt(d[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
   }
 }
 
-// Packed pages bound for a range's partial last page: only the page's own
+// Packed units bound for a range's partial last unit: only the unit's own
 // bytes are written.  One lane per slot finds them; the wave copies each.
 __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_t* packed, const uint64_t* page_va,
-                                                     const uint64_t* n_kept, uint64_t cap) {
+                                                     const uint64_t* n_kept, uint64_t cap, uint32_t ushift) {
   __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
+  const uint64_t unit = 1ull << ushift;
   load_fences(fences, rt, lane, kWave);
   __syncthreads();
   const uint64_t n = min(*n_kept, cap);
@@ -623,19 +661,22 @@ __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_
       va = page_va[s0 + lane];
       const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
       if (a >= 0) {
+        const uint64_t base = rt.stride == 1u ? fences.base[a] : ld8g(rt.base + a);
         const uint64_t end = rt.stride == 1u ? fences.end[a] : ld8g(rt.end + a);
-        if (va + kPage > end) len = (uint32_t)(end - va);
+        if (((va - base) & (unit - 1ull)) == 0ull && va + unit > end) len = (uint32_t)(end - va);
       }
     }
     for (uint64_t m = __ballot(len != 0u); m != 0ull; m &= m - 1ull) {
       const int32_t L = __ffsll((long long)m) - 1;
       const uint64_t dva = __shfl((unsigned long long)va, L, 64);
       const uint32_t dlen = __shfl(len, L, 64);
-      const uint64_t src = (uint64_t)packed + (s0 + (uint64_t)L) * kPage;
+      const uint64_t src = (uint64_t)packed + ((s0 + (uint64_t)L) << ushift);
+      for (uint32_t o0 = 0; o0 < dlen; o0 += kPage) {
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) {
-        const uint32_t o = j * 1024u + lane * 16u;
-        if (o < dlen) st_bytes(dva + o, ld16nt(src + o), dlen - o);  // never past the range's end
+        for (uint32_t j = 0; j < 4; ++j) {
+          const uint32_t o = o0 + j * 1024u + lane * 16u;
+          if (o < dlen) st_bytes(dva + o, ld16nt(src + o), dlen - o);  // never past the range's end
+        }
       }
     }
   }
@@ -832,11 +873,11 @@ hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool s
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t grid,
+hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t ushift, uint32_t grid,
                              hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   grid = std::max(1u, std::min(grid, n_tiles));
-  hipLaunchKernelGGL(k_probe_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm);
+  hipLaunchKernelGGL(k_probe_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, ushift);
   return hipGetLastError();
 }
 
@@ -861,36 +902,37 @@ hipError_t launch_scan(const ScanSrc& src, uint64_t* out, uint64_t* block_sums, 
 
 hipError_t launch_gather(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
                          const uint64_t* changed_bm, const uint64_t* word_prefix, uint8_t* packed,
-                         uint64_t* page_va, uint64_t cap_pages, uint32_t grid, hipStream_t s) {
+                         uint64_t* page_va, uint64_t cap_pages, uint32_t ushift, uint32_t grid, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   grid = std::max(1u, std::min(grid, n_tiles));
   hipLaunchKernelGGL(k_gather, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm, word_prefix,
-                     packed, page_va, cap_pages);
+                     packed, page_va, cap_pages, ushift);
   return hipGetLastError();
 }
 
 hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64_t* zero_bm,
-                               const uint64_t* changed_bm, unsigned long long* n_bad, uint32_t grid,
+                               const uint64_t* changed_bm, unsigned long long* n_bad, uint32_t ushift, uint32_t grid,
                                hipStream_t s) {
   grid = std::max(1u, std::min(grid, std::max(1u, n_tiles)));
-  hipLaunchKernelGGL(k_restore_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm, n_bad);
+  hipLaunchKernelGGL(k_restore_zero, dim3(grid), dim3(64), 0, s, tiles, n_tiles, zero_bm, changed_bm, n_bad,
+                     ushift);
   return hipGetLastError();
 }
 
 hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, const uint64_t* page_va,
                                   const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad,
-                                  bool ragged, uint32_t grid, hipStream_t s) {
+                                  bool ragged, uint32_t ushift, uint32_t grid, hipStream_t s) {
   if (cap_pages == 0) return hipSuccess;
-  const uint64_t groups = (cap_pages + 3) / 4;
+  const uint64_t groups = ((cap_pages << (ushift - 12u)) + 3) / 4;  // four 4 KiB blocks per wave round
   grid = (uint32_t)(groups < grid ? groups : grid);
   grid = grid < 1u ? 1u : grid;
   hipLaunchKernelGGL(k_restore_scatter, dim3(grid), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
-                     n_bad);
+                     n_bad, ushift);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ragged) return e;
   const uint64_t groups64 = (cap_pages + 63) / 64;
   const uint32_t grid_t = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(groups64, 1024));
-  hipLaunchKernelGGL(k_restore_tail, dim3(grid_t), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages);
+  hipLaunchKernelGGL(k_restore_tail, dim3(grid_t), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages, ushift);
   return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
            "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
            "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest", "kc_perturb",
-           "kc_compare_noalloc"]
+           "kc_compare_noalloc", "kc_rangeset_create_unit"]
 
 
 class KCError(RuntimeError):
@@ -138,6 +138,7 @@ def lib() -> ctypes.CDLL:
             "kc_pairset_destroy": ([vp], None),
             "kc_compare_pairset": ([vp, vp, vp, vp], i32),
             "kc_compare_noalloc": ([vp, P(Pair), u32, vp, vp], i32),
+            "kc_rangeset_create_unit": ([vp, P(Range), u32, u64, P(vp), P(u64)], i32),
             "kc_snapshot_save": ([vp, vp, ctypes.c_char_p, u64, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)],
                                  i32),
             "kc_snapshot_load": ([vp, vp, ctypes.c_char_p, vp, vp, vp, vp, vp, vp, u64, u64, vp, P(IoStats)], i32),
@@ -251,15 +252,18 @@ class Context:
 
 
 class RangeSet:
-    """Uploaded range table (tracked allocations) plus the scratch its calls use."""
+    """Uploaded range table (tracked allocations) plus the scratch its calls use.
+    ``unit``: the hash unit in bytes (4 KiB pages by default, a power of two up
+    to 2 MiB); ``n_pages`` and ``n_words`` then count units."""
 
-    def __init__(self, ctx: Context, ranges):
+    def __init__(self, ctx: Context, ranges, unit: int = PAGE):
         self.ctx = ctx
         self.ranges = [(int(b), int(s)) for b, s in ranges]
+        self.unit = int(unit)
         self.handle = ctypes.c_void_p()
         n = ctypes.c_uint64(0)
-        _check(lib().kc_rangeset_create(ctx.handle, _ranges(self.ranges), len(self.ranges),
-                                        ctypes.byref(self.handle), ctypes.byref(n)), "kc_rangeset_create")
+        _check(lib().kc_rangeset_create_unit(ctx.handle, _ranges(self.ranges), len(self.ranges), self.unit,
+                                             ctypes.byref(self.handle), ctypes.byref(n)), "kc_rangeset_create_unit")
         self.n_pages = int(n.value)
         self.n_words = (self.n_pages + 63) // 64
 
@@ -341,11 +345,11 @@ def page_hash(ctx: Context, rs: RangeSet, seed: int = 0, prior: torch.Tensor | N
 
 def compact(ctx: Context, rs: RangeSet, zero_bm, changed_bm=None, cap_pages: int | None = None, out=None,
             stream=None):
-    """Returns (packed u8[cap*4096], page_va int64[cap], n_kept int64[1]) device tensors."""
+    """Returns (packed u8[cap*unit], page_va int64[cap], n_kept int64[1]) device tensors."""
     dev = torch.device("cuda", ctx.device)
     cap = rs.n_pages if cap_pages is None else int(cap_pages)
     packed, va, nk = out if out is not None else (
-        torch.empty(max(1, cap) * PAGE, dtype=torch.uint8, device=dev), _u64(cap, dev), _u64(1, dev))
+        torch.empty(max(1, cap) * rs.unit, dtype=torch.uint8, device=dev), _u64(cap, dev), _u64(1, dev))
     _check(lib().kc_compact(ctx.handle, rs.handle, _ptr(zero_bm), _ptr(changed_bm), _ptr(packed), _ptr(va),
                             cap, _ptr(nk), _stream(stream)), "kc_compact")
     return packed, va, nk
@@ -359,7 +363,7 @@ def snapshot(ctx: Context, rs: RangeSet, seed: int = 0, prior=None, cap_pages: i
     if out is None:
         out = dict(hash=_u64(rs.n_pages, dev), zero_bm=_u64(rs.n_words, dev),
                    changed_bm=_u64(rs.n_words, dev) if prior is not None else None,
-                   packed=torch.empty(max(1, cap) * PAGE, dtype=torch.uint8, device=dev),
+                   packed=torch.empty(max(1, cap) * rs.unit, dtype=torch.uint8, device=dev),
                    page_va=_u64(cap, dev), n_kept=_u64(1, dev))
     _check(lib().kc_snapshot(ctx.handle, rs.handle, seed & (2**64 - 1), _ptr(prior), _ptr(out["hash"]),
                              _ptr(out["zero_bm"]), _ptr(out.get("changed_bm")), _ptr(out["packed"]),
@@ -519,7 +523,7 @@ def snapshot_load(ctx: Context, rs: RangeSet, directory: str, cap_pages: int | N
     cap = rs.n_pages if cap_pages is None else int(cap_pages)
     out = dict(hash=_u64(rs.n_pages, dev), zero_bm=_u64(rs.n_words, dev),
                changed_bm=_u64(rs.n_words, dev) if delta else None,
-               packed=torch.empty(max(1, cap) * PAGE, dtype=torch.uint8, device=dev),
+               packed=torch.empty(max(1, cap) * rs.unit, dtype=torch.uint8, device=dev),
                page_va=_u64(cap, dev), n_kept=_u64(1, dev))
     st = IoStats()
     _check(lib().kc_snapshot_load(ctx.handle, rs.handle, directory.encode(), _ptr(out["hash"]), _ptr(out["zero_bm"]),

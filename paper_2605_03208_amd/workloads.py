@@ -292,6 +292,44 @@ def ragged_case(device="cpu", n_ranges: int = 40, seed: int = 9, max_bytes: int 
     return SnapshotCase("ragged", arena, dict(ptr=ptr, sentinel=SENTINEL))
 
 
+def units_case(device="cpu", unit: int = 64 * KiB, n_ranges: int = 24, seed: int = 21,
+               max_units: int = 5) -> SnapshotCase:
+    """Ranges for hash units larger than the page: byte sizes up to
+    ``max_units`` units (a few whole multiples of the unit, a few under one
+    unit), on page-aligned bases 0-3 pages apart, gaps filled with
+    ``SENTINEL``.  About a quarter of the units (partial ones included) are
+    all zero, a few more have only their first 4 KiB page zero (so a probe of
+    the first bytes alone would misjudge them), and about 0.2 % of the words
+    wholly inside a range hold addresses inside some range."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, max_units * unit + 1, size=n_ranges)
+    sizes[::5] = (sizes[::5] + unit - 1) // unit * unit
+    sizes[2::7] = rng.integers(1, PAGE, size=len(sizes[2::7]))
+    lay = make_layout(rng, sizes, gap_pages=(0, 3))
+    arena = Arena(lay, device)
+    arena.buf.fill_(SENTINEL)
+    ranges = arena.ranges()
+    content = rng.integers(0, 256, size=lay.total, dtype=np.uint8)
+    cum = lay.cum()
+    for a in range(n_ranges):   # pointers first: the zeroing below clears those in zeroed units
+        for w in np.flatnonzero(rng.random(int(sizes[a]) // 8) < 0.002):
+            b = int(rng.integers(0, n_ranges))
+            v = ranges[b][0] + int(rng.integers(0, int(sizes[b])))
+            content[int(cum[a]) + 8 * int(w): int(cum[a]) + 8 * int(w) + 8] = np.frombuffer(
+                np.uint64(v).tobytes(), dtype=np.uint8)
+    for a in range(n_ranges):
+        for u in range((int(sizes[a]) + unit - 1) // unit):
+            lo = int(cum[a]) + u * unit
+            hi = min(lo + unit, int(cum[a + 1]))
+            r = rng.random()
+            if r < 0.25:
+                content[lo:hi] = 0
+            elif r < 0.35:
+                content[lo:min(lo + PAGE, hi)] = 0
+    arena.load_concat(content)
+    return SnapshotCase("units", arena, dict(unit=unit, sentinel=SENTINEL))
+
+
 # --------------------------------------------------------------------------
 # pointer graphs: a planted sparse digraph between ranges
 # --------------------------------------------------------------------------
