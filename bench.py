@@ -210,7 +210,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip graph / batching / serving measurements")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
     ap.add_argument("--retune", action="store_true", help="sweep launch shapes even if a tuned table has them")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the c5 serving run at 200 req/s (after a 2 s warm-up run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB three times (counter calibration) and exit")
     ap.add_argument("--c1-only", action="store_true",
@@ -402,6 +403,8 @@ def main() -> int:
         line["region_diff"] = region_diff_pass(torch, kc, ctx, rs, out, case, N, args.steps, tune=not args.no_tune)
         log("graph replay of the step")
         line["graph"] = graph_step(torch, step, res, pair_list, kc, args.steps)
+        log("hash units of 4 KiB, 64 KiB and 2 MiB: snapshot and restore of the same pool")
+        line["hash_units"] = hash_units(torch, kc, ctx, case, ranges, args.steps)
         state["ps"].close()
         rs.close()
         del case, golden, out, state, pair_list, rs
@@ -417,6 +420,62 @@ def main() -> int:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
+
+
+def hash_units(torch, kc, ctx, case, ranges, reps: int) -> dict:
+    """The snapshot (probe, keep scan, hashing pass with the packed writes; no
+    closure scan) and the restore of the same pool at hash units of 4 KiB,
+    64 KiB and 2 MiB, each in its own range set.  Algorithmic bytes: the
+    ranges' bytes read, 8 B of hash and a zero bit per unit, a packed slot of
+    `unit` bytes and an 8 B page VA per kept unit (restore: the packed slots
+    read, the ranges' bytes written, the page VAs read)."""
+    import numpy as np
+    dev = case.arena.buf.device
+    pool = sum(int(s) for _, s in ranges)
+    res = {}
+    for unit in (4096, 64 << 10, 2 << 20):
+        rs = kc.RangeSet(ctx, ranges, unit=unit)
+        n = rs.n_pages
+        out = dict(hash=torch.empty(n, dtype=torch.int64, device=dev),
+                   zero_bm=torch.empty(rs.n_words, dtype=torch.int64, device=dev), changed_bm=None,
+                   packed=torch.empty(n * unit, dtype=torch.uint8, device=dev),
+                   page_va=torch.empty(n, dtype=torch.int64, device=dev),
+                   n_kept=torch.empty(1, dtype=torch.int64, device=dev))
+        kc.snapshot(ctx, rs, out=out)
+        torch.cuda.synchronize()
+        kept = int(out["n_kept"].item())
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.enable_timing(True)
+        kms = []
+        ev0.record()
+        for _ in range(reps):
+            kc.snapshot(ctx, rs, out=out)
+            kms.append(ctx.kernel_ms(kc.OP_SNAPSHOT))
+        ev1.record()
+        torch.cuda.synchronize()
+        snap_ms = ev0.elapsed_time(ev1) / reps
+        rms = []
+        ev0.record()
+        for _ in range(reps):
+            kc.restore(ctx, rs, out["zero_bm"], None, out["packed"], out["page_va"], out["n_kept"])
+            rms.append(ctx.kernel_ms(kc.OP_RESTORE))
+        ev1.record()
+        torch.cuda.synchronize()
+        ctx.enable_timing(False)
+        restore_ms = ev0.elapsed_time(ev1) / reps
+        snap_bytes = pool + 8 * n + n // 8 + kept * (unit + 8)
+        restore_bytes = kept * (unit + 8) + pool
+        res[f"{unit // 1024}KiB"] = {
+            "units": n, "kept_units": kept,
+            "snapshot_ms": round(snap_ms, 4), "snapshot_GBps": round(snap_bytes / snap_ms / 1e6, 1),
+            "hash_pass_ms": round(float(np.mean(kms)), 4),
+            "restore_ms": round(restore_ms, 4), "restore_GBps": round(restore_bytes / restore_ms / 1e6, 1),
+            "restore_scatter_ms": round(float(np.mean(rms)), 4)}
+        del out
+        rs.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return res
 
 
 def copy_ceiling(torch, dev, gib: int = 4, reps: int = 5) -> dict:
@@ -834,8 +893,10 @@ def serving(torch, kc, W, dev, seconds: float) -> dict:
     reqs = W.c5_requests(rate_hz=200.0, duration_s=seconds)
     reqs = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in reqs]
     ex = serve.DeviceExecutor(golds, dtypes, n_streams=4)
+    log("serving: 2 s warm-up run of the same schedule law (another seed)")
+    warm_reqs = W.c5_requests(rate_hz=200.0, duration_s=2.0, seed=55)
     warm = serve.Server(ex, 32 << 30)
-    warm.run(reqs[:8])
+    warm.run([serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in warm_reqs])
     torch.cuda.synchronize()
     srv = serve.Server(ex, 32 << 30)
     t0 = time.perf_counter()

@@ -53,6 +53,8 @@ class Completed:
     materialize_s: float = 0.0   # device time of the batch's candidate materialisation
     compare_s: float = 0.0       # device time of the batch's compare
     host_launch_s: float = 0.0   # host time spent issuing the batch (materialisation and compare calls)
+    dev_start_s: float = 0.0     # device clock, from the start of the run: the batch's first and last event
+    dev_end_s: float = 0.0
 
     @property
     def latency_s(self) -> float:
@@ -200,9 +202,19 @@ class DeviceExecutor:
     def done(self, h, now: float) -> bool:
         return h["ev"].query()
 
+    def begin(self) -> None:
+        """Marks the start of a run on the device clock (a reference event that
+        every batch's events are timed against)."""
+        self.ref = self.torch.cuda.Event(enable_timing=True)
+        self.ref.record(self.streams[0])
+
     def split(self, h) -> tuple:
         """(materialise, compare) device seconds of a finished batch."""
         return h["ev0"].elapsed_time(h["ev_mat"]) / 1e3, h["ev_mat"].elapsed_time(h["ev"]) / 1e3
+
+    def interval(self, h) -> tuple:
+        """(start, end) of a finished batch on the device, in seconds from begin()."""
+        return self.ref.elapsed_time(h["ev0"]) / 1e3, self.ref.elapsed_time(h["ev"]) / 1e3
 
     def finish(self, h):
         out = self.kc.decode_cmp(h["res"], h["n"])
@@ -246,6 +258,8 @@ class Server:
         admitted = []          # (req, admit_s)
         running = []           # (handle, [(req, admit_s)], launch_s, host_launch_s)
         done = []
+        if hasattr(self.ex, "begin"):
+            self.ex.begin()
         t0 = self.clock()
         now = 0.0
         while pending or queue or admitted or running:
@@ -272,10 +286,11 @@ class Server:
                     results = self.ex.finish(h)
                     t_done = self.clock() - t0 if real_time else now
                     mat_s, cmp_s = self.ex.split(h) if hasattr(self.ex, "split") else (0.0, 0.0)
+                    d0, d1 = self.ex.interval(h) if hasattr(self.ex, "interval") else (0.0, 0.0)
                     for (r, t_adm), res in zip(batch, results):
                         self.budget.give(self.ex.request_bytes(r))
                         done.append(Completed(r.rid, r.arrival_s, t_adm, t_launch, t_done,
-                                              self.ex.request_bytes(r), res, mat_s, cmp_s, host_s))
+                                              self.ex.request_bytes(r), res, mat_s, cmp_s, host_s, d0, d1))
                     progressed = True
                 else:
                     still.append((h, batch, t_launch, host_s))
@@ -297,7 +312,9 @@ def summarize(done, wall_s: float) -> dict:
     """Latency percentiles, split into queue (arrival to admission), wait
     (arrival to the start of its batch's launch), the host time of issuing
     the batch, and the device time of the materialisation and the compare of
-    each request's batch; aggregate compared bytes (both sides) per second."""
+    each request's batch; aggregate compared bytes (both sides) per second;
+    the device-busy fraction: the union of the batches' device intervals
+    (first event to last, over all streams) divided by the wall time."""
     def pct(values, p):
         return round(float(np.percentile(np.array(values) if values else np.zeros(1), p)) * 1e3, 3)
 
@@ -308,6 +325,11 @@ def summarize(done, wall_s: float) -> dict:
     mat = [d.materialize_s for d in done]
     cmp_ = [d.compare_s for d in done]
     nbytes = sum(2 * d.nbytes for d in done)
+    busy, end = 0.0, float("-inf")
+    for a, b in sorted({(d.dev_start_s, d.dev_end_s) for d in done}):
+        if b > end:
+            busy += b - max(a, end)
+            end = b
     return dict(requests=len(done), p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
                 queue_p50_ms=pct(q, 50), queue_p99_ms=pct(q, 99),
                 wait_p50_ms=pct(wait, 50), wait_p99_ms=pct(wait, 99),
@@ -315,4 +337,4 @@ def summarize(done, wall_s: float) -> dict:
                 materialize_p50_ms=pct(mat, 50), materialize_p99_ms=pct(mat, 99),
                 compare_p50_ms=pct(cmp_, 50), compare_p99_ms=pct(cmp_, 99),
                 aggregate_GBps=round(nbytes / max(wall_s, 1e-9) / 1e9, 1), compared_bytes=nbytes,
-                wall_s=round(wall_s, 3))
+                busy_frac=round(busy / max(wall_s, 1e-9), 4), wall_s=round(wall_s, 3))

@@ -88,3 +88,13 @@ def test_run_pauses_and_restores_the_cycle_collector():
         assert not gc.isenabled()
     finally:
         gc.enable()
+
+
+def test_busy_fraction_is_the_union_of_device_intervals():
+    """Requests of one batch share its device interval; overlapping batches on
+    different streams count once: busy = |[0,2] u [1,3] u [5,6]| = 4 of 10 s."""
+    mk = lambda rid, a, b: serve.Completed(rid, 0.0, 0.0, 0.0, 1.0, 1, [], 0.0, 0.0, 0.0, a, b)
+    done = [mk(0, 0.0, 2.0), mk(1, 0.0, 2.0), mk(2, 1.0, 3.0), mk(3, 5.0, 6.0)]
+    s = serve.summarize(done, 10.0)
+    assert s["busy_frac"] == 0.4 and s["requests"] == 4
+    assert serve.summarize([mk(0, 2.0, 3.0), mk(1, 2.5, 2.75)], 2.0)["busy_frac"] == 0.5
