@@ -437,8 +437,10 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
   KernelTimer timer(c, op, s);
   // read-only hashing runs best with twice the waves of the fused snapshot (which also writes and scans)
   uint32_t grid = grid_for(c, op, op == KC_OP_PAGE_HASH ? 8 : 4);
-  // large units give few tiles, each a long serial chain: one wave per tile rather than two tiles on some waves
+  // large units give few tiles, each a long serial chain: one wave per tile rather than two tiles on some
+  // waves, each wave keeping two chunks in flight
   if (rs->ushift > kMinUnitShift) grid = std::max(grid, std::min(rs->n_tiles, 16u * c->n_cu));
+  const bool deep = rs->ushift > kMinUnitShift && rs->n_tiles < 16u * c->n_cu && !scan;
   hp.ushift = rs->ushift;
   if (!c->tune[op].per_item) {
     hp.tiles = rs->tiles;
@@ -446,7 +448,7 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     hp.tile0 = 0;
     hp.ragged = rs->ragged;
     hp.n_ragged = rs->n_ragged;
-    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, c->n_cu, s));
+    KC_HIP(launch_page_hash(hp, gather, prior, scan, deep, grid, c->n_cu, s));
     return KC_OK;
   }
   for (uint32_t r = 0; r < rs->n_ranges; ++r) {
@@ -456,7 +458,7 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     const bool rg = rs->ragged_of[r] != UINT32_MAX;
     hp.ragged = rg ? rs->ragged + rs->ragged_of[r] : nullptr;
     hp.n_ragged = rg ? 1u : 0u;
-    KC_HIP(launch_page_hash(hp, gather, prior, scan, grid, c->n_cu, s));
+    KC_HIP(launch_page_hash(hp, gather, prior, scan, deep, grid, c->n_cu, s));
   }
   return KC_OK;
 }
@@ -746,7 +748,9 @@ int plan_pairs(const kc_pair* pairs, uint32_t n_pairs, uint32_t tile_bytes, std:
     if (!(pr.atol >= 0.0) || !(pr.rtol >= 0.0)) return KC_EINVAL;  // negative or NaN tolerances
     if (pr.n_elems > 0) {
       if (pr.cand_d == nullptr || pr.gold_d == nullptr) return KC_EINVAL;
-      if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & 15u) return KC_EALIGN;
+      // element-aligned buffers; those not 16-byte aligned take the element-wise path
+      if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & (elem_size(pr.dtype) - 1u))
+        return KC_EALIGN;
     }
     const uint64_t nb = pr.n_elems * elem_size(pr.dtype);
     const uint64_t nt = nb == 0 ? 1 : (nb + tile_bytes - 1) / tile_bytes;

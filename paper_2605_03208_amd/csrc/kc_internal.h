@@ -223,7 +223,8 @@ enum : uint32_t {
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint64_t* c, uint64_t nc,
                         hipStream_t s);
-hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan,
+// deep: the two-chunk pipeline of large units (few tiles, about one wave per SIMD); not with scan
+hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, bool deep,
                             uint32_t grid, uint32_t n_cu, hipStream_t s);
 hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t ushift,
                              uint32_t grid, hipStream_t s);

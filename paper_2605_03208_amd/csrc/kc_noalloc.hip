@@ -68,7 +68,9 @@ int kc_compare_noalloc(kc_ctx* c, const kc_pair* pairs, uint32_t n_pairs, kc_cmp
     if (!(pr.atol >= 0.0) || !(pr.rtol >= 0.0)) return KC_EINVAL;
     if (pr.n_elems > 0) {
       if (pr.cand_d == nullptr || pr.gold_d == nullptr) return KC_EINVAL;
-      if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & 15u) return KC_EALIGN;
+      // element-aligned buffers; those not 16-byte aligned take the element-wise path
+      if ((reinterpret_cast<uintptr_t>(pr.cand_d) | reinterpret_cast<uintptr_t>(pr.gold_d)) & (elem_size(pr.dtype) - 1u))
+        return KC_EALIGN;
     }
     if (i % kArgPairs == 0) chunk_tiles = 0;
     const uint64_t nb = pr.n_elems * elem_size(pr.dtype);

@@ -306,6 +306,102 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
   }
 }
 
+// The hashing pass for large units, whose few tiles leave about one wave per
+// SIMD: with no other wave to switch to, a wave must cover the memory latency
+// itself.  Two chunks are in flight (registers a and b alternate): while chunk
+// c is staged, stored and hashed, chunk c+1 is already loading, and the loads
+// of chunk c+2 are issued after chunk c's stores, so waiting for chunk c+1
+// never waits for those stores.  Whole units only (partial last units go to
+// the ragged launch of k_page_hash); no closure scan (it runs as its own pass
+// at units above 4 KiB).
+template <bool GATHER, bool PRIOR>
+__global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_page_hash_deep(
+    HashParams p) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage_all[kHashWaves][kTilePages * kStageStride];
+  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+  uint8_t* const stage = stage_all[wv];
+  const uint32_t q = lane >> 2, k = lane & 3u;
+  const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
+  const uint32_t ushift = p.ushift, unit = 1u << ushift;
+  const uint32_t n_chunks = unit / kChunk;  // even: units are 4 KiB or more
+  const uint32_t wave = blockIdx.x * wpb + wv, n_waves = gridDim.x * wpb;
+  for (uint32_t t = wave; t < p.n_tiles; t += n_waves) {
+    const Tile tile = p.tiles[t];
+    if (tile.last_len != unit) continue;  // left to the ragged launch
+    const uint32_t np = tile.npages;
+    const uint64_t va = tile.va;
+    uint32_t keep = (1u << np) - 1u;
+    uint64_t slot_j[8];
+    if (GATHER) {
+      uint64_t slot = 0;
+      bool kept = false;
+      if (lane < np) {
+        const uint64_t g = (uint64_t)tile.g + lane;
+        const uint64_t zw = p.zero_bm[g >> 6];
+        kept = ((zw >> (g & 63u)) & 1ull) == 0ull;
+        slot = p.word_prefix[g >> 6] + (uint64_t)__popcll(~zw & ((1ull << (g & 63u)) - 1ull));
+      }
+      keep = (uint32_t)__ballot(kept);
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) slot_j[j] = __shfl(slot, 2 * j + half, 64);
+      if (kept && slot < p.cap_pages) p.page_va[slot] = va + ((uint64_t)lane << ushift);
+    }
+    uint32_t nonzero = 0;
+    uint64_t acc = acc_init(p.seed, k);
+    auto load = [&](uint4 (&r)[8], uint32_t c) {
+      const uint32_t on = c < n_chunks ? keep : 0u;
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t pg = 2 * j + half;
+        r[j] = ((on >> pg) & 1u) ? ld16nt(va + ((uint64_t)pg << ushift) + c * kChunk + off16) : make_uint4(0, 0, 0, 0);
+      }
+    };
+    // chunk c in r: stage (and store to the packed slots), reload r with chunk c + 2, hash chunk c
+    auto step = [&](uint4 (&r)[8], uint32_t c) {
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t pg = 2 * j + half;
+        const uint4 v = r[j];
+        if (!GATHER) {
+          const uint64_t b = __ballot(nz16(v));
+          nonzero |= ((uint32_t)((uint32_t)b != 0u) << (2 * j)) | ((uint32_t)((b >> 32) != 0ull) << (2 * j + 1));
+        }
+        if (GATHER && ((keep >> pg) & 1u) && slot_j[j] < p.cap_pages)
+          st16nt((uint64_t)p.packed + (slot_j[j] << ushift) + c * kChunk + off16, v);
+        *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
+      }
+      wave_lds_order();
+      load(r, c + 2);
+      const uint8_t* row = stage + q * kStageStride + k * 8u;
+#pragma unroll
+      for (uint32_t s = 0; s < kChunk / 32; ++s) acc = xround(acc, *reinterpret_cast<const uint64_t*>(row + s * 32u));
+      wave_lds_order();
+    };
+    uint4 a[8], b[8];
+    load(a, 0);
+    load(b, 1);
+#pragma unroll 1
+    for (uint32_t c = 0; c < n_chunks; c += 2) {
+      step(a, c);
+      step(b, c + 1);
+    }
+    const uint64_t merged = xxh64_merge4(acc, k);  // every lane of the quad takes part
+    const uint64_t h = xxh64_avalanche(merged + unit);
+    const bool mine = (k == 0u) && (q < np);
+    if (mine) p.hash[tile.g + q] = h;
+    const uint32_t valid = (1u << np) - 1u;
+    if (!GATHER) {
+      const uint32_t zero = ~nonzero & valid;
+      if (lane == 0) or_page_bits(p.zero_bm, tile.g, np, zero);
+    }
+    if (PRIOR) {
+      const bool ch = mine && (h != p.prior[tile.g + q]);
+      const uint32_t cb = quad_bits(__ballot(ch));
+      if (lane == 0) or_page_bits(p.changed_bm, tile.g, np, cb);
+    }
+  }
+}
+
 // ------------------------------------------------------------ zero probe --
 // Exact zero bitmap.  A wave takes four tiles at a time, one lane per unit:
 // each lane reads the first 16 bytes of its unit; a unit whose first 16 bytes
@@ -848,13 +944,28 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t grid,
+hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, bool deep, uint32_t grid,
                             uint32_t n_cu, hipStream_t s) {
   if (p.n_tiles == 0) return hipSuccess;
   uint32_t blocks = 1, wpb = 1, blocks_r = 1, wpb_r = 1;  // grid counts waves
   wide_shape(std::min(grid, p.n_tiles), n_cu, &blocks, &wpb, kHashWaves);
   wide_shape(std::min(grid, std::max(1u, p.n_ragged)), n_cu, &blocks_r, &wpb_r, kHashWaves);
   const size_t lds = scan ? wide_lds_bytes(p.scan.rt) : 0;
+  if (deep && !scan) {  // whole units through the two-chunk pipeline, partial last units through the ragged launch
+#define KC_DEEP_CASE(G, P)                                                                                 \
+    if (gather == G && prior == P) {                                                                       \
+      hipLaunchKernelGGL((k_page_hash_deep<G, P>), dim3(blocks), dim3(wpb * kWave), 0, s, p);             \
+      hipError_t e = hipGetLastError();                                                                   \
+      if (e != hipSuccess || p.n_ragged == 0) return e;                                                   \
+      hipLaunchKernelGGL((k_page_hash<G, P, false, true>), dim3(blocks_r), dim3(wpb_r * kWave), 0, s, p); \
+      return hipGetLastError();                                                                           \
+    }
+    KC_DEEP_CASE(false, false)
+    KC_DEEP_CASE(false, true)
+    KC_DEEP_CASE(true, false)
+#undef KC_DEEP_CASE
+    return hipErrorInvalidValue;
+  }
 #define KC_HASH_CASE(G, P, S)                                                                              \
   if (gather == G && prior == P && scan == S) {                                                           \
     hipLaunchKernelGGL((k_page_hash<G, P, S, false>), dim3(blocks), dim3(wpb * kWave), lds, s, p);        \

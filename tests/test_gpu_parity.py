@@ -432,11 +432,49 @@ def test_compare_c3_scaled(kc, ctx):
         c2.close()
 
 
+def test_compare_unaligned_views(kc, ctx):
+    """Views at odd element offsets (both sides, one side, different offsets)
+    on every element type: each report equal to the oracle's, and to the
+    aligned copies' report."""
+    say("compare views at odd element offsets vs oracle")
+    rng = np.random.default_rng(91)
+    gen = torch.Generator().manual_seed(91)
+    pairs, aligned = [], []
+    for dt in ALL_DTS:
+        t = W.TORCH_DTYPE[dt]
+        for n, (oc, og) in ((1000, (1, 1)), (4099, (3, 0)), (70001, (0, 5)), (65536, (2, 7)), (5, (1, 2))):
+            if t in W.INT_TYPES:
+                gold = torch.randint(-100, 100, (n,), generator=gen, dtype=torch.int64).to(t)
+            elif dt == W.DT_U8:
+                gold = torch.randint(0, 256, (n,), generator=gen, dtype=torch.int64).to(torch.uint8)
+            else:
+                gold = (torch.randn(n, generator=gen, dtype=torch.float64)).to(t)
+            gold = gold.cuda()
+            if dt == W.DT_U8:
+                cand = gold.clone()
+                idx = torch.from_numpy(rng.choice(n, size=min(n, 9), replace=False)).cuda()
+                cand[idx] ^= 0x11
+            else:
+                nan = 0 if t in W.INT_TYPES or n < 10 else 2
+                cand = W.perturb_pair(gold, dt, rng, max(1, n // 300), 4, n_nan=nan, ulp_tol=2).cand
+            cbuf = torch.empty(n + 8, dtype=t, device="cuda")
+            gbuf = torch.empty(n + 8, dtype=t, device="cuda")
+            cbuf[oc:oc + n] = cand
+            gbuf[og:og + n] = gold
+            pairs.append((cbuf[oc:oc + n], gbuf[og:og + n], dt, 2, 1e-7, 1e-4))
+            aligned.append((cand, gold, dt, 2, 1e-7, 1e-4))
+    got = cmp_vs_oracle(kc, ctx, pairs)
+    assert got == kc.decode_cmp(kc.compare(ctx, aligned), len(aligned))
+    assert sum(r["n_mismatch_elems"] for r in got) > 0
+    for tb in (16384, 65536):   # several tiles per pair, tiles ending mid-pair
+        assert cmp_vs_oracle(kc, ctx, pairs, tile_bytes=tb) == got
+
+
 def test_compare_errors(kc, ctx):
     say("compare argument errors")
     a = torch.zeros(64, dtype=torch.uint8, device="cuda")
-    with pytest.raises(kc.KCError) as ei:
-        kc.compare(ctx, [(a[1:33], a[1:33], W.DT_U8, 0)])
+    with pytest.raises(kc.KCError) as ei:                # fp32 elements at an odd byte address
+        kc.compare(ctx, [(a[1:33], a[1:33], W.DT_F32, 0)])
     assert ei.value.code == kc.EALIGN
     arr, n = kc.make_pairs([(a, a, W.DT_U8, 0)])
     arr[0].dtype = 13
