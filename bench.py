@@ -32,6 +32,7 @@ import argparse
 import hashlib
 import json
 import os
+import shutil
 import sys
 import time
 
@@ -218,6 +219,8 @@ def main() -> int:
                     help="only measure the small latency-bound case (64 MiB snapshot + restore + compare) and exit")
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the serving measurement (c5 and the overload burst) and exit")
+    ap.add_argument("--units-only", action="store_true",
+                    help="only measure snapshot and restore of the pool at 4 KiB, 64 KiB and 2 MiB hash units")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -253,6 +256,10 @@ def main() -> int:
     log(f"generating the MoE pool at scale {args.scale}")
     case = W.c4_snapshot("cuda", scale=args.scale)
     ranges = case.ranges()
+    if args.units_only:
+        ctx = kc.Context(0)
+        print(json.dumps({"hash_units": hash_units(torch, kc, ctx, case, ranges, args.steps)}), flush=True)
+        return 0
     golden = case.arena.buf.clone()
     ctx = kc.Context(0)
     rs = kc.RangeSet(ctx, ranges)
@@ -854,33 +861,97 @@ def batching(torch, kc, W, dev, tune: bool = True) -> dict:
     return out
 
 
+def _mount_of(path: str) -> dict:
+    """The mount holding ``path`` (longest matching mount point in
+    /proc/mounts): device, file system type, and whether it is held in memory."""
+    path = os.path.realpath(path)
+    best = ("", "", "")
+    try:
+        with open("/proc/mounts") as f:
+            for line in f:
+                dev, mnt, fs = line.split()[:3]
+                mnt = mnt.replace("\\040", " ")
+                if (path == mnt or path.startswith(mnt.rstrip("/") + "/")) and len(mnt) >= len(best[1]):
+                    best = (dev, mnt, fs)
+    except OSError:
+        pass
+    dev, mnt, fs = best
+    info = {"device": dev, "mount": mnt, "fstype": fs, "in_memory": fs in ("tmpfs", "ramfs")}
+    name = os.path.basename(dev)
+    for blk in (name, name.rstrip("0123456789").rstrip("p") if name.startswith("nvme") else name.rstrip("0123456789")):
+        model = f"/sys/block/{blk}/device/model"
+        if blk and os.path.exists(model):
+            info["model"] = open(model).read().strip()
+            info["rotational"] = open(f"/sys/block/{blk}/queue/rotational").read().strip() == "1"
+            break
+    return info
+
+
+def _disk_dir(min_free: int):
+    """A directory on a block device (not a memory file system) with room to spare, else None."""
+    cands = [os.environ.get("GRAFT_REPO_ROOT", ""), os.path.dirname(os.path.abspath(__file__)), "/var/tmp",
+             os.path.expanduser("~"), "/tmp"]
+    for c in cands:
+        if c and os.path.isdir(c) and os.access(c, os.W_OK):
+            m = _mount_of(c)
+            if not m["in_memory"] and m["fstype"] not in ("", "proc", "sysfs") and \
+                    shutil.disk_usage(c).free > min_free:
+                return c, m
+    return None, None
+
+
 def snapshot_files(torch, kc, W, dev) -> dict:
     """The packed snapshot of the 2 GiB / 4096-range pool streamed to host
     files and loaded back (the paper's capture writes regions to files at
-    ~1.7 GB/s, Sec. 5.3), through 64 MiB pinned double buffers."""
-    import shutil
+    ~1.7 GB/s, Sec. 5.3), through four 64 MiB pinned buffers, to a memory file
+    system and to a directory on a block device.  Each side reports the wall
+    time split into waiting for device copies and file I/O.  On the block
+    device the save is also made durable (fsync of every file, timed apart),
+    the files' cached pages are then dropped (fadvise), and the load reads
+    them back from the device."""
     import tempfile
-    log("snapshot files: c2 full snapshot saved and loaded back")
+    log("snapshot files: c2 full snapshot saved and loaded back, RAM and block-device targets")
     case = W.c2_snapshot("cuda")
     ctx = kc.Context(0)
     rs = kc.RangeSet(ctx, case.ranges())
     out = kc.snapshot(ctx, rs, seed=2)
     torch.cuda.synchronize()
-    base = "/dev/shm" if os.path.isdir("/dev/shm") and shutil.disk_usage("/dev/shm").free > (8 << 30) else None
-    d = tempfile.mkdtemp(prefix="kc_snap_", dir=base)
-    try:
-        save = kc.snapshot_save(ctx, rs, os.path.join(d, "s"), out, seed=2)
-        back, load = kc.snapshot_load(ctx, rs, os.path.join(d, "s"))
-        ok = bool(torch.equal(back["packed"][: int(out["n_kept"].item()) * PAGE],
-                              out["packed"][: int(out["n_kept"].item()) * PAGE]))
-    finally:
-        shutil.rmtree(d, ignore_errors=True)
-    res = {"workload": "c2 full snapshot (4096 ranges, 2 GiB)", "target": base or tempfile.gettempdir(),
-           "bytes": save["bytes"], "save_GBps": round(save["bytes"] / save["seconds"] / 1e9, 2),
-           "load_GBps": round(load["bytes"] / load["seconds"] / 1e9, 2), "reload_identical": ok}
+    n_kept = int(out["n_kept"].item())
+    shm = "/dev/shm" if os.path.isdir("/dev/shm") and shutil.disk_usage("/dev/shm").free > (8 << 30) else None
+    disk, disk_mount = _disk_dir(8 << 30)
+    res = {"workload": "c2 full snapshot (4096 ranges, 2 GiB)"}
+    for label, base, mount in (("ram", shm, _mount_of(shm) if shm else None), ("disk", disk, disk_mount)):
+        if base is None:
+            res[label] = None
+            continue
+        d = tempfile.mkdtemp(prefix="kc_snap_", dir=base)
+        try:
+            sd = os.path.join(d, "s")
+            save = kc.snapshot_save(ctx, rs, sd, out, seed=2)
+            r = {"dir": base, "mount": mount, "bytes": save["bytes"],
+                 "save_GBps": round(save["bytes"] / save["seconds"] / 1e9, 2), "save_s": round(save["seconds"], 4),
+                 "save_copy_wait_s": round(save["copy_wait_s"], 4), "save_file_s": round(save["file_s"], 4)}
+            if label == "disk":
+                t0 = time.perf_counter()
+                for name in os.listdir(sd):
+                    fd = os.open(os.path.join(sd, name), os.O_RDONLY)
+                    os.fsync(fd)
+                    os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)   # the load must come from the device
+                    os.close(fd)
+                fs = time.perf_counter() - t0
+                r["fsync_s"] = round(fs, 4)
+                r["save_durable_GBps"] = round(save["bytes"] / (save["seconds"] + fs) / 1e9, 2)
+            back, load = kc.snapshot_load(ctx, rs, sd)
+            r.update(load_GBps=round(load["bytes"] / load["seconds"] / 1e9, 2), load_s=round(load["seconds"], 4),
+                     load_copy_wait_s=round(load["copy_wait_s"], 4), load_file_s=round(load["file_s"], 4),
+                     reload_identical=bool(torch.equal(back["packed"][: n_kept * PAGE], out["packed"][: n_kept * PAGE])))
+            del back
+        finally:
+            shutil.rmtree(d, ignore_errors=True)
+        res[label] = r
     rs.close()
     ctx.close()
-    del case, out, back
+    del case, out
     torch.cuda.empty_cache()
     return res
 
@@ -907,8 +978,9 @@ def serving(torch, kc, W, dev, seconds: float) -> dict:
     summ.update(offered_req_per_s=200.0, budget_GiB=32, budget_peak_GiB=round(srv.budget.peak / 2**30, 2),
                 streams=4, pool_buffers=len(golds),
                 pool_GiB=round(sum(g.numel() * g.element_size() for g in golds) / 2**30, 2))
-    log(f"serving: overload burst (2,000 req/s for {seconds / 3:.1f} s)")
-    burst = W.c5_requests(rate_hz=2000.0, duration_s=seconds / 3)
+    burst_s = min(2.0, seconds / 3)   # long enough to fill the budget; longer only lengthens the queue
+    log(f"serving: overload burst (2,000 req/s for {burst_s:.1f} s)")
+    burst = W.c5_requests(rate_hz=2000.0, duration_s=burst_s)
     burst = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in burst]
     srv2 = serve.Server(ex, 32 << 30)
     t0 = time.perf_counter()

@@ -70,7 +70,7 @@ extern "C" {
 #endif
 
 #define KC_PAGE_SIZE 4096u
-#define KC_ABI_VERSION 5
+#define KC_ABI_VERSION 6
 #define KC_GRAPH_MAX_RANGES 16384u /* kc_pointer_graph: at most 32 MiB of edges */
 #define KC_NOALLOC_MAX_PAIRS 4096u /* kc_compare_noalloc: pairs per call (2 MiB of static scratch) */
 
@@ -79,7 +79,7 @@ enum {
   KC_OK = 0,
   KC_EINVAL = -1,  /* null where non-null is required, empty range, base 0,
                       bad window, size overflow                            */
-  KC_EALIGN = -2,  /* range base not 4096-aligned / buffer not 16-byte aligned */
+  KC_EALIGN = -2,  /* range base not 4096-aligned / buffer not aligned to its element size */
   KC_EORDER = -3,  /* ranges unsorted or overlapping                       */
   KC_ENOMEM = -4,  /* device or pinned host allocation failed             */
   KC_EHIP = -5,    /* a HIP runtime call failed; see kc_last_error()       */
@@ -145,8 +145,11 @@ typedef struct {
   uint64_t oob_cap;
 } kc_scan_args;
 
-/* One candidate / golden pair for kc_compare.  Both buffers 16-byte aligned
- * device memory of n_elems elements of `dtype`. */
+/* One candidate / golden pair for kc_compare.  Both buffers device memory of
+ * n_elems elements of `dtype`, each aligned to the element size (else
+ * KC_EALIGN).  Pairs whose buffers are both 16-byte aligned stream 16-byte
+ * runs; others (views at odd element offsets) are read element by element,
+ * with the same results. */
 typedef struct {
   const void *cand_d;
   const void *gold_d;
@@ -494,8 +497,10 @@ int kc_perturb(kc_ctx *ctx, void *arena_d, uint64_t arena_elems, uint32_t dtype,
  *      fixed-size chunks, metadata written before the data) ------------------ */
 
 typedef struct {
-  uint64_t bytes;  /* data bytes moved (metadata files not counted) */
-  double seconds;  /* wall time of the call                          */
+  uint64_t bytes;     /* data bytes moved (metadata files not counted)       */
+  double seconds;     /* wall time of the call                                 */
+  double copy_wait_s; /* of which the host waited for device copies           */
+  double file_s;      /* of which the host spent in file writes (reads)       */
 } kc_io_stats;
 
 /* Write a snapshot to directory `dir` (created if missing): manifest.json
@@ -503,8 +508,11 @@ typedef struct {
  * header.bin + ranges.bin (the same metadata, binary) first, then hash.bin
  * (N u64), zero_bm.bin, changed_bm.bin (delta snapshots: changed_bm_d non-NULL),
  * page_va.bin (min(n_kept, cap_pages) u64) and packed.bin (that many pages).
- * Device-to-host copies go through two pinned buffers of chunk_bytes (0 = 64
- * MiB) on `stream`, overlapping the file writes.  Synchronous: returns when the
+ * Device-to-host copies go through four pinned buffers of chunk_bytes (0 = 64
+ * MiB) on `stream`: while one chunk is written, the copies of the next three
+ * are in flight.  *stats (may be NULL) receives the data bytes, the wall time,
+ * and how much of it the host spent waiting for copies and inside file
+ * writes (which of the two bounds the save).  Synchronous: returns when the
  * files are complete.  Allocates pinned memory for the call.  Errors:
  * KC_EINVAL (bad arguments, file system errors; see kc_last_error), KC_EHIP. */
 int kc_snapshot_save(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
@@ -523,8 +531,10 @@ int kc_snapshot_save(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
  * truncated (cap_pages below its kept count at save time, so fewer packed
  * pages than kept pages) is refused with KC_ELIMIT: a restore from it would
  * leave the missing pages unwritten.  On success *n_kept_d equals the number
- * of packed pages loaded.  Host-to-device copies are chunked and
- * double-buffered like the save.  Synchronous. */
+ * of packed pages loaded.  Host-to-device copies are chunked like the save
+ * (a chunk is read while the copies of up to three earlier ones are in
+ * flight); *stats splits the time into copy waits and file reads.
+ * Synchronous. */
 int kc_snapshot_load(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
                      uint64_t *hash_d, uint64_t *zero_bm_d,
                      uint64_t *changed_bm_d, void *packed_d,

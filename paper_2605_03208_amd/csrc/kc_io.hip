@@ -1,5 +1,6 @@
 // kc_io.hip -- snapshot files: the packed snapshot streamed to host files
-// through pinned, double-buffered chunks, and loaded back for a restore.
+// through pinned chunk buffers (copies running ahead of the file writes), and
+// loaded back for a restore.
 #include <errno.h>
 #include <fcntl.h>
 #include <sys/stat.h>
@@ -16,17 +17,20 @@
 
 namespace kc {
 
+// Pinned staging: kIoBufs chunk buffers, so that up to kIoBufs - 1 copies
+// run ahead of the file reads or writes.
+constexpr int kIoBufs = 4;
 struct Pinned {
-  uint8_t* p[2] = {nullptr, nullptr};
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  uint8_t* p[kIoBufs] = {};
+  hipEvent_t ev[kIoBufs] = {};
   ~Pinned() {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kIoBufs; ++i) {
       if (ev[i]) (void)hipEventDestroy(ev[i]);
       if (p[i]) (void)hipHostFree(p[i]);
     }
   }
   hipError_t init(size_t bytes) {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kIoBufs; ++i) {
       hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p[i]), bytes, hipHostMallocDefault);
       if (e != hipSuccess) return e;
       e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
@@ -35,6 +39,14 @@ struct Pinned {
     return hipSuccess;
   }
 };
+
+// Where the host thread's time went: waiting for device copies, and inside
+// file reads or writes.
+struct IoClock {
+  double copy_wait = 0.0, file = 0.0;
+};
+
+double now_s();
 
 namespace {
 
@@ -60,9 +72,10 @@ bool read_all(int fd, uint8_t* p, size_t n) {
 
 }  // namespace
 
-// Device -> file in chunks: chunk i+1 is copied while chunk i is written.
+// Device -> file in chunks: while chunk i is written, the copies of the
+// next kIoBufs - 1 chunks are in flight.
 int stream_to_file(const std::string& path, const void* src_d, uint64_t bytes, Pinned& pin, size_t chunk,
-                   hipStream_t s, std::string& err) {
+                   hipStream_t s, IoClock& ck, std::string& err) {
   const int fd = ::open(path.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
   if (fd < 0) {
     err = "cannot create " + path;
@@ -70,30 +83,39 @@ int stream_to_file(const std::string& path, const void* src_d, uint64_t bytes, P
   }
   const uint8_t* src = static_cast<const uint8_t*>(src_d);
   const uint64_t n_chunks = (bytes + chunk - 1) / chunk;
+  uint64_t issued = 0;
   int st = KC_OK;
-  for (uint64_t i = 0; i <= n_chunks && st == KC_OK; ++i) {
-    if (i < n_chunks) {
-      const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
-      hipError_t e = hipMemcpyAsync(pin.p[i & 1], src + off, len, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipEventRecord(pin.ev[i & 1], s);
+  for (uint64_t i = 0; i < n_chunks && st == KC_OK; ++i) {
+    // chunk j goes to buffer j % kIoBufs, free once chunk j - kIoBufs has been written
+    for (; issued < n_chunks && issued < i + kIoBufs; ++issued) {
+      const uint64_t off = issued * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+      hipError_t e = hipMemcpyAsync(pin.p[issued % kIoBufs], src + off, len, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(pin.ev[issued % kIoBufs], s);
       if (e != hipSuccess) {
         err = std::string("D2H copy: ") + hipGetErrorName(e);
         st = KC_EHIP;
         break;
       }
     }
-    if (i > 0) {
-      const uint64_t j = i - 1, off = j * chunk, len = std::min<uint64_t>(chunk, bytes - off);
-      hipError_t e = hipEventSynchronize(pin.ev[j & 1]);
-      if (e != hipSuccess) {
-        err = std::string("D2H wait: ") + hipGetErrorName(e);
-        st = KC_EHIP;
-      } else if (!write_all(fd, pin.p[j & 1], len)) {
-        err = "short write to " + path;
-        st = KC_EINVAL;
-      }
+    if (st != KC_OK) break;
+    const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+    double t = now_s();
+    hipError_t e = hipEventSynchronize(pin.ev[i % kIoBufs]);
+    ck.copy_wait += now_s() - t;
+    if (e != hipSuccess) {
+      err = std::string("D2H wait: ") + hipGetErrorName(e);
+      st = KC_EHIP;
+      break;
+    }
+    t = now_s();
+    const bool ok = write_all(fd, pin.p[i % kIoBufs], len);
+    ck.file += now_s() - t;
+    if (!ok) {
+      err = "short write to " + path;
+      st = KC_EINVAL;
     }
   }
+  if (st != KC_OK) (void)hipStreamSynchronize(s);  // no copy may still target the staging buffers
   if (::close(fd) != 0 && st == KC_OK) {
     err = "close " + path;
     st = KC_EINVAL;
@@ -101,9 +123,10 @@ int stream_to_file(const std::string& path, const void* src_d, uint64_t bytes, P
   return st;
 }
 
-// File -> device in chunks: chunk i+1 is read while chunk i is copied.
+// File -> device in chunks: chunk i is read while the copies of the previous
+// chunks (up to kIoBufs - 1) are in flight.
 int stream_from_file(const std::string& path, void* dst_d, uint64_t bytes, Pinned& pin, size_t chunk,
-                     hipStream_t s, std::string& err) {
+                     hipStream_t s, IoClock& ck, std::string& err) {
   const int fd = ::open(path.c_str(), O_RDONLY);
   if (fd < 0) {
     err = "cannot open " + path;
@@ -120,33 +143,39 @@ int stream_from_file(const std::string& path, void* dst_d, uint64_t bytes, Pinne
   int st = KC_OK;
   for (uint64_t i = 0; i < n_chunks && st == KC_OK; ++i) {
     const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
-    if (i >= 2) {  // the buffer's previous copy must have left it
-      hipError_t e = hipEventSynchronize(pin.ev[i & 1]);
+    const int b = (int)(i % kIoBufs);
+    if (i >= (uint64_t)kIoBufs) {  // the buffer's previous copy must have left it
+      const double t = now_s();
+      hipError_t e = hipEventSynchronize(pin.ev[b]);
+      ck.copy_wait += now_s() - t;
       if (e != hipSuccess) {
         err = std::string("H2D wait: ") + hipGetErrorName(e);
         st = KC_EHIP;
         break;
       }
     }
-    if (!read_all(fd, pin.p[i & 1], len)) {
+    const double t = now_s();
+    const bool ok = read_all(fd, pin.p[b], len);
+    ck.file += now_s() - t;
+    if (!ok) {
       err = "short read from " + path;
       st = KC_EINVAL;
       break;
     }
-    hipError_t e = hipMemcpyAsync(dst + off, pin.p[i & 1], len, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(pin.ev[i & 1], s);
+    hipError_t e = hipMemcpyAsync(dst + off, pin.p[b], len, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(pin.ev[b], s);
     if (e != hipSuccess) {
       err = std::string("H2D copy: ") + hipGetErrorName(e);
       st = KC_EHIP;
     }
   }
   ::close(fd);
-  if (st == KC_OK) {
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      err = std::string("H2D drain: ") + hipGetErrorName(e);
-      st = KC_EHIP;
-    }
+  const double t = now_s();
+  hipError_t e = hipStreamSynchronize(s);  // also on failure: no copy may still read the staging buffers
+  ck.copy_wait += now_s() - t;
+  if (st == KC_OK && e != hipSuccess) {
+    err = std::string("H2D drain: ") + hipGetErrorName(e);
+    st = KC_EHIP;
   }
   return st;
 }
@@ -270,6 +299,7 @@ int kc_snapshot_save(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   }
   Pinned pin;
   KC_HIP(pin.init(chunk));
+  IoClock ck;
   std::string err;
   struct Part {
     const char* name;
@@ -283,7 +313,7 @@ int kc_snapshot_save(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   uint64_t total = 0;
   for (const Part& p : parts) {
     if (p.src == nullptr && std::strcmp(p.name, "changed_bm.bin") == 0) continue;
-    const int st = stream_to_file(join(dir, p.name), p.src, p.bytes, pin, chunk, s, err);
+    const int st = stream_to_file(join(dir, p.name), p.src, p.bytes, pin, chunk, s, ck, err);
     if (st != KC_OK) {
       set_error_text(err.c_str());
       return st;
@@ -293,6 +323,8 @@ int kc_snapshot_save(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   if (stats) {
     stats->bytes = total;
     stats->seconds = now_s() - t0;
+    stats->copy_wait_s = ck.copy_wait;
+    stats->file_s = ck.file;
   }
   return KC_OK;
 }
@@ -346,6 +378,7 @@ int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   if (h.delta && changed_bm_d == nullptr) return KC_EINVAL;
   Pinned pin;
   KC_HIP(pin.init(chunk));
+  IoClock ck;
   std::string err;
   struct Part {
     const char* name;
@@ -359,7 +392,7 @@ int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   uint64_t total = 0;
   for (const Part& p : parts) {
     if (p.dst == nullptr || p.bytes == 0) continue;
-    const int st = stream_from_file(join(dir, p.name), p.dst, p.bytes, pin, chunk, s, err);
+    const int st = stream_from_file(join(dir, p.name), p.dst, p.bytes, pin, chunk, s, ck, err);
     if (st != KC_OK) {
       set_error_text(err.c_str());
       return st;
@@ -371,6 +404,8 @@ int kc_snapshot_load(kc_ctx* c, const kc_rangeset* rs, const char* dir, uint64_t
   if (stats) {
     stats->bytes = total;
     stats->seconds = now_s() - t0;
+    stats->copy_wait_s = ck.copy_wait;
+    stats->file_s = ck.file;
   }
   return KC_OK;
 }

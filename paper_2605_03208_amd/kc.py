@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
-ABI_VERSION = 5  # layout of the structs, the entry-point set and the range rules below
+ABI_VERSION = 6  # layout of the structs, the entry-point set and the range rules below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT, ERELOC = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
@@ -90,7 +90,8 @@ class CmpResult(ctypes.Structure):
 
 
 class IoStats(ctypes.Structure):
-    _fields_ = [("bytes", ctypes.c_uint64), ("seconds", ctypes.c_double)]
+    _fields_ = [("bytes", ctypes.c_uint64), ("seconds", ctypes.c_double), ("copy_wait_s", ctypes.c_double),
+                ("file_s", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -513,7 +514,8 @@ def snapshot_save(ctx: Context, rs: RangeSet, directory: str, out: dict, seed: i
                                   _ptr(out["zero_bm"]), _ptr(out.get("changed_bm")), _ptr(out["packed"]),
                                   _ptr(out["page_va"]), _ptr(out["n_kept"]), cap, chunk_bytes, _stream(stream),
                                   ctypes.byref(st)), "kc_snapshot_save")
-    return dict(bytes=int(st.bytes), seconds=float(st.seconds))
+    return dict(bytes=int(st.bytes), seconds=float(st.seconds), copy_wait_s=float(st.copy_wait_s),
+                file_s=float(st.file_s))
 
 
 def snapshot_load(ctx: Context, rs: RangeSet, directory: str, cap_pages: int | None = None, delta: bool = False,
@@ -530,7 +532,8 @@ def snapshot_load(ctx: Context, rs: RangeSet, directory: str, cap_pages: int | N
                                   _ptr(out["changed_bm"]), _ptr(out["packed"]), _ptr(out["page_va"]),
                                   _ptr(out["n_kept"]), cap, chunk_bytes, _stream(stream), ctypes.byref(st)),
            "kc_snapshot_load")
-    return out, dict(bytes=int(st.bytes), seconds=float(st.seconds))
+    return out, dict(bytes=int(st.bytes), seconds=float(st.seconds), copy_wait_s=float(st.copy_wait_s),
+                     file_s=float(st.file_s))
 
 
 class PairSet:

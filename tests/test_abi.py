@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(kc):
 
 
 def test_abi_version_and_strerror(kc):
-    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 5
+    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 6
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert kc.strerror(code) not in ("", "unknown status")
 

@@ -181,10 +181,13 @@ def test_serving_alone_equals_mix_and_oracle(kc):
     from paper_2605_03208_amd import serve
     golds, dtypes = W.c5_pool("cuda", scale=1 / 64, n_buffers=24)
     raw = W.c5_requests(rate_hz=2000.0, duration_s=0.02, n_buffers=24, max_k=6)
-    reqs = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in raw][:40]
+    # the first twelve arrive together, so that the first loop pass launches a batch on every stream before
+    # any can complete; the rest keep their Poisson arrival times and join while others are in flight
+    reqs = [serve.Request(r.rid, 0.0 if i < 12 else r.arrival_s, r.golden_ids, r.ulp_tol, r.seed)
+            for i, r in enumerate(raw[:40])]
     ex = serve.DeviceExecutor(golds, dtypes, n_streams=3)
-    budget = int(np.sort([ex.request_bytes(r) for r in reqs])[-1] * 3)
-    srv = serve.Server(ex, budget, max_batch=5)
+    budget = int(np.sort([ex.request_bytes(r) for r in reqs])[-1] * 8)
+    srv = serve.Server(ex, budget, max_batch=2)
     mix = {d.rid: d for d in srv.run(reqs)}
     assert len(mix) == len(reqs) and srv.budget.peak <= budget
     # the mix really mixed: some batch held several requests, and some batch
