@@ -440,7 +440,8 @@ def hash_units(torch, kc, ctx, case, ranges, reps: int) -> dict:
     dev = case.arena.buf.device
     pool = sum(int(s) for _, s in ranges)
     res = {}
-    for unit in (4096, 64 << 10, 2 << 20):
+    for unit, depth in ((4096, 0), (64 << 10, 0), (64 << 10, 2), (2 << 20, 0), (2 << 20, 4)):
+        ctx.set_tuning(kc.OP_SNAPSHOT, depth=depth)
         rs = kc.RangeSet(ctx, ranges, unit=unit)
         n = rs.n_pages
         out = dict(hash=torch.empty(n, dtype=torch.int64, device=dev),
@@ -472,7 +473,7 @@ def hash_units(torch, kc, ctx, case, ranges, reps: int) -> dict:
         restore_ms = ev0.elapsed_time(ev1) / reps
         snap_bytes = pool + 8 * n + n // 8 + kept * (unit + 8)
         restore_bytes = kept * (unit + 8) + pool
-        res[f"{unit // 1024}KiB"] = {
+        res[f"{unit // 1024}KiB" + (f"_depth{depth}" if depth else "")] = {
             "units": n, "kept_units": kept,
             "snapshot_ms": round(snap_ms, 4), "snapshot_GBps": round(snap_bytes / snap_ms / 1e6, 1),
             "hash_pass_ms": round(float(np.mean(kms)), 4),
@@ -482,6 +483,7 @@ def hash_units(torch, kc, ctx, case, ranges, reps: int) -> dict:
         rs.close()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    ctx.set_tuning(kc.OP_SNAPSHOT)
     return res
 
 

@@ -26,6 +26,7 @@
  *                    reachable from the kernel-argument words
  *   kc_perturb       the validation server's candidates: goldens moved by a
  *                    seeded perturbation, in place on the device
+ *   kc_materialize   the same candidates copied and moved in one pass
  *
  * Conventions
  *  - Pointers suffixed _d are device pointers owned by the caller; the
@@ -70,7 +71,7 @@ extern "C" {
 #endif
 
 #define KC_PAGE_SIZE 4096u
-#define KC_ABI_VERSION 6
+#define KC_ABI_VERSION 7
 #define KC_GRAPH_MAX_RANGES 16384u /* kc_pointer_graph: at most 32 MiB of edges */
 #define KC_NOALLOC_MAX_PAIRS 4096u /* kc_compare_noalloc: pairs per call (2 MiB of static scratch) */
 
@@ -200,7 +201,9 @@ typedef struct {
                            four-wave workgroups per compute unit)           */
   uint32_t tile_bytes;  /* compare: bytes of each side per work item        */
   uint32_t per_item;    /* 1 = one launch per range / pair (no batching)    */
-  uint32_t reserved;
+  uint32_t depth;       /* hashing pass without a fused scan: chunks in flight
+                           per wave, 1, 2 or 4 (more when few tiles leave
+                           about one wave per SIMD); 0 = built-in choice     */
 } kc_tuning;
 
 enum {
@@ -492,6 +495,32 @@ typedef struct {
 int kc_perturb(kc_ctx *ctx, void *arena_d, uint64_t arena_elems, uint32_t dtype,
                const kc_perturb_buf *bufs, uint32_t n_bufs, uint64_t block,
                uint32_t kmax, void *stream);
+
+/* One candidate to materialise: its golden (device, 16-byte aligned), its
+ * place in the arena (element offset; arena_d + offset elements 16-byte
+ * aligned), its length in elements and its seed (the low 31 bits are used). */
+typedef struct {
+  const void *src_d;
+  uint64_t offset, length;
+  uint32_t seed, reserved;
+} kc_materialize_buf;
+
+/* Copy and perturb in one pass: buffer b of arena_d becomes its golden moved
+ * by exactly the perturbation kc_perturb applies (same block, kmax and seed
+ * rules), so that the result equals a copy of each golden into the arena
+ * followed by kc_perturb, at one read of the golden and one write of the
+ * candidate.  Nothing outside [offset, offset + length) of each buffer is
+ * written and nothing past each golden is read.  Buffers may not overlap each
+ * other or their goldens.  The caller owns arena_d and every src_d; bufs
+ * (host) is read during the call only.  Asynchronous on `stream`; the buffer
+ * list goes in kernel arguments (no allocation, no host sync).  Errors, all
+ * detected before any launch except the last: KC_EINVAL (no context, a
+ * buffer past arena_elems, a null golden of nonzero length, block or kmax 0),
+ * KC_EDTYPE (KC_U8), KC_EALIGN (a golden or a destination not 16-byte
+ * aligned), KC_EHIP (a launch failed; kc_last_error names it). */
+int kc_materialize(kc_ctx *ctx, void *arena_d, uint64_t arena_elems, uint32_t dtype,
+                   const kc_materialize_buf *bufs, uint32_t n_bufs, uint64_t block,
+                   uint32_t kmax, void *stream);
 
 /* ---- snapshot files (Sec. 4.2.1: every region streamed to files in
  *      fixed-size chunks, metadata written before the data) ------------------ */

@@ -25,15 +25,15 @@ from . import kc
 ARCH = "gfx950"
 
 CANDIDATES = {
-    kc.OP_PAGE_HASH: [dict(grid_per_cu=g) for g in (2, 3, 4, 6, 8, 12)],
+    kc.OP_PAGE_HASH: [dict(grid_per_cu=g) for g in (2, 3, 4, 6, 8, 12, 16, 24)],
     kc.OP_SNAPSHOT: [dict(grid_per_cu=g) for g in (2, 3, 4, 6, 8, 12)],
-    kc.OP_COMPACT: [dict(grid_per_cu=g) for g in (4, 8, 16, 32)],
-    kc.OP_RESTORE: [dict(grid_per_cu=g) for g in (8, 12, 16, 24, 32)],
+    kc.OP_COMPACT: [dict(grid_per_cu=g) for g in (4, 8, 16, 32, 48, 64, 96, 128)],
+    kc.OP_RESTORE: [dict(grid_per_cu=g) for g in (8, 12, 16, 24, 32, 48, 64, 96, 128)],
     kc.OP_CLOSURE: [dict(grid_per_cu=g) for g in (4, 8, 16)],
     kc.OP_COMPARE: [dict(grid_per_cu=g, tile_bytes=t) for g in (1, 2, 3, 4)
                     for t in (32 << 10, 64 << 10, 128 << 10, 256 << 10)],
-    kc.OP_GRAPH: [dict(grid_per_cu=g) for g in (4, 8, 12, 16)],
-    kc.OP_REGION_DIFF: [dict(grid_per_cu=g) for g in (8, 12, 16, 20, 32)],
+    kc.OP_GRAPH: [dict(grid_per_cu=g) for g in (4, 8, 12, 16, 24, 32)],
+    kc.OP_REGION_DIFF: [dict(grid_per_cu=g) for g in (8, 12, 16, 20, 32, 48, 64)],
 }
 
 OP_NAMES = {kc.OP_PAGE_HASH: "page_hash", kc.OP_SNAPSHOT: "snapshot", kc.OP_COMPACT: "compact",

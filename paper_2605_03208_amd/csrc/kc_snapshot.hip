@@ -306,32 +306,55 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
   }
 }
 
-// The hashing pass for large units, whose few tiles leave about one wave per
-// SIMD: with no other wave to switch to, a wave must cover the memory latency
-// itself.  Two chunks are in flight (registers a and b alternate): while chunk
-// c is staged, stored and hashed, chunk c+1 is already loading, and the loads
-// of chunk c+2 are issued after chunk c's stores, so waiting for chunk c+1
-// never waits for those stores.  Whole units only (partial last units go to
-// the ragged launch of k_page_hash); no closure scan (it runs as its own pass
-// at units above 4 KiB).
-template <bool GATHER, bool PRIOR>
+// Buffer resource over [base, base + bytes) (gfx9 raw buffer, no stride):
+// loads outside it return zeros and stores outside it are dropped.  base and
+// bytes must be the same in every lane of the wave.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(uint64_t base, uint32_t bytes) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0,
+                                           (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+constexpr uint32_t kOutside = 0x80000000u;  // an offset beyond any resource made here (tiles are below 64 MiB)
+constexpr int kNt = 2;                      // cache policy: non-temporal
+
+// The hashing pass with DEPTH (2 or 4) chunks in flight per wave, for large
+// units whose few tiles leave about one wave per SIMD: with no other wave to
+// switch to, a wave must cover the memory latency itself.  DEPTH register sets
+// take turns: while chunk c is staged, stored and hashed, chunks c+1 ..
+// c+DEPTH-1 are already loading, and the loads of chunk c+DEPTH are issued
+// after chunk c's stores, so waiting for chunk c+1 never waits for those
+// stores.  The loads and stores go through
+// buffer resources bounded to the tile's bytes and to its kept units' packed
+// slots, so no lane branches around a memory access (a branch that may skip
+// one leaves the compiler unsure how many are in flight, and it then waits
+// for all of them): skipped units (zero units of a full snapshot, lanes past
+// the tile, chunks past the unit) use an offset outside the resource.  Every
+// tile goes through it, a tile's partial last unit included (at these sizes a
+// separate launch for the partial units would run as long as the main one,
+// after it); no closure scan (it runs as its own pass at units above 4 KiB).
+template <bool GATHER, bool PRIOR, uint32_t DEPTH>
 __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_page_hash_deep(
     HashParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t stage_all[kHashWaves][kTilePages * kStageStride];
+  __shared__ uint64_t tail_all[kHashWaves][kTilePages][4];  // a partial unit's bytes past its last whole stripe
   const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, wpb = blockDim.x / kWave;
   uint8_t* const stage = stage_all[wv];
+  uint64_t(*const tail_lds)[4] = tail_all[wv];
   const uint32_t q = lane >> 2, k = lane & 3u;
   const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
   const uint32_t ushift = p.ushift, unit = 1u << ushift;
-  const uint32_t n_chunks = unit / kChunk;  // even: units are 4 KiB or more
+  const uint32_t n_chunks = unit / kChunk;  // a multiple of DEPTH: units are 4 KiB (8 chunks) or more
   const uint32_t wave = blockIdx.x * wpb + wv, n_waves = gridDim.x * wpb;
   for (uint32_t t = wave; t < p.n_tiles; t += n_waves) {
     const Tile tile = p.tiles[t];
-    if (tile.last_len != unit) continue;  // left to the ragged launch
     const uint32_t np = tile.npages;
     const uint64_t va = tile.va;
+    const uint32_t last_pg = np - 1u, last_len = tile.last_len;  // only the last unit can be partial
     uint32_t keep = (1u << np) - 1u;
     uint64_t slot_j[8];
+    uint32_t st_off[8];  // each load's unit in the packed slots resource
+    __amdgpu_buffer_rsrc_t dst = raw_rsrc((uint64_t)p.packed, 0u);  // no slots: every store dropped
     if (GATHER) {
       uint64_t slot = 0;
       bool kept = false;
@@ -345,48 +368,89 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) slot_j[j] = __shfl(slot, 2 * j + half, 64);
       if (kept && slot < p.cap_pages) p.page_va[slot] = va + ((uint64_t)lane << ushift);
+      // the tile's kept units have consecutive slots from the first one's; those below the capacity are written
+      const uint64_t slot0 = __shfl(slot, keep ? __builtin_ctz(keep) : 0, 64);
+      const uint64_t n_kept = (uint64_t)__popc(keep);
+      const uint64_t room = slot0 < p.cap_pages ? min(n_kept, p.cap_pages - slot0) : 0ull;
+      dst = raw_rsrc((uint64_t)p.packed + (slot0 << ushift), (uint32_t)(room << ushift));
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j)
+        st_off[j] = ((keep >> (2 * j + half)) & 1u) ? (uint32_t)((slot_j[j] - slot0) << ushift) : kOutside;
+    }
+    // the tile's bytes, the last 16-byte block of a partial unit included (its bytes past the end are cleared
+    // when staged); loads of skipped units read nothing
+    const __amdgpu_buffer_rsrc_t src = raw_rsrc(va, ((last_pg << ushift) + last_len + 15u) & ~15u);
+    uint32_t ld_off[8];
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+      const uint32_t pg = 2 * j + half;
+      ld_off[j] = ((keep >> pg) & 1u) ? (pg << ushift) + off16 : kOutside;
     }
     uint32_t nonzero = 0;
     uint64_t acc = acc_init(p.seed, k);
+    // this lane's quad: stripes of its unit, and the bytes past the last stripe
+    const uint32_t qlen = q == last_pg ? last_len : unit;
+    const uint32_t lim = qlen / 32u, rem = qlen & 31u;
     auto load = [&](uint4 (&r)[8], uint32_t c) {
-      const uint32_t on = c < n_chunks ? keep : 0u;
+      const uint32_t so = c < n_chunks ? c * kChunk : kOutside;  // chunks past the unit: nothing
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t pg = 2 * j + half;
-        r[j] = ((on >> pg) & 1u) ? ld16nt(va + ((uint64_t)pg << ushift) + c * kChunk + off16) : make_uint4(0, 0, 0, 0);
+        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(src, ld_off[j], so, kNt);
+        r[j] = make_uint4(x[0], x[1], x[2], x[3]);
       }
     };
-    // chunk c in r: stage (and store to the packed slots), reload r with chunk c + 2, hash chunk c
+    // chunk c in r: stage (and store to the packed slots), reload r with chunk c + DEPTH, hash chunk c
     auto step = [&](uint4 (&r)[8], uint32_t c) {
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
         const uint32_t pg = 2 * j + half;
-        const uint4 v = r[j];
+        const uint4 v = clip16(r[j], c * kChunk + off16, pg == last_pg ? last_len : unit);
         if (!GATHER) {
           const uint64_t b = __ballot(nz16(v));
           nonzero |= ((uint32_t)((uint32_t)b != 0u) << (2 * j)) | ((uint32_t)((b >> 32) != 0ull) << (2 * j + 1));
         }
-        if (GATHER && ((keep >> pg) & 1u) && slot_j[j] < p.cap_pages)
-          st16nt((uint64_t)p.packed + (slot_j[j] << ushift) + c * kChunk + off16, v);
+        if (GATHER) {  // a partial unit's slot: zeros after its bytes
+          const v4u x = {v.x, v.y, v.z, v.w};
+          __builtin_amdgcn_raw_buffer_store_b128(x, dst, st_off[j] + off16, c * kChunk, kNt);
+        }
         *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
       }
       wave_lds_order();
-      load(r, c + 2);
+      load(r, c + DEPTH);
+      // the chunk's 16 words of this lane, read from the stage before the serial chain starts (one LDS wait)
       const uint8_t* row = stage + q * kStageStride + k * 8u;
+      uint64_t w[kChunk / 32];
 #pragma unroll
-      for (uint32_t s = 0; s < kChunk / 32; ++s) acc = xround(acc, *reinterpret_cast<const uint64_t*>(row + s * 32u));
+      for (uint32_t s = 0; s < kChunk / 32; ++s) w[s] = *reinterpret_cast<const uint64_t*>(row + s * 32u);
+      if (rem != 0u && c == lim / (kChunk / 32))  // a partial unit's last bytes are in this chunk
+        tail_lds[q][k] = *reinterpret_cast<const uint64_t*>(stage + q * kStageStride + (lim * 32u - c * kChunk) + 8u * k);
       wave_lds_order();
+      const uint32_t s_end = lim > c * (kChunk / 32) ? min(lim - c * (kChunk / 32), kChunk / 32) : 0u;
+#pragma unroll
+      for (uint32_t s = 0; s < kChunk / 32; ++s)
+        if (s < s_end) acc = xround(acc, w[s]);
     };
-    uint4 a[8], b[8];
-    load(a, 0);
-    load(b, 1);
+    uint4 r[DEPTH][8];
+#pragma unroll
+    for (uint32_t d = 0; d < DEPTH; ++d) {
+      load(r[d], d);
+      __builtin_amdgcn_sched_barrier(0);  // all of chunk d's loads before chunk d + 1's
+    }
 #pragma unroll 1
-    for (uint32_t c = 0; c < n_chunks; c += 2) {
-      step(a, c);
-      step(b, c + 1);
+    for (uint32_t c = 0; c < n_chunks; c += DEPTH) {
+#pragma unroll
+      for (uint32_t d = 0; d < DEPTH; ++d) {
+        step(r[d], c + d);
+        __builtin_amdgcn_sched_barrier(0);  // the steps in program order: each chunk's loads behind the last's
+      }
     }
     const uint64_t merged = xxh64_merge4(acc, k);  // every lane of the quad takes part
-    const uint64_t h = xxh64_avalanche(merged + unit);
+    uint64_t h = (lim > 0u ? merged : p.seed + kP5) + qlen;
+    if (rem != 0u) {
+      const uint64_t tail[4] = {tail_lds[q][0], tail_lds[q][1], tail_lds[q][2], tail_lds[q][3]};
+      h = xxh64_tail(h, tail, rem);
+    }
+    h = xxh64_avalanche(h);
     const bool mine = (k == 0u) && (q < np);
     if (mine) p.hash[tile.g + q] = h;
     const uint32_t valid = (1u << np) - 1u;
@@ -944,25 +1008,25 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, bool deep, uint32_t grid,
+hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t depth, uint32_t grid,
                             uint32_t n_cu, hipStream_t s) {
   if (p.n_tiles == 0) return hipSuccess;
   uint32_t blocks = 1, wpb = 1, blocks_r = 1, wpb_r = 1;  // grid counts waves
   wide_shape(std::min(grid, p.n_tiles), n_cu, &blocks, &wpb, kHashWaves);
   wide_shape(std::min(grid, std::max(1u, p.n_ragged)), n_cu, &blocks_r, &wpb_r, kHashWaves);
   const size_t lds = scan ? wide_lds_bytes(p.scan.rt) : 0;
-  if (deep && !scan) {  // whole units through the two-chunk pipeline, partial last units through the ragged launch
-#define KC_DEEP_CASE(G, P)                                                                                 \
-    if (gather == G && prior == P) {                                                                       \
-      hipLaunchKernelGGL((k_page_hash_deep<G, P>), dim3(blocks), dim3(wpb * kWave), 0, s, p);             \
-      hipError_t e = hipGetLastError();                                                                   \
-      if (e != hipSuccess || p.n_ragged == 0) return e;                                                   \
-      hipLaunchKernelGGL((k_page_hash<G, P, false, true>), dim3(blocks_r), dim3(wpb_r * kWave), 0, s, p); \
-      return hipGetLastError();                                                                           \
+  if (depth > 1u && !scan) {  // every tile, partial last units included, through the pipelined pass
+#define KC_DEEP_CASE(G, P, D)                                                                     \
+    if (gather == G && prior == P && depth == D) {                                                \
+      hipLaunchKernelGGL((k_page_hash_deep<G, P, D>), dim3(blocks), dim3(wpb * kWave), 0, s, p); \
+      return hipGetLastError();                                                                  \
     }
-    KC_DEEP_CASE(false, false)
-    KC_DEEP_CASE(false, true)
-    KC_DEEP_CASE(true, false)
+    KC_DEEP_CASE(false, false, 2u)
+    KC_DEEP_CASE(false, true, 2u)
+    KC_DEEP_CASE(true, false, 2u)
+    KC_DEEP_CASE(false, false, 4u)
+    KC_DEEP_CASE(false, true, 4u)
+    KC_DEEP_CASE(true, false, 4u)
 #undef KC_DEEP_CASE
     return hipErrorInvalidValue;
   }

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkc.so")
 PAGE = 4096
-ABI_VERSION = 6  # layout of the structs, the entry-point set and the range rules below
+ABI_VERSION = 7  # layout of the structs, the entry-point set and the range rules below
 
 OK, EINVAL, EALIGN, EORDER, ENOMEM, EHIP, EDTYPE, ELIMIT, ERELOC = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, BF16, F16, FP8_E4M3FN, U8 = 0, 1, 2, 3, 4
@@ -37,7 +37,7 @@ SYMBOLS = ["kc_strerror", "kc_last_error", "kc_abi_version", "kc_range_check", "
            "kc_restore", "kc_closure_scan", "kc_compare", "kc_pairset_create", "kc_pairset_destroy",
            "kc_compare_pairset", "kc_snapshot_save", "kc_snapshot_load", "kc_pointer_graph", "kc_graph_reach",
            "kc_region_diff", "kc_vaspace_create", "kc_vaspace_destroy", "kc_vaspace_suggest", "kc_perturb",
-           "kc_compare_noalloc", "kc_rangeset_create_unit"]
+           "kc_compare_noalloc", "kc_rangeset_create_unit", "kc_materialize"]
 
 
 class KCError(RuntimeError):
@@ -79,6 +79,16 @@ _PERTURB_NP = np.dtype([("offset", "<u8"), ("length", "<u8"), ("seed", "<u4"), (
 assert _PERTURB_NP.itemsize == ctypes.sizeof(PerturbBuf)
 
 
+class MaterializeBuf(ctypes.Structure):
+    _fields_ = [("src_d", ctypes.c_uint64), ("offset", ctypes.c_uint64), ("length", ctypes.c_uint64),
+                ("seed", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_MATERIALIZE_NP = np.dtype([("src_d", "<u8"), ("offset", "<u8"), ("length", "<u8"), ("seed", "<u4"),
+                            ("reserved", "<u4")])
+assert _MATERIALIZE_NP.itemsize == ctypes.sizeof(MaterializeBuf)
+
+
 class CmpResult(ctypes.Structure):
     _fields_ = [("n_elems", ctypes.c_uint64), ("n_mismatch_elems", ctypes.c_uint64),
                 ("n_mismatch_bytes", ctypes.c_uint64), ("first_mismatch", ctypes.c_uint64),
@@ -96,7 +106,7 @@ class IoStats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("grid_per_cu", ctypes.c_uint32), ("tile_bytes", ctypes.c_uint32),
-                ("per_item", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("per_item", ctypes.c_uint32), ("depth", ctypes.c_uint32)]
 
 
 RESULT_BYTES = 488
@@ -150,6 +160,7 @@ def lib() -> ctypes.CDLL:
             "kc_vaspace_destroy": ([vp], None),
             "kc_vaspace_suggest": ([i32, u64, P(u64)], i32),
             "kc_perturb": ([vp, vp, u64, u32, P(PerturbBuf), u32, u64, u32, vp], i32),
+            "kc_materialize": ([vp, vp, u64, u32, P(MaterializeBuf), u32, u64, u32, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -219,14 +230,15 @@ class Context:
         self.handle = ctypes.c_void_p()
         _check(lib().kc_ctx_create(ctypes.byref(self.handle), device), "kc_ctx_create")
 
-    def set_tuning(self, op: int, grid_per_cu: int = 0, tile_bytes: int = 0, per_item: int = 0) -> None:
-        t = Tuning(grid_per_cu, tile_bytes, per_item, 0)
+    def set_tuning(self, op: int, grid_per_cu: int = 0, tile_bytes: int = 0, per_item: int = 0,
+                   depth: int = 0) -> None:
+        t = Tuning(grid_per_cu, tile_bytes, per_item, depth)
         _check(lib().kc_ctx_set_tuning(self.handle, op, ctypes.byref(t)), "kc_ctx_set_tuning")
 
     def get_tuning(self, op: int) -> dict:
         t = Tuning()
         _check(lib().kc_ctx_get_tuning(self.handle, op, ctypes.byref(t)), "kc_ctx_get_tuning")
-        return dict(grid_per_cu=t.grid_per_cu, tile_bytes=t.tile_bytes, per_item=t.per_item)
+        return dict(grid_per_cu=t.grid_per_cu, tile_bytes=t.tile_bytes, per_item=t.per_item, depth=t.depth)
 
     timing = False
 
@@ -503,6 +515,24 @@ def perturb(ctx: Context, arena: torch.Tensor, offsets, lengths, seeds, block: i
     arr = (PerturbBuf * max(1, n)).from_buffer(a)
     _check(lib().kc_perturb(ctx.handle, _ptr(arena), arena.numel(), dt, arr, n, int(block), int(kmax),
                             _stream(stream)), "kc_perturb")
+
+
+def materialize(ctx: Context, arena: torch.Tensor, src_ptrs, offsets, lengths, seeds, block: int, kmax: int,
+                stream=None) -> None:
+    """kc_materialize: buffer b of the 1-D typed ``arena`` (element ``offsets[b]``,
+    ``lengths[b]`` elements) becomes the golden at device address ``src_ptrs[b]``
+    moved by the perturbation of ``seeds[b]``: a copy and kc_perturb in one pass."""
+    dt = TORCH_TO_KC.get(arena.dtype)
+    if dt is None:
+        raise KCError(EDTYPE, "kc_materialize")
+    n = len(offsets)
+    a = np.zeros(max(1, n), dtype=_MATERIALIZE_NP)
+    a["src_d"][:n] = np.asarray(src_ptrs, dtype=np.uint64)
+    a["offset"][:n], a["length"][:n] = np.asarray(offsets, dtype=np.int64), np.asarray(lengths, dtype=np.int64)
+    a["seed"][:n] = np.asarray(seeds, dtype=np.int64) & 0xFFFFFFFF
+    arr = (MaterializeBuf * max(1, n)).from_buffer(a)
+    _check(lib().kc_materialize(ctx.handle, _ptr(arena), arena.numel(), dt, arr, n, int(block), int(kmax),
+                                _stream(stream)), "kc_materialize")
 
 
 def snapshot_save(ctx: Context, rs: RangeSet, directory: str, out: dict, seed: int = 0, cap_pages=None,

@@ -134,6 +134,7 @@ class DeviceExecutor:
         self.numel_arr = np.array([g.numel() for g in goldens], dtype=np.int64)
         self.gold_ptr = np.array([g.data_ptr() for g in goldens], dtype=np.uint64)
         self.flat = [g.reshape(-1) for g in goldens]
+        self.one_pass = bool(np.all(self.gold_ptr % np.uint64(16) == 0))  # kc_materialize needs 16-byte goldens
         self.n_elems_arr = self.sizes // np.array([kc.ELEM_SIZE[d] for d in self.dtypes], dtype=np.int64)
         self.n_streams = n_streams
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
@@ -155,10 +156,12 @@ class DeviceExecutor:
         return (int(req.seed) * 1000003 + int(gid)) & 0x7FFFFFFF
 
     def launch(self, stream: int, reqs, now: float):
-        """Materialise the batch's candidates (per element type: one copy of
-        the goldens into a fresh arena, one kc_perturb launch) and run all
-        its pairs in one kc_compare launch.  The pair list is built from
-        arrays of addresses (no tensor per pair), in request order."""
+        """Materialise the batch's candidates (per element type: one
+        kc_materialize launch that copies and moves the goldens into a fresh
+        arena, or a copy and a kc_perturb launch where a golden is not 16-byte
+        aligned) and run all its pairs in one kc_compare launch.  The pair
+        list is built from arrays of addresses (no tensor per pair), in
+        request order."""
         torch, kc = self.torch, self.kc
         s = self.streams[stream]
         counts = np.array([len(r.golden_ids) for r in reqs], dtype=np.int64)
@@ -181,12 +184,16 @@ class DeviceExecutor:
                 padded = -(-lens // align) * align
                 offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
                 arena = torch.empty(int(padded.sum()), dtype=golds[0].dtype, device=s.device)
-                if np.array_equal(padded, lens):
-                    torch.cat(golds, out=arena)
+                if self.one_pass:
+                    kc.materialize(self.ctxs[stream], arena, self.gold_ptr[gids[sel]], offs, lens, seeds[sel],
+                                   self.block, self.kmax, stream=s)
                 else:
-                    for g, o, n in zip(golds, offs.tolist(), lens.tolist()):
-                        arena[o: o + n].copy_(g)
-                kc.perturb(self.ctxs[stream], arena, offs, lens, seeds[sel], self.block, self.kmax, stream=s)
+                    if np.array_equal(padded, lens):
+                        torch.cat(golds, out=arena)
+                    else:
+                        for g, o, n in zip(golds, offs.tolist(), lens.tolist()):
+                            arena[o: o + n].copy_(g)
+                    kc.perturb(self.ctxs[stream], arena, offs, lens, seeds[sel], self.block, self.kmax, stream=s)
                 arenas.append(arena)
                 cand_ptr[sel] = np.uint64(arena.data_ptr()) + offs.astype(np.uint64) * np.uint64(esz)
             pairs = kc.pairs_from_arrays(cand_ptr, self.gold_ptr[gids], self.n_elems_arr[gids], dts,

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(kc):
 
 
 def test_abi_version_and_strerror(kc):
-    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 6
+    assert kc.lib().kc_abi_version() == kc.ABI_VERSION == 7
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert kc.strerror(code) not in ("", "unknown status")
 
@@ -142,6 +142,28 @@ def test_perturb_rejects_bad_arguments_before_any_device_call(kc):
     assert L.kc_perturb(dummy, 0x1000, 10, kc.F32, bufs, 1, 0, 16, None) == kc.EINVAL
     assert L.kc_perturb(dummy, 0x1000, 10, kc.F32, bufs, 1, 1, 0, None) == kc.EINVAL
     assert L.kc_perturb(dummy, 0x1002, 10, kc.F32, bufs, 1, 1, 16, None) == kc.EALIGN
+
+
+def test_materialize_rejects_bad_arguments_before_any_device_call(kc):
+    """kc_materialize validates its arguments on the host: no context, an
+    unknown element type, a buffer past the arena, a null golden, block or
+    kmax 0, a golden or a destination off 16 bytes."""
+    L = kc.lib()
+    bufs = (kc.MaterializeBuf * 1)()
+    bufs[0].src_d, bufs[0].offset, bufs[0].length, bufs[0].seed = 0x2000, 4, 10, 1
+    assert L.kc_materialize(None, 0x1000, 14, kc.F32, bufs, 1, 1, 16, None) == kc.EINVAL
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.kc_materialize(dummy, 0x1000, 14, kc.U8, bufs, 1, 1, 16, None) == kc.EDTYPE
+    assert L.kc_materialize(dummy, 0x1000, 13, kc.F32, bufs, 1, 1, 16, None) == kc.EINVAL
+    assert L.kc_materialize(dummy, 0x1000, 14, kc.F32, bufs, 1, 0, 16, None) == kc.EINVAL
+    assert L.kc_materialize(dummy, 0x1000, 14, kc.F32, bufs, 1, 1, 0, None) == kc.EINVAL
+    assert L.kc_materialize(dummy, 0x1008, 14, kc.F32, bufs, 1, 1, 16, None) == kc.EALIGN
+    bufs[0].offset = 3
+    assert L.kc_materialize(dummy, 0x1000, 14, kc.F32, bufs, 1, 1, 16, None) == kc.EALIGN
+    bufs[0].offset, bufs[0].src_d = 4, 0x2004
+    assert L.kc_materialize(dummy, 0x1000, 14, kc.F32, bufs, 1, 1, 16, None) == kc.EALIGN
+    bufs[0].src_d = 0
+    assert L.kc_materialize(dummy, 0x1000, 14, kc.F32, bufs, 1, 1, 16, None) == kc.EINVAL
 
 
 def test_pair_arrays_marshal_like_pair_structs(kc):

@@ -283,6 +283,41 @@ def test_kc_perturb_equals_generator(kc, dt):
     ctx.close()
 
 
+@pytest.mark.parametrize("dt", [W.DT_F32, W.DT_BF16, W.DT_F64, W.DT_FP8_E4M3FNUZ, W.DT_I8, W.DT_I16, W.DT_I64])
+def test_kc_materialize_equals_copy_then_generator(kc, dt):
+    """One-pass candidates: each golden copied into its place in the arena and
+    moved exactly as the seeded generator moves it on the CPU; ragged lengths
+    (short last vectors, empty buffers), more buffers than one launch carries,
+    and the arena outside the buffers left as it was."""
+    say(f"kc_materialize vs copy + the generator, dtype {dt}")
+    ctx = kc.Context(0)
+    esz = W.ELEM_SIZE[dt]
+    rng = np.random.default_rng(100 + dt)
+    lens = rng.integers(0, 900, size=150)
+    lens[:6] = [0, 1, 16 // esz - 1, 16 // esz, 16 // esz + 1, 3]
+    host = _perturb_inputs(dt, int(lens.sum()), 11 + dt)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    golds = [host[a: a + n].to("cuda") for a, n in zip(starts.tolist(), lens.tolist())]
+    align = 16 // esz
+    room = -(-lens // align) * align + align      # a gap of at least one vector after every buffer
+    offs = np.concatenate([[0], np.cumsum(room)[:-1]]).astype(np.int64)
+    seeds = rng.integers(0, 2**31, size=len(lens))
+    iv = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}[esz]
+    for p_pert, kmax in ((1.0, 16), (1 / 3, 5), (1e-2, 16)):
+        block = max(1, int(round(1.0 / p_pert)))
+        arena = torch.full((int(room.sum()) * esz,), 0x5A, dtype=torch.uint8, device="cuda").view(host.dtype)
+        want = arena.cpu().clone()
+        for g, o, n in zip(golds, offs.tolist(), lens.tolist()):
+            want[o: o + n] = g.cpu()
+        W.perturb_many(want, dt, offs, lens, seeds, p_pert, kmax)
+        kc.materialize(ctx, arena, [g.data_ptr() for g in golds], offs, lens, seeds, block, kmax)
+        torch.cuda.synchronize()
+        assert torch.equal(arena.cpu().view(iv), want.view(iv)), p_pert
+    for g, a, n in zip(golds, starts.tolist(), lens.tolist()):   # goldens untouched
+        assert torch.equal(g.cpu().view(iv), host[a: a + n].view(iv))
+    ctx.close()
+
+
 def test_kc_perturb_offsets_past_4g_elements(kc):
     """Element offsets and moved-element indices past 2^32: a 4.5 GiB int8
     arena whose second buffer starts below 2^32 and ends above it."""

@@ -188,6 +188,44 @@ def test_units_snapshot_restore_scan_diff_files(kc, ctx, tmp_path, unit, n_range
     rs.close()
 
 
+@pytest.mark.parametrize("unit", [4096, 65536, 1 << 21])
+def test_hashing_depths_agree(kc, unit):
+    """The hashing pass with one chunk in flight per wave, with two and with
+    four (the pipeline of large units, forced here at every unit) gives the
+    same snapshot and delta, equal to the oracle."""
+    say(f"units {unit}: hashing pass at depth 1, 2 and 4")
+    case = W.units_case("cuda", unit=max(unit, 8192), n_ranges=20, seed=31)
+    ranges = case.ranges()
+    host = case.arena.host_copy().copy()
+    views = W.host_views(case.layout, host)
+    outs = []
+    for depth in (1, 2, 4):
+        c = kc.Context(0)
+        for op in (kc.OP_SNAPSHOT, kc.OP_PAGE_HASH):
+            c.set_tuning(op, depth=depth)
+            with pytest.raises(kc.KCError) as ei:
+                c.set_tuning(op, depth=3)
+            assert ei.value.code == kc.EINVAL and c.get_tuning(op)["depth"] == depth
+        rs = kc.RangeSet(c, ranges, unit=unit)
+        s1 = kc.snapshot(c, rs, seed=4)
+        h2, z2, c2 = kc.page_hash(c, rs, seed=5, prior=s1["hash"])
+        torch.cuda.synchronize()
+        outs.append([u64(s1["hash"])[:rs.n_pages].copy(), u64(s1["zero_bm"])[:rs.n_words].copy(),
+                     s1["packed"][:int(u64(s1["n_kept"])[0]) * unit].cpu().numpy(), u64(h2)[:rs.n_pages].copy(),
+                     u64(c2)[:rs.n_words].copy()])
+        rs.close()
+        c.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+    oh, oz, _ = oracle.page_hash(ranges, views, seed=4, unit=unit)
+    assert np.array_equal(outs[0][0], oh) and np.array_equal(outs[0][1], oz)
+    op, _, _ = oracle.compact(ranges, views, oz, unit=unit)
+    assert np.array_equal(outs[1][2], op)
+    h5, _, ch = oracle.page_hash(ranges, views, seed=5, prior=oh, unit=unit)
+    assert np.array_equal(outs[1][3], h5) and np.array_equal(outs[1][4], ch)
+
+
 @pytest.mark.parametrize("unit", [65536, 1 << 21])
 def test_units_c2_full(kc, ctx, unit):
     """The 2 GiB set of 4096 ranges (sizes 4 KiB to 64 MiB): most ranges end in
