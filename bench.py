@@ -44,14 +44,15 @@ HBM_PEAK_GBS = 8000.0
 PAGE = 4096
 
 # HBM traffic of the main kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
-# then WRITE_SIZE) of `bench.py --steps 2 --warmup 1 --no-cpu --no-extras --no-tune`,
-# per launch, scaled by the factors a plain 4 GiB device copy gives (fetch
-# x2.0, write x1.0).  Valid only for the kernel sources they were taken from.
+# then WRITE_SIZE) of `bench.py --steps 2 --warmup 1 --no-cpu --no-extras`
+# (the tuned launch shapes), per launch, scaled by the factors a plain 4 GiB
+# device copy gives (fetch x2.0, write x1.0).  Valid only for the kernel
+# sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "4be9976e1bda75246a64f3be37f53a0b2d4ad225e572b5ff7233df10c0187253",
-    "snapshot": 62869163698,   # fetch 31385134299 + write 31484029399
-    "restore": 62955240909,    # fetch 31598339200 + write 31356901709
-    "compare": 64456637517,    # fetch 64456637517 + write 0
+    "source_sha256": "52def113c959c13c7d78226a2059ae884517d59515373537880cc6d28457417e",
+    "snapshot": 62869532979,   # fetch 31385126912 + write 31484406067
+    "restore": 62954953216,    # fetch 31598717542 + write 31356235674
+    "compare": 64456638464,    # fetch 64456638464 + write 0
 }
 
 
