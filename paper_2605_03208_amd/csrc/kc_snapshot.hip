@@ -318,21 +318,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(uint64_t base, uint32
 constexpr uint32_t kOutside = 0x80000000u;  // an offset beyond any resource made here (tiles are below 64 MiB)
 constexpr int kNt = 2;                      // cache policy: non-temporal
 
-// The hashing pass with DEPTH (2 or 4) chunks in flight per wave, for large
-// units whose few tiles leave about one wave per SIMD: with no other wave to
-// switch to, a wave must cover the memory latency itself.  DEPTH register sets
-// take turns: while chunk c is staged, stored and hashed, chunks c+1 ..
-// c+DEPTH-1 are already loading, and the loads of chunk c+DEPTH are issued
-// after chunk c's stores, so waiting for chunk c+1 never waits for those
-// stores.  The loads and stores go through
-// buffer resources bounded to the tile's bytes and to its kept units' packed
-// slots, so no lane branches around a memory access (a branch that may skip
-// one leaves the compiler unsure how many are in flight, and it then waits
-// for all of them): skipped units (zero units of a full snapshot, lanes past
-// the tile, chunks past the unit) use an offset outside the resource.  Every
-// tile goes through it, a tile's partial last unit included (at these sizes a
-// separate launch for the partial units would run as long as the main one,
-// after it); no closure scan (it runs as its own pass at units above 4 KiB).
+// The hashing pass with DEPTH (2 or 4) chunks in flight per wave, for units
+// above 4 KiB.  Large units give few tiles, about one wave per SIMD for 2 MiB
+// units: with no other wave to switch to, a wave must cover the memory latency
+// itself.  DEPTH register sets take turns: while round c is staged, stored and
+// hashed, rounds c+1 .. c+DEPTH-1 are already loading, and the loads of round
+// c+DEPTH are issued after round c's stores, so waiting for round c+1 never
+// waits for those stores.
+//
+// The quads run skewed: in round c, quad q works on chunk c - q of its unit.
+// The 16 units of a tile start 2^ushift bytes apart, a multiple of 64 KiB, so
+// without the skew one load instruction's 16 pieces (equal offsets in 16
+// units) would all sit at addresses congruent modulo 64 KiB; with it they are
+// 512 bytes apart in that congruence as well.  A tile takes 15 rounds more
+// than it has chunks (a quad idles before its first and after its last chunk).
+//
+// The loads and stores go through buffer resources bounded to the tile's
+// bytes and to its kept units' packed slots, so no lane branches around a
+// memory access (a branch that may skip one leaves the compiler unsure how
+// many are in flight, and it then waits for all of them): skipped units (zero
+// units of a full snapshot, lanes past the tile) and chunks outside a unit use
+// an offset outside the resource.  Every tile goes through it, a tile's
+// partial last unit included; no closure scan (it runs as its own pass at
+// units above 4 KiB).
 template <bool GATHER, bool PRIOR, uint32_t DEPTH>
 __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_page_hash_deep(
     HashParams p) {
@@ -344,7 +352,9 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
   const uint32_t q = lane >> 2, k = lane & 3u;
   const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
   const uint32_t ushift = p.ushift, unit = 1u << ushift;
-  const uint32_t n_chunks = unit / kChunk;  // a multiple of DEPTH: units are 4 KiB (8 chunks) or more
+  const uint32_t n_chunks = unit / kChunk;
+  constexpr uint32_t kSkew = kTilePages - 1u;  // rounds the last quad starts after the first
+  const uint32_t n_rounds = (n_chunks + kSkew + DEPTH - 1u) / DEPTH * DEPTH;
   const uint32_t wave = blockIdx.x * wpb + wv, n_waves = gridDim.x * wpb;
   for (uint32_t t = wave; t < p.n_tiles; t += n_waves) {
     const Tile tile = p.tiles[t];
@@ -352,8 +362,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
     const uint64_t va = tile.va;
     const uint32_t last_pg = np - 1u, last_len = tile.last_len;  // only the last unit can be partial
     uint32_t keep = (1u << np) - 1u;
-    uint64_t slot_j[8];
-    uint32_t st_off[8];  // each load's unit in the packed slots resource
+    uint32_t st_base[8];  // each load's unit in the packed slots resource
     __amdgpu_buffer_rsrc_t dst = raw_rsrc((uint64_t)p.packed, 0u);  // no slots: every store dropped
     if (GATHER) {
       uint64_t slot = 0;
@@ -365,8 +374,6 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
         slot = p.word_prefix[g >> 6] + (uint64_t)__popcll(~zw & ((1ull << (g & 63u)) - 1ull));
       }
       keep = (uint32_t)__ballot(kept);
-#pragma unroll
-      for (uint32_t j = 0; j < 8; ++j) slot_j[j] = __shfl(slot, 2 * j + half, 64);
       if (kept && slot < p.cap_pages) p.page_va[slot] = va + ((uint64_t)lane << ushift);
       // the tile's kept units have consecutive slots from the first one's; those below the capacity are written
       const uint64_t slot0 = __shfl(slot, keep ? __builtin_ctz(keep) : 0, 64);
@@ -374,58 +381,66 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
       const uint64_t room = slot0 < p.cap_pages ? min(n_kept, p.cap_pages - slot0) : 0ull;
       dst = raw_rsrc((uint64_t)p.packed + (slot0 << ushift), (uint32_t)(room << ushift));
 #pragma unroll
-      for (uint32_t j = 0; j < 8; ++j)
-        st_off[j] = ((keep >> (2 * j + half)) & 1u) ? (uint32_t)((slot_j[j] - slot0) << ushift) : kOutside;
+      for (uint32_t j = 0; j < 8; ++j) {
+        const uint64_t sj = __shfl(slot, 2 * j + half, 64);
+        st_base[j] = ((keep >> (2 * j + half)) & 1u) ? (uint32_t)((sj - slot0) << ushift) : kOutside;
+      }
     }
     // the tile's bytes, the last 16-byte block of a partial unit included (its bytes past the end are cleared
     // when staged); loads of skipped units read nothing
     const __amdgpu_buffer_rsrc_t src = raw_rsrc(va, ((last_pg << ushift) + last_len + 15u) & ~15u);
-    uint32_t ld_off[8];
+    uint32_t ld_base[8];
 #pragma unroll
     for (uint32_t j = 0; j < 8; ++j) {
       const uint32_t pg = 2 * j + half;
-      ld_off[j] = ((keep >> pg) & 1u) ? (pg << ushift) + off16 : kOutside;
+      ld_base[j] = ((keep >> pg) & 1u) ? (pg << ushift) + off16 : kOutside;
     }
     uint32_t nonzero = 0;
     uint64_t acc = acc_init(p.seed, k);
     // this lane's quad: stripes of its unit, and the bytes past the last stripe
     const uint32_t qlen = q == last_pg ? last_len : unit;
     const uint32_t lim = qlen / 32u, rem = qlen & 31u;
+    // offset of page pg's chunk in round c within a resource, or kOutside when that chunk is not in the unit
+    auto at = [&](uint32_t base, uint32_t pg, uint32_t c) -> uint32_t {
+      const uint32_t cp = c - pg;  // wraps past n_chunks when c < pg
+      return base != kOutside && cp < n_chunks ? base + cp * kChunk : kOutside;
+    };
     auto load = [&](uint4 (&r)[8], uint32_t c) {
-      const uint32_t so = c < n_chunks ? c * kChunk : kOutside;  // chunks past the unit: nothing
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
-        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(src, ld_off[j], so, kNt);
+        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(src, at(ld_base[j], 2 * j + half, c), 0, kNt);
         r[j] = make_uint4(x[0], x[1], x[2], x[3]);
       }
     };
-    // chunk c in r: stage (and store to the packed slots), reload r with chunk c + DEPTH, hash chunk c
+    // round c in r: stage (and store to the packed slots), reload r with round c + DEPTH, hash this quad's chunk
     auto step = [&](uint4 (&r)[8], uint32_t c) {
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t pg = 2 * j + half;
-        const uint4 v = clip16(r[j], c * kChunk + off16, pg == last_pg ? last_len : unit);
+        const uint32_t pg = 2 * j + half, cp = c - pg;
+        // outside the unit the load returned zeros; inside, a partial unit's bytes past its end are cleared
+        const uint4 v = cp < n_chunks ? clip16(r[j], cp * kChunk + off16, pg == last_pg ? last_len : unit) : r[j];
         if (!GATHER) {
           const uint64_t b = __ballot(nz16(v));
           nonzero |= ((uint32_t)((uint32_t)b != 0u) << (2 * j)) | ((uint32_t)((b >> 32) != 0ull) << (2 * j + 1));
         }
         if (GATHER) {  // a partial unit's slot: zeros after its bytes
           const v4u x = {v.x, v.y, v.z, v.w};
-          __builtin_amdgcn_raw_buffer_store_b128(x, dst, st_off[j] + off16, c * kChunk, kNt);
+          __builtin_amdgcn_raw_buffer_store_b128(x, dst, at(st_base[j], pg, c) + off16, 0, kNt);
         }
         *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
       }
       wave_lds_order();
       load(r, c + DEPTH);
       // the chunk's 16 words of this lane, read from the stage before the serial chain starts (one LDS wait)
+      const uint32_t cq = c - q;  // this quad's chunk; wraps past n_chunks while the quad idles
       const uint8_t* row = stage + q * kStageStride + k * 8u;
       uint64_t w[kChunk / 32];
 #pragma unroll
       for (uint32_t s = 0; s < kChunk / 32; ++s) w[s] = *reinterpret_cast<const uint64_t*>(row + s * 32u);
-      if (rem != 0u && c == lim / (kChunk / 32))  // a partial unit's last bytes are in this chunk
-        tail_lds[q][k] = *reinterpret_cast<const uint64_t*>(stage + q * kStageStride + (lim * 32u - c * kChunk) + 8u * k);
+      if (rem != 0u && cq == lim / (kChunk / 32))  // a partial unit's last bytes are in this chunk
+        tail_lds[q][k] = *reinterpret_cast<const uint64_t*>(stage + q * kStageStride + (lim * 32u - cq * kChunk) + 8u * k);
       wave_lds_order();
-      const uint32_t s_end = lim > c * (kChunk / 32) ? min(lim - c * (kChunk / 32), kChunk / 32) : 0u;
+      const uint32_t s_end = cq < n_chunks && lim > cq * (kChunk / 32) ? min(lim - cq * (kChunk / 32), kChunk / 32) : 0u;
 #pragma unroll
       for (uint32_t s = 0; s < kChunk / 32; ++s)
         if (s < s_end) acc = xround(acc, w[s]);
@@ -434,14 +449,14 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
 #pragma unroll
     for (uint32_t d = 0; d < DEPTH; ++d) {
       load(r[d], d);
-      __builtin_amdgcn_sched_barrier(0);  // all of chunk d's loads before chunk d + 1's
+      __builtin_amdgcn_sched_barrier(0);  // all of round d's loads before round d + 1's
     }
 #pragma unroll 1
-    for (uint32_t c = 0; c < n_chunks; c += DEPTH) {
+    for (uint32_t c = 0; c < n_rounds; c += DEPTH) {
 #pragma unroll
       for (uint32_t d = 0; d < DEPTH; ++d) {
         step(r[d], c + d);
-        __builtin_amdgcn_sched_barrier(0);  // the steps in program order: each chunk's loads behind the last's
+        __builtin_amdgcn_sched_barrier(0);  // the steps in program order: each round's loads behind the last's
       }
     }
     const uint64_t merged = xxh64_merge4(acc, k);  // every lane of the quad takes part
