@@ -49,10 +49,10 @@ PAGE = 4096
 # device copy gives (fetch x2.0, write x1.0).  Valid only for the kernel
 # sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "52def113c959c13c7d78226a2059ae884517d59515373537880cc6d28457417e",
-    "snapshot": 62869532979,   # fetch 31385126912 + write 31484406067
-    "restore": 62954953216,    # fetch 31598717542 + write 31356235674
-    "compare": 64456638464,    # fetch 64456638464 + write 0
+    "source_sha256": "48eaadbc4195d94373c4dfce7d0fc367a5b924701a340c12a3ff90b91fccd9b0",
+    "snapshot": 62869513114,   # fetch 31385116672 + write 31484396442
+    "restore": 62955044352,    # fetch 31598715699 + write 31356328653
+    "compare": 64456638874,    # fetch 64456638874 + write 0
 }
 
 

@@ -27,7 +27,7 @@ ARCH = "gfx950"
 CANDIDATES = {
     kc.OP_PAGE_HASH: [dict(grid_per_cu=g) for g in (2, 3, 4, 6, 8, 12, 16, 24)],
     kc.OP_SNAPSHOT: [dict(grid_per_cu=g) for g in (2, 3, 4, 6, 8, 12)],
-    kc.OP_COMPACT: [dict(grid_per_cu=g) for g in (4, 8, 16, 32, 48, 64, 96, 128)],
+    kc.OP_COMPACT: [dict(grid_per_cu=g) for g in (4, 8, 16, 32, 48, 64, 96, 128, 192, 256)],
     kc.OP_RESTORE: [dict(grid_per_cu=g) for g in (8, 12, 16, 24, 32, 48, 64, 96, 128)],
     kc.OP_CLOSURE: [dict(grid_per_cu=g) for g in (4, 8, 16)],
     kc.OP_COMPARE: [dict(grid_per_cu=g, tile_bytes=t) for g in (1, 2, 3, 4)

@@ -108,6 +108,17 @@ def test_units_snapshot_restore_scan_diff_files(kc, ctx, tmp_path, unit, n_range
     r2, l2 = scan2.result()
     o2, ol2 = oracle.closure_scan(ranges, views, oob_cap=3)
     assert r2 == o2 and l2 == ol2
+    # the fused entry point under the same capacity: slots past it are not written (guard bytes after them)
+    guard = dict(hash=torch.empty_like(out["hash"]), zero_bm=torch.empty_like(out["zero_bm"]), changed_bm=None,
+                 packed=torch.full(((cap + 2) * unit,), 0xA5, dtype=torch.uint8, device="cuda"),
+                 page_va=torch.full((cap + 2,), -1, dtype=torch.int64, device="cuda"),
+                 n_kept=torch.empty(1, dtype=torch.int64, device="cuda"))
+    kc.snapshot(ctx, rs, seed=7, cap_pages=cap, out=guard)
+    torch.cuda.synchronize()
+    assert int(u64(guard["n_kept"])[0]) == onk and torch.equal(guard["hash"], out["hash"])
+    assert np.array_equal(u64(guard["page_va"])[:cap], ova2)
+    assert np.array_equal(guard["packed"][:cap * unit].cpu().numpy(), op2)
+    assert bool((guard["packed"][cap * unit:] == 0xA5).all()) and bool((guard["page_va"][cap:] == -1).all())
 
     say(f"units {unit}: clobber the ranges, restore, outside bytes untouched")
     before = case.arena.buf.cpu().numpy().copy()
