@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["kc_api.hip", "kc_snapshot.hip", "kc_compare.hip", "kc_io.hip", "kc_vaspace.hip", "kc_graph.hip",
-           "kc_perturb.hip", "kc_noalloc.hip"]
+           "kc_perturb.hip", "kc_noalloc.hip", "kc_units.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

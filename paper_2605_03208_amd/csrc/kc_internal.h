@@ -227,6 +227,9 @@ hipError_t launch_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
 // wave per SIMD); not with scan.  0 or 1: the pass with one chunk in flight.
 hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t depth,
                             uint32_t grid, uint32_t n_cu, hipStream_t s);
+// The pipelined pass of units above 4 KiB (kc_units.hip), depth 2 or 4, on a launch shape already chosen.
+hipError_t launch_page_hash_deep(const HashParams& p, bool gather, bool prior, uint32_t depth, uint32_t blocks,
+                                 uint32_t waves_per_block, hipStream_t s);
 hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t ushift,
                              uint32_t grid, hipStream_t s);
 hipError_t launch_scan(const ScanSrc& src, uint64_t* out, uint64_t* block_sums,

@@ -11,106 +11,10 @@
 
 #include "kc_device.h"
 #include "kc_internal.h"
+#include "kc_xxh64.h"
 
 namespace kc {
 namespace {
-
-// ---------------------------------------------------------------- XXH64 ----
-// Public xxHash definition: four accumulators over 32-byte stripes.
-constexpr uint64_t kP1 = 0x9E3779B185EBCA87ull;
-constexpr uint64_t kP2 = 0xC2B2AE3D27D4EB4Full;
-constexpr uint64_t kP3 = 0x165667B19E3779F9ull;
-constexpr uint64_t kP4 = 0x85EBCA77C2B2AE63ull;
-constexpr uint64_t kP5 = 0x27D4EB2F165667C5ull;
-
-__device__ __forceinline__ uint64_t rotl64(uint64_t x, uint32_t r) {
-  return (x << r) | (x >> (64u - r));
-}
-
-__device__ __forceinline__ uint64_t xround(uint64_t acc, uint64_t in) {
-  acc += in * kP2;
-  acc = rotl64(acc, 31);
-  return acc * kP1;
-}
-
-// 64-bit DPP move inside a lane quad (quad_perm control word).
-template <int CTRL>
-__device__ __forceinline__ uint64_t quad64(uint64_t x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, true);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-// Lane k of a quad holds accumulator k of one page after its stripes.
-// Returns the merged accumulators (before the length is added) in every lane
-// of the quad.
-__device__ __forceinline__ uint64_t xxh64_merge4(uint64_t acc, uint32_t k) {
-  const uint32_t rot = k == 0 ? 1u : (k == 1 ? 7u : (k == 2 ? 12u : 18u));
-  uint64_t r = rotl64(acc, rot);
-  const uint64_t m = xround(0, acc);
-  r += quad64<0xB1>(r);  // quad_perm(1,0,3,2)
-  r += quad64<0x4E>(r);  // quad_perm(2,3,0,1)
-  uint64_t h = r;
-  h = (h ^ quad64<0x00>(m)) * kP1 + kP4;
-  h = (h ^ quad64<0x55>(m)) * kP1 + kP4;
-  h = (h ^ quad64<0xAA>(m)) * kP1 + kP4;
-  h = (h ^ quad64<0xFF>(m)) * kP1 + kP4;
-  return h;
-}
-
-// The bytes past the last whole 32-byte stripe (r = 1..31 of them, held
-// little-endian in t[0..3]): 8-byte lanes, then a 4-byte lane, then bytes.
-__device__ __forceinline__ uint64_t xxh64_tail(uint64_t h, const uint64_t (&t)[4], uint32_t r) {
-#pragma unroll
-  for (uint32_t i = 0; i < 3; ++i)
-    if (r >= 8u * (i + 1u)) h = rotl64(h ^ xround(0, t[i]), 27) * kP1 + kP4;
-  const uint32_t n8 = r >> 3;
-  const uint64_t rest = n8 == 0 ? t[0] : (n8 == 1 ? t[1] : (n8 == 2 ? t[2] : t[3]));
-  uint32_t rr = r & 7u, sh = 0;
-  if (rr >= 4u) {
-    h = rotl64(h ^ (uint64_t)(uint32_t)rest * kP1, 23) * kP2 + kP3;
-    sh = 32u;
-    rr -= 4u;
-  }
-#pragma unroll
-  for (uint32_t i = 0; i < 3; ++i)
-    if (i < rr) h = rotl64(h ^ ((rest >> (sh + 8u * i)) & 0xFFull) * kP5, 11) * kP1;
-  return h;
-}
-
-__device__ __forceinline__ uint64_t xxh64_avalanche(uint64_t h) {
-  h ^= h >> 33;
-  h *= kP2;
-  h ^= h >> 29;
-  h *= kP3;
-  h ^= h >> 32;
-  return h;
-}
-
-__device__ __forceinline__ uint64_t acc_init(uint64_t seed, uint32_t k) {
-  return k == 0 ? seed + kP1 + kP2 : (k == 1 ? seed + kP2 : (k == 2 ? seed : seed - kP1));
-}
-
-// ------------------------------------------------------------- helpers ----
-__device__ __forceinline__ bool nz16(uint4 v) { return (v.x | v.y | v.z | v.w) != 0u; }
-
-// OR page bits (bit i = page g0+i) into a bitmap; one lane calls this.
-__device__ __forceinline__ void or_page_bits(uint64_t* bm, uint32_t g0, uint32_t np, uint32_t bits) {
-  if (bits == 0u) return;
-  const uint32_t w = g0 >> 6, s = g0 & 63u;
-  const uint64_t b = (uint64_t)bits;
-  if ((b << s) != 0ull) atomicOr(reinterpret_cast<unsigned long long*>(bm + w), (unsigned long long)(b << s));
-  if (s + np > 64u && (b >> (64u - s)) != 0ull)
-    atomicOr(reinterpret_cast<unsigned long long*>(bm + w + 1), (unsigned long long)(b >> (64u - s)));
-}
-
-// Compress ballot bits at lanes 4q (q < 16) into bit q.
-__device__ __forceinline__ uint32_t quad_bits(uint64_t ballot) {
-  uint32_t out = 0;
-#pragma unroll
-  for (uint32_t q = 0; q < 16; ++q) out |= (uint32_t)((ballot >> (4u * q)) & 1ull) << q;
-  return out;
-}
 
 // --------------------------------------------------------------- fill -----
 __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
@@ -131,7 +35,6 @@ __global__ void k_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint
 }
 
 // ---------------------------------------------------------- page hash -----
-constexpr uint32_t kHashWaves = 4;  // most waves per workgroup of the hash pass
 // One wave hashes a tile of up to 16 pages: lane quad q owns page q, lane k of
 // the quad runs XXH64 accumulator k over the words 8k + 32s of each stripe s.
 // The wave streams the tile in 8 chunks of 512 bytes per page: 8 loads of
@@ -302,181 +205,6 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
     const uint32_t a = wave_sum_u32(n_ptr), b = wave_sum_u32(n_in);
     if (lane == 0) {
       add_scan_counts(p.scan.counts, wave, a, b);
-    }
-  }
-}
-
-// Buffer resource over [base, base + bytes) (gfx9 raw buffer, no stride):
-// loads outside it return zeros and stores outside it are dropped.  base and
-// bytes must be the same in every lane of the wave.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(uint64_t base, uint32_t bytes) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-  return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0,
-                                           (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
-}
-constexpr uint32_t kOutside = 0x80000000u;  // an offset beyond any resource made here (tiles are below 64 MiB)
-constexpr int kNt = 2;                      // cache policy: non-temporal
-
-// The hashing pass with DEPTH (2 or 4) chunks in flight per wave, for units
-// above 4 KiB.  Large units give few tiles, about one wave per SIMD for 2 MiB
-// units: with no other wave to switch to, a wave must cover the memory latency
-// itself.  DEPTH register sets take turns: while round c is staged, stored and
-// hashed, rounds c+1 .. c+DEPTH-1 are already loading, and the loads of round
-// c+DEPTH are issued after round c's stores, so waiting for round c+1 never
-// waits for those stores.
-//
-// The quads run skewed: in round c, quad q works on chunk c - q of its unit.
-// The 16 units of a tile start 2^ushift bytes apart, a multiple of 64 KiB, so
-// without the skew one load instruction's 16 pieces (equal offsets in 16
-// units) would all sit at addresses congruent modulo 64 KiB; with it they are
-// 512 bytes apart in that congruence as well.  A tile takes 15 rounds more
-// than it has chunks (a quad idles before its first and after its last chunk).
-//
-// The loads and stores go through buffer resources bounded to the tile's
-// bytes and to its kept units' packed slots, so no lane branches around a
-// memory access (a branch that may skip one leaves the compiler unsure how
-// many are in flight, and it then waits for all of them): skipped units (zero
-// units of a full snapshot, lanes past the tile) and chunks outside a unit use
-// an offset outside the resource.  Every tile goes through it, a tile's
-// partial last unit included; no closure scan (it runs as its own pass at
-// units above 4 KiB).
-template <bool GATHER, bool PRIOR, uint32_t DEPTH>
-__global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_page_hash_deep(
-    HashParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t stage_all[kHashWaves][kTilePages * kStageStride];
-  __shared__ uint64_t tail_all[kHashWaves][kTilePages][4];  // a partial unit's bytes past its last whole stripe
-  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, wpb = blockDim.x / kWave;
-  uint8_t* const stage = stage_all[wv];
-  uint64_t(*const tail_lds)[4] = tail_all[wv];
-  const uint32_t q = lane >> 2, k = lane & 3u;
-  const uint32_t half = lane >> 5, off16 = (lane & 31u) * 16u;
-  const uint32_t ushift = p.ushift, unit = 1u << ushift;
-  const uint32_t n_chunks = unit / kChunk;
-  constexpr uint32_t kSkew = kTilePages - 1u;  // rounds the last quad starts after the first
-  const uint32_t n_rounds = (n_chunks + kSkew + DEPTH - 1u) / DEPTH * DEPTH;
-  const uint32_t wave = blockIdx.x * wpb + wv, n_waves = gridDim.x * wpb;
-  for (uint32_t t = wave; t < p.n_tiles; t += n_waves) {
-    const Tile tile = p.tiles[t];
-    const uint32_t np = tile.npages;
-    const uint64_t va = tile.va;
-    const uint32_t last_pg = np - 1u, last_len = tile.last_len;  // only the last unit can be partial
-    uint32_t keep = (1u << np) - 1u;
-    uint32_t st_base[8];  // each load's unit in the packed slots resource
-    __amdgpu_buffer_rsrc_t dst = raw_rsrc((uint64_t)p.packed, 0u);  // no slots: every store dropped
-    if (GATHER) {
-      uint64_t slot = 0;
-      bool kept = false;
-      if (lane < np) {
-        const uint64_t g = (uint64_t)tile.g + lane;
-        const uint64_t zw = p.zero_bm[g >> 6];
-        kept = ((zw >> (g & 63u)) & 1ull) == 0ull;
-        slot = p.word_prefix[g >> 6] + (uint64_t)__popcll(~zw & ((1ull << (g & 63u)) - 1ull));
-      }
-      keep = (uint32_t)__ballot(kept);
-      if (kept && slot < p.cap_pages) p.page_va[slot] = va + ((uint64_t)lane << ushift);
-      // the tile's kept units have consecutive slots from the first one's; those below the capacity are written
-      const uint64_t slot0 = __shfl(slot, keep ? __builtin_ctz(keep) : 0, 64);
-      const uint64_t n_kept = (uint64_t)__popc(keep);
-      const uint64_t room = slot0 < p.cap_pages ? min(n_kept, p.cap_pages - slot0) : 0ull;
-      dst = raw_rsrc((uint64_t)p.packed + (slot0 << ushift), (uint32_t)(room << ushift));
-#pragma unroll
-      for (uint32_t j = 0; j < 8; ++j) {
-        const uint64_t sj = __shfl(slot, 2 * j + half, 64);
-        st_base[j] = ((keep >> (2 * j + half)) & 1u) ? (uint32_t)((sj - slot0) << ushift) : kOutside;
-      }
-    }
-    // the tile's bytes, the last 16-byte block of a partial unit included (its bytes past the end are cleared
-    // when staged); loads of skipped units read nothing
-    const __amdgpu_buffer_rsrc_t src = raw_rsrc(va, ((last_pg << ushift) + last_len + 15u) & ~15u);
-    uint32_t ld_base[8];
-#pragma unroll
-    for (uint32_t j = 0; j < 8; ++j) {
-      const uint32_t pg = 2 * j + half;
-      ld_base[j] = ((keep >> pg) & 1u) ? (pg << ushift) + off16 : kOutside;
-    }
-    uint32_t nonzero = 0;
-    uint64_t acc = acc_init(p.seed, k);
-    // this lane's quad: stripes of its unit, and the bytes past the last stripe
-    const uint32_t qlen = q == last_pg ? last_len : unit;
-    const uint32_t lim = qlen / 32u, rem = qlen & 31u;
-    // offset of page pg's chunk in round c within a resource, or kOutside when that chunk is not in the unit
-    auto at = [&](uint32_t base, uint32_t pg, uint32_t c) -> uint32_t {
-      const uint32_t cp = c - pg;  // wraps past n_chunks when c < pg
-      return base != kOutside && cp < n_chunks ? base + cp * kChunk : kOutside;
-    };
-    auto load = [&](uint4 (&r)[8], uint32_t c) {
-#pragma unroll
-      for (uint32_t j = 0; j < 8; ++j) {
-        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(src, at(ld_base[j], 2 * j + half, c), 0, kNt);
-        r[j] = make_uint4(x[0], x[1], x[2], x[3]);
-      }
-    };
-    // round c in r: stage (and store to the packed slots), reload r with round c + DEPTH, hash this quad's chunk
-    auto step = [&](uint4 (&r)[8], uint32_t c) {
-#pragma unroll
-      for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t pg = 2 * j + half, cp = c - pg;
-        // outside the unit the load returned zeros; inside, a partial unit's bytes past its end are cleared
-        const uint4 v = cp < n_chunks ? clip16(r[j], cp * kChunk + off16, pg == last_pg ? last_len : unit) : r[j];
-        if (!GATHER) {
-          const uint64_t b = __ballot(nz16(v));
-          nonzero |= ((uint32_t)((uint32_t)b != 0u) << (2 * j)) | ((uint32_t)((b >> 32) != 0ull) << (2 * j + 1));
-        }
-        if (GATHER) {  // a partial unit's slot: zeros after its bytes
-          const v4u x = {v.x, v.y, v.z, v.w};
-          __builtin_amdgcn_raw_buffer_store_b128(x, dst, at(st_base[j], pg, c) + off16, 0, kNt);
-        }
-        *reinterpret_cast<uint4*>(stage + pg * kStageStride + off16) = v;
-      }
-      wave_lds_order();
-      load(r, c + DEPTH);
-      // the chunk's 16 words of this lane, read from the stage before the serial chain starts (one LDS wait)
-      const uint32_t cq = c - q;  // this quad's chunk; wraps past n_chunks while the quad idles
-      const uint8_t* row = stage + q * kStageStride + k * 8u;
-      uint64_t w[kChunk / 32];
-#pragma unroll
-      for (uint32_t s = 0; s < kChunk / 32; ++s) w[s] = *reinterpret_cast<const uint64_t*>(row + s * 32u);
-      if (rem != 0u && cq == lim / (kChunk / 32))  // a partial unit's last bytes are in this chunk
-        tail_lds[q][k] = *reinterpret_cast<const uint64_t*>(stage + q * kStageStride + (lim * 32u - cq * kChunk) + 8u * k);
-      wave_lds_order();
-      const uint32_t s_end = cq < n_chunks && lim > cq * (kChunk / 32) ? min(lim - cq * (kChunk / 32), kChunk / 32) : 0u;
-#pragma unroll
-      for (uint32_t s = 0; s < kChunk / 32; ++s)
-        if (s < s_end) acc = xround(acc, w[s]);
-    };
-    uint4 r[DEPTH][8];
-#pragma unroll
-    for (uint32_t d = 0; d < DEPTH; ++d) {
-      load(r[d], d);
-      __builtin_amdgcn_sched_barrier(0);  // all of round d's loads before round d + 1's
-    }
-#pragma unroll 1
-    for (uint32_t c = 0; c < n_rounds; c += DEPTH) {
-#pragma unroll
-      for (uint32_t d = 0; d < DEPTH; ++d) {
-        step(r[d], c + d);
-        __builtin_amdgcn_sched_barrier(0);  // the steps in program order: each round's loads behind the last's
-      }
-    }
-    const uint64_t merged = xxh64_merge4(acc, k);  // every lane of the quad takes part
-    uint64_t h = (lim > 0u ? merged : p.seed + kP5) + qlen;
-    if (rem != 0u) {
-      const uint64_t tail[4] = {tail_lds[q][0], tail_lds[q][1], tail_lds[q][2], tail_lds[q][3]};
-      h = xxh64_tail(h, tail, rem);
-    }
-    h = xxh64_avalanche(h);
-    const bool mine = (k == 0u) && (q < np);
-    if (mine) p.hash[tile.g + q] = h;
-    const uint32_t valid = (1u << np) - 1u;
-    if (!GATHER) {
-      const uint32_t zero = ~nonzero & valid;
-      if (lane == 0) or_page_bits(p.zero_bm, tile.g, np, zero);
-    }
-    if (PRIOR) {
-      const bool ch = mine && (h != p.prior[tile.g + q]);
-      const uint32_t cb = quad_bits(__ballot(ch));
-      if (lane == 0) or_page_bits(p.changed_bm, tile.g, np, cb);
     }
   }
 }
@@ -1030,21 +758,8 @@ hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool s
   wide_shape(std::min(grid, p.n_tiles), n_cu, &blocks, &wpb, kHashWaves);
   wide_shape(std::min(grid, std::max(1u, p.n_ragged)), n_cu, &blocks_r, &wpb_r, kHashWaves);
   const size_t lds = scan ? wide_lds_bytes(p.scan.rt) : 0;
-  if (depth > 1u && !scan) {  // every tile, partial last units included, through the pipelined pass
-#define KC_DEEP_CASE(G, P, D)                                                                     \
-    if (gather == G && prior == P && depth == D) {                                                \
-      hipLaunchKernelGGL((k_page_hash_deep<G, P, D>), dim3(blocks), dim3(wpb * kWave), 0, s, p); \
-      return hipGetLastError();                                                                  \
-    }
-    KC_DEEP_CASE(false, false, 2u)
-    KC_DEEP_CASE(false, true, 2u)
-    KC_DEEP_CASE(true, false, 2u)
-    KC_DEEP_CASE(false, false, 4u)
-    KC_DEEP_CASE(false, true, 4u)
-    KC_DEEP_CASE(true, false, 4u)
-#undef KC_DEEP_CASE
-    return hipErrorInvalidValue;
-  }
+  if (depth > 1u && !scan)  // every tile, partial last units included, through the pipelined pass
+    return launch_page_hash_deep(p, gather, prior, depth, blocks, wpb, s);
 #define KC_HASH_CASE(G, P, S)                                                                              \
   if (gather == G && prior == P && scan == S) {                                                           \
     hipLaunchKernelGGL((k_page_hash<G, P, S, false>), dim3(blocks), dim3(wpb * kWave), lds, s, p);        \

@@ -43,6 +43,9 @@ def test_source_digest_ignores_comments_not_code():
     commented[name] = "// a new comment\n/* and a block\n   comment */\n" + texts[name].replace("\n", "\n  \n", 3)
     assert bench.source_digest(lambda n: commented[n]) == base
     changed = dict(texts)
-    assert "= 4;" in texts[name]
-    changed[name] = texts[name].replace("= 4;", "= 5;", 1)
+    changed[name] = texts[name] + "\nstatic int kc_digest_probe = 1;\n"
     assert bench.source_digest(lambda n: changed[n]) != base
+    for n in bench.STEP_KERNEL_SOURCES:  # every listed source takes part
+        other = dict(texts)
+        other[n] = texts[n] + "\n;\n"
+        assert bench.source_digest(lambda m: other[m]) != base, n
