@@ -117,7 +117,10 @@ class MockExecutor:
 
 
 class DeviceExecutor:
-    """Runs batches on ``n_streams`` HIP streams (one kc context each)."""
+    """Runs batches on ``n_streams`` HIP streams (one kc context each).  The
+    goldens must be written by work already enqueued on the current stream
+    when the executor is made (or finished): its streams wait for that work,
+    since they do not order themselves after the current stream otherwise."""
 
     def __init__(self, goldens, dtypes, n_streams: int = 4, device=0, p_pert: float = 1e-4, kmax: int = 16):
         import torch
@@ -138,6 +141,11 @@ class DeviceExecutor:
         self.n_elems_arr = self.sizes // np.array([kc.ELEM_SIZE[d] for d in self.dtypes], dtype=np.int64)
         self.n_streams = n_streams
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        # the goldens may still be being written on the current stream: a batch read them too early otherwise
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream(device))
+        for st in self.streams:
+            st.wait_event(ready)
         self.ctxs = [kc.Context(device) for _ in range(n_streams)]
         self.busy = [None] * n_streams
         self.p_pert, self.kmax = p_pert, kmax

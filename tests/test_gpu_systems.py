@@ -336,6 +336,30 @@ def test_kc_perturb_offsets_past_4g_elements(kc):
     ctx.close()
 
 
+def test_kc_materialize_past_4g_elements(kc):
+    """Vector and element indices past 2^32: a 4.5 GiB int8 golden copied and
+    moved into an arena at an offset, its buffer crossing element 2^32 of the
+    arena, next to a small buffer with a short last vector."""
+    say("kc_materialize: 4.5 GiB int8 golden, its place crossing arena element 2^32")
+    ctx = kc.Context(0)
+    n = (9 << 29)
+    g = torch.randint(-128, 128, (1 << 26,), dtype=torch.int8, generator=torch.Generator().manual_seed(9)).repeat(72)
+    small = torch.arange(37, dtype=torch.int64).to(torch.int8)
+    gold, gold_small = g.to("cuda"), small.to("cuda")
+    offs, lens, seeds = [1 << 20, (1 << 20) + n + 16], [n, 37], [5, 6]
+    arena = torch.zeros(offs[1] + 48, dtype=torch.int8, device="cuda")
+    kc.materialize(ctx, arena, [gold.data_ptr(), gold_small.data_ptr()], offs, lens, seeds, 1000, 16)
+    torch.cuda.synchronize()
+    want = torch.zeros(offs[1] + 48, dtype=torch.int8)
+    want[offs[0]: offs[0] + n] = g
+    want[offs[1]: offs[1] + 37] = small
+    W.perturb_many(want, W.DT_I8, offs, lens, seeds, p_pert=1e-3, kmax=16)
+    assert torch.equal(arena.cpu(), want)
+    assert not torch.equal(want[(1 << 32): offs[0] + n], g[(1 << 32) - offs[0]:])
+    del arena, gold
+    ctx.close()
+
+
 def test_kc_perturb_errors(kc):
     say("kc_perturb argument errors")
     ctx = kc.Context(0)
