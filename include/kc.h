@@ -202,8 +202,9 @@ typedef struct {
   uint32_t tile_bytes;  /* compare: bytes of each side per work item        */
   uint32_t per_item;    /* 1 = one launch per range / pair (no batching)    */
   uint32_t depth;       /* hashing pass without a fused scan: chunks in flight
-                           per wave, 1, 2 or 4 (more when few tiles leave
-                           about one wave per SIMD); 0 = built-in choice     */
+                           per wave, 1 to 4; 2 to 4 select the pipelined,
+                           skewed pass of units above 4 KiB; 0 = built-in
+                           choice (2 above 4 KiB, else 1)                    */
 } kc_tuning;
 
 enum {

@@ -223,7 +223,7 @@ int kc_ctx_kernel_ms(kc_ctx* c, uint32_t op, float* ms) {
 
 int kc_ctx_set_tuning(kc_ctx* c, uint32_t op, const kc_tuning* t) {
   if (c == nullptr || t == nullptr || op >= KC_OP_COUNT) return KC_EINVAL;
-  if (t->grid_per_cu > 1024u || !(t->depth <= 2u || t->depth == 4u)) return KC_EINVAL;
+  if (t->grid_per_cu > 1024u || t->depth > 4u) return KC_EINVAL;
   if (t->tile_bytes != 0 && (t->tile_bytes % 16u != 0 || t->tile_bytes < 4096u || t->tile_bytes > (64u << 20)))
     return KC_EINVAL;
   c->tune[op] = *t;

@@ -223,11 +223,11 @@ enum : uint32_t {
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_zero3(uint64_t* a, uint64_t na, uint64_t* b, uint64_t nb, uint64_t* c, uint64_t nc,
                         hipStream_t s);
-// depth 2 or 4: the pipelined pass of large units with that many chunks in flight per wave (few tiles, about one
+// depth 2 to 4: the pipelined pass of large units with that many chunks in flight per wave (few tiles, about one
 // wave per SIMD); not with scan.  0 or 1: the pass with one chunk in flight.
 hipError_t launch_page_hash(const HashParams& p, bool gather, bool prior, bool scan, uint32_t depth,
                             uint32_t grid, uint32_t n_cu, hipStream_t s);
-// The pipelined pass of units above 4 KiB (kc_units.hip), depth 2 or 4, on a launch shape already chosen.
+// The pipelined pass of units above 4 KiB (kc_units.hip), depth 2 to 4, on a launch shape already chosen.
 hipError_t launch_page_hash_deep(const HashParams& p, bool gather, bool prior, uint32_t depth, uint32_t blocks,
                                  uint32_t waves_per_block, hipStream_t s);
 hipError_t launch_probe_zero(const Tile* tiles, uint32_t n_tiles, uint64_t* zero_bm, uint32_t ushift,

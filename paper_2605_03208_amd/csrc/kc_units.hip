@@ -22,7 +22,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(uint64_t base, uint32
 constexpr uint32_t kOutside = 0x80000000u;  // an offset beyond any resource made here (tiles are below 64 MiB)
 constexpr int kNt = 2;                      // cache policy: non-temporal
 
-// The hashing pass with DEPTH (2 or 4) chunks in flight per wave, for units
+// The hashing pass with DEPTH (2 to 4) chunks in flight per wave, for units
 // above 4 KiB.  Large units give few tiles, about one wave per SIMD for 2 MiB
 // units: with no other wave to switch to, a wave must cover the memory latency
 // itself.  DEPTH register sets take turns: while round c is staged, stored and
@@ -200,6 +200,9 @@ hipError_t launch_page_hash_deep(const HashParams& p, bool gather, bool prior, u
   KC_DEEP_CASE(false, false, 2u)
   KC_DEEP_CASE(false, true, 2u)
   KC_DEEP_CASE(true, false, 2u)
+  KC_DEEP_CASE(false, false, 3u)
+  KC_DEEP_CASE(false, true, 3u)
+  KC_DEEP_CASE(true, false, 3u)
   KC_DEEP_CASE(false, false, 4u)
   KC_DEEP_CASE(false, true, 4u)
   KC_DEEP_CASE(true, false, 4u)

@@ -201,21 +201,21 @@ def test_units_snapshot_restore_scan_diff_files(kc, ctx, tmp_path, unit, n_range
 
 @pytest.mark.parametrize("unit", [4096, 65536, 1 << 21])
 def test_hashing_depths_agree(kc, unit):
-    """The hashing pass with one chunk in flight per wave, with two and with
-    four (the pipeline of large units, forced here at every unit) gives the
-    same snapshot and delta, equal to the oracle."""
-    say(f"units {unit}: hashing pass at depth 1, 2 and 4")
+    """The hashing pass with one chunk in flight per wave and with two to four
+    (the pipeline of large units, forced here at every unit) gives the same
+    snapshot and delta, equal to the oracle."""
+    say(f"units {unit}: hashing pass at depth 1 to 4")
     case = W.units_case("cuda", unit=max(unit, 8192), n_ranges=20, seed=31)
     ranges = case.ranges()
     host = case.arena.host_copy().copy()
     views = W.host_views(case.layout, host)
     outs = []
-    for depth in (1, 2, 4):
+    for depth in (1, 2, 3, 4):
         c = kc.Context(0)
         for op in (kc.OP_SNAPSHOT, kc.OP_PAGE_HASH):
             c.set_tuning(op, depth=depth)
             with pytest.raises(kc.KCError) as ei:
-                c.set_tuning(op, depth=3)
+                c.set_tuning(op, depth=5)
             assert ei.value.code == kc.EINVAL and c.get_tuning(op)["depth"] == depth
         rs = kc.RangeSet(c, ranges, unit=unit)
         s1 = kc.snapshot(c, rs, seed=4)
