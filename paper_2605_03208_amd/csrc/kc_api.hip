@@ -438,7 +438,7 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
   // read-only hashing runs best with twice the waves of the fused snapshot (which also writes and scans)
   uint32_t grid = grid_for(c, op, op == KC_OP_PAGE_HASH ? 8 : 4);
   // large units give few tiles, each a long serial chain: one wave per tile rather than two tiles on some
-  // waves, each wave keeping two chunks in flight (four measured no faster) in the skewed pass
+  // waves, each wave keeping two chunks in flight in the skewed pass (three or four measured no faster)
   if (rs->ushift > kMinUnitShift) grid = std::max(grid, std::min(rs->n_tiles, 16u * c->n_cu));
   uint32_t depth = c->tune[op].depth;
   if (depth == 0u && rs->ushift > kMinUnitShift) depth = 2u;
