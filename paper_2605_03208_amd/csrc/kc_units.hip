@@ -31,13 +31,15 @@ constexpr int kNt = 2;                      // cache policy: non-temporal
 // waits for those stores.
 //
 // The quads run skewed: in round c, quad q works on chunk c - q*skew of its
-// unit, skew = n_chunks / 32 clamped to 1..8.  The 16 units of a tile start
-// 2^ushift bytes apart, so without the skew one load instruction's 16 pieces
-// (equal offsets in 16 units) would all sit at addresses congruent modulo the
-// unit size; with it they are skew*512 bytes apart in that congruence.  A tile takes 15*skew rounds more than it has chunks (a
-// quad idles before its first and after its last chunk).  Measured on the
-// 30 GiB pool: 64 KiB units fastest at skew 4, 2 MiB units at skew 8 (15 %
-// faster than skew 1, and than skew 16).
+// unit, skew = n_chunks / 32 clamped to 1..8.  The units of a tile start
+// 2^ushift bytes apart, so without the skew one load instruction's pieces
+// (equal offsets in up to 16 units) would all sit at addresses congruent
+// modulo the unit size; with it they are skew*512 bytes apart in that
+// congruence.  A tile of np units takes (np-1)*skew rounds more than it has
+// chunks (a quad idles before its first and after its last chunk).  Measured
+// on the 30 GiB pool: 64 KiB units fastest at skew 4, 2 MiB units at skew 8
+// (15 % faster than skew 1, and than skew 16).  Tiles hold 16 units, or 8
+// when 16 would leave fewer than two waves per SIMD (the range set decides).
 //
 // The loads and stores go through buffer resources bounded to the tile's
 // bytes and to its kept units' packed slots, so no lane branches around a
@@ -61,13 +63,13 @@ __global__ __launch_bounds__(kHashWaves * kWave) __attribute__((amdgpu_waves_per
   const uint32_t n_chunks = unit / kChunk;
   // chunks each quad starts after the one before it: 2 KiB apart at 64 KiB units, 4 KiB from 128 KiB up
   const uint32_t skew = min(8u, max(1u, n_chunks / 32u));
-  const uint32_t n_rounds = (n_chunks + (kTilePages - 1u) * skew + DEPTH - 1u) / DEPTH * DEPTH;
   const uint32_t wave = blockIdx.x * wpb + wv, n_waves = gridDim.x * wpb;
   for (uint32_t t = wave; t < p.n_tiles; t += n_waves) {
     const Tile tile = p.tiles[t];
     const uint32_t np = tile.npages;
     const uint64_t va = tile.va;
     const uint32_t last_pg = np - 1u, last_len = tile.last_len;  // only the last unit can be partial
+    const uint32_t n_rounds = (n_chunks + last_pg * skew + DEPTH - 1u) / DEPTH * DEPTH;  // the last quad ends last
     uint32_t keep = (1u << np) - 1u;
     uint32_t st_base[8];  // each load's unit in the packed slots resource
     __amdgpu_buffer_rsrc_t dst = raw_rsrc((uint64_t)p.packed, 0u);  // no slots: every store dropped
