@@ -72,6 +72,46 @@ __device__ __forceinline__ int32_t search_fences(uint64_t w, const uint64_t* fba
   return w < ld8g(rt.end + a) ? (int32_t)a : -1;
 }
 
+// The same search for a value that is the same in every lane of the wave,
+// straight from the range set's arrays through the scalar cache (they are a
+// few KiB and read-only while a kernel runs), for kernels that search once
+// per wave and would rather not load a fence table into LDS: the bucket index
+// gives the fences (every stride-th range) to search, then the ranges of that
+// fence are searched.  Returns the range index (or -1) and its base and end.
+#define KC_CONST __attribute__((address_space(4)))
+struct RangeHit {
+  int32_t a;
+  uint64_t base, end;
+};
+__device__ __forceinline__ RangeHit range_find_uniform(uint64_t w, const RangeTable& rt) {
+  RangeHit h{-1, 0, 0};
+  if (rt.n == 0u || w - rt.lo >= rt.span) return h;
+  const KC_CONST uint64_t* base = (const KC_CONST uint64_t*)rt.base;
+  const KC_CONST uint64_t* end = (const KC_CONST uint64_t*)rt.end;
+  const KC_CONST uint32_t* bucket2 = (const KC_CONST uint32_t*)rt.bucket;  // two 16-bit entries a word
+  const auto bucket = [&](uint32_t k) -> uint32_t {
+    const uint32_t v = bucket2[k >> 1];
+    return (k & 1u) ? (v >> 16) : (v & 0xFFFFu);
+  };
+  const uint32_t bk = __builtin_amdgcn_readfirstlane((uint32_t)((w - rt.lo) >> rt.shift));
+  uint32_t i = bucket(bk);
+  uint32_t j = bk + 1u < kBuckets ? bucket(bk + 1u) : rt.n_fence - 1u;
+  while (i < j) {
+    const uint32_t m = (i + j + 1u) >> 1;
+    if (base[(uint64_t)m * rt.stride] <= w) i = m; else j = m - 1u;
+  }
+  uint32_t lo = i * rt.stride;
+  uint32_t hi = min(lo + rt.stride, rt.n);
+  while (hi - lo > 1u) {
+    const uint32_t m = (lo + hi) >> 1;
+    if (base[m] <= w) lo = m; else hi = m;
+  }
+  h.base = base[lo];
+  h.end = end[lo];
+  if (w < h.end) h.a = (int32_t)lo;
+  return h;
+}
+
 // Index of the range holding w, or -1 (table of up to kFences fences).
 __device__ __forceinline__ int32_t range_index(uint64_t w, const FenceLds& f, const RangeTable& rt) {
   return search_fences(w, f.base, f.end, f.bucket, rt.stride, rt.n_fence, rt);

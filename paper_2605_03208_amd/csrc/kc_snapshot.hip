@@ -497,53 +497,43 @@ __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t
   }
 }
 
-// Packed units back to their VAs in 4 KiB blocks, four blocks per wave round:
-// lanes 0..3 read the page-VA entry of their block's slot and validate it
-// (4 KiB aligned, inside a range, the start of a unit of that range); the
-// whole wave then copies the four blocks.
+// Packed units back to their VAs, one 4 KiB block per wave and one wave per
+// workgroup, the grid covering every block (no persistent stride): block b of
+// the packed snapshot belongs to slot b >> (ushift - 12); the wave reads that
+// slot's page-VA entry (one scalar load for the whole wave), validates it (4 KiB
+// aligned, inside a range, the start of a unit of that range) with a scalar
+// search of the range set's arrays, and copies the block with four 16-byte
+// loads and stores per lane.  Workgroups are dispatched in block order, so the waves
+// in flight cover one compact, advancing window of both buffers: against a
+// persistent grid striding four-block groups over the snapshot (with a range
+// table loaded into LDS per workgroup) it runs at the speed of a plain copy
+// kernel between the same buffers.
 __global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uint8_t* packed,
                                                         const uint64_t* page_va, const uint64_t* n_kept,
                                                         uint64_t cap, unsigned long long* n_bad, uint32_t ushift) {
-  __shared__ FenceLds fences;
   const uint32_t lane = threadIdx.x;
   const uint32_t bshift = ushift - 12u;  // 4 KiB blocks per unit: 1 << bshift
   const uint64_t unit = 1ull << ushift;
-  load_fences(fences, rt, lane, kWave);
-  __syncthreads();
-  const uint64_t n = min(*n_kept, cap);
-  const uint64_t nblk = n << bshift;
-  for (uint64_t s0 = (uint64_t)blockIdx.x * 4; s0 < nblk; s0 += (uint64_t)gridDim.x * 4) {
-    uint64_t dst = 0;
-    bool ok = false;
-    if (lane < 4 && s0 + lane < nblk) {
-      const uint64_t blk = s0 + lane, sub = blk & ((1ull << bshift) - 1ull);
-      const uint64_t va = page_va[blk >> bshift];
-      const int32_t a = (va & (kPage - 1)) == 0 ? range_index(va, fences, rt) : -1;
-      bool good = false;
-      if (a >= 0) {  // a range's partial last unit is left to k_restore_tail
-        const uint64_t base = rt.stride == 1u ? fences.base[a] : ld8g(rt.base + a);
-        const uint64_t end = rt.stride == 1u ? fences.end[a] : ld8g(rt.end + a);
-        good = ((va - base) & (unit - 1ull)) == 0ull;
-        ok = good && va + unit <= end;
+  const uint64_t nblk = min(*n_kept, cap) << bshift;
+  for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const uint64_t sub = blk & ((1ull << bshift) - 1ull);
+    const uint64_t va = ((const KC_CONST uint64_t*)page_va)[blk >> bshift];  // one scalar load for the wave
+    bool good = false, ok = false;
+    if ((va & (kPage - 1)) == 0) {
+      const RangeHit r = range_find_uniform(va, rt);
+      if (r.a >= 0) {  // a range's partial last unit is left to k_restore_tail
+        good = ((va - r.base) & (unit - 1ull)) == 0ull;
+        ok = good && va + unit <= r.end;
       }
-      if (!good && sub == 0) atomicAdd(n_bad, 1ull);  // counted once per slot
-      dst = va + (sub << 12);
     }
-    const uint32_t okm = (uint32_t)__ballot(ok);
-    uint64_t d[4];
-    uint4 x[16];
+    if (!good && sub == 0 && lane == 0) atomicAdd(n_bad, 1ull);  // counted once per slot
+    if (!ok) continue;
+    const uint64_t src = (uint64_t)packed + blk * kPage + lane * 16u, dst = va + (sub << 12) + lane * 16u;
+    uint4 x[4];
 #pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) {
-      d[i] = __shfl(dst, i, 64);
+    for (uint32_t j = 0; j < 4; ++j) x[j] = ld16nt(src + j * 1024u);
 #pragma unroll
-      for (uint32_t j = 0; j < 4; ++j)
-        if ((okm >> i) & 1u) x[i * 4 + j] = ld16nt((uint64_t)packed + (s0 + i) * kPage + j * 1024u + lane * 16u);
-    }
-#pragma unroll
-    for (uint32_t i = 0; i < 4; ++i)
-#pragma unroll
-      for (uint32_t j = 0; j < 4; ++j)
-        if ((okm >> i) & 1u) st16nt(d[i] + j * 1024u + lane * 16u, x[i * 4 + j]);
+    for (uint32_t j = 0; j < 4; ++j) st16nt(dst + j * 1024u, x[j]);
   }
 }
 
@@ -828,10 +818,12 @@ hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, c
                                   const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad,
                                   bool ragged, uint32_t ushift, uint32_t grid, hipStream_t s) {
   if (cap_pages == 0) return hipSuccess;
-  const uint64_t groups = ((cap_pages << (ushift - 12u)) + 3) / 4;  // four 4 KiB blocks per wave round
-  grid = (uint32_t)(groups < grid ? groups : grid);
-  grid = grid < 1u ? 1u : grid;
-  hipLaunchKernelGGL(k_restore_scatter, dim3(grid), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
+  // one workgroup per 4 KiB block of the capacity (blocks past the kept count exit at once); the kernel strides
+  // only if a capacity ever exceeded the grid limit
+  const uint32_t bshift = ushift - 12u;
+  const uint64_t kMaxGrid = 0x7FFFFFFFull;
+  const uint32_t grid_s = cap_pages > (kMaxGrid >> bshift) ? (uint32_t)kMaxGrid : (uint32_t)(cap_pages << bshift);
+  hipLaunchKernelGGL(k_restore_scatter, dim3(grid_s), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
                      n_bad, ushift);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ragged) return e;
