@@ -30,8 +30,8 @@ CANDIDATES = {
     kc.OP_COMPACT: [dict(grid_per_cu=g) for g in (4, 8, 16, 32, 48, 64, 96, 128, 192, 256)],
     kc.OP_RESTORE: [dict(grid_per_cu=g) for g in (8, 12, 16, 24, 32, 48, 64, 96, 128)],
     kc.OP_CLOSURE: [dict(grid_per_cu=g) for g in (4, 8, 16)],
-    kc.OP_COMPARE: [dict(grid_per_cu=g, tile_bytes=t) for g in (1, 2, 3, 4)
-                    for t in (32 << 10, 64 << 10, 128 << 10, 256 << 10)],
+    kc.OP_COMPARE: [dict(grid_per_cu=g, tile_bytes=t) for g in (1, 2, 3, 4, 16, 64, 128, 256, 512, 1024)
+                    for t in (16 << 10, 32 << 10, 64 << 10, 128 << 10, 256 << 10, 512 << 10, 1 << 20)],
     kc.OP_GRAPH: [dict(grid_per_cu=g) for g in (4, 8, 12, 16, 24, 32)],
     kc.OP_REGION_DIFF: [dict(grid_per_cu=g) for g in (8, 12, 16, 20, 32, 48, 64)],
 }
