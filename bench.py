@@ -49,10 +49,10 @@ PAGE = 4096
 # device copy gives (fetch x2.0, write x1.0).  Valid only for the kernel
 # sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "e545b8870bc16c98e75a0a28210206c38f874149be99048937cb53fe6eddf319",
-    "snapshot": 62869293746,   # fetch 31385133714 + write 31484160032
-    "restore": 62953830809,    # fetch 31598762086 + write 31355068723
-    "compare": 64456637619,    # fetch 64456637619 + write 0
+    "source_sha256": "55c6224fd5b4aaa3efa1c2438a69aea09fb4a58d5615695283faf46b4646083f",
+    "snapshot": 62869444306,   # fetch 31385113271 + write 31484331035
+    "restore": 63687422029,    # fetch 32333169280 + write 31354252749
+    "compare": 64440931994,    # fetch 64440931994 + write 0
 }
 
 
@@ -413,6 +413,8 @@ def main() -> int:
         line["graph"] = graph_step(torch, step, res, pair_list, kc, args.steps)
         log("hash units of 4 KiB, 64 KiB and 2 MiB: snapshot and restore of the same pool")
         line["hash_units"] = hash_units(torch, kc, ctx, case, ranges, args.steps)
+        log("plain copies between the restore's own buffers, both directions (the pool is clobbered after this)")
+        line["copy_same_buffers"] = same_buffer_copies(torch, case, out, n_kept, avg["restore"], avg["snapshot"])
         state["ps"].close()
         rs.close()
         del case, golden, out, state, pair_list, rs
@@ -428,6 +430,32 @@ def main() -> int:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
+
+
+def same_buffer_copies(torch, case, out, n_kept: int, restore_ms: float, snapshot_ms: float, reps: int = 3) -> dict:
+    """A plain elementwise copy kernel (torch, 16-byte vectors) moving the
+    restore's bytes (n_kept pages) between the restore's own two buffers:
+    packed snapshot -> pool (the restore's direction) and pool -> packed (the
+    fused snapshot pass's direction).  The copy's GB/s count read + write;
+    *_speed_vs_copy is the copy's time over the kernel's (1.0 = as fast as
+    the copy in its direction).  Leaves the pool holding packed bytes."""
+    nbytes = n_kept * PAGE
+    packed = out["packed"][:nbytes].view(torch.int32)
+    pool = case.arena.buf[:nbytes].view(torch.int32)
+    res = {"bytes_copied": nbytes}
+    for name, src, dst in (("packed_to_pool", packed, pool), ("pool_to_packed", pool, packed)):
+        torch.mul(src, 1, out=dst)  # warm
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.mul(src, 1, out=dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": round(ms, 4), "GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}
+    res["restore_scatter_speed_vs_copy"] = round(res["packed_to_pool"]["ms"] / restore_ms, 4)
+    res["snapshot_pass_speed_vs_copy"] = round(res["pool_to_packed"]["ms"] / snapshot_ms, 4)
+    return res
 
 
 def hash_units(torch, kc, ctx, case, ranges, reps: int) -> dict:
