@@ -992,10 +992,13 @@ def serving(torch, kc, W, dev, seconds: float) -> dict:
     from paper_2605_03208_amd import serve
     log(f"serving: c5 for {seconds:.1f} s at 200 req/s")
     torch.cuda.empty_cache()  # arenas come from the server's streams, which cannot reuse earlier cached blocks
+    free, total = torch.cuda.mem_get_info()
+    log(f"serving: device memory free {free / 2**30:.1f} of {total / 2**30:.1f} GiB, torch holds "
+        f"{torch.cuda.memory_allocated() / 2**30:.1f} GiB allocated, {torch.cuda.memory_reserved() / 2**30:.1f} GiB reserved")
     golds, dtypes = W.c5_pool("cuda")
     reqs = W.c5_requests(rate_hz=200.0, duration_s=seconds)
     reqs = [serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed) for r in reqs]
-    ex = serve.DeviceExecutor(golds, dtypes, n_streams=4)
+    ex = serve.DeviceExecutor(golds, dtypes, n_streams=4, arena_bytes=32 << 30)
     log("serving: 2 s warm-up run of the same schedule law (another seed)")
     warm_reqs = W.c5_requests(rate_hz=200.0, duration_s=2.0, seed=55)
     warm = serve.Server(ex, 32 << 30)
@@ -1019,6 +1022,9 @@ def serving(torch, kc, W, dev, seconds: float) -> dict:
     serve.Server(ex, 32 << 30).run([serve.Request(r.rid, r.arrival_s, r.golden_ids, r.ulp_tol, r.seed)
                                     for r in warm_burst])
     torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    log(f"serving: after the warm-up burst, device memory free {free / 2**30:.1f} GiB, torch reserved "
+        f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB")
     srv2 = serve.Server(ex, 32 << 30)
     t0 = time.perf_counter()
     done2 = srv2.run(burst)

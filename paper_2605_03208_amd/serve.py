@@ -122,7 +122,8 @@ class DeviceExecutor:
     when the executor is made (or finished): its streams wait for that work,
     since they do not order themselves after the current stream otherwise."""
 
-    def __init__(self, goldens, dtypes, n_streams: int = 4, device=0, p_pert: float = 1e-4, kmax: int = 16):
+    def __init__(self, goldens, dtypes, n_streams: int = 4, device=0, p_pert: float = 1e-4, kmax: int = 16,
+                 arena_bytes: int | None = None):
         import torch
 
         from . import kc
@@ -148,6 +149,8 @@ class DeviceExecutor:
             st.wait_event(ready)
         self.ctxs = [kc.Context(device) for _ in range(n_streams)]
         self.busy = [None] * n_streams
+        self.arena_cache = {}  # stream -> byte buffer reused by that stream's batches
+        self.arena_bytes = arena_bytes  # size of each stream's buffer when given (e.g. the server's budget)
         self.p_pert, self.kmax = p_pert, kmax
         self.block = max(1, int(round(1.0 / p_pert)))  # one moved element per block, as in W.perturb_many
 
@@ -181,17 +184,23 @@ class DeviceExecutor:
         cand_ptr = np.zeros(len(gids), dtype=np.uint64)
         ev0, ev_mat, ev = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         arenas = []
+        # one arena per element type, carved from the stream's buffer at 256-byte aligned byte offsets
+        plan, total = [], 0
+        for dt in np.unique(dts):
+            sel = np.nonzero(dts == dt)[0]
+            lens = self.numel_arr[gids[sel]]
+            esz = self.flat[int(gids[sel[0]])].element_size()
+            align = max(1, 16 // esz)   # keep every candidate 16-byte aligned
+            padded = -(-lens // align) * align
+            plan.append((sel, lens, esz, padded, total))
+            total += -(-int(padded.sum()) * esz // 256) * 256
         with torch.cuda.stream(s):
             ev0.record(s)
-            for dt in np.unique(dts):
-                sel = np.nonzero(dts == dt)[0]
+            buf = self.arena(stream, total)
+            for sel, lens, esz, padded, at in plan:
                 golds = [self.flat[g] for g in gids[sel].tolist()]
-                lens = self.numel_arr[gids[sel]]
-                esz = golds[0].element_size()
-                align = max(1, 16 // esz)   # keep every candidate 16-byte aligned
-                padded = -(-lens // align) * align
                 offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
-                arena = torch.empty(int(padded.sum()), dtype=golds[0].dtype, device=s.device)
+                arena = buf[at: at + int(padded.sum()) * esz].view(golds[0].dtype)
                 if self.one_pass:
                     kc.materialize(self.ctxs[stream], arena, self.gold_ptr[gids[sel]], offs, lens, seeds[sel],
                                    self.block, self.kmax, stream=s)
@@ -213,6 +222,28 @@ class DeviceExecutor:
                  owners=np.repeat([r.rid for r in reqs], counts).tolist())
         self.busy[stream] = h
         return h
+
+    def arena(self, stream: int, nbytes: int):
+        """The candidate bytes of a batch on ``stream``: a view of one buffer
+        per stream, reused since a stream runs one batch at a time.  With
+        ``arena_bytes`` each buffer is made that size on first use (a server
+        passes its budget, which bounds any batch); otherwise it grows in whole
+        GiB to the largest batch seen, an outgrown buffer going back to the
+        device (a synchronising free).  Fresh device allocations of budget-sized
+        arenas in every batch stalled the loop for up to a second now and then
+        (the allocator's retry path)."""
+        buf = self.arena_cache.get(stream)
+        need = max(256, nbytes)
+        if buf is None or buf.numel() < need:
+            self.arena_cache[stream] = None
+            if buf is not None:  # hand the outgrown buffer back to the device rather than to torch's cache
+                del buf
+                self.torch.cuda.empty_cache()
+            grain = 1 << 30
+            size = max(-(-need // grain) * grain, self.arena_bytes or 0)
+            buf = self.torch.empty(size, dtype=self.torch.uint8, device=self.streams[stream].device)
+            self.arena_cache[stream] = buf
+        return buf[:need]
 
     def done(self, h, now: float) -> bool:
         return h["ev"].query()
