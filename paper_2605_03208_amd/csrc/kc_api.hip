@@ -603,7 +603,7 @@ int kc_restore(kc_ctx* c, const kc_rangeset* crs, const uint64_t* zero_bm_d, con
   KC_HIP(launch_restore_zero(rs->tiles, rs->n_tiles, zero_bm_d, changed_bm_d, bad, rs->ushift, grid, s));
   KernelTimer timer(c, KC_OP_RESTORE, s);
   KC_HIP(launch_restore_scatter(rs->rt, static_cast<const uint8_t*>(packed_d), page_va_d, n_kept_d, cap_pages,
-                                bad, rs->n_ragged > 0, rs->ushift, grid, s));
+                                bad, rs->n_ragged > 0, changed_bm_d != nullptr, rs->ushift, grid, s));
   return KC_OK;
 }
 

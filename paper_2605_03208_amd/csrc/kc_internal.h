@@ -244,7 +244,7 @@ hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64
 hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed,
                                   const uint64_t* page_va, const uint64_t* n_kept,
                                   uint64_t cap_pages, unsigned long long* n_bad,
-                                  bool ragged, uint32_t ushift, uint32_t grid, hipStream_t s);
+                                  bool ragged, bool delta, uint32_t ushift, uint32_t grid, hipStream_t s);
 hipError_t launch_closure(const Tile* tiles, uint32_t n_tiles, uint32_t tile0,
                           const ScanDev& sd, uint32_t grid, uint32_t n_cu, hipStream_t s);
 hipError_t launch_pointer_graph(const Tile* tiles, uint32_t n_tiles, uint64_t lo, uint64_t span,

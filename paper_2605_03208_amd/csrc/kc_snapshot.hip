@@ -497,25 +497,32 @@ __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t
   }
 }
 
-// Packed units back to their VAs, one 4 KiB block per wave and one wave per
-// workgroup, the grid covering every block (no persistent stride): block b of
-// the packed snapshot belongs to slot b >> (ushift - 12); the wave reads that
-// slot's page-VA entry (one scalar load for the whole wave), validates it (4 KiB
-// aligned, inside a range, the start of a unit of that range) with a scalar
-// search of the range set's arrays, and copies the block with four 16-byte
-// loads and stores per lane.  Workgroups are dispatched in block order, so the waves
-// in flight cover one compact, advancing window of both buffers: against a
-// persistent grid striding four-block groups over the snapshot (with a range
-// table loaded into LDS per workgroup) it runs at the speed of a plain copy
-// kernel between the same buffers.
-__global__ __launch_bounds__(64) void k_restore_scatter(RangeTable rt, const uint8_t* packed,
-                                                        const uint64_t* page_va, const uint64_t* n_kept,
-                                                        uint64_t cap, unsigned long long* n_bad, uint32_t ushift) {
-  const uint32_t lane = threadIdx.x;
+// Packed units back to their VAs, one 4 KiB block per wave and WAVES waves
+// (that many consecutive blocks) per workgroup, the grid covering every block
+// of the capacity (no persistent stride).  Block b of the packed snapshot
+// belongs to slot b >> (ushift - 12); the wave reads that slot's page-VA entry
+// (one scalar load for the whole wave), validates it (4 KiB aligned, inside a
+// range, the start of a unit of that range) with a scalar search of the range
+// set's arrays, and copies the block with four 16-byte loads and stores per
+// lane.  Workgroups are dispatched in block order, so the waves in flight cover
+// one compact, advancing window of both buffers: against a persistent grid
+// striding four-block groups over the snapshot (with a range table loaded into
+// LDS per workgroup) the one-wave form runs at the speed of a plain copy
+// kernel between the same buffers.  Four-wave workgroups copy a full snapshot
+// about 5 % slower (a workgroup's slot is freed only when its last wave ends)
+// but dispatch a quarter of the workgroups, which is what a delta restore pays
+// for when its kept count is far below the capacity the grid covers.
+template <uint32_t WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_restore_scatter(RangeTable rt, const uint8_t* packed,
+                                                                   const uint64_t* page_va, const uint64_t* n_kept,
+                                                                   uint64_t cap, unsigned long long* n_bad,
+                                                                   uint32_t ushift) {
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // so the block index is scalar
   const uint32_t bshift = ushift - 12u;  // 4 KiB blocks per unit: 1 << bshift
   const uint64_t unit = 1ull << ushift;
   const uint64_t nblk = min(*n_kept, cap) << bshift;
-  for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  for (uint64_t blk = (uint64_t)blockIdx.x * WAVES + wave; blk < nblk; blk += (uint64_t)gridDim.x * WAVES) {
     const uint64_t sub = blk & ((1ull << bshift) - 1ull);
     const uint64_t va = ((const KC_CONST uint64_t*)page_va)[blk >> bshift];  // one scalar load for the wave
     bool good = false, ok = false;
@@ -814,17 +821,28 @@ hipError_t launch_restore_zero(const Tile* tiles, uint32_t n_tiles, const uint64
   return hipGetLastError();
 }
 
-hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, const uint64_t* page_va,
-                                  const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad,
-                                  bool ragged, uint32_t ushift, uint32_t grid, hipStream_t s) {
-  if (cap_pages == 0) return hipSuccess;
-  // one workgroup per 4 KiB block of the capacity (blocks past the kept count exit at once); the kernel strides
-  // only if a capacity ever exceeded the grid limit
+template <uint32_t WAVES>
+void launch_scatter_waves(const RangeTable& rt, const uint8_t* packed, const uint64_t* page_va,
+                          const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad, uint32_t ushift,
+                          hipStream_t s) {
+  // WAVES blocks per workgroup over every 4 KiB block of the capacity (blocks past the kept count exit at once);
+  // the kernel strides only if a capacity ever exceeded the grid limit
   const uint32_t bshift = ushift - 12u;
   const uint64_t kMaxGrid = 0x7FFFFFFFull;
-  const uint32_t grid_s = cap_pages > (kMaxGrid >> bshift) ? (uint32_t)kMaxGrid : (uint32_t)(cap_pages << bshift);
-  hipLaunchKernelGGL(k_restore_scatter, dim3(grid_s), dim3(64), 0, s, rt, packed, page_va, n_kept, cap_pages,
-                     n_bad, ushift);
+  const uint64_t wgs = cap_pages > ((kMaxGrid * WAVES) >> bshift) ? kMaxGrid
+                                                                   : ((cap_pages << bshift) + WAVES - 1) / WAVES;
+  hipLaunchKernelGGL(k_restore_scatter<WAVES>, dim3((uint32_t)wgs), dim3(WAVES * kWave), 0, s, rt, packed, page_va,
+                     n_kept, cap_pages, n_bad, ushift);
+}
+
+hipError_t launch_restore_scatter(const RangeTable& rt, const uint8_t* packed, const uint64_t* page_va,
+                                  const uint64_t* n_kept, uint64_t cap_pages, unsigned long long* n_bad,
+                                  bool ragged, bool delta, uint32_t ushift, uint32_t grid, hipStream_t s) {
+  if (cap_pages == 0) return hipSuccess;
+  if (delta)
+    launch_scatter_waves<4>(rt, packed, page_va, n_kept, cap_pages, n_bad, ushift, s);
+  else
+    launch_scatter_waves<1>(rt, packed, page_va, n_kept, cap_pages, n_bad, ushift, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ragged) return e;
   const uint64_t groups64 = (cap_pages + 63) / 64;

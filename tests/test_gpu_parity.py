@@ -138,6 +138,19 @@ def test_restore_roundtrip_c1(kc, ctx):
                           u64(va)[:nk], nk) == 2
     host2, views2 = host_of(case)
     assert all(np.array_equal(a, b) for a, b in zip(views2, o_views))
+    say("delta restore (every page marked changed) with the same corrupted entries")
+    for i in range(case.layout.n):
+        case.arena.view(i).fill_(0xA5)
+    every = torch.full((rs.n_words,), -1, dtype=torch.int64, device="cuda")
+    n_bad.zero_()
+    kc.restore(ctx, rs, out["zero_bm"], every, out["packed"], va, out["n_kept"], n_bad=n_bad)
+    torch.cuda.synchronize()
+    assert int(n_bad.item()) == 2
+    o_views = [np.full_like(v, 0xA5) for v in views]
+    assert oracle.restore(ranges, o_views, u64(out["zero_bm"])[: rs.n_words], u64(every), packed[: nk * PAGE],
+                          u64(va)[:nk], nk) == 2
+    host3, views3 = host_of(case)
+    assert all(np.array_equal(a, b) for a, b in zip(views3, o_views))
 
 
 def _tuned_context(kc, signature, ops):
