@@ -49,10 +49,10 @@ PAGE = 4096
 # device copy gives (fetch x2.0, write x1.0).  Valid only for the kernel
 # sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "55c6224fd5b4aaa3efa1c2438a69aea09fb4a58d5615695283faf46b4646083f",
-    "snapshot": 62869444306,   # fetch 31385113271 + write 31484331035
-    "restore": 63687422029,    # fetch 32333169280 + write 31354252749
-    "compare": 64440931994,    # fetch 64440931994 + write 0
+    "source_sha256": "780549f84bfb3f989e297280991776f48325c14db47f28341ed63f67ec42789d",
+    "snapshot": 62869768124,   # fetch 31385126839 + write 31484641285
+    "restore": 63687454976,    # fetch 32333170509 + write 31354284467
+    "compare": 64440929178,    # fetch 64440929178 + write 0
 }
 
 
