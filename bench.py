@@ -49,10 +49,10 @@ PAGE = 4096
 # device copy gives (fetch x2.0, write x1.0).  Valid only for the kernel
 # sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "780549f84bfb3f989e297280991776f48325c14db47f28341ed63f67ec42789d",
-    "snapshot": 62869768124,   # fetch 31385126839 + write 31484641285
-    "restore": 63687454976,    # fetch 32333170509 + write 31354284467
-    "compare": 64440929178,    # fetch 64440929178 + write 0
+    "source_sha256": "aa7340bfa8ef49f4b63f63e3c9191bcfdc9adbd396137300cecb363312c01cb2",
+    "snapshot": 62869757801,   # fetch 31385125120 + write 31484632681
+    "restore": 63687368192,    # fetch 32333170304 + write 31354197888
+    "compare": 64440923955,    # fetch 64440923955 + write 0
 }
 
 

@@ -296,16 +296,30 @@ int kc_rangeset_create_unit(kc_ctx* c, const kc_range* ranges, uint32_t n, uint6
   // Units above 4 KiB: when 16-unit tiles would leave fewer than two waves per SIMD for the pipelined hashing
   // pass, tiles of 8 units give twice the waves (each with half its quads busy), and two waves per SIMD cover
   // each other's instruction latencies (2 MiB units of a 30 GiB pool: 11.4-12.6 ms against 16.5-17.2 ms).
-  uint32_t per_tile = kTilePages;
+  // That pass takes tiles of 32 units up to 256 KiB units (each lane quad hashes two units in turn) when those
+  // still give two waves per SIMD: the skew of its quads then idles them for a smaller share of its rounds.
+  // Measured at 64 KiB units on the 30 GiB pool, averages of three rounds in one process: 11.95 ms against
+  // 12.68 at one unit per quad and 12.53 at four (128 KiB: 12.35 / 12.47 / 12.38).
+  uint32_t per_tile = kTilePages, deep_per_tile = kTilePages;
   if (ushift > kMinUnitShift) {
-    uint64_t t16 = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-      const uint64_t units = (ranges[i].size + (1ull << ushift) - 1) >> ushift;
-      t16 += (units + kTilePages - 1) / kTilePages;
-    }
-    if (t16 < 8ull * c->n_cu) per_tile = kTilePages / 2;
+    auto n_tiles_of = [&](uint64_t per) {
+      uint64_t t = 0;
+      for (uint32_t i = 0; i < n; ++i) t += (((ranges[i].size + (1ull << ushift) - 1) >> ushift) + per - 1) / per;
+      return t;
+    };
+    const uint64_t want = 8ull * c->n_cu;
+    if (n_tiles_of(kTilePages) < want) per_tile = kTilePages / 2;
+    deep_per_tile = per_tile;
+    for (uint32_t u = ushift <= 18 ? 2u : 1u; u > 1u; u /= 2u)
+      if (n_tiles_of(kTilePages * u) >= want) {
+        deep_per_tile = kTilePages * u;
+        break;
+      }
   }
   const uint64_t n_units = build_tiles(ushift, per_tile, tiles, rs->range_tile, &ragged, &rs->ragged_of);
+  std::vector<Tile> deep_tiles;
+  if (deep_per_tile != per_tile) build_tiles(ushift, deep_per_tile, deep_tiles, rs->deep_range_tile, nullptr, nullptr);
+  else rs->deep_range_tile = rs->range_tile;
   if (ushift != kMinUnitShift)
     build_tiles(kMinUnitShift, kTilePages, scan_tiles, rs->scan_range_tile, nullptr, nullptr);
   else rs->scan_range_tile = rs->range_tile;
@@ -319,10 +333,12 @@ int kc_rangeset_create_unit(kc_ctx* c, const kc_range* ranges, uint32_t n, uint6
   rs->n_words = (n_units + 63) / 64;
   rs->n_tiles = (uint32_t)tiles.size();
   rs->n_scan_tiles = ushift != kMinUnitShift ? (uint32_t)scan_tiles.size() : rs->n_tiles;
+  rs->n_deep_tiles = deep_per_tile != per_tile ? (uint32_t)deep_tiles.size() : rs->n_tiles;
 
   const uint64_t nb_words = (rs->n_words + 2047) / 2048, nb_tiles = ((uint64_t)rs->n_scan_tiles + 2047) / 2048;
   const size_t sz_tiles = align_up(sizeof(Tile) * std::max<size_t>(1, tiles.size()), 256);
   const size_t sz_st = align_up(sizeof(Tile) * scan_tiles.size(), 256);  // 4 KiB page tiles of the scans
+  const size_t sz_dt = align_up(sizeof(Tile) * deep_tiles.size(), 256);  // tiles of the pipelined pass
   const size_t sz_r = align_up(8 * std::max<size_t>(1, n), 256);
   const size_t sz_oob = align_up(4 * std::max<size_t>(1, rs->n_scan_tiles), 256);
   const size_t sz_tp = align_up(8 * std::max<size_t>(1, rs->n_scan_tiles), 256);
@@ -331,7 +347,7 @@ int kc_rangeset_create_unit(kc_ctx* c, const kc_range* ranges, uint32_t n, uint6
   const size_t sz_misc = 256 + align_up(8 * kScanCountWords, 256);
   const size_t sz_bk = 2 * align_up(sizeof(uint16_t) * kBuckets, 256);  // bucket index of each fence table
   const size_t sz_rg = align_up(4 * std::max<size_t>(1, ragged.size()), 256);
-  const size_t total = sz_tiles + sz_st + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
+  const size_t total = sz_tiles + sz_st + sz_dt + 2 * sz_r + sz_oob + sz_tp + sz_wp + sz_bs + sz_misc + sz_bk + sz_rg;
   hipError_t e = hipMalloc(&rs->dev, total);
   if (e != hipSuccess) {
     set_error("hipMalloc(rangeset)", e);
@@ -341,6 +357,7 @@ int kc_rangeset_create_unit(kc_ctx* c, const kc_range* ranges, uint32_t n, uint6
   uint8_t* p = static_cast<uint8_t*>(rs->dev);
   rs->tiles = reinterpret_cast<Tile*>(p); p += sz_tiles;
   rs->scan_tiles = ushift != kMinUnitShift ? reinterpret_cast<Tile*>(p) : rs->tiles; p += sz_st;
+  rs->deep_tiles = deep_tiles.empty() ? rs->tiles : reinterpret_cast<Tile*>(p); p += sz_dt;
   rs->bases = reinterpret_cast<uint64_t*>(p); p += sz_r;
   rs->ends = reinterpret_cast<uint64_t*>(p); p += sz_r;
   rs->tile_oob = reinterpret_cast<uint32_t*>(p); p += sz_oob;
@@ -388,6 +405,9 @@ int kc_rangeset_create_unit(kc_ctx* c, const kc_range* ranges, uint32_t n, uint6
   if (!scan_tiles.empty() && (e = hipMemcpy(rs->scan_tiles, scan_tiles.data(), sizeof(Tile) * scan_tiles.size(),
                                             hipMemcpyHostToDevice)) != hipSuccess)
     return fail("hipMemcpy(scan tiles)", e);
+  if (!deep_tiles.empty() && (e = hipMemcpy(rs->deep_tiles, deep_tiles.data(), sizeof(Tile) * deep_tiles.size(),
+                                            hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("hipMemcpy(pipelined pass tiles)", e);
   if (n > 0) {
     if ((e = hipMemcpy(rs->bases, bases.data(), 8 * n, hipMemcpyHostToDevice)) != hipSuccess)
       return fail("hipMemcpy(bases)", e);
@@ -451,16 +471,20 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
   KernelTimer timer(c, op, s);
   // read-only hashing runs best with twice the waves of the fused snapshot (which also writes and scans)
   uint32_t grid = grid_for(c, op, op == KC_OP_PAGE_HASH ? 8 : 4);
-  // large units give few tiles, each a long serial chain: one wave per tile rather than two tiles on some
-  // waves, each wave keeping two chunks in flight in the skewed pass (three or four measured no faster)
-  if (rs->ushift > kMinUnitShift) grid = std::max(grid, std::min(rs->n_tiles, 16u * c->n_cu));
   uint32_t depth = c->tune[op].depth;
   if (depth == 0u && rs->ushift > kMinUnitShift) depth = 2u;
   if (scan) depth = 1u;
+  // the pipelined pass walks its own tiles
+  const bool deep = depth > 1u;
+  Tile* const tiles = deep ? rs->deep_tiles : rs->tiles;
+  const std::vector<uint32_t>& range_tile = deep ? rs->deep_range_tile : rs->range_tile;
+  // large units give few tiles, each a long serial chain: one wave per tile rather than two tiles on some
+  // waves, each wave keeping two chunks in flight in the skewed pass (three or four measured no faster)
+  if (rs->ushift > kMinUnitShift) grid = std::max(grid, std::min(deep ? rs->n_deep_tiles : rs->n_tiles, 16u * c->n_cu));
   hp.ushift = rs->ushift;
   if (!c->tune[op].per_item) {
-    hp.tiles = rs->tiles;
-    hp.n_tiles = rs->n_tiles;
+    hp.tiles = tiles;
+    hp.n_tiles = deep ? rs->n_deep_tiles : rs->n_tiles;
     hp.tile0 = 0;
     hp.ragged = rs->ragged;
     hp.n_ragged = rs->n_ragged;
@@ -468,9 +492,9 @@ static int run_hash(kc_rangeset* rs, HashParams hp, bool gather, bool prior, boo
     return KC_OK;
   }
   for (uint32_t r = 0; r < rs->n_ranges; ++r) {
-    hp.tile0 = rs->range_tile[r];
-    hp.tiles = rs->tiles + hp.tile0;
-    hp.n_tiles = rs->range_tile[r + 1] - hp.tile0;
+    hp.tile0 = range_tile[r];
+    hp.tiles = tiles + hp.tile0;
+    hp.n_tiles = range_tile[r + 1] - hp.tile0;
     const bool rg = rs->ragged_of[r] != UINT32_MAX;
     hp.ragged = rg ? rs->ragged + rs->ragged_of[r] : nullptr;
     hp.n_ragged = rg ? 1u : 0u;

@@ -63,7 +63,7 @@ constexpr uint32_t kMinUnitShift = 12, kMaxUnitShift = 21;
 struct Tile {
   uint64_t va;              // VA of the first unit
   uint32_t g;               // global index of the first unit
-  uint32_t npages : 8;      // 1..16 units
+  uint32_t npages : 8;      // 1..16 units (1..64 in the tiles of the pipelined hashing pass)
   uint32_t last_len : 24;   // 1..unit bytes
 };
 static_assert(sizeof(Tile) == 16, "tile layout");
@@ -351,6 +351,12 @@ struct kc_rangeset {
   uint32_t n_scan_tiles = 0;
   std::vector<uint32_t> scan_range_tile;
   kc::Tile* scan_tiles = nullptr;
+  // tiles of the pipelined hashing pass of large units: up to 32 units of one
+  // range, each lane quad hashing up to two of them in turn (the same list as
+  // `tiles` when a quad takes one unit)
+  uint32_t n_deep_tiles = 0;
+  std::vector<uint32_t> deep_range_tile;
+  kc::Tile* deep_tiles = nullptr;
   void* dev = nullptr;
   kc::Tile* tiles = nullptr;
   uint64_t* bases = nullptr;

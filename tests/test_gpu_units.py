@@ -237,6 +237,70 @@ def test_hashing_depths_agree(kc, unit):
     assert np.array_equal(outs[1][3], h5) and np.array_equal(outs[1][4], ch)
 
 
+def test_unit_runs_per_quad(kc):
+    """2400 ranges of up to 40 units of 8 KiB: enough tiles that the
+    pipelined pass gives each lane quad a run of two units (32-unit tiles) on a
+    256-CU device, with zero units, partial last units and ranges under one
+    unit among them.  At two to four chunks in flight: the snapshot (and under
+    a capacity below the kept count), the read-only hash with its zero bits,
+    and the delta against the set after a rewrite, all against the oracle."""
+    unit = 8192
+    say("units 8192: 2400 ranges, runs of units per quad, depths 2-4")
+    case = W.units_case("cuda", unit=unit, n_ranges=2400, seed=41, max_units=40)
+    ranges = case.ranges()
+    host = case.arena.host_copy().copy()
+    views = W.host_views(case.layout, host)
+    oh, oz, _ = oracle.page_hash(ranges, views, seed=9, unit=unit)
+    op, ova, onk = oracle.compact(ranges, views, oz, unit=unit)
+    cap = onk - onk // 3
+    op2, ova2, _ = oracle.compact(ranges, views, oz, cap_pages=cap, unit=unit)
+    rng = np.random.default_rng(41)
+    picks = rng.choice(len(ranges), size=300, replace=False)
+    outs = []
+    for depth in (2, 3, 4):
+        c = kc.Context(0)
+        for op_ in (kc.OP_SNAPSHOT, kc.OP_PAGE_HASH):
+            c.set_tuning(op_, depth=depth)
+        rs = kc.RangeSet(c, ranges, unit=unit)
+        say(f"units 8192: depth {depth}: snapshot, capacity {cap} of {onk}, read-only hash")
+        out = kc.snapshot(c, rs, seed=9)
+        torch.cuda.synchronize()
+        assert np.array_equal(u64(out["hash"])[:rs.n_pages], oh)
+        assert np.array_equal(u64(out["zero_bm"])[:rs.n_words], oz)
+        assert int(u64(out["n_kept"])[0]) == onk
+        assert np.array_equal(u64(out["page_va"])[:onk], ova)
+        assert np.array_equal(out["packed"][:onk * unit].cpu().numpy(), op)
+        guard = dict(hash=torch.empty_like(out["hash"]), zero_bm=torch.empty_like(out["zero_bm"]), changed_bm=None,
+                     packed=torch.full(((cap + 2) * unit,), 0xA5, dtype=torch.uint8, device="cuda"),
+                     page_va=torch.full((cap + 2,), -1, dtype=torch.int64, device="cuda"),
+                     n_kept=torch.empty(1, dtype=torch.int64, device="cuda"))
+        kc.snapshot(c, rs, seed=9, cap_pages=cap, out=guard)
+        h, z, _ = kc.page_hash(c, rs, seed=9)
+        torch.cuda.synchronize()
+        assert int(u64(guard["n_kept"])[0]) == onk
+        assert np.array_equal(u64(guard["page_va"])[:cap], ova2)
+        assert np.array_equal(guard["packed"][:cap * unit].cpu().numpy(), op2)
+        assert bool((guard["packed"][cap * unit:] == 0xA5).all()) and bool((guard["page_va"][cap:] == -1).all())
+        assert np.array_equal(u64(h)[:rs.n_pages], oh) and np.array_equal(u64(z)[:rs.n_words], oz)
+        outs.append((c, rs, out))
+    say("units 8192: rewrite a byte in 300 ranges (zero units among them), delta at depths 2-4")
+    for a in picks:
+        o, sz = int(case.layout.offsets[a]), int(case.layout.sizes[a])
+        pos = o + int(rng.integers(0, sz))
+        case.arena.buf[pos] = (int(host[pos]) + 1) % 256
+    v2 = W.host_views(case.layout, case.arena.host_copy())
+    dh, dz, dc = oracle.page_hash(ranges, v2, seed=9, prior=oh, unit=unit)
+    assert words_to_bits(dc, len(oh)).sum() == 300
+    for c, rs, out in outs:
+        h2, z2, c2 = kc.page_hash(c, rs, seed=9, prior=out["hash"])
+        torch.cuda.synchronize()
+        assert np.array_equal(u64(h2)[:rs.n_pages], dh)
+        assert np.array_equal(u64(z2)[:rs.n_words], dz)
+        assert np.array_equal(u64(c2)[:rs.n_words], dc)
+        rs.close()
+        c.close()
+
+
 @pytest.mark.parametrize("unit", [65536, 1 << 21])
 def test_units_c2_full(kc, ctx, unit):
     """The 2 GiB set of 4096 ranges (sizes 4 KiB to 64 MiB): most ranges end in
