@@ -241,9 +241,10 @@ def test_unit_runs_per_quad(kc):
     """2400 ranges of up to 40 units of 8 KiB: enough tiles that the
     pipelined pass gives each lane quad a run of two units (32-unit tiles) on a
     256-CU device, with zero units, partial last units and ranges under one
-    unit among them.  At two to four chunks in flight: the snapshot (and under
-    a capacity below the kept count), the read-only hash with its zero bits,
-    and the delta against the set after a rewrite, all against the oracle."""
+    unit among them.  At two to four chunks in flight, and with one launch per
+    range: the snapshot (and under a capacity below the kept count), the
+    read-only hash with its zero bits, and the delta against the set after a
+    rewrite, all against the oracle."""
     unit = 8192
     say("units 8192: 2400 ranges, runs of units per quad, depths 2-4")
     case = W.units_case("cuda", unit=unit, n_ranges=2400, seed=41, max_units=40)
@@ -257,12 +258,13 @@ def test_unit_runs_per_quad(kc):
     rng = np.random.default_rng(41)
     picks = rng.choice(len(ranges), size=300, replace=False)
     outs = []
-    for depth in (2, 3, 4):
+    for depth, per_item in ((2, 0), (3, 0), (4, 0), (2, 1)):
         c = kc.Context(0)
         for op_ in (kc.OP_SNAPSHOT, kc.OP_PAGE_HASH):
-            c.set_tuning(op_, depth=depth)
+            c.set_tuning(op_, depth=depth, per_item=per_item)
         rs = kc.RangeSet(c, ranges, unit=unit)
-        say(f"units 8192: depth {depth}: snapshot, capacity {cap} of {onk}, read-only hash")
+        say(f"units 8192: depth {depth}, one launch per range {per_item}: snapshot, capacity {cap} of {onk}, "
+            "read-only hash")
         out = kc.snapshot(c, rs, seed=9)
         torch.cuda.synchronize()
         assert np.array_equal(u64(out["hash"])[:rs.n_pages], oh)
@@ -283,7 +285,7 @@ def test_unit_runs_per_quad(kc):
         assert bool((guard["packed"][cap * unit:] == 0xA5).all()) and bool((guard["page_va"][cap:] == -1).all())
         assert np.array_equal(u64(h)[:rs.n_pages], oh) and np.array_equal(u64(z)[:rs.n_words], oz)
         outs.append((c, rs, out))
-    say("units 8192: rewrite a byte in 300 ranges (zero units among them), delta at depths 2-4")
+    say("units 8192: rewrite a byte in 300 ranges (zero units among them), delta in each context")
     for a in picks:
         o, sz = int(case.layout.offsets[a]), int(case.layout.sizes[a])
         pos = o + int(rng.integers(0, sz))
