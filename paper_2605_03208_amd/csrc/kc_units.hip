@@ -1,6 +1,7 @@
 // kc_units.hip -- the hashing pass of hash units above 4 KiB (8 KiB to 2 MiB):
-// a lane quad per unit as in the 4 KiB pass, with several chunks in flight per
-// wave and the quads skewed over the unit's chunks.
+// a lane quad per unit at a time as in the 4 KiB pass, each quad hashing a run
+// of one or more units in turn, with several chunks in flight per wave and the
+// quads skewed over their runs' chunks.
 #include <algorithm>
 
 #include "kc_device.h"
