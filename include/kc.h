@@ -563,8 +563,8 @@ int kc_snapshot_save(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
  * leave the missing pages unwritten.  On success *n_kept_d equals the number
  * of packed pages loaded.  Host-to-device copies are chunked like the save
  * (a chunk is read while the copies of up to three earlier ones are in
- * flight); *stats splits the time into copy waits and file reads.
- * Synchronous. */
+ * flight), each chunk read by up to four host threads on slices of it;
+ * *stats splits the time into copy waits and file reads.  Synchronous. */
 int kc_snapshot_load(kc_ctx *ctx, const kc_rangeset *rs, const char *dir,
                      uint64_t *hash_d, uint64_t *zero_bm_d,
                      uint64_t *changed_bm_d, void *packed_d,

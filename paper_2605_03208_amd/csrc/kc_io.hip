@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kc_internal.h"
@@ -68,6 +69,44 @@ bool read_all(int fd, uint8_t* p, size_t n) {
     n -= (size_t)r;
   }
   return true;
+}
+
+// [p, p + n) from the file at offset off, split into up to kIoThreads
+// contiguous 1 MiB-aligned slices on as many threads: a page-cache copy runs at
+// one core's memory bandwidth, and reads of one file proceed in parallel, so
+// the slices' copies add up (2 GiB from a memory file system: 19-20 GB/s
+// against 8.6-8.9 on one thread).  Writes stay on one thread: writes to one
+// file take its inode lock in turn, and sliced writes measured no faster.  A
+// thread that cannot be started has its slice read on the calling thread.
+constexpr int kIoThreads = 4;
+bool read_at(int fd, uint8_t* p, size_t n, uint64_t off) {
+  const auto one = [fd, p, off](size_t a, size_t b) -> bool {
+    while (a < b) {
+      const ssize_t r = ::pread(fd, p + a, b - a, (off_t)(off + a));
+      if (r <= 0) return false;
+      a += (size_t)r;
+    }
+    return true;
+  };
+  const size_t slice = ((n + kIoThreads - 1) / kIoThreads + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+  if (n <= slice) return one(0, n);
+  std::thread th[kIoThreads];
+  bool ok[kIoThreads] = {};
+  int k = 0;
+  for (size_t a = slice; a < n; a += slice, ++k) {
+    const size_t b = std::min(n, a + slice);
+    try {
+      th[k] = std::thread([&one, &ok, a, b, k] { ok[k] = one(a, b); });
+    } catch (...) {
+      ok[k] = one(a, b);
+    }
+  }
+  bool all = one(0, slice);
+  for (int i = 0; i < k; ++i) {
+    if (th[i].joinable()) th[i].join();
+    all = all && ok[i];
+  }
+  return all;
 }
 
 }  // namespace
@@ -155,7 +194,7 @@ int stream_from_file(const std::string& path, void* dst_d, uint64_t bytes, Pinne
       }
     }
     const double t = now_s();
-    const bool ok = read_all(fd, pin.p[b], len);
+    const bool ok = read_at(fd, pin.p[b], len, off);
     ck.file += now_s() - t;
     if (!ok) {
       err = "short read from " + path;
