@@ -49,10 +49,10 @@ PAGE = 4096
 # device copy gives (fetch x2.0, write x1.0).  Valid only for the kernel
 # sources they were taken from.
 PMC_TRAFFIC = {
-    "source_sha256": "aa7340bfa8ef49f4b63f63e3c9191bcfdc9adbd396137300cecb363312c01cb2",
-    "snapshot": 62869757801,   # fetch 31385125120 + write 31484632681
-    "restore": 63687368192,    # fetch 32333170304 + write 31354197888
-    "compare": 64440923955,    # fetch 64440923955 + write 0
+    "source_sha256": "e1c6a004cddd500c648e60c69194f8845c910135b386660677fe57bc9c581063",
+    "snapshot": 62869523365,   # fetch 31385126181 + write 31484397184
+    "restore": 63687466317,    # fetch 32333170304 + write 31354296013
+    "compare": 64440925107,    # fetch 64440925107 + write 0
 }
 
 

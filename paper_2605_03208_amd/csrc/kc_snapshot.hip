@@ -503,8 +503,8 @@ __global__ __launch_bounds__(64) void k_restore_zero(const Tile* tiles, uint32_t
 // belongs to slot b >> (ushift - 12); the wave reads that slot's page-VA entry
 // (one scalar load for the whole wave), validates it (4 KiB aligned, inside a
 // range, the start of a unit of that range) with a scalar search of the range
-// set's arrays, and copies the block with four 16-byte loads and stores per
-// lane.  Workgroups are dispatched in block order, so the waves in flight cover
+// set's arrays, and copies the block, if it lies wholly inside the range, with
+// four 16-byte loads and stores per lane.  Workgroups are dispatched in block order, so the waves in flight cover
 // one compact, advancing window of both buffers: against a persistent grid
 // striding four-block groups over the snapshot (with a range table loaded into
 // LDS per workgroup) the one-wave form runs at the speed of a plain copy
@@ -528,9 +528,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_restore_scatter(RangeTable rt
     bool good = false, ok = false;
     if ((va & (kPage - 1)) == 0) {
       const RangeHit r = range_find_uniform(va, rt);
-      if (r.a >= 0) {  // a range's partial last unit is left to k_restore_tail
+      if (r.a >= 0) {  // of a range's partial last unit, the bytes past its last whole block go to k_restore_tail
         good = ((va - r.base) & (unit - 1ull)) == 0ull;
-        ok = good && va + unit <= r.end;
+        ok = good && va + (sub << 12) + kPage <= r.end;
       }
     }
     if (!good && sub == 0 && lane == 0) atomicAdd(n_bad, 1ull);  // counted once per slot
@@ -544,8 +544,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_restore_scatter(RangeTable rt
   }
 }
 
-// Packed units bound for a range's partial last unit: only the unit's own
-// bytes are written.  One lane per slot finds them; the wave copies each.
+// Packed units bound for a range's partial last unit: the restore scatter
+// copies its whole 4 KiB blocks; here only its last bytes past them are
+// written, never past the range's end.  One lane per slot finds such units;
+// the wave copies each one's remainder (under 4 KiB).
 __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_t* packed, const uint64_t* page_va,
                                                      const uint64_t* n_kept, uint64_t cap, uint32_t ushift) {
   __shared__ FenceLds fences;
@@ -563,7 +565,8 @@ __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_
       if (a >= 0) {
         const uint64_t base = rt.stride == 1u ? fences.base[a] : ld8g(rt.base + a);
         const uint64_t end = rt.stride == 1u ? fences.end[a] : ld8g(rt.end + a);
-        if (((va - base) & (unit - 1ull)) == 0ull && va + unit > end) len = (uint32_t)(end - va);
+        if (((va - base) & (unit - 1ull)) == 0ull && va + unit > end && ((end - va) & (kPage - 1)) != 0ull)
+          len = (uint32_t)(end - va);
       }
     }
     for (uint64_t m = __ballot(len != 0u); m != 0ull; m &= m - 1ull) {
@@ -571,12 +574,11 @@ __global__ __launch_bounds__(64) void k_restore_tail(RangeTable rt, const uint8_
       const uint64_t dva = __shfl((unsigned long long)va, L, 64);
       const uint32_t dlen = __shfl(len, L, 64);
       const uint64_t src = (uint64_t)packed + ((s0 + (uint64_t)L) << ushift);
-      for (uint32_t o0 = 0; o0 < dlen; o0 += kPage) {
+      const uint32_t o0 = dlen & ~(kPage - 1u);  // the bytes before it went with the scatter's whole blocks
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) {
-          const uint32_t o = o0 + j * 1024u + lane * 16u;
-          if (o < dlen) st_bytes(dva + o, ld16nt(src + o), dlen - o);  // never past the range's end
-        }
+      for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t o = o0 + j * 1024u + lane * 16u;
+        if (o < dlen) st_bytes(dva + o, ld16nt(src + o), dlen - o);  // never past the range's end
       }
     }
   }
